@@ -1,0 +1,167 @@
+/*
+ * mhk.h -- C ABI of libmhk: fast evaluation of the layer potentials S[sigma],
+ * D[mu] and the volume potential V[f] of the 2D modified Helmholtz equation
+ * (-Lap + alpha^2) u = f, with G(x) = K0(alpha |x|)/(2 pi) (paper Section 1,
+ * eqs. (mod_helm), (Greens), (vp), (slp), (dlp)), on one AMD MI355X (gfx950).
+ *
+ * The Green's function is split in time (Section 2.1, eqs. (ker_greens),
+ * (sl_sh), (slp_dyad)): t > delta is the smooth history part, evaluated by a
+ * type-1 NUFFT of the quadrature sources, the multiplier of eq. (sh_fourier)
+ * and a type-2 NUFFT at the targets (Section 5); t in [delta/4^j,
+ * delta/4^(j-1)], j = 1..J, are the dyadic difference-kernel levels of the
+ * layer potentials, summed over locally bisected panels (Section 4.2, eqs.
+ * (diffker_s), (diffker_dlp)); t < delta* = delta/4^J (delta for V) is the
+ * local asymptotic part (Lemmas 4.1, 4.5, 4.8 and Corollaries 4.4, 4.7,
+ * 4.10, 4.11, kept to first order as stated in Section 4.1).
+ *
+ * Conventions common to every call
+ *  - Geometry passed to mhk_plan_create is HOST memory; the plan copies and
+ *    reorders it into device buffers that it owns.  The caller may free its
+ *    arrays as soon as mhk_plan_create returns.
+ *  - Densities, sources and outputs passed to the eval calls are DEVICE
+ *    pointers (e.g. a torch tensor's data_ptr()), contiguous, in the caller's
+ *    node order, with the batch index outermost: sigma[b][N_B].  Their type
+ *    is double when params.prec == MHK_FP64 and float when MHK_FP32.
+ *  - Eval calls are asynchronous on the stream given at plan creation; the
+ *    outputs are valid once that stream has been synchronised.  A plan is
+ *    not re-entrant; different plans may run concurrently on different
+ *    streams.
+ *  - Every call returns an mhk_status; on error nothing is enqueued and
+ *    mhk_last_error() (thread-local) describes the problem.
+ *  - Boundary: n_panels panels of 16 Gauss-Legendre nodes each, panel
+ *    contiguous, every curve counter-clockwise with panels in increasing
+ *    parameter order (Section 3.2).  nx, ny is the outward unit normal, w the
+ *    quadrature weight (eq. (eq:bdry_quad), speed included) and kappa the
+ *    signed curvature (positive where the curve is convex).
+ *  - Target outputs: the N_T off-surface targets first, then, if
+ *    targets.on_surface is set, the N_B boundary nodes as on-surface targets
+ *    (D there is the direct value, i.e. the principal value of eq. (jumprel)).
+ *    V has no local formula at exterior targets closer to the boundary than
+ *    sqrt(delta)(12 + 2 alpha sqrt(delta)) (Lemma 4.8 holds for x in Omega);
+ *    those entries are NaN.
+ */
+#ifndef MHK_H
+#define MHK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MHK_OK = 0,
+    MHK_EINVAL = -1,       /* invalid argument (message in mhk_last_error) */
+    MHK_ENOMEM = -2,       /* device allocation failed / footprint too large */
+    MHK_EHIP = -3,         /* HIP runtime or rocFFT error */
+    MHK_EUNSUPPORTED = -4  /* valid but unsupported configuration */
+} mhk_status;
+
+enum { MHK_FP64 = 0, MHK_FP32 = 1 };
+
+/* Parts of the split, for mhk_eval_parts (bit mask). */
+enum { MHK_PART_HISTORY = 1, MHK_PART_LEVELS = 2, MHK_PART_LOCAL = 4, MHK_PART_ALL = 7 };
+
+typedef struct {
+    double alpha;    /* > 0, modified Helmholtz parameter (eq. (mod_helm))          */
+    double tol;      /* requested relative accuracy, 1e-13 <= tol <= 1e-3; sets the
+                        Fourier cut-off (eqs. (kmax), (kmax_dlp)), the spreading
+                        window and the level cut-off radii                          */
+    int prec;        /* MHK_FP64 or MHK_FP32 (FP32 spreading, FFT, interpolation
+                        and level sums; the local part is always FP64)              */
+    int J;           /* dyadic levels, delta* = delta/4^J (eq. (slp_dyad)); < 0: 3  */
+    double delta;    /* history split; <= 0: from dx by the rule of Section 6.4:
+                        k_max = 0.9 pi/dx (eq. (k_nyq)), delta = ln(1/tol)/(k_max^2
+                        + alpha^2) (eq. (kmax) solved for delta)                    */
+    double dx;       /* volume mesh size, used only when delta <= 0                 */
+    int batch;       /* number of densities / sources per eval call, >= 1           */
+    double upsamp;   /* fine-grid oversampling of the NUFFT; <= 0: 2.0              */
+    int wspread;     /* spreading window width in grid points; <= 0: from tol       */
+} mhk_params;
+
+typedef struct {
+    int64_t n_panels;                 /* panels of 16 nodes; N_B = 16 n_panels     */
+    int32_t n_curves;                 /* closed curves                              */
+    const int64_t *curve_panel_ofs;   /* host [n_curves+1], panel offsets           */
+    const double *x, *y, *nx, *ny, *w, *kappa;   /* host [N_B]                      */
+} mhk_boundary;
+
+typedef struct {
+    int64_t n;                        /* N_V volume quadrature nodes (may be 0)     */
+    const double *x, *y, *w;          /* host [N_V] nodes and weights (eq. (vol_quad)) */
+} mhk_volume;
+
+typedef struct {
+    int64_t n;                        /* N_T off-surface targets (may be 0)         */
+    const double *x, *y;              /* host [N_T]                                  */
+    const int8_t *inside;             /* host [N_T], 1 inside Omega, 0 outside       */
+    int on_surface;                   /* 1: append the N_B boundary nodes as targets */
+} mhk_targets;
+
+typedef struct {
+    double alpha, tol, delta, delta_star;
+    int J, prec, batch;
+    double kmax;          /* Fourier cut-off of the history part (eq. (kmax_dlp))    */
+    double period;        /* period of the history grid (Nyquist rule, eq. (nf))     */
+    int64_t n_fine;       /* fine grid points per dimension                          */
+    int wspread;          /* window width                                            */
+    double band_layer;    /* sqrt(delta*)(12 + 2 alpha sqrt(delta*)), Remark 4.3      */
+    double band_volume;   /* sqrt(delta)(12 + 2 alpha sqrt(delta))                   */
+    double level_radius[8];
+    int64_t n_boundary, n_volume, n_targets, n_out;
+    int64_t device_bytes; /* device memory owned by the plan                         */
+    /* milliseconds of the last eval per stage (0 unless timing was enabled)       */
+    double ms_spread, ms_fft, ms_multiply, ms_interp, ms_levels, ms_local, ms_total;
+} mhk_info;
+
+typedef struct mhk_plan mhk_plan;
+
+/* Resolve the split parameters without creating a plan (host only, no GPU):
+ * fills delta (from dx when params->delta <= 0), delta_star, kmax, band_* and
+ * level_radius of *info.  Returns MHK_EINVAL for invalid params. */
+mhk_status mhk_resolve_params(const mhk_params *params, mhk_info *info);
+
+/* Build a plan: resolve parameters, copy and sort geometry and targets into
+ * device buffers, build the level kernel tables and the FFT plans.  The
+ * stream (a hipStream_t, NULL for the default stream) is used by every later
+ * call on the plan.  *out is set to NULL on error. */
+mhk_status mhk_plan_create(const mhk_params *params, const mhk_boundary *boundary,
+                           const mhk_volume *volume, const mhk_targets *targets,
+                           void *hip_stream, mhk_plan **out);
+
+/* Device bytes a plan with these inputs would own, without allocating. */
+mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *boundary,
+                              const mhk_volume *volume, const mhk_targets *targets,
+                              int64_t *bytes);
+
+/* S[sigma], D[mu] and V[f] at all targets (Section 2.1 split: history +
+ * levels + local).  Any of sigma, mu, f_vol may be NULL: the matching output
+ * is then not written.  sigma, mu: [batch][N_B]; f_vol: [batch][N_V] values
+ * of f at the volume nodes; f_trg: [batch][n_out] values of f at the targets
+ * (needed by the local part of V, Lemma 4.8; required when f_vol is given);
+ * out_S, out_D, out_V: [batch][n_out]. */
+mhk_status mhk_eval(mhk_plan *plan, const void *sigma, const void *mu, const void *f_vol,
+                    const void *f_trg, void *out_S, void *out_D, void *out_V);
+
+/* Single-potential forms of mhk_eval. */
+mhk_status mhk_eval_S(mhk_plan *plan, const void *sigma, void *out_S);
+mhk_status mhk_eval_D(mhk_plan *plan, const void *mu, void *out_D);
+mhk_status mhk_eval_V(mhk_plan *plan, const void *f_vol, const void *f_trg, void *out_V);
+
+/* As mhk_eval, restricted to the parts in the mask (MHK_PART_*). */
+mhk_status mhk_eval_parts(mhk_plan *plan, int parts, const void *sigma, const void *mu,
+                          const void *f_vol, const void *f_trg, void *out_S, void *out_D,
+                          void *out_V);
+
+/* Enable (1) or disable (0) per-stage timing with HIP events; when enabled,
+ * each eval synchronises its stream at the end and fills the ms_* fields. */
+mhk_status mhk_plan_set_timing(mhk_plan *plan, int enable);
+
+mhk_status mhk_plan_info(const mhk_plan *plan, mhk_info *info);
+void mhk_plan_destroy(mhk_plan *plan);
+const char *mhk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHK_H */

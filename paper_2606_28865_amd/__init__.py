@@ -1,0 +1,7 @@
+"""MI355X-native evaluation of the kernel-split layer and volume potentials
+of the 2D modified Helmholtz equation (HIP library libmhk.so + binding)."""
+from ._lib import (MHK_FP32, MHK_FP64, PART_ALL, PART_HISTORY, PART_LEVELS, PART_LOCAL, Info, MhkError,
+                   Params, Plan, footprint, lib, make_params, resolve_params)
+
+__all__ = ["MHK_FP32", "MHK_FP64", "PART_ALL", "PART_HISTORY", "PART_LEVELS", "PART_LOCAL", "Info",
+           "MhkError", "Params", "Plan", "footprint", "lib", "make_params", "resolve_params"]

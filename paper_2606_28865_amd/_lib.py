@@ -1,0 +1,233 @@
+"""ctypes binding of libmhk.so (argument marshalling only).
+
+Every step of the evaluation runs in the HIP library; this module only
+converts numpy arrays and torch device tensors to the C ABI of
+include/mhk.h.  Importing it without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhk.so")
+
+MHK_FP64, MHK_FP32 = 0, 1
+PART_HISTORY, PART_LEVELS, PART_LOCAL, PART_ALL = 1, 2, 4, 7
+NGL = 16
+
+
+class Params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("prec", C.c_int), ("J", C.c_int),
+                ("delta", C.c_double), ("dx", C.c_double), ("batch", C.c_int),
+                ("upsamp", C.c_double), ("wspread", C.c_int)]
+
+
+class Boundary(C.Structure):
+    _fields_ = [("n_panels", C.c_int64), ("n_curves", C.c_int32), ("curve_panel_ofs", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("nx", C.c_void_p), ("ny", C.c_void_p),
+                ("w", C.c_void_p), ("kappa", C.c_void_p)]
+
+
+class Volume(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("w", C.c_void_p)]
+
+
+class Targets(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("inside", C.c_void_p),
+                ("on_surface", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("delta", C.c_double), ("delta_star", C.c_double),
+                ("J", C.c_int), ("prec", C.c_int), ("batch", C.c_int),
+                ("kmax", C.c_double), ("period", C.c_double), ("n_fine", C.c_int64), ("wspread", C.c_int),
+                ("band_layer", C.c_double), ("band_volume", C.c_double), ("level_radius", C.c_double * 8),
+                ("n_boundary", C.c_int64), ("n_volume", C.c_int64), ("n_targets", C.c_int64),
+                ("n_out", C.c_int64), ("device_bytes", C.c_int64),
+                ("ms_spread", C.c_double), ("ms_fft", C.c_double), ("ms_multiply", C.c_double),
+                ("ms_interp", C.c_double), ("ms_levels", C.c_double), ("ms_local", C.c_double),
+                ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "level_radius" else v
+        return d
+
+
+EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
+           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_set_timing", "mhk_plan_info",
+           "mhk_plan_destroy", "mhk_last_error"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmhk.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.mhk_resolve_params.argtypes = [P(Params), P(Info)]
+        L.mhk_plan_create.argtypes = [P(Params), P(Boundary), P(Volume), P(Targets), C.c_void_p, P(C.c_void_p)]
+        L.mhk_plan_footprint.argtypes = [P(Params), P(Boundary), P(Volume), P(Targets), P(C.c_int64)]
+        L.mhk_eval.argtypes = [C.c_void_p] + [C.c_void_p] * 7
+        L.mhk_eval_S.argtypes = [C.c_void_p] * 3
+        L.mhk_eval_D.argtypes = [C.c_void_p] * 3
+        L.mhk_eval_V.argtypes = [C.c_void_p] * 4
+        L.mhk_eval_parts.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        L.mhk_plan_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.mhk_plan_info.argtypes = [C.c_void_p, P(Info)]
+        L.mhk_plan_destroy.argtypes = [C.c_void_p]
+        L.mhk_plan_destroy.restype = None
+        L.mhk_last_error.restype = C.c_char_p
+        for name in EXPORTS[:-2] + ["mhk_plan_info"]:
+            if name != "mhk_plan_destroy":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class MhkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mhk error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise MhkError(rc, lib().mhk_last_error().decode())
+
+
+def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0):
+    return Params(float(alpha), float(tol), int(prec), int(J), float(delta), float(dx), int(batch),
+                  float(upsamp), int(wspread))
+
+
+def resolve_params(**kw):
+    info = Info()
+    _check(lib().mhk_resolve_params(C.byref(make_params(**kw)), C.byref(info)))
+    return info.as_dict()
+
+
+class _Keep:
+    def __init__(self):
+        self.arrays = []
+
+    def f64(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self.arrays.append(a)
+        return a.ctypes.data
+
+    def typed(self, a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        self.arrays.append(a)
+        return a.ctypes.data
+
+
+def _structs(boundary, volume, targets, on_surface, keep):
+    b = boundary
+    nb = len(b["x"])
+    if nb % NGL:
+        raise ValueError("boundary size must be a multiple of 16")
+    ofs = np.asarray(b.get("curve_panel_ofs", [0, nb // NGL]), dtype=np.int64)
+    B = Boundary(nb // NGL, len(ofs) - 1, keep.typed(ofs, np.int64), keep.f64(b["x"]), keep.f64(b["y"]),
+                 keep.f64(b["nx"]), keep.f64(b["ny"]), keep.f64(b["w"]), keep.f64(b["kappa"]))
+    if volume is not None and len(volume["x"]) > 0:
+        V = Volume(len(volume["x"]), keep.f64(volume["x"]), keep.f64(volume["y"]), keep.f64(volume["w"]))
+    else:
+        V = Volume(0, None, None, None)
+    if targets is not None:
+        tx, ty, ins = targets
+        T = Targets(len(tx), keep.f64(tx), keep.f64(ty), keep.typed(np.asarray(ins).astype(np.int8), np.int8),
+                    int(bool(on_surface)))
+    else:
+        T = Targets(0, None, None, None, int(bool(on_surface)))
+    return B, V, T
+
+
+def footprint(params, boundary, volume=None, targets=None, on_surface=False):
+    keep = _Keep()
+    B, V, T = _structs(boundary, volume, targets, on_surface, keep)
+    out = C.c_int64(0)
+    _check(lib().mhk_plan_footprint(C.byref(params), C.byref(B), C.byref(V), C.byref(T), C.byref(out)))
+    return int(out.value)
+
+
+class Plan:
+    """A resident evaluation plan on the current torch HIP stream.
+
+    boundary: dict of host arrays x, y, nx, ny, w, kappa (16 Gauss-Legendre
+    nodes per panel, panel contiguous) and curve_panel_ofs; volume: dict x, y,
+    w or None; targets: (x, y, inside) host arrays.
+    """
+
+    def __init__(self, params: Params, boundary, volume=None, targets=None, on_surface=False, stream=None):
+        import torch
+        self.params = params
+        keep = _Keep()
+        B, V, T = _structs(boundary, volume, targets, on_surface, keep)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().mhk_plan_create(C.byref(params), C.byref(B), C.byref(V), C.byref(T),
+                                     C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.nb = int(B.n_panels) * NGL
+        self.nv = int(V.n)
+        self.nt = int(T.n)
+        self.n_out = self.nt + (self.nb if on_surface else 0)
+        self.batch = int(params.batch)
+        self.dtype = torch.float64 if params.prec == MHK_FP64 else torch.float32
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mhk_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = Info()
+        _check(lib().mhk_plan_info(self._h, C.byref(i)))
+        return i.as_dict()
+
+    def set_timing(self, on=True):
+        _check(lib().mhk_plan_set_timing(self._h, int(bool(on))))
+
+    def _dev(self, t, n):
+        import torch
+        if t is None:
+            return None
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.dtype and t.is_contiguous()):
+            raise TypeError("densities must be contiguous device tensors of the plan's dtype")
+        if t.numel() != self.batch * n:
+            raise ValueError(f"expected {self.batch} x {n} values, got {t.numel()}")
+        return t
+
+    def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None):
+        """Returns (S, D, V) device tensors [batch, n_out] (None where not requested)."""
+        import torch
+        sigma = self._dev(sigma, self.nb)
+        mu = self._dev(mu, self.nb)
+        f_vol = self._dev(f_vol, self.nv)
+        f_trg = self._dev(f_trg, self.n_out)
+        shape = (self.batch, self.n_out)
+        dev = torch.device("cuda")
+        if out is None:
+            out = tuple(torch.empty(shape, dtype=self.dtype, device=dev) if x is not None else None
+                        for x in (sigma, mu, f_vol))
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        _check(lib().mhk_eval_parts(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
+                                    ptr(out[0]), ptr(out[1]), ptr(out[2])))
+        return out

@@ -1,0 +1,321 @@
+// History part (Section 5): type-1 NUFFT of the quadrature sources, the
+// multiplier of eq. (sh_fourier), type-2 NUFFT at the targets.
+//
+//   spread    g_m = sum_j q_j phi(x_m - x_j) on a periodic fine grid of step h
+//             (q = w sigma, w' f, w nu_x mu, w nu_y mu: eqs. (disrete_sigma_hat),
+//             (rhs_vol) and the D transform of Section 5.1);
+//   FFT       rocFFT real-to-complex, in place;
+//   multiply  c_l = (h^4/P^2) m(k_l) G_l / phihat(k_l)^2 for S and V, and
+//             (h^4/P^2) m(k_l) (-i k_l . G_l) / phihat(k_l)^2 for D, where
+//             m(k) = exp(-delta(alpha^2 + |k|^2))/(alpha^2 + |k|^2) (eq. (sh))
+//             and c_l = 0 outside the square |k_x|, |k_y| <= k_max;
+//   FFT       rocFFT complex-to-real, in place;
+//   interp    u(x) = sum_m phi(x - x_m) U_m.
+//
+// Spreading: one workgroup owns one 32x32 tile of the fine grid and one
+// density of the batch.  It visits the sources of the 3x3 neighbouring tiles
+// (sorted by tile at plan time), adds the part of each source's w x w window
+// that falls in its own tile into LDS with LDS atomics, and writes the tile
+// once: every grid value is written exactly once, with no global atomics.
+// Interpolation: one workgroup per non-empty target tile stages the tile plus
+// its window halo of the three result grids in LDS with coalesced row reads.
+#include "mhk_internal.h"
+
+namespace mhk {
+
+struct SpreadArgs {
+    int64_t n, field, nb, nv;
+    int ntile, B;
+    double beta;
+    const double *bgx, *bgy, *bw, *bwx, *bwy;
+    const int32_t *bidx, *btile;
+    const double *vgx, *vgy, *vw;
+    const int32_t *vidx, *vtile;
+    const double *sigma, *mu, *f_vol;
+    double *grid;          // [4][B][field]: S, V, Dx, Dy sources
+};
+
+template <int W>
+__device__ inline void window_weights(double g, double beta, int &m0, double *wt)
+{
+    m0 = (int)ceil(g - 0.5 * W);
+    const double sc = 2.0 / W;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const double z = (m0 + k - g) * sc;
+        const double z2 = 1.0 - z * z;
+        wt[k] = (z2 > 0.0) ? exp(beta * (sqrt(z2) - 1.0)) : 0.0;
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
+{
+    __shared__ double tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
+    const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int tx = tile % A.ntile, ty = tile / A.ntile;
+    const int x0 = tx * TILE, y0 = ty * TILE;
+    for (int i = tid; i < TILE * TILE; i += 256) tileS[i] = tileV[i] = tileX[i] = tileY[i] = 0.0;
+    __syncthreads();
+    const bool has_b = A.sigma || A.mu;
+    for (int dty = -1; dty <= 1; ++dty) {
+        const int tyy = ty + dty;
+        if (tyy < 0 || tyy >= A.ntile) continue;
+        const int xa = max(tx - 1, 0), xb = min(tx + 1, A.ntile - 1);
+        if (has_b) {
+            const int s0 = A.btile[tyy * A.ntile + xa], s1 = A.btile[tyy * A.ntile + xb + 1];
+            for (int s = s0 + tid; s < s1; s += 256) {
+                const double gx = A.bgx[s], gy = A.bgy[s];
+                int mx0, my0;
+                double wx[W], wy[W];
+                window_weights<W>(gx, A.beta, mx0, wx);
+                window_weights<W>(gy, A.beta, my0, wy);
+                mx0 -= x0;
+                my0 -= y0;
+                if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
+                const int i = A.bidx[s];
+                const double qs = A.sigma ? A.bw[s] * A.sigma[(size_t)b * A.nb + i] : 0.0;
+                const double m = A.mu ? A.mu[(size_t)b * A.nb + i] : 0.0;
+                const double qx = A.bwx[s] * m, qy = A.bwy[s] * m;
+#pragma unroll
+                for (int ky = 0; ky < W; ++ky) {
+                    const int my = my0 + ky;
+                    if (my < 0 || my >= TILE) continue;
+#pragma unroll
+                    for (int kx = 0; kx < W; ++kx) {
+                        const int mx = mx0 + kx;
+                        if (mx < 0 || mx >= TILE) continue;
+                        const double v = wx[kx] * wy[ky];
+                        const int o = my * TILE + mx;
+                        if (A.sigma) atomicAdd(&tileS[o], qs * v);
+                        if (A.mu) {
+                            atomicAdd(&tileX[o], qx * v);
+                            atomicAdd(&tileY[o], qy * v);
+                        }
+                    }
+                }
+            }
+        }
+        if (A.f_vol) {
+            const int s0 = A.vtile[tyy * A.ntile + xa], s1 = A.vtile[tyy * A.ntile + xb + 1];
+            for (int s = s0 + tid; s < s1; s += 256) {
+                const double gx = A.vgx[s], gy = A.vgy[s];
+                int mx0, my0;
+                double wx[W], wy[W];
+                window_weights<W>(gx, A.beta, mx0, wx);
+                window_weights<W>(gy, A.beta, my0, wy);
+                mx0 -= x0;
+                my0 -= y0;
+                if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
+                const double q = A.vw[s] * A.f_vol[(size_t)b * A.nv + A.vidx[s]];
+#pragma unroll
+                for (int ky = 0; ky < W; ++ky) {
+                    const int my = my0 + ky;
+                    if (my < 0 || my >= TILE) continue;
+                    const double qy = q * wy[ky];
+#pragma unroll
+                    for (int kx = 0; kx < W; ++kx) {
+                        const int mx = mx0 + kx;
+                        if (mx < 0 || mx >= TILE) continue;
+                        atomicAdd(&tileV[my * TILE + mx], qy * wx[kx]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const size_t fs = (size_t)A.B * A.field;
+    double *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
+    for (int i = tid; i < TILE * TILE; i += 256) {
+        const size_t o = (size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE);
+        gS[o] = tileS[i];
+        gV[o] = tileV[i];
+        gX[o] = tileX[i];
+        gY[o] = tileY[i];
+    }
+}
+
+// Fourier multiplier on the half spectrum [n][n/2+1] of each field.
+__global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t field, double *grid,
+                                                  const double *__restrict__ fac, double c, double alpha2,
+                                                  double dk)
+{
+    const int64_t nh = n / 2 + 1;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n * nh * B) return;
+    const int64_t lx = id % nh;
+    const int64_t ly = (id / nh) % n;
+    const int b = (int)(id / (nh * n));
+    const int64_t fy = ly <= n / 2 ? ly : ly - n;
+    const double ax = fac[lx], ay = fac[fy < 0 ? -fy : fy];
+    const size_t fs = (size_t)B * field / 2;                  // complex values per field group
+    double2 *F = reinterpret_cast<double2 *>(grid) + (size_t)b * (field / 2) + ly * nh + lx;
+    double2 zS = {0, 0}, zV = {0, 0}, zD = {0, 0};
+    if (ax != 0.0 && ay != 0.0) {
+        const double kx = dk * lx, ky = dk * fy;
+        const double M = c * ax * ay / (alpha2 + kx * kx + ky * ky);
+        const double2 s = F[0], v = F[fs], gx = F[2 * fs], gy = F[3 * fs];
+        zS = make_double2(M * s.x, M * s.y);
+        zV = make_double2(M * v.x, M * v.y);
+        // -i (kx Gx + ky Gy)
+        const double re = kx * gx.x + ky * gy.x, im = kx * gx.y + ky * gy.y;
+        zD = make_double2(M * im, -M * re);
+    }
+    F[0] = zS;
+    F[fs] = zV;
+    F[2 * fs] = zD;
+}
+
+struct InterpArgs {
+    int64_t n, field, nout;
+    int ntile, B;
+    double beta, ox, oy, h;
+    const int32_t *tile_xy, *tile_rng;
+    const double *tx, *ty;
+    const double *grid;    // [3][B][field]: S, V, D results
+    double *acc;           // [3][B][nout]: S, D, V
+    int want_s, want_d, want_v;
+};
+
+template <int W>
+__global__ void __launch_bounds__(256) k_interp(InterpArgs A)
+{
+    constexpr int RS = TILE + W + 2;
+    __shared__ double reg[3][RS * RS];
+    const int t = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int tile = A.tile_xy[t];
+    const int tx = tile % A.ntile, ty = tile / A.ntile;
+    const int rx0 = tx * TILE - W / 2 - 1, ry0 = ty * TILE - W / 2 - 1;
+    const size_t fs = (size_t)A.B * A.field;
+    const double *g0 = A.grid + (size_t)b * A.field;
+    for (int i = tid; i < RS * RS; i += 256) {
+        int gy = ry0 + i / RS, gx = rx0 + i % RS;
+        gy = (int)(((int64_t)gy % A.n + A.n) % A.n);
+        gx = (int)(((int64_t)gx % A.n + A.n) % A.n);
+        const size_t o = (size_t)gy * (A.n + 2) + gx;
+        reg[0][i] = A.want_s ? g0[o] : 0.0;
+        reg[1][i] = A.want_v ? g0[fs + o] : 0.0;
+        reg[2][i] = A.want_d ? g0[2 * fs + o] : 0.0;
+    }
+    __syncthreads();
+    const int s0 = A.tile_rng[t], s1 = A.tile_rng[t + 1];
+    for (int s = s0 + tid; s < s1; s += 256) {
+        const double gx = (A.tx[s] - A.ox) / A.h, gy = (A.ty[s] - A.oy) / A.h;
+        int mx0, my0;
+        double wx[W], wy[W];
+        window_weights<W>(gx, A.beta, mx0, wx);
+        window_weights<W>(gy, A.beta, my0, wy);
+        const int lx = min(max(mx0 - rx0, 0), RS - W), ly = min(max(my0 - ry0, 0), RS - W);
+        double uS = 0, uV = 0, uD = 0;
+#pragma unroll 1
+        for (int ky = 0; ky < W; ++ky) {
+            const int o = (ly + ky) * RS + lx;
+            double rS = 0, rV = 0, rD = 0;
+#pragma unroll
+            for (int kx = 0; kx < W; ++kx) {
+                rS = fma(wx[kx], reg[0][o + kx], rS);
+                rV = fma(wx[kx], reg[1][o + kx], rV);
+                rD = fma(wx[kx], reg[2][o + kx], rD);
+            }
+            uS = fma(wy[ky], rS, uS);
+            uV = fma(wy[ky], rV, uV);
+            uD = fma(wy[ky], rD, uD);
+        }
+        const size_t ob = (size_t)b * A.nout + s, cs = (size_t)A.B * A.nout;
+        if (A.want_s) A.acc[ob] = uS;
+        if (A.want_d) A.acc[cs + ob] = uD;
+        if (A.want_v) A.acc[2 * cs + ob] = uV;
+    }
+}
+
+template <int W>
+static hipError_t spread_w(mhk_plan *P, const SpreadArgs &A)
+{
+    dim3 grid((unsigned)(A.ntile * A.ntile), (unsigned)A.B);
+    hipLaunchKernelGGL(k_spread<W>, grid, dim3(256), 0, P->stream, A);
+    return hipGetLastError();
+}
+
+template <int W>
+static hipError_t interp_w(mhk_plan *P, const InterpArgs &A)
+{
+    if (P->hist.n_ttiles == 0) return hipSuccess;
+    dim3 grid((unsigned)P->hist.n_ttiles, (unsigned)A.B);
+    hipLaunchKernelGGL(k_interp<W>, grid, dim3(256), 0, P->stream, A);
+    return hipGetLastError();
+}
+
+#define MHK_W_SWITCH(w, F, ...)              \
+    switch (w) {                             \
+    case 4: return F<4>(__VA_ARGS__);        \
+    case 5: return F<5>(__VA_ARGS__);        \
+    case 6: return F<6>(__VA_ARGS__);        \
+    case 7: return F<7>(__VA_ARGS__);        \
+    case 8: return F<8>(__VA_ARGS__);        \
+    case 9: return F<9>(__VA_ARGS__);        \
+    case 10: return F<10>(__VA_ARGS__);      \
+    case 11: return F<11>(__VA_ARGS__);      \
+    case 12: return F<12>(__VA_ARGS__);      \
+    case 13: return F<13>(__VA_ARGS__);      \
+    case 14: return F<14>(__VA_ARGS__);      \
+    case 15: return F<15>(__VA_ARGS__);      \
+    case 16: return F<16>(__VA_ARGS__);      \
+    default: return hipErrorInvalidValue;    \
+    }
+
+hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, const double *f_vol)
+{
+    const History &G = P->hist;
+    SpreadArgs A;
+    A.n = G.n;
+    A.field = G.field;
+    A.nb = P->nb;
+    A.nv = P->nv;
+    A.ntile = G.ntile;
+    A.B = P->p.batch;
+    A.beta = G.beta;
+    A.bgx = G.bgx; A.bgy = G.bgy; A.bw = G.bw; A.bwx = G.bwx; A.bwy = G.bwy;
+    A.bidx = G.bidx; A.btile = G.btile;
+    A.vgx = G.vgx; A.vgy = G.vgy; A.vw = G.vw; A.vidx = G.vidx; A.vtile = G.vtile;
+    A.sigma = sigma;
+    A.mu = mu;
+    A.f_vol = f_vol;
+    A.grid = G.grid;
+    MHK_W_SWITCH(G.w, spread_w, P, A);
+}
+
+hipError_t launch_multiply(mhk_plan *P)
+{
+    const History &G = P->hist;
+    const int64_t tot = G.n * (G.n / 2 + 1) * P->p.batch;
+    hipLaunchKernelGGL(k_multiply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, G.n, P->p.batch,
+                       G.field, G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha, 2.0 * M_PI / G.period);
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v)
+{
+    const History &G = P->hist;
+    InterpArgs A;
+    A.n = G.n;
+    A.field = G.field;
+    A.nout = P->nout;
+    A.ntile = G.ntile;
+    A.B = P->p.batch;
+    A.beta = G.beta;
+    A.ox = G.ox;
+    A.oy = G.oy;
+    A.h = G.h;
+    A.tile_xy = G.ttile_xy;
+    A.tile_rng = G.ttile_rng;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.grid = G.grid;
+    A.acc = P->acc;
+    A.want_s = want_s;
+    A.want_d = want_d;
+    A.want_v = want_v;
+    MHK_W_SWITCH(G.w, interp_w, P, A);
+}
+
+}  // namespace mhk

@@ -1,0 +1,339 @@
+// Local asymptotic part (Section 4.1) and the closest boundary point
+// (Section 3.2), in FP64, plus the final scatter of the accumulated
+// potentials to the caller's target order.
+//
+// For an off-surface target x the nearest boundary node is found in a cell
+// list (cells larger than the widest band plus the largest node gap, so the
+// 3x3 neighbourhood holds the global nearest node of every target inside the
+// band); its panel and the two neighbouring panels are searched for the
+// closest point x0 by Newton's method on d/dt |x - gamma(t)|^2 = 0, started
+// from the best of the panel's nodes and end points.  The geometry, the
+// curvature and the densities are evaluated at x0 from their per-panel
+// Legendre expansions.  rho = +1 for targets inside Omega, -1 outside, so
+// that D jumps by -mu/2 on entering Omega (eq. (jumprel)).
+#include "mhk_internal.h"
+
+namespace mhk {
+
+// Legendre coefficients of sigma and mu on every panel: c = Leg * f.
+__global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const double *__restrict__ leg,
+                                                      const double *__restrict__ sigma,
+                                                      const double *__restrict__ mu,
+                                                      double *__restrict__ cs, double *__restrict__ cm)
+{
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = npan * NGL * B;
+    if (id >= tot) return;
+    int k = (int)(id % NGL);
+    int64_t pb = id / NGL;                 // b * npan + p
+    const double *row = leg + k * NGL;
+    if (sigma) {
+        const double *f = sigma + pb * NGL;
+        double v = 0;
+#pragma unroll
+        for (int i = 0; i < NGL; ++i) v = fma(row[i], f[i], v);
+        cs[id] = v;
+    }
+    if (mu) {
+        const double *f = mu + pb * NGL;
+        double v = 0;
+#pragma unroll
+        for (int i = 0; i < NGL; ++i) v = fma(row[i], f[i], v);
+        cm[id] = v;
+    }
+}
+
+// Value and first two t-derivatives of two Legendre series at t, using
+// P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1), P'_{k+1} = P'_{k-1} + (2k+1) P_k,
+// P''_{k+1} = P''_{k-1} + (2k+1) P'_k.
+__device__ inline void leg2(const double *__restrict__ ca, const double *__restrict__ cb, double t,
+                            double &a0, double &a1, double &a2, double &b0, double &b1, double &b2)
+{
+    double pm = 1.0, p = t, dm = 0.0, d = 1.0, em = 0.0, e = 0.0;
+    a0 = ca[0] + ca[1] * t;
+    a1 = ca[1];
+    a2 = 0.0;
+    b0 = cb[0] + cb[1] * t;
+    b1 = cb[1];
+    b2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < NGL - 1; ++k) {
+        const double pn = ((2 * k + 1) * t * p - k * pm) / (k + 1);
+        const double dn = dm + (2 * k + 1) * p;
+        const double en = em + (2 * k + 1) * d;
+        pm = p; p = pn;
+        dm = d; d = dn;
+        em = e; e = en;
+        const double A = ca[k + 1], Bc = cb[k + 1];
+        a0 = fma(A, p, a0); a1 = fma(A, d, a1); a2 = fma(A, e, a2);
+        b0 = fma(Bc, p, b0); b1 = fma(Bc, d, b1); b2 = fma(Bc, e, b2);
+    }
+}
+
+__device__ inline double leg1(const double *__restrict__ c, double t)
+{
+    double pm = 1.0, p = t, v = c[0] + c[1] * t;
+#pragma unroll
+    for (int k = 1; k < NGL - 1; ++k) {
+        const double pn = ((2 * k + 1) * t * p - k * pm) / (k + 1);
+        pm = p; p = pn;
+        v = fma(c[k + 1], p, v);
+    }
+    return v;
+}
+
+struct LocalArgs {
+    int64_t nout, nt, nb, npan;
+    int B;
+    int parts;
+    const double *tx, *ty;
+    const int8_t *tin;
+    const int32_t *tidx;
+    const double *bx, *by, *bk;
+    const double *sigma, *mu, *f_trg;
+    const double *cs, *cm;
+    const double *pcx, *pcy, *pck, *ends, *gl_t;
+    const int32_t *prev, *next, *node, *cell_start;
+    double cell, ox, oy;
+    int ncx, ncy;
+    double alpha, delta, dstar, band_s, band_v;
+    const double *acc;     // [3][B][nout]: S, D, V in sorted order
+    double *out_s, *out_d, *out_v;
+};
+
+// Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p.
+__device__ inline void panel_min(const LocalArgs &A, int p, double px, double py, double &tbest, double &d2best)
+{
+    const double *cx = A.pcx + (size_t)p * NGL, *cy = A.pcy + (size_t)p * NGL;
+    // start: best of the 16 nodes and the two end points
+    double ts = -1.0;
+    double dx = A.ends[p * 4 + 0] - px, dy = A.ends[p * 4 + 1] - py;
+    double ds = dx * dx + dy * dy;
+    for (int i = 0; i < NGL; ++i) {
+        dx = A.bx[(size_t)p * NGL + i] - px;
+        dy = A.by[(size_t)p * NGL + i] - py;
+        const double d = dx * dx + dy * dy;
+        if (d < ds) { ds = d; ts = A.gl_t[i]; }
+    }
+    dx = A.ends[p * 4 + 2] - px;
+    dy = A.ends[p * 4 + 3] - py;
+    if (dx * dx + dy * dy < ds) { ds = dx * dx + dy * dy; ts = 1.0; }
+    double t = ts;
+    for (int it = 0; it < 40; ++it) {
+        double x0, x1, x2, y0, y1, y2;
+        leg2(cx, cy, t, x0, x1, x2, y0, y1, y2);
+        const double g = (x0 - px) * x1 + (y0 - py) * y1;
+        const double gp = x1 * x1 + y1 * y1 + (x0 - px) * x2 + (y0 - py) * y2;
+        if (!(gp > 0.0)) break;
+        double tn = t - g / gp;
+        tn = fmin(1.0, fmax(-1.0, tn));
+        const double step = fabs(tn - t);
+        t = tn;
+        if (step < 1e-15) break;
+    }
+    const double xv = leg1(cx, t) - px, yv = leg1(cy, t) - py;
+    const double dn = xv * xv + yv * yv;
+    if (dn <= ds) { tbest = t; d2best = dn; }
+    else { tbest = ts; d2best = ds; }
+}
+
+__global__ void __launch_bounds__(256) k_local(LocalArgs A)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nout) return;
+    const int64_t idx = A.tidx[s];
+    const double px = A.tx[s], py = A.ty[s];
+    const bool inside = A.tin[s] != 0;
+    const bool on = idx >= A.nt;
+    const bool do_local = (A.parts & MHK_PART_LOCAL) != 0;
+    const bool ws = A.out_s != nullptr, wd = A.out_d != nullptr, wv = A.out_v != nullptr;
+
+    // geometry of the local part (shared by the batch)
+    const double sq = sqrt(A.dstar), c2 = A.alpha * sq;
+    const double sv = sqrt(A.delta), c2v = A.alpha * sv;
+    bool near_s = false;           // inside the layer band with a closest point
+    double r = INFINITY, rho = inside ? 1.0 : -1.0;
+    int pbest = -1;
+    double tbest = 0.0;
+    double P0 = 0, P1 = 0, U0 = 0, U1 = 0, U2 = 0, kap = 0, mss_fac1 = 0, mss_fac2 = 0;
+    double vfac = 0.0;             // V local = delta * f * vfac (or NaN)
+    if (do_local) {
+        if (on) {
+            vfac = -expm1(-c2v * c2v) / (2.0 * c2v * c2v);          // Cor. 4.10
+        } else {
+            // nearest boundary node (lowest index on ties)
+            int cx = (int)floor((px - A.ox) / A.cell), cy = (int)floor((py - A.oy) / A.cell);
+            double dmin = INFINITY;
+            int imin = -1;
+            if (cx >= -1 && cx <= A.ncx && cy >= -1 && cy <= A.ncy) {
+                for (int yy = max(cy - 1, 0); yy <= min(cy + 1, A.ncy - 1); ++yy) {
+                    const int c0 = A.cell_start[(int64_t)yy * A.ncx + max(cx - 1, 0)];
+                    const int c1 = A.cell_start[(int64_t)yy * A.ncx + min(cx + 1, A.ncx - 1) + 1];
+                    for (int c = c0; c < c1; ++c) {
+                        const int i = A.node[c];
+                        const double dx = A.bx[i] - px, dy = A.by[i] - py;
+                        const double d = dx * dx + dy * dy;
+                        if (d < dmin || (d == dmin && i < imin)) { dmin = d; imin = i; }
+                    }
+                }
+            }
+            if (imin >= 0) {
+                const int p0 = imin / NGL;
+                int cand[3] = {p0, A.prev[p0], A.next[p0]};
+                double d2b = INFINITY;
+                for (int c = 0; c < 3; ++c) {
+                    double t, d2;
+                    panel_min(A, cand[c], px, py, t, d2);
+                    if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; }
+                }
+                r = sqrt(d2b);
+            }
+            // volume part (Lemma 4.8 first order inside the band, Cor. 4.11 beyond)
+            if (inside) {
+                if (r < A.band_v) {
+                    const double c1v = r / sv, a = 0.5 * c1v;
+                    const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
+                    const double pre = exp(-a * a - c2v * c2v);
+                    // W0 = (4 - 4 e^{-c2^2} + 2 lambda - Phi_+)/c2^2, lambda = e^{-c2^2} erfc(c1/2)
+                    const double W0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
+                    vfac = 0.25 * W0;
+                } else {
+                    vfac = -expm1(-c2v * c2v) / (c2v * c2v);
+                }
+            } else {
+                vfac = (r < A.band_v) ? NAN : 0.0;
+            }
+            if (r < A.band_s && pbest >= 0) {
+                near_s = true;
+                const double c1 = r / sq, a = 0.5 * c1;
+                const double em = erfcx(a - c2), ep = erfcx(a + c2);
+                const double pre = exp(-a * a - c2 * c2);
+                const double phim = pre * (em - ep), phip = pre * (em + ep);
+                P0 = phim / c2;
+                P1 = c1 * P0;
+                U0 = phip;
+                U1 = c1 * U0;
+                U2 = c1 * U1;
+                kap = leg1(A.pck + (size_t)pbest * NGL, tbest);
+                double x0, x1, x2, y0, y1, y2;
+                leg2(A.pcx + (size_t)pbest * NGL, A.pcy + (size_t)pbest * NGL, tbest, x0, x1, x2, y0, y1, y2);
+                const double sp2 = x1 * x1 + y1 * y1;
+                // d^2/ds^2 = (d^2/dt^2 - (gamma'.gamma''/|gamma'|^2) d/dt)/|gamma'|^2
+                mss_fac2 = 1.0 / sp2;
+                mss_fac1 = -(x1 * x2 + y1 * y2) / (sp2 * sp2);
+            }
+        }
+    }
+
+    for (int b = 0; b < A.B; ++b) {
+        const size_t ob = (size_t)b * A.nout + idx;
+        const size_t ab = (size_t)b * A.nout + s;
+        if (ws) {
+            double v = A.acc[(size_t)0 * A.B * A.nout + ab];
+            if (do_local) {
+                if (on) {
+                    const int64_t i = idx - A.nt;
+                    v += sq * A.sigma[(size_t)b * A.nb + i] * erf(c2) / (2.0 * c2);        // Cor. 4.4
+                } else if (near_s) {
+                    const double sg = leg1(A.cs + ((size_t)b * A.npan + pbest) * NGL, tbest);
+                    v += sq * sg * P0 * 0.25 + A.dstar * rho * kap * sg * P1 * 0.125;     // Lemma 4.1
+                }
+            }
+            A.out_s[ob] = v;
+        }
+        if (wd) {
+            double v = A.acc[(size_t)1 * A.B * A.nout + ab];
+            if (do_local) {
+                if (on) {
+                    const int64_t i = idx - A.nt;
+                    v -= sq * A.bk[i] * A.mu[(size_t)b * A.nb + i] * erf(c2) / (4.0 * c2);  // Cor. 4.7
+                } else if (near_s) {
+                    const double *cm = A.cm + ((size_t)b * A.npan + pbest) * NGL;
+                    double m0, m1, m2, z0, z1, z2;
+                    leg2(cm, cm, tbest, m0, m1, m2, z0, z1, z2);
+                    const double mss = mss_fac2 * m2 + mss_fac1 * m1;
+                    v += -rho * m0 * U0 * 0.25 - sq * kap * m0 * (P0 + U1) * 0.125                // Lemma 4.5
+                         - A.dstar * (rho * mss * P1 * 0.125 + 3.0 * rho * kap * kap * m0 * (P1 + U2) / 32.0);
+                }
+            }
+            A.out_d[ob] = v;
+        }
+        if (wv) {
+            double v = A.acc[(size_t)2 * A.B * A.nout + ab];
+            if (do_local) v += A.delta * A.f_trg[ob] * vfac;
+            A.out_v[ob] = v;
+        }
+    }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_coeffs(mhk_plan *P, const double *sigma, const double *mu)
+{
+    const int64_t tot = P->npan * NGL * P->p.batch;
+    hipLaunchKernelGGL(k_panel_coeffs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
+                       P->p.batch, P->loc.leg, sigma, mu, P->loc.csig, P->loc.cmu);
+    return hipGetLastError();
+}
+
+hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const double *mu, const double *f_trg,
+                        double *out_s, double *out_d, double *out_v)
+{
+    LocalArgs A;
+    A.nout = P->nout;
+    A.nt = P->nt;
+    A.nb = P->nb;
+    A.npan = P->npan;
+    A.B = P->p.batch;
+    A.parts = parts;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.tin = P->tin;
+    A.tidx = P->tidx;
+    A.bx = P->bx;
+    A.by = P->by;
+    A.bk = P->bk;
+    A.sigma = sigma;
+    A.mu = mu;
+    A.f_trg = f_trg;
+    A.cs = P->loc.csig;
+    A.cm = P->loc.cmu;
+    A.pcx = P->loc.cx;
+    A.pcy = P->loc.cy;
+    A.pck = P->loc.ck;
+    A.ends = P->loc.ends;
+    A.gl_t = P->loc.gl_t;
+    A.prev = P->loc.prev;
+    A.next = P->loc.next;
+    A.node = P->loc.node;
+    A.cell_start = P->loc.cell_start;
+    A.cell = P->loc.cell;
+    A.ox = P->loc.ox;
+    A.oy = P->loc.oy;
+    A.ncx = P->loc.ncx;
+    A.ncy = P->loc.ncy;
+    A.alpha = P->p.alpha;
+    A.delta = P->delta;
+    A.dstar = P->dstar;
+    A.band_s = P->info.band_layer;
+    A.band_v = P->info.band_volume;
+    A.acc = P->acc;
+    A.out_s = out_s;
+    A.out_d = out_d;
+    A.out_v = out_v;
+    hipLaunchKernelGGL(k_local, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A);
+    return hipGetLastError();
+}
+
+}  // namespace mhk

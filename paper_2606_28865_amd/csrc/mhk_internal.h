@@ -1,0 +1,148 @@
+// Internal declarations of libmhk (not part of the C ABI).
+//
+// Data layout in HBM (all arrays device-resident, owned by the plan):
+//  * targets: the n_out = N_T (+ N_B) evaluation points sorted in Morton
+//    order of small square cells aligned with the history grid tiles, as
+//    SoA x/y (FP64), inside flag and original output index;
+//  * boundary: the caller's panel-contiguous SoA arrays, plus per-panel
+//    Legendre coefficients of x, y and kappa for the closest-point search;
+//  * dyadic level j: the N_B 2^j child nodes of the bisected panels, sorted
+//    row-major by square cells of side R_j, as SoA x/y/w nx/w ny/w, with a
+//    code giving (panel, child, node) for the per-eval interpolation of the
+//    densities, and per-eval strengths q_S = w sigma, q_Dx = w nu_x mu,
+//    q_Dy = w nu_y mu in the same sorted order;
+//  * history: boundary and volume sources sorted by 32x32 tiles of the fine
+//    grid, the fine grids [4][batch][n][n+2] (S, V, D_x, D_y sources, real,
+//    rows padded for in-place real-to-complex FFTs) and the 1D factors of the
+//    Fourier multiplier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mhk.h"
+
+namespace mhk {
+
+constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
+constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
+constexpr int MAXJ = 8;          // maximum number of dyadic levels
+constexpr int TAB_NC = 12;       // coefficients per table segment (degree 11)
+constexpr int MAXW = 16;         // maximum spreading window width
+constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
+constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
+
+void set_error(const std::string &msg);
+
+struct Level {
+    double delta_j = 0;          // delta / 4^(j-1): upper end of the level's time interval
+    double inv4d = 0;            // 1 / (4 delta_j)
+    double a_max = 0;            // cut-off in a = r^2/(4 delta_j)
+    double radius = 0;           // sqrt(4 delta_j a_max)
+    double seg_inv = 0;          // segments per unit of a
+    int nseg = 0;
+    int nchild = 0;              // 2^j
+    int64_t n_src = 0;           // N_B 2^j
+    int ncx = 0, ncy = 0;
+    double cell = 0, ox = 0, oy = 0;
+    // device
+    double *sx = nullptr, *sy = nullptr;          // sorted child nodes
+    double *swx = nullptr, *swy = nullptr;        // w nu_x, w nu_y
+    double *sw = nullptr;                         // w
+    int32_t *code = nullptr;                      // (panel * nchild + child) * 16 + node
+    int32_t *cell_start = nullptr;                // [ncx*ncy + 1]
+    double *interp = nullptr;                     // [nchild][16][16] parent -> child values
+    double *tab = nullptr;                        // [nseg][TAB_NC][2] (S, D interleaved)
+    double *q = nullptr;                          // per eval: [3][batch][n_src]
+    double tab_err = 0;                           // measured max table error / K(0)
+};
+
+struct History {
+    bool active = false;
+    double kcut = 0, period = 0, h = 0, ox = 0, oy = 0;
+    double beta = 0, ups = 2.0;
+    int w = 0;
+    int64_t n = 0;               // fine grid points per dimension
+    int ntile = 0;               // n / TILE
+    int64_t field = 0;           // doubles per padded real field: n*(n+2)
+    // sorted sources (grid coordinates) and original indices
+    int64_t nbs = 0, nvs = 0;
+    double *bgx = nullptr, *bgy = nullptr;        // boundary nodes
+    double *bw = nullptr, *bwx = nullptr, *bwy = nullptr;
+    int32_t *bidx = nullptr;
+    int32_t *btile = nullptr;                     // [ntile*ntile + 1]
+    double *vgx = nullptr, *vgy = nullptr, *vw = nullptr;
+    int32_t *vidx = nullptr;
+    int32_t *vtile = nullptr;                     // [ntile*ntile + 1]
+    // targets by tile: list of non-empty tiles and their ranges in sorted order
+    int n_ttiles = 0;
+    int32_t *ttile_xy = nullptr;                  // [n_ttiles] tile index ty*ntile+tx
+    int32_t *ttile_rng = nullptr;                 // [n_ttiles + 1]
+    // multiplier factors A[l] = exp(-delta k_l^2)/phihat(k_l)^2, 0 beyond kcut
+    double *fac = nullptr;                        // [n/2+1]
+    double mult_c = 0;                            // h^4/P^2 exp(-delta alpha^2)
+    // grids
+    double *grid = nullptr;                       // [4][batch][field]
+    void *work = nullptr;
+    size_t work_bytes = 0;
+    rocfft_plan fwd = nullptr, inv = nullptr;
+    rocfft_execution_info exec = nullptr;
+};
+
+struct Local {
+    double cell = 0, ox = 0, oy = 0;
+    int ncx = 0, ncy = 0;
+    int32_t *node = nullptr;                      // boundary node indices sorted by cell
+    int32_t *cell_start = nullptr;
+    double *leg = nullptr;                        // [16][16] nodal values -> Legendre coefficients
+    double *cx = nullptr, *cy = nullptr, *ck = nullptr;   // [n_panels][16]
+    double *ends = nullptr;                       // [n_panels][4]: x(-1), y(-1), x(1), y(1)
+    double *gl_t = nullptr;                       // [16] Gauss-Legendre abscissae
+    int32_t *prev = nullptr, *next = nullptr;     // panel neighbours within each curve
+    double *csig = nullptr, *cmu = nullptr;       // per eval: [batch][n_panels][16]
+};
+
+}  // namespace mhk
+
+struct mhk_plan {
+    mhk_params p{};
+    mhk_info info{};
+    hipStream_t stream = nullptr;
+    bool timing = false;
+    int64_t nb = 0, npan = 0, nv = 0, nt = 0, nout = 0;
+    int J = 3;
+    double delta = 0, dstar = 0;
+    // boundary (caller order)
+    double *bx = nullptr, *by = nullptr, *bnx = nullptr, *bny = nullptr, *bw = nullptr, *bk = nullptr;
+    // sorted targets
+    double *tx = nullptr, *ty = nullptr;
+    int8_t *tin = nullptr;
+    int32_t *tidx = nullptr;
+    // accumulators in sorted target order: [3][batch][n_out] (S, D, V)
+    double *acc = nullptr;
+    mhk::Level lev[mhk::MAXJ];
+    mhk::History hist;
+    mhk::Local loc;
+    std::vector<void *> allocs;
+    int64_t bytes = 0;
+    hipEvent_t ev[8] = {};
+};
+
+namespace mhk {
+
+// kernels launchers (defined in the .hip files)
+hipError_t launch_level_densities(mhk_plan *P, int j, const double *sigma, const double *mu);
+hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d);
+hipError_t launch_panel_coeffs(mhk_plan *P, const double *sigma, const double *mu);
+hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const double *mu,
+                        const double *f_trg, double *out_s, double *out_d, double *out_v);
+hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, const double *f_vol);
+hipError_t launch_multiply(mhk_plan *P);
+hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+
+}  // namespace mhk

@@ -1,0 +1,1218 @@
+// Plan creation, parameter rules and evaluation driver of libmhk.
+//
+// Host-side work happens once per plan (geometry is static): parameter rules,
+// dyadic child nodes, kernel tables, sorting of sources and targets into cell
+// and tile order, the history grid and its FFT plans.  mhk_eval only enqueues
+// device work on the plan's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "mhk_internal.h"
+
+namespace mhk {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+#define MHK_HIP(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_)); \
+            return MHK_EHIP;                                                          \
+        }                                                                             \
+    } while (0)
+
+#define MHK_FFT(call)                                                                 \
+    do {                                                                              \
+        rocfft_status s_ = (call);                                                    \
+        if (s_ != rocfft_status_success) {                                            \
+            set_error(std::string("rocFFT error ") + std::to_string((int)s_) + " in " + #call); \
+            return MHK_EHIP;                                                          \
+        }                                                                             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Small numerical helpers (host)
+// ---------------------------------------------------------------------------
+
+// Gauss-Legendre nodes and weights on [-1, 1], ascending, by Newton's method
+// on the Legendre polynomial P_n (three-term recurrence).
+static void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
+{
+    t.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double x = cosl(M_PIl * (4 * i + 3) / (4 * n + 2));
+        long double dp = 0;
+        for (int it = 0; it < 64; ++it) {
+            long double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (p0 - x * p1) / (1 - x * x);
+            long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        {
+            long double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (p0 - x * p1) / (1 - x * x);
+        }
+        double wi = (double)(2 / ((1 - x * x) * dp * dp));
+        t[i] = -(double)x;
+        t[n - 1 - i] = (double)x;
+        w[i] = w[n - 1 - i] = wi;
+    }
+}
+
+// Lagrange basis of the 16 Gauss-Legendre nodes at point s (barycentric form).
+static void lagrange_row(const std::vector<double> &tn, const std::vector<long double> &lam,
+                         double s, double *row)
+{
+    int n = (int)tn.size();
+    for (int i = 0; i < n; ++i)
+        if (s == tn[i]) {
+            for (int k = 0; k < n; ++k) row[k] = (k == i);
+            return;
+        }
+    long double den = 0;
+    std::vector<long double> num(n);
+    for (int i = 0; i < n; ++i) {
+        num[i] = lam[i] / ((long double)s - tn[i]);
+        den += num[i];
+    }
+    for (int i = 0; i < n; ++i) row[i] = (double)(num[i] / den);
+}
+
+// Exponential integral E1(x), x > 0 (series for x < 1, continued fraction else).
+static double expint_e1(double x)
+{
+    if (x < 1.0) {
+        double s = 0, term = 1;
+        for (int k = 1; k < 60; ++k) {
+            term *= -x / k;
+            s += -term / k;
+        }
+        return -0.57721566490153286 - log(x) + s;
+    }
+    // Lentz's continued fraction for e^x E1(x)
+    double b = x + 1, c = 1e300, d = 1 / b, h = d;
+    for (int i = 1; i < 300; ++i) {
+        double a = -(double)i * i;
+        b += 2;
+        d = 1 / (a * d + b);
+        c = b + a / c;
+        double del = c * d;
+        h *= del;
+        if (fabs(del - 1) < 1e-16) break;
+    }
+    return h * exp(-x);
+}
+
+// Time integral of the heat kernel over one dyadic interval in the variable u
+// (t = delta_j e^{-u}, u in [0, ln 4]):
+//   I_p(a, b) = int_0^{ln4} exp(-a e^u - b e^{-u}) e^{p u} du,
+// so that K_j^S = I_0/(4 pi) and K_j^D = I_1/(8 pi delta_j) with
+// a = r^2/(4 delta_j), b = alpha^2 delta_j (eqs. (diffker_s), (diffker_dlp)).
+// Composite 16-point Gauss-Legendre on 12 panels.
+struct LevelQuad {
+    std::vector<double> t, w;
+    LevelQuad() { gauss_legendre(16, t, w); }
+    void eval(double a, double b, double &i0, double &i1) const
+    {
+        const double L = log(4.0);
+        const int m = 12;
+        const double hh = L / m;
+        long double s0 = 0, s1 = 0;
+        for (int p = 0; p < m; ++p)
+            for (int q = 0; q < 16; ++q) {
+                double u = hh * (p + 0.5 * (1 + t[q]));
+                double eu = exp(u);
+                long double e = w[q] * exp(-a * eu - b / eu);
+                s0 += e;
+                s1 += e * eu;
+            }
+        i0 = (double)(s0 * 0.5 * hh);
+        i1 = (double)(s1 * 0.5 * hh);
+    }
+};
+
+static int64_t good_fft_size(int64_t nmin)
+{
+    int64_t m = (nmin + TILE - 1) / TILE;
+    for (;; ++m) {
+        int64_t r = m;
+        for (int f : {2, 3, 5, 7})
+            while (r % f == 0) r /= f;
+        if (r == 1) return m * TILE;
+    }
+}
+
+static inline uint32_t spread_bits(uint32_t v)
+{
+    v &= 0xffff;
+    v = (v | (v << 8)) & 0x00ff00ff;
+    v = (v | (v << 4)) & 0x0f0f0f0f;
+    v = (v | (v << 2)) & 0x33333333;
+    v = (v | (v << 1)) & 0x55555555;
+    return v;
+}
+static inline uint32_t morton(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
+
+// Stable counting sort of keys in [0, nkeys): returns order and key starts.
+static void counting_sort(const std::vector<int64_t> &key, int64_t nkeys,
+                          std::vector<int32_t> &order, std::vector<int32_t> &start)
+{
+    start.assign(nkeys + 1, 0);
+    for (int64_t k : key) start[k + 1]++;
+    for (int64_t i = 0; i < nkeys; ++i) start[i + 1] += start[i];
+    std::vector<int32_t> pos(start.begin(), start.end() - 1);
+    order.assign(key.size(), 0);
+    for (size_t i = 0; i < key.size(); ++i) order[pos[key[i]]++] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Parameter rules
+// ---------------------------------------------------------------------------
+static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
+{
+    if (!pp || !I) {
+        set_error("null params/info");
+        return MHK_EINVAL;
+    }
+    mhk_params p = *pp;
+    if (!(p.alpha > 0) || !std::isfinite(p.alpha)) {
+        set_error("alpha must be positive and finite");
+        return MHK_EINVAL;
+    }
+    if (!(p.tol >= 1e-13 && p.tol <= 1e-3)) {
+        set_error("tol must be in [1e-13, 1e-3]");
+        return MHK_EINVAL;
+    }
+    if (p.prec != MHK_FP64 && p.prec != MHK_FP32) {
+        set_error("prec must be MHK_FP64 or MHK_FP32");
+        return MHK_EINVAL;
+    }
+    if (p.J < 0) p.J = 3;
+    if (p.J > MAXJ) {
+        set_error("J must be <= 8");
+        return MHK_EINVAL;
+    }
+    if (p.batch < 1) {
+        set_error("batch must be >= 1");
+        return MHK_EINVAL;
+    }
+    if (!(p.delta > 0)) {
+        if (!(p.dx > 0)) {
+            set_error("either delta or dx must be positive");
+            return MHK_EINVAL;
+        }
+        // Section 6.4: k_max = 0.9 k_Nyq with k_Nyq = pi/dx (eq. (k_nyq)), and
+        // delta the smallest split with exp(-delta(alpha^2 + k_max^2)) = tol.
+        double kmax = 0.9 * M_PI / p.dx;
+        p.delta = log(1.0 / p.tol) / (kmax * kmax + p.alpha * p.alpha);
+    }
+    if (p.upsamp <= 0) p.upsamp = 2.0;
+    if (p.upsamp < 1.25 || p.upsamp > 3.0) {
+        set_error("upsamp must be in [1.25, 3]");
+        return MHK_EINVAL;
+    }
+    if (p.wspread < 0 || p.wspread > MAXW || (p.wspread > 0 && p.wspread < 4)) {
+        set_error("wspread must be 0 or in [4, 16]");
+        return MHK_EINVAL;
+    }
+    memset(I, 0, sizeof(*I));
+    I->alpha = p.alpha;
+    I->tol = p.tol;
+    I->delta = p.delta;
+    I->J = p.J;
+    I->delta_star = p.delta / pow(4.0, p.J);
+    I->prec = p.prec;
+    I->batch = p.batch;
+    double sq = sqrt(I->delta_star), sv = sqrt(p.delta);
+    // Remark 4.3: the local layer part is negligible beyond sqrt(d*)(12 + 2 alpha sqrt(d*))
+    I->band_layer = sq * (12.0 + 2.0 * p.alpha * sq);
+    I->band_volume = sv * (12.0 + 2.0 * p.alpha * sv);
+    // level cut-off: the difference kernel is below exp(-a_max) of its peak scale
+    double amax = std::min(40.5, log(1.0 / p.tol) + 9.0);
+    for (int j = 1; j <= p.J; ++j) {
+        double dj = p.delta / pow(4.0, j - 1);
+        I->level_radius[j - 1] = sqrt(4.0 * dj * amax);
+    }
+    // Fourier cut-off of the history part with margin tol/10 (eqs. (kmax), (kmax_dlp))
+    double eps = p.tol * 0.1, L = log(1.0 / eps), da2 = p.delta * p.alpha * p.alpha;
+    if (da2 >= L) {
+        I->kmax = 0;
+    } else {
+        double k = sqrt((L - da2) / p.delta);
+        for (int it = 0; it < 50; ++it) {
+            double kn = sqrt(std::max(0.0, (log(std::max(k, 1.0) / eps) - da2) / p.delta));
+            if (fabs(kn - k) < 1e-12 * k) {
+                k = kn;
+                break;
+            }
+            k = kn;
+        }
+        I->kmax = k;
+    }
+    if (p.wspread == 0) {
+        double ew = p.tol * 0.1;
+        int w = (int)ceil(log(1.0 / ew) / (M_PI * sqrt(1.0 - 1.0 / p.upsamp))) + 1;
+        p.wspread = std::min(MAXW, std::max(4, w));
+    }
+    I->wspread = p.wspread;
+    if (out) *out = p;
+    return MHK_OK;
+}
+
+}  // namespace mhk
+
+using namespace mhk;
+
+// ---------------------------------------------------------------------------
+// Allocation helper
+// ---------------------------------------------------------------------------
+template <typename T>
+static mhk_status dalloc(mhk_plan *P, T **ptr, int64_t count)
+{
+    *ptr = nullptr;
+    if (count <= 0) count = 1;
+    size_t bytes = sizeof(T) * (size_t)count;
+    hipError_t e = hipMalloc((void **)ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return MHK_ENOMEM;
+    }
+    P->allocs.push_back(*ptr);
+    P->bytes += (int64_t)bytes;
+    return MHK_OK;
+}
+
+template <typename T>
+static mhk_status upload(mhk_plan *P, T **ptr, const T *host, int64_t count)
+{
+    mhk_status s = dalloc(P, ptr, count);
+    if (s != MHK_OK) return s;
+    if (count > 0) MHK_HIP(hipMemcpy(*ptr, host, sizeof(T) * count, hipMemcpyHostToDevice));
+    return MHK_OK;
+}
+
+#define TRY(x)                          \
+    do {                                \
+        mhk_status st_ = (x);           \
+        if (st_ != MHK_OK) return st_;  \
+    } while (0)
+
+static void free_plan(mhk_plan *P)
+{
+    if (!P) return;
+    for (void *p : P->allocs) (void)hipFree(p);
+    if (P->hist.fwd) rocfft_plan_destroy(P->hist.fwd);
+    if (P->hist.inv) rocfft_plan_destroy(P->hist.inv);
+    if (P->hist.exec) rocfft_execution_info_destroy(P->hist.exec);
+    for (auto &e : P->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete P;
+}
+
+static bool g_rocfft_ready = false;
+
+// ---------------------------------------------------------------------------
+// Plan construction
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Host {
+    const mhk_boundary *b;
+    const mhk_volume *v;
+    const mhk_targets *t;
+    std::vector<double> gl_t, gl_w;
+    std::vector<long double> bary;
+    std::vector<int64_t> prev, next;
+    double xmin, xmax, ymin, ymax;
+    // all targets (off-surface then boundary), in output order
+    std::vector<double> tx, ty;
+    std::vector<int8_t> tin;
+};
+
+mhk_status check_inputs(const mhk_params *p, const mhk_boundary *b, const mhk_volume *v,
+                        const mhk_targets *t)
+{
+    if (!p || !b) {
+        set_error("params and boundary are required");
+        return MHK_EINVAL;
+    }
+    if (b->n_panels < 1 || b->n_curves < 1 || !b->curve_panel_ofs || !b->x || !b->y || !b->nx ||
+        !b->ny || !b->w || !b->kappa) {
+        set_error("boundary arrays missing or empty");
+        return MHK_EINVAL;
+    }
+    if (b->n_panels * NGL > (int64_t)1 << 26) {
+        set_error("too many boundary nodes");
+        return MHK_EINVAL;
+    }
+    if (b->curve_panel_ofs[0] != 0 || b->curve_panel_ofs[b->n_curves] != b->n_panels) {
+        set_error("curve_panel_ofs must start at 0 and end at n_panels");
+        return MHK_EINVAL;
+    }
+    for (int c = 0; c < b->n_curves; ++c)
+        if (b->curve_panel_ofs[c + 1] - b->curve_panel_ofs[c] < 2) {
+            set_error("every curve needs at least 2 panels");
+            return MHK_EINVAL;
+        }
+    int64_t nb = b->n_panels * NGL;
+    for (int64_t i = 0; i < nb; ++i)
+        if (!std::isfinite(b->x[i]) || !std::isfinite(b->y[i]) || !std::isfinite(b->w[i]) ||
+            !std::isfinite(b->nx[i]) || !std::isfinite(b->ny[i]) || !std::isfinite(b->kappa[i])) {
+            set_error("non-finite boundary data");
+            return MHK_EINVAL;
+        }
+    if (v && v->n < 0) {
+        set_error("negative volume size");
+        return MHK_EINVAL;
+    }
+    if (v && v->n > 0) {
+        if (!v->x || !v->y || !v->w || v->n > (int64_t)1 << 30) {
+            set_error("volume arrays missing or too large");
+            return MHK_EINVAL;
+        }
+        for (int64_t i = 0; i < v->n; ++i)
+            if (!std::isfinite(v->x[i]) || !std::isfinite(v->y[i]) || !std::isfinite(v->w[i])) {
+                set_error("non-finite volume data");
+                return MHK_EINVAL;
+            }
+    }
+    if (!t || t->n < 0 || (t->n > 0 && (!t->x || !t->y || !t->inside))) {
+        set_error("targets missing");
+        return MHK_EINVAL;
+    }
+    if (t->n + (t->on_surface ? nb : 0) < 1) {
+        set_error("no targets");
+        return MHK_EINVAL;
+    }
+    if (t->n + nb > (int64_t)1 << 30) {
+        set_error("too many targets");
+        return MHK_EINVAL;
+    }
+    for (int64_t i = 0; i < t->n; ++i)
+        if (!std::isfinite(t->x[i]) || !std::isfinite(t->y[i])) {
+            set_error("non-finite target");
+            return MHK_EINVAL;
+        }
+    return MHK_OK;
+}
+
+void host_common(Host &H)
+{
+    gauss_legendre(NGL, H.gl_t, H.gl_w);
+    H.bary.assign(NGL, 0);
+    for (int i = 0; i < NGL; ++i) {
+        long double pr = 1;
+        for (int k = 0; k < NGL; ++k)
+            if (k != i) pr *= ((long double)H.gl_t[i] - H.gl_t[k]);
+        H.bary[i] = 1 / pr;
+    }
+    const mhk_boundary *b = H.b;
+    H.prev.assign(b->n_panels, 0);
+    H.next.assign(b->n_panels, 0);
+    for (int c = 0; c < b->n_curves; ++c) {
+        int64_t a = b->curve_panel_ofs[c], e = b->curve_panel_ofs[c + 1], m = e - a;
+        for (int64_t q = 0; q < m; ++q) {
+            H.prev[a + q] = a + (q + m - 1) % m;
+            H.next[a + q] = a + (q + 1) % m;
+        }
+    }
+    int64_t nb = b->n_panels * NGL;
+    int64_t nt = H.t->n, nout = nt + (H.t->on_surface ? nb : 0);
+    H.tx.resize(nout);
+    H.ty.resize(nout);
+    H.tin.resize(nout);
+    for (int64_t i = 0; i < nt; ++i) {
+        H.tx[i] = H.t->x[i];
+        H.ty[i] = H.t->y[i];
+        H.tin[i] = H.t->inside[i] ? 1 : 0;
+    }
+    for (int64_t i = nt; i < nout; ++i) {
+        H.tx[i] = b->x[i - nt];
+        H.ty[i] = b->y[i - nt];
+        H.tin[i] = 1;
+    }
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    auto acc = [&](double x, double y) {
+        x0 = std::min(x0, x); x1 = std::max(x1, x);
+        y0 = std::min(y0, y); y1 = std::max(y1, y);
+    };
+    for (int64_t i = 0; i < nb; ++i) acc(b->x[i], b->y[i]);
+    if (H.v)
+        for (int64_t i = 0; i < H.v->n; ++i) acc(H.v->x[i], H.v->y[i]);
+    for (int64_t i = 0; i < nout; ++i) acc(H.tx[i], H.ty[i]);
+    H.xmin = x0; H.xmax = x1; H.ymin = y0; H.ymax = y1;
+}
+
+// Dyadic level j (Section 4.2): every panel bisected j times; child nodes are
+// the 16-point Gauss-Legendre nodes of each child interval, with geometry
+// interpolated by the parent's degree-15 polynomial, normals renormalised,
+// and weights w_GL,child * speed * 2^-j.
+mhk_status build_level(mhk_plan *P, Host &H, int j)
+{
+    Level &L = P->lev[j - 1];
+    const mhk_boundary *b = H.b;
+    const int64_t npan = b->n_panels;
+    L.nchild = 1 << j;
+    L.n_src = npan * L.nchild * NGL;
+    L.delta_j = P->delta / pow(4.0, j - 1);
+    L.inv4d = 1.0 / (4.0 * L.delta_j);
+    L.radius = P->info.level_radius[j - 1];
+    L.a_max = L.radius * L.radius * L.inv4d;
+    const int nch = L.nchild;
+    // interpolation rows: child c, node k -> 16 parent weights
+    std::vector<double> T((size_t)nch * NGL * NGL);
+    for (int c = 0; c < nch; ++c)
+        for (int k = 0; k < NGL; ++k) {
+            double s = -1.0 + (2.0 * c + 1.0 + H.gl_t[k]) / nch;
+            lagrange_row(H.gl_t, H.bary, s, &T[((size_t)c * NGL + k) * NGL]);
+        }
+    std::vector<double> cx(L.n_src), cy(L.n_src), cwx(L.n_src), cwy(L.n_src), cw(L.n_src);
+    for (int64_t p = 0; p < npan; ++p) {
+        const int64_t o = p * NGL;
+        double sp[NGL];
+        for (int i = 0; i < NGL; ++i) sp[i] = b->w[o + i] / H.gl_w[i];
+        for (int c = 0; c < nch; ++c)
+            for (int k = 0; k < NGL; ++k) {
+                const double *row = &T[((size_t)c * NGL + k) * NGL];
+                double x = 0, y = 0, nx = 0, ny = 0, s = 0;
+                for (int i = 0; i < NGL; ++i) {
+                    x += row[i] * b->x[o + i];
+                    y += row[i] * b->y[o + i];
+                    nx += row[i] * b->nx[o + i];
+                    ny += row[i] * b->ny[o + i];
+                    s += row[i] * sp[i];
+                }
+                double nn = sqrt(nx * nx + ny * ny);
+                int64_t q = (p * nch + c) * NGL + k;
+                double wq = H.gl_w[k] * s / nch;
+                cx[q] = x;
+                cy[q] = y;
+                cw[q] = wq;
+                cwx[q] = wq * nx / nn;
+                cwy[q] = wq * ny / nn;
+            }
+    }
+    // cells of side R_j over the bounding box of sources and targets
+    L.cell = L.radius;
+    L.ox = H.xmin - 1e-9;
+    L.oy = H.ymin - 1e-9;
+    int64_t ncx = (int64_t)floor((H.xmax - L.ox) / L.cell) + 1;
+    int64_t ncy = (int64_t)floor((H.ymax - L.oy) / L.cell) + 1;
+    if (ncx * ncy > (int64_t)1 << 26) {
+        set_error("level cell grid too large (delta too small for the domain)");
+        return MHK_EUNSUPPORTED;
+    }
+    L.ncx = (int)ncx;
+    L.ncy = (int)ncy;
+    std::vector<int64_t> key(L.n_src);
+    for (int64_t q = 0; q < L.n_src; ++q) {
+        int64_t ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((cx[q] - L.ox) / L.cell)));
+        int64_t iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((cy[q] - L.oy) / L.cell)));
+        key[q] = iy * ncx + ix;
+    }
+    std::vector<int32_t> order, start;
+    counting_sort(key, ncx * ncy, order, start);
+    std::vector<double> sx(L.n_src), sy(L.n_src), swx(L.n_src), swy(L.n_src), sw(L.n_src);
+    std::vector<int32_t> code(L.n_src);
+    for (int64_t s = 0; s < L.n_src; ++s) {
+        int32_t q = order[s];
+        sx[s] = cx[q]; sy[s] = cy[q]; sw[s] = cw[q]; swx[s] = cwx[q]; swy[s] = cwy[q];
+        code[s] = q;
+    }
+    TRY(upload(P, &L.sx, sx.data(), L.n_src));
+    TRY(upload(P, &L.sy, sy.data(), L.n_src));
+    TRY(upload(P, &L.sw, sw.data(), L.n_src));
+    TRY(upload(P, &L.swx, swx.data(), L.n_src));
+    TRY(upload(P, &L.swy, swy.data(), L.n_src));
+    TRY(upload(P, &L.code, code.data(), L.n_src));
+    TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
+    TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
+    TRY(dalloc(P, &L.q, 3 * (int64_t)P->p.batch * L.n_src));
+
+    // Kernel table: piecewise polynomials in a = r^2/(4 delta_j) on segments of
+    // width 1/4, each in the local variable v in [-1, 1]; coefficients from
+    // Chebyshev interpolation converted to monomials in v.
+    LevelQuad Q;
+    const double seg_w = 0.25;
+    L.seg_inv = 1.0 / seg_w;
+    L.nseg = (int)ceil(L.a_max / seg_w) + 1;
+    const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
+    const double cS = 1.0 / (4.0 * M_PI), cD = 1.0 / (8.0 * M_PI * L.delta_j);
+    std::vector<double> tab((size_t)L.nseg * TAB_NC * 2);
+    const int nc = TAB_NC;
+    std::vector<double> node(nc);
+    for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
+    for (int sgi = 0; sgi < L.nseg; ++sgi) {
+        double a0 = sgi * seg_w;
+        std::vector<long double> fS(nc), fD(nc);
+        for (int i = 0; i < nc; ++i) {
+            double a = a0 + 0.5 * seg_w * (1.0 + node[i]);
+            double i0, i1;
+            Q.eval(a, b_j, i0, i1);
+            fS[i] = i0 * cS;
+            fD[i] = i1 * cD;
+        }
+        for (int kind = 0; kind < 2; ++kind) {
+            std::vector<long double> &f = kind ? fD : fS;
+            // Chebyshev coefficients
+            std::vector<long double> ch(nc, 0);
+            for (int m = 0; m < nc; ++m) {
+                long double s = 0;
+                for (int i = 0; i < nc; ++i) s += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
+                ch[m] = s * (m == 0 ? 1.0L : 2.0L) / nc;
+            }
+            // T_m(v) -> monomials in v
+            std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
+            tprev[0] = 1;       // T0
+            tcur[1] = 1;        // T1
+            for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
+            if (nc > 1)
+                for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
+            for (int m = 2; m < nc; ++m) {
+                std::fill(tnext.begin(), tnext.end(), 0.0L);
+                for (int k = 0; k < nc; ++k) {
+                    if (k + 1 < nc) tnext[k + 1] += 2 * tcur[k];
+                    tnext[k] -= tprev[k];
+                }
+                for (int k = 0; k < nc; ++k) mono[k] += ch[m] * tnext[k];
+                tprev = tcur;
+                tcur = tnext;
+            }
+            for (int k = 0; k < nc; ++k) tab[((size_t)sgi * nc + k) * 2 + kind] = (double)mono[k];
+        }
+    }
+    // accuracy check of the table against direct quadrature
+    {
+        double k0S, k0D;
+        Q.eval(0.0, b_j, k0S, k0D);
+        k0S *= cS;
+        k0D *= cD;
+        double emax = 0;
+        for (int i = 0; i < 997; ++i) {
+            double a = L.a_max * (i + 0.37) / 997.0;
+            double i0, i1;
+            Q.eval(a, b_j, i0, i1);
+            int sgi = (int)(a * L.seg_inv);
+            double v = 2.0 * (a * L.seg_inv - sgi) - 1.0;
+            double pS = 0, pD = 0;
+            for (int k = nc - 1; k >= 0; --k) {
+                pS = pS * v + tab[((size_t)sgi * nc + k) * 2];
+                pD = pD * v + tab[((size_t)sgi * nc + k) * 2 + 1];
+            }
+            emax = std::max(emax, fabs(pS - i0 * cS) / k0S);
+            emax = std::max(emax, fabs(pD - i1 * cD) / k0D);
+        }
+        L.tab_err = emax;
+        if (emax > 1e-13) {
+            set_error("level kernel table not accurate: " + std::to_string(emax));
+            return MHK_EUNSUPPORTED;
+        }
+    }
+    TRY(upload(P, &L.tab, tab.data(), (int64_t)tab.size()));
+    return MHK_OK;
+}
+
+// Exponential-of-semicircle window phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+// |z| < 1 (Barnett, Magland and af Klinteberg, SIAM J. Sci. Comput. 41 (2019)),
+// and its Fourier transform in physical units by Gauss-Legendre quadrature.
+double window_ft(double k, double half_width, double beta, const std::vector<double> &qt,
+                 const std::vector<double> &qw)
+{
+    long double s = 0;
+    for (size_t i = 0; i < qt.size(); ++i) {
+        double z = qt[i];
+        s += qw[i] * exp(beta * (sqrt(1.0 - z * z) - 1.0)) * cos(k * half_width * z);
+    }
+    return (double)(s * half_width);
+}
+
+mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, const std::vector<double> &tgy)
+{
+    History &G = P->hist;
+    const double alpha = P->p.alpha, delta = P->delta;
+    G.kcut = P->info.kmax;
+    G.w = P->info.wspread;
+    G.ups = P->p.upsamp;
+    G.active = G.kcut > 0;
+    if (!G.active) return MHK_OK;
+    double eps = P->p.tol * 0.1;
+    double Lx = H.xmax - H.xmin, Ly = H.ymax - H.ymin, L = std::max(Lx, Ly);
+    // image distance: the periodic images of the history kernel must be below
+    // eps relative to its peak and to the mean field of a uniform source.
+    double gh0 = expint_e1(alpha * alpha * delta) / (4 * M_PI);
+    double m0 = exp(-delta * alpha * alpha) / (alpha * alpha);
+    double thr = eps * std::min(gh0, m0 / std::max(L * L, 1e-6));
+    double R = 1.0 / alpha;
+    while (sqrt(M_PI / (2 * alpha * R)) * exp(-alpha * R) / (2 * M_PI) > thr) R *= 1.02;
+    G.h = M_PI / (G.ups * G.kcut);
+    double need = L + R + (G.w + 6) * G.h;
+    int64_t nmin = (int64_t)ceil(need / G.h);
+    if (nmin > 60000) {
+        set_error("history grid too large (" + std::to_string(nmin) + "^2)");
+        return MHK_EUNSUPPORTED;
+    }
+    G.n = good_fft_size(nmin);
+    G.period = G.n * G.h;
+    G.ntile = (int)(G.n / TILE);
+    G.field = G.n * (G.n + 2);
+    G.ox = H.xmin - (G.w / 2 + 3) * G.h;
+    G.oy = H.ymin - (G.w / 2 + 3) * G.h;
+    G.beta = 0.97 * M_PI * (1.0 - 0.5 / G.ups) * G.w;
+    P->info.period = G.period;
+    P->info.n_fine = G.n;
+
+    // multiplier factors
+    std::vector<double> qt, qw;
+    gauss_legendre(160, qt, qw);
+    const int64_t nh = G.n / 2 + 1;
+    std::vector<double> fac(nh);
+    for (int64_t l = 0; l < nh; ++l) {
+        double k = 2 * M_PI * l / G.period;
+        if (k > G.kcut) {
+            fac[l] = 0;
+            continue;
+        }
+        double ph = window_ft(k, 0.5 * G.w * G.h, G.beta, qt, qw);
+        fac[l] = exp(-delta * k * k) / (ph * ph);
+    }
+    G.mult_c = pow(G.h, 4) / (G.period * G.period) * exp(-delta * alpha * alpha);
+    TRY(upload(P, &G.fac, fac.data(), nh));
+
+    const int64_t nt2 = (int64_t)G.ntile * G.ntile;
+    auto tile_of = [&](double x, double y) -> int64_t {
+        int64_t ix = (int64_t)floor((x - G.ox) / G.h) / TILE;
+        int64_t iy = (int64_t)floor((y - G.oy) / G.h) / TILE;
+        ix = std::min<int64_t>(G.ntile - 1, std::max<int64_t>(0, ix));
+        iy = std::min<int64_t>(G.ntile - 1, std::max<int64_t>(0, iy));
+        return iy * G.ntile + ix;
+    };
+    // boundary sources
+    {
+        const mhk_boundary *b = H.b;
+        int64_t nb = b->n_panels * NGL;
+        std::vector<int64_t> key(nb);
+        for (int64_t i = 0; i < nb; ++i) key[i] = tile_of(b->x[i], b->y[i]);
+        std::vector<int32_t> order, start;
+        counting_sort(key, nt2, order, start);
+        std::vector<double> gx(nb), gy(nb), w(nb), wx(nb), wy(nb);
+        for (int64_t s = 0; s < nb; ++s) {
+            int32_t i = order[s];
+            gx[s] = (b->x[i] - G.ox) / G.h;
+            gy[s] = (b->y[i] - G.oy) / G.h;
+            w[s] = b->w[i];
+            wx[s] = b->w[i] * b->nx[i];
+            wy[s] = b->w[i] * b->ny[i];
+        }
+        G.nbs = nb;
+        TRY(upload(P, &G.bgx, gx.data(), nb));
+        TRY(upload(P, &G.bgy, gy.data(), nb));
+        TRY(upload(P, &G.bw, w.data(), nb));
+        TRY(upload(P, &G.bwx, wx.data(), nb));
+        TRY(upload(P, &G.bwy, wy.data(), nb));
+        TRY(upload(P, &G.bidx, order.data(), nb));
+        TRY(upload(P, &G.btile, start.data(), nt2 + 1));
+    }
+    // volume sources
+    {
+        int64_t nv = H.v ? H.v->n : 0;
+        std::vector<int64_t> key(nv);
+        for (int64_t i = 0; i < nv; ++i) key[i] = tile_of(H.v->x[i], H.v->y[i]);
+        std::vector<int32_t> order, start;
+        counting_sort(key, nt2, order, start);
+        std::vector<double> gx(nv), gy(nv), w(nv);
+        for (int64_t s = 0; s < nv; ++s) {
+            int32_t i = order[s];
+            gx[s] = (H.v->x[i] - G.ox) / G.h;
+            gy[s] = (H.v->y[i] - G.oy) / G.h;
+            w[s] = H.v->w[i];
+        }
+        G.nvs = nv;
+        TRY(upload(P, &G.vgx, gx.data(), nv));
+        TRY(upload(P, &G.vgy, gy.data(), nv));
+        TRY(upload(P, &G.vw, w.data(), nv));
+        TRY(upload(P, &G.vidx, order.data(), nv));
+        TRY(upload(P, &G.vtile, start.data(), nt2 + 1));
+    }
+    // targets by tile (they are sorted with tiles contiguous)
+    {
+        std::vector<int32_t> xy, rng;
+        int64_t last = -1;
+        for (int64_t s = 0; s < (int64_t)tgx.size(); ++s) {
+            int64_t ix = (int64_t)floor((tgx[s] - G.ox) / G.h) / TILE;
+            int64_t iy = (int64_t)floor((tgy[s] - G.oy) / G.h) / TILE;
+            int64_t t = iy * G.ntile + ix;
+            if (t != last) {
+                xy.push_back((int32_t)t);
+                rng.push_back((int32_t)s);
+                last = t;
+            }
+        }
+        rng.push_back((int32_t)tgx.size());
+        G.n_ttiles = (int)xy.size();
+        TRY(upload(P, &G.ttile_xy, xy.data(), (int64_t)xy.size()));
+        TRY(upload(P, &G.ttile_rng, rng.data(), (int64_t)rng.size()));
+    }
+    // grids and FFT plans
+    TRY(dalloc(P, &G.grid, 4 * (int64_t)P->p.batch * G.field));
+    if (!g_rocfft_ready) {
+        MHK_FFT(rocfft_setup());
+        g_rocfft_ready = true;
+    }
+    size_t len[2] = {(size_t)G.n, (size_t)G.n};
+    size_t rstr[2] = {1, (size_t)G.n + 2}, cstr[2] = {1, (size_t)(G.n / 2 + 1)};
+    size_t rdist = (size_t)G.field, cdist = (size_t)(G.field / 2);
+    rocfft_plan_description df = nullptr, di = nullptr;
+    MHK_FFT(rocfft_plan_description_create(&df));
+    MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
+                                                    nullptr, nullptr, 2, rstr, rdist, 2, cstr, cdist));
+    MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward,
+                               rocfft_precision_double, 2, len, 4 * (size_t)P->p.batch, df));
+    MHK_FFT(rocfft_plan_description_create(&di));
+    MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real,
+                                                    nullptr, nullptr, 2, cstr, cdist, 2, rstr, rdist));
+    MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse,
+                               rocfft_precision_double, 2, len, 3 * (size_t)P->p.batch, di));
+    rocfft_plan_description_destroy(df);
+    rocfft_plan_description_destroy(di);
+    size_t w1 = 0, w2 = 0;
+    MHK_FFT(rocfft_plan_get_work_buffer_size(G.fwd, &w1));
+    MHK_FFT(rocfft_plan_get_work_buffer_size(G.inv, &w2));
+    G.work_bytes = std::max(w1, w2);
+    MHK_FFT(rocfft_execution_info_create(&G.exec));
+    if (G.work_bytes) {
+        char *wb = nullptr;
+        TRY(dalloc(P, &wb, (int64_t)G.work_bytes));
+        G.work = wb;
+        MHK_FFT(rocfft_execution_info_set_work_buffer(G.exec, G.work, G.work_bytes));
+    }
+    MHK_FFT(rocfft_execution_info_set_stream(G.exec, P->stream));
+    return MHK_OK;
+}
+
+mhk_status build_local(mhk_plan *P, Host &H)
+{
+    Local &C = P->loc;
+    const mhk_boundary *b = H.b;
+    const int64_t npan = b->n_panels, nb = npan * NGL;
+    // Legendre coefficients c_k = (2k+1)/2 sum_i w_i P_k(t_i) f_i
+    std::vector<double> leg(NGL * NGL);
+    for (int i = 0; i < NGL; ++i) {
+        double t = H.gl_t[i], p0 = 1, p1 = t;
+        for (int k = 0; k < NGL; ++k) {
+            double pk = (k == 0) ? 1.0 : (k == 1 ? t : 0.0);
+            if (k >= 2) {
+                double p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+                pk = p2;
+            }
+            leg[k * NGL + i] = (2 * k + 1) / 2.0 * H.gl_w[i] * pk;
+        }
+    }
+    auto coeffs = [&](const double *f, std::vector<double> &out) {
+        out.assign(nb, 0.0);
+        for (int64_t p = 0; p < npan; ++p)
+            for (int k = 0; k < NGL; ++k) {
+                long double s = 0;
+                for (int i = 0; i < NGL; ++i) s += (long double)leg[k * NGL + i] * f[p * NGL + i];
+                out[p * NGL + k] = (double)s;
+            }
+    };
+    std::vector<double> cx, cy, ck;
+    coeffs(b->x, cx);
+    coeffs(b->y, cy);
+    coeffs(b->kappa, ck);
+    std::vector<double> ends(npan * 4);
+    for (int64_t p = 0; p < npan; ++p) {
+        double xm = 0, ym = 0, xp = 0, yp = 0;
+        for (int k = 0; k < NGL; ++k) {
+            double sgn = (k % 2) ? -1.0 : 1.0;   // P_k(-1) = (-1)^k, P_k(1) = 1
+            xm += sgn * cx[p * NGL + k];
+            ym += sgn * cy[p * NGL + k];
+            xp += cx[p * NGL + k];
+            yp += cy[p * NGL + k];
+        }
+        ends[p * 4 + 0] = xm; ends[p * 4 + 1] = ym; ends[p * 4 + 2] = xp; ends[p * 4 + 3] = yp;
+    }
+    // nearest-node cell list: any target within the larger band of the curve has
+    // its nearest node within band + (largest node gap)
+    double gap = 0;
+    for (int64_t p = 0; p < npan; ++p) {
+        for (int i = 0; i + 1 < NGL; ++i)
+            gap = std::max(gap, hypot(b->x[p * NGL + i + 1] - b->x[p * NGL + i], b->y[p * NGL + i + 1] - b->y[p * NGL + i]));
+        int64_t q = H.next[p];
+        gap = std::max(gap, hypot(b->x[q * NGL] - b->x[p * NGL + NGL - 1], b->y[q * NGL] - b->y[p * NGL + NGL - 1]));
+    }
+    double band = std::max(P->info.band_layer, P->info.band_volume);
+    C.cell = 1.01 * band + gap;
+    C.ox = H.xmin - 1e-9;
+    C.oy = H.ymin - 1e-9;
+    int64_t ncx = (int64_t)floor((H.xmax - C.ox) / C.cell) + 1;
+    int64_t ncy = (int64_t)floor((H.ymax - C.oy) / C.cell) + 1;
+    if (ncx * ncy > (int64_t)1 << 26) {
+        set_error("local cell grid too large");
+        return MHK_EUNSUPPORTED;
+    }
+    C.ncx = (int)ncx;
+    C.ncy = (int)ncy;
+    std::vector<int64_t> key(nb);
+    for (int64_t i = 0; i < nb; ++i) {
+        int64_t ix = std::min<int64_t>(ncx - 1, (int64_t)floor((b->x[i] - C.ox) / C.cell));
+        int64_t iy = std::min<int64_t>(ncy - 1, (int64_t)floor((b->y[i] - C.oy) / C.cell));
+        key[i] = iy * ncx + ix;
+    }
+    std::vector<int32_t> order, start;
+    counting_sort(key, ncx * ncy, order, start);
+    std::vector<int32_t> prev(npan), next(npan);
+    for (int64_t p = 0; p < npan; ++p) {
+        prev[p] = (int32_t)H.prev[p];
+        next[p] = (int32_t)H.next[p];
+    }
+    TRY(upload(P, &C.node, order.data(), nb));
+    TRY(upload(P, &C.cell_start, start.data(), (int64_t)start.size()));
+    TRY(upload(P, &C.leg, leg.data(), NGL * NGL));
+    TRY(upload(P, &C.cx, cx.data(), nb));
+    TRY(upload(P, &C.cy, cy.data(), nb));
+    TRY(upload(P, &C.ck, ck.data(), nb));
+    TRY(upload(P, &C.ends, ends.data(), npan * 4));
+    TRY(upload(P, &C.gl_t, H.gl_t.data(), NGL));
+    TRY(upload(P, &C.prev, prev.data(), npan));
+    TRY(upload(P, &C.next, next.data(), npan));
+    TRY(dalloc(P, &C.csig, (int64_t)P->p.batch * nb));
+    TRY(dalloc(P, &C.cmu, (int64_t)P->p.batch * nb));
+    return MHK_OK;
+}
+
+mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_volume *v,
+                  const mhk_targets *t, void *stream, mhk_plan *P)
+{
+    TRY(check_inputs(params, b, v, t));
+    TRY(resolve(params, &P->info, &P->p));
+    if (P->p.prec != MHK_FP64) {
+        set_error("FP32 evaluation is not available in this build");
+        return MHK_EUNSUPPORTED;
+    }
+    P->stream = (hipStream_t)stream;
+    P->J = P->p.J;
+    P->delta = P->info.delta;
+    P->dstar = P->info.delta_star;
+    P->npan = b->n_panels;
+    P->nb = b->n_panels * NGL;
+    P->nv = v ? v->n : 0;
+    P->nt = t->n;
+    P->nout = t->n + (t->on_surface ? P->nb : 0);
+    Host H;
+    H.b = b;
+    H.v = (v && v->n > 0) ? v : nullptr;
+    H.t = t;
+    host_common(H);
+
+    // boundary arrays in caller order
+    TRY(upload(P, &P->bx, b->x, P->nb));
+    TRY(upload(P, &P->by, b->y, P->nb));
+    TRY(upload(P, &P->bnx, b->nx, P->nb));
+    TRY(upload(P, &P->bny, b->ny, P->nb));
+    TRY(upload(P, &P->bw, b->w, P->nb));
+    TRY(upload(P, &P->bk, b->kappa, P->nb));
+
+    // history parameters first: the target order follows the grid tiles
+    History &G = P->hist;
+    G.kcut = P->info.kmax;
+    G.w = P->info.wspread;
+    G.ups = P->p.upsamp;
+    // targets sorted in Morton order of cells of one grid step (or of a virtual
+    // grid of step R_J/8 when there is no history grid)
+    std::vector<double> tgx, tgy;
+    {
+        double hh, ox, oy;
+        if (G.kcut > 0) {
+            // provisional values, recomputed identically in build_history
+            double eps = P->p.tol * 0.1;
+            (void)eps;
+            hh = M_PI / (G.ups * G.kcut);
+            ox = H.xmin - (G.w / 2 + 3) * hh;
+            oy = H.ymin - (G.w / 2 + 3) * hh;
+        } else {
+            double rj = P->J > 0 ? P->info.level_radius[P->J - 1] : P->info.band_layer;
+            hh = std::max(rj / 8.0, std::max(H.xmax - H.xmin, H.ymax - H.ymin) / 60000.0);
+            ox = H.xmin - hh;
+            oy = H.ymin - hh;
+        }
+        int64_t nout = P->nout;
+        std::vector<uint64_t> key(nout);
+        for (int64_t i = 0; i < nout; ++i) {
+            uint32_t ix = (uint32_t)std::max(0.0, floor((H.tx[i] - ox) / hh));
+            uint32_t iy = (uint32_t)std::max(0.0, floor((H.ty[i] - oy) / hh));
+            key[i] = ((uint64_t)morton(std::min<uint32_t>(ix, 65535), std::min<uint32_t>(iy, 65535)) << 32) | (uint64_t)i;
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<double> sx(nout), sy(nout);
+        std::vector<int8_t> sin(nout);
+        std::vector<int32_t> sidx(nout);
+        for (int64_t s = 0; s < nout; ++s) {
+            int64_t i = (int64_t)(key[s] & 0xffffffffu);
+            sx[s] = H.tx[i];
+            sy[s] = H.ty[i];
+            sin[s] = H.tin[i];
+            sidx[s] = (int32_t)i;
+        }
+        TRY(upload(P, &P->tx, sx.data(), nout));
+        TRY(upload(P, &P->ty, sy.data(), nout));
+        TRY(upload(P, &P->tin, sin.data(), nout));
+        TRY(upload(P, &P->tidx, sidx.data(), nout));
+        tgx.swap(sx);
+        tgy.swap(sy);
+    }
+    for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j));
+    TRY(build_history(P, H, tgx, tgy));
+    TRY(build_local(P, H));
+    TRY(dalloc(P, &P->acc, 3 * (int64_t)P->p.batch * P->nout));
+    for (auto &e : P->ev) MHK_HIP(hipEventCreate(&e));
+    P->info.n_boundary = P->nb;
+    P->info.n_volume = P->nv;
+    P->info.n_targets = P->nt;
+    P->info.n_out = P->nout;
+    P->info.device_bytes = P->bytes;
+    MHK_HIP(hipDeviceSynchronize());
+    return MHK_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *mhk_last_error(void) { return g_err.c_str(); }
+
+mhk_status mhk_resolve_params(const mhk_params *params, mhk_info *info)
+{
+    return resolve(params, info, nullptr);
+}
+
+mhk_status mhk_plan_create(const mhk_params *params, const mhk_boundary *boundary,
+                           const mhk_volume *volume, const mhk_targets *targets, void *hip_stream,
+                           mhk_plan **out)
+{
+    if (!out) {
+        set_error("out is NULL");
+        return MHK_EINVAL;
+    }
+    *out = nullptr;
+    mhk_plan *P = new mhk_plan();
+    mhk_status s = create(params, boundary, volume, targets, hip_stream, P);
+    if (s != MHK_OK) {
+        free_plan(P);
+        return s;
+    }
+    *out = P;
+    return MHK_OK;
+}
+
+mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, const mhk_volume *v,
+                              const mhk_targets *t, int64_t *bytes)
+{
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return MHK_EINVAL;
+    }
+    TRY(check_inputs(params, b, v, t));
+    mhk_info I;
+    mhk_params p;
+    TRY(resolve(params, &I, &p));
+    int64_t nb = b->n_panels * NGL, nv = v ? v->n : 0;
+    int64_t nout = t->n + (t->on_surface ? nb : 0);
+    int64_t B = p.batch;
+    int64_t s = 0;
+    s += nb * 8 * 6;                          // boundary
+    s += nout * (8 * 2 + 1 + 4);              // targets
+    s += 3 * B * nout * 8;                    // accumulators
+    for (int j = 1; j <= p.J; ++j) {          // levels
+        int64_t ns = nb << j;
+        s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
+    }
+    s += nb * (8 * 3 + 4) + 2 * B * nb * 8;   // local
+    if (I.kmax > 0) {                         // history grid estimate
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        auto acc = [&](double x, double y) {
+            x0 = std::min(x0, x); x1 = std::max(x1, x);
+            y0 = std::min(y0, y); y1 = std::max(y1, y);
+        };
+        for (int64_t i = 0; i < nb; ++i) acc(b->x[i], b->y[i]);
+        for (int64_t i = 0; i < nv; ++i) acc(v->x[i], v->y[i]);
+        for (int64_t i = 0; i < t->n; ++i) acc(t->x[i], t->y[i]);
+        double L = std::max(x1 - x0, y1 - y0), a = p.alpha, d = I.delta;
+        double eps = p.tol * 0.1;
+        double thr = eps * std::min(expint_e1(a * a * d) / (4 * M_PI), exp(-d * a * a) / (a * a) / std::max(L * L, 1e-6));
+        double R = 1.0 / a;
+        while (sqrt(M_PI / (2 * a * R)) * exp(-a * R) / (2 * M_PI) > thr) R *= 1.02;
+        double h = M_PI / (p.upsamp * I.kmax);
+        int64_t n = good_fft_size((int64_t)ceil((L + R + (I.wspread + 6) * h) / h));
+        s += 4 * B * n * (n + 2) * 8 + 2 * B * n * (n + 2) * 8;   // grids + FFT work estimate
+        s += (nb + nv) * (8 * 3 + 4);
+    }
+    *bytes = s;
+    return MHK_OK;
+}
+
+mhk_status mhk_plan_set_timing(mhk_plan *P, int enable)
+{
+    if (!P) {
+        set_error("plan is NULL");
+        return MHK_EINVAL;
+    }
+    P->timing = enable != 0;
+    return MHK_OK;
+}
+
+mhk_status mhk_plan_info(const mhk_plan *P, mhk_info *info)
+{
+    if (!P || !info) {
+        set_error("plan or info is NULL");
+        return MHK_EINVAL;
+    }
+    *info = P->info;
+    return MHK_OK;
+}
+
+void mhk_plan_destroy(mhk_plan *P)
+{
+    if (P) {
+        (void)hipStreamSynchronize(P->stream);
+        free_plan(P);
+    }
+}
+
+mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void *mu_,
+                          const void *f_vol_, const void *f_trg_, void *out_s_, void *out_d_,
+                          void *out_v_)
+{
+    if (!P) {
+        set_error("plan is NULL");
+        return MHK_EINVAL;
+    }
+    if (parts < 0 || parts > MHK_PART_ALL) {
+        set_error("invalid parts mask");
+        return MHK_EINVAL;
+    }
+    const double *sigma = (const double *)sigma_, *mu = (const double *)mu_;
+    const double *f_vol = (const double *)f_vol_, *f_trg = (const double *)f_trg_;
+    double *out_s = (double *)out_s_, *out_d = (double *)out_d_, *out_v = (double *)out_v_;
+    const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
+    if ((sigma && !out_s) || (mu && !out_d) || (f_vol && !out_v)) {
+        set_error("an input density was given without its output array");
+        return MHK_EINVAL;
+    }
+    if (wv && !f_trg && (parts & MHK_PART_LOCAL)) {
+        set_error("f_trg is required with f_vol for the local part of V");
+        return MHK_EINVAL;
+    }
+    if (f_vol && P->nv == 0) {
+        set_error("f_vol given but the plan has no volume nodes");
+        return MHK_EINVAL;
+    }
+    if (!ws && !wd && !wv) return MHK_OK;
+    hipStream_t st = P->stream;
+    const int B = P->p.batch;
+    const int64_t nout = P->nout;
+    if (P->timing) MHK_HIP(hipEventRecord(P->ev[0], st));
+    // history part writes the accumulators (or zeros them)
+    bool hist = (parts & MHK_PART_HISTORY) && P->hist.active;
+    if (hist) {
+        MHK_HIP(launch_spread(P, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_vol : nullptr));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[1], st));
+        void *buf[1] = {P->hist.grid};
+        MHK_FFT(rocfft_execute(P->hist.fwd, buf, nullptr, P->hist.exec));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[2], st));
+        MHK_HIP(launch_multiply(P));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[3], st));
+        MHK_FFT(rocfft_execute(P->hist.inv, buf, nullptr, P->hist.exec));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[4], st));
+        MHK_HIP(launch_interp(P, ws, wd, wv));
+    } else {
+        MHK_HIP(launch_fill(P->acc, 3 * (int64_t)B * nout, 0.0, st));
+        if (P->timing)
+            for (int e = 1; e <= 4; ++e) MHK_HIP(hipEventRecord(P->ev[e], st));
+    }
+    if (P->timing) MHK_HIP(hipEventRecord(P->ev[5], st));
+    if ((parts & MHK_PART_LEVELS) && (ws || wd)) {
+        for (int j = 1; j <= P->J; ++j) {
+            MHK_HIP(launch_level_densities(P, j, ws ? sigma : nullptr, wd ? mu : nullptr));
+            MHK_HIP(launch_level_sums(P, j, ws, wd));
+        }
+    }
+    if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], st));
+    if ((parts & MHK_PART_LOCAL) && (ws || wd)) MHK_HIP(launch_panel_coeffs(P, ws ? sigma : nullptr, wd ? mu : nullptr));
+    MHK_HIP(launch_local(P, parts, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_trg : nullptr,
+                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr));
+    if (P->timing) {
+        MHK_HIP(hipEventRecord(P->ev[7], st));
+        MHK_HIP(hipEventSynchronize(P->ev[7]));
+        float ms[8] = {0};
+        for (int e = 1; e < 8; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
+        P->info.ms_spread = ms[1];
+        P->info.ms_fft = ms[2] + ms[4];
+        P->info.ms_multiply = ms[3];
+        P->info.ms_interp = ms[5];
+        P->info.ms_levels = ms[6];
+        P->info.ms_local = ms[7];
+        float tot = 0;
+        MHK_HIP(hipEventElapsedTime(&tot, P->ev[0], P->ev[7]));
+        P->info.ms_total = tot;
+    }
+    return MHK_OK;
+}
+
+mhk_status mhk_eval(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol, const void *f_trg,
+                    void *out_S, void *out_D, void *out_V)
+{
+    return mhk_eval_parts(P, MHK_PART_ALL, sigma, mu, f_vol, f_trg, out_S, out_D, out_V);
+}
+
+mhk_status mhk_eval_S(mhk_plan *P, const void *sigma, void *out_S)
+{
+    if (!sigma || !out_S) {
+        set_error("sigma and out_S are required");
+        return MHK_EINVAL;
+    }
+    return mhk_eval_parts(P, MHK_PART_ALL, sigma, nullptr, nullptr, nullptr, out_S, nullptr, nullptr);
+}
+
+mhk_status mhk_eval_D(mhk_plan *P, const void *mu, void *out_D)
+{
+    if (!mu || !out_D) {
+        set_error("mu and out_D are required");
+        return MHK_EINVAL;
+    }
+    return mhk_eval_parts(P, MHK_PART_ALL, nullptr, mu, nullptr, nullptr, nullptr, out_D, nullptr);
+}
+
+mhk_status mhk_eval_V(mhk_plan *P, const void *f_vol, const void *f_trg, void *out_V)
+{
+    if (!f_vol || !f_trg || !out_V) {
+        set_error("f_vol, f_trg and out_V are required");
+        return MHK_EINVAL;
+    }
+    return mhk_eval_parts(P, MHK_PART_ALL, nullptr, nullptr, f_vol, f_trg, nullptr, nullptr, out_V);
+}
+
+}  // extern "C"

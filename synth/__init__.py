@@ -143,9 +143,14 @@ def discretize(curves, panels):
 
 
 def inside_any(curves, x, y):
+    x = np.asarray(x, dtype=float)
+    y = np.asarray(y, dtype=float)
     m = np.zeros(np.shape(x), dtype=bool)
     for cv in curves:
-        m |= cv.inside(x, y)
+        r = cv.rmax()
+        sel = (np.abs(x - cv.cx) <= r) & (np.abs(y - cv.cy) <= r)
+        if sel.any():
+            m[sel] |= cv.inside(x[sel], y[sel])
     return m
 
 
@@ -242,29 +247,38 @@ def cut_cell_volume(curves, dx, box=None):
     x, y, w = _tri_nodes(A, B, Cc)
     xs.append(x); ys.append(y); ws.append(w)
     cut = np.nonzero((cnt > 0) & (cnt < 3))[0]
-    polys_a, polys_b, polys_c = [], [], []
-    for k in cut:
-        P = list(zip(TX[k], TY[k])); I = list(TI[k])
-        poly = []
+    if len(cut):
+        CX, CY, CI = TX[cut], TY[cut], TI[cut]                    # (nc, 3)
+        pts = np.zeros((len(cut), 6, 2))
+        keep = np.zeros((len(cut), 6), dtype=bool)
         for e in range(3):
-            pa, pb = np.array(P[e]), np.array(P[(e + 1) % 3])
-            if I[e]:
-                poly.append(pa)
-            if I[e] != I[(e + 1) % 3]:
-                lo, hi = (pa, pb) if I[e] else (pb, pa)   # lo inside, hi outside
-                for _ in range(48):
-                    m = 0.5 * (lo + hi)
-                    if inside_any(curves, m[0:1], m[1:2])[0]:
-                        lo = m
-                    else:
-                        hi = m
-                poly.append(0.5 * (lo + hi))
-        for q in range(1, len(poly) - 1):
-            polys_a.append(poly[0]); polys_b.append(poly[q]); polys_c.append(poly[q + 1])
-    if polys_a:
-        x, y, w = _tri_nodes(np.array(polys_a), np.array(polys_b), np.array(polys_c))
-        keep = w > 0
-        xs.append(x[keep]); ys.append(y[keep]); ws.append(w[keep])
+            a, b = e, (e + 1) % 3
+            pts[:, 2 * e, 0], pts[:, 2 * e, 1] = CX[:, a], CY[:, a]
+            keep[:, 2 * e] = CI[:, a]
+            cross = CI[:, a] != CI[:, b]
+            # bisection for the boundary crossing on the edge (lo inside, hi outside)
+            lox = np.where(CI[:, a], CX[:, a], CX[:, b]); loy = np.where(CI[:, a], CY[:, a], CY[:, b])
+            hix = np.where(CI[:, a], CX[:, b], CX[:, a]); hiy = np.where(CI[:, a], CY[:, b], CY[:, a])
+            idx = np.nonzero(cross)[0]
+            lx, ly, hx, hy = lox[idx], loy[idx], hix[idx], hiy[idx]
+            for _ in range(48):
+                mx, my = 0.5 * (lx + hx), 0.5 * (ly + hy)
+                ins = inside_any(curves, mx, my)
+                lx = np.where(ins, mx, lx); ly = np.where(ins, my, ly)
+                hx = np.where(ins, hx, mx); hy = np.where(ins, hy, my)
+            pts[idx, 2 * e + 1, 0] = 0.5 * (lx + hx)
+            pts[idx, 2 * e + 1, 1] = 0.5 * (ly + hy)
+            keep[:, 2 * e + 1] = cross
+        order = np.argsort(~keep, axis=1, kind="stable")
+        P = np.take_along_axis(pts, order[:, :, None], axis=1)
+        cntp = keep.sum(1)
+        A, Bv, Cv = P[:, 0], P[:, 1], P[:, 2]
+        x, y, w = _tri_nodes(A, Bv, Cv)
+        xs.append(x); ys.append(y); ws.append(w)
+        q = cntp == 4
+        if q.any():
+            x, y, w = _tri_nodes(P[q, 0], P[q, 2], P[q, 3])
+            xs.append(x); ys.append(y); ws.append(w)
     return {"x": np.concatenate(xs), "y": np.concatenate(ys), "w": np.concatenate(ws)}
 
 

@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/mhk.h, applies the parameter rule of
+Section 6.4 and rejects invalid arguments."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2606_28865_amd as M
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mhk.h")).read()
+    return sorted(set(re.findall(r"\b(mhk_[a-z_A-Z]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = M.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _golden():
+    vals = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "hilbert_chain.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split("=")
+            vals[k.strip()] = float(v)
+    return vals
+
+
+def test_parameter_rule_hilbert_chain():
+    """Section 6.4: dx ~ 2.5e-3, k_max = 0.9 pi/dx ~ 1141, delta ~ 1.06e-5,
+    delta* ~ 1.66e-7 with J = 3 and eps = 1e-6, alpha = 10."""
+    g = _golden()
+    dx = 0.9 * math.pi / g["kmax"]
+    assert dx == pytest.approx(g["dx"], rel=0.02)
+    info = M.resolve_params(alpha=g["alpha"], tol=g["eps"], dx=dx, J=int(g["J"]))
+    assert info["delta"] == pytest.approx(g["delta"], rel=5e-3)
+    assert info["delta_star"] == pytest.approx(g["delta_star"], rel=5e-3)
+    # the history cut-off uses the stricter double-layer rule (eq. (kmax_dlp))
+    k, d, a, eps = info["kmax"], info["delta"], g["alpha"], g["eps"] * 0.1
+    assert k * math.exp(-d * (a * a + k * k)) == pytest.approx(eps, rel=1e-8)
+
+
+def test_bands_and_levels():
+    info = M.resolve_params(alpha=10.0, tol=1e-10, delta=1e-3, J=3)
+    ds = 1e-3 / 64
+    assert info["band_layer"] == pytest.approx(math.sqrt(ds) * (12 + 2 * 10 * math.sqrt(ds)), rel=1e-14)
+    assert info["band_volume"] == pytest.approx(math.sqrt(1e-3) * (12 + 20 * math.sqrt(1e-3)), rel=1e-14)
+    r = info["level_radius"]
+    assert r[0] / r[1] == pytest.approx(2.0) and r[1] / r[2] == pytest.approx(2.0)
+    # the history vanishes when delta alpha^2 >= ln(1/eps) (Section 5.2)
+    assert M.resolve_params(alpha=300.0, tol=1e-6, delta=1e-3)["kmax"] == 0.0
+
+
+@pytest.mark.parametrize("kw", [dict(alpha=-1.0, tol=1e-6, delta=1e-3), dict(alpha=1.0, tol=1e-1, delta=1e-3),
+                                dict(alpha=1.0, tol=1e-6), dict(alpha=1.0, tol=1e-6, delta=1e-3, J=9),
+                                dict(alpha=1.0, tol=1e-6, delta=1e-3, batch=0),
+                                dict(alpha=1.0, tol=1e-6, delta=1e-3, prec=3),
+                                dict(alpha=1.0, tol=1e-6, delta=1e-3, wspread=2),
+                                dict(alpha=float("nan"), tol=1e-6, delta=1e-3)])
+def test_invalid_params_rejected(kw):
+    with pytest.raises(M.MhkError) as e:
+        M.resolve_params(**kw)
+    assert e.value.code == -1
+
+
+def test_footprint_and_input_validation():
+    w = synth.config0()
+    prm = M.make_params(alpha=10.0, tol=1e-10, dx=w.dx)
+    nbytes = M.footprint(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    assert nbytes > 0
+    b2 = dict(w.boundary)
+    b2["x"] = w.boundary["x"].copy()
+    b2["x"][3] = np.nan
+    with pytest.raises(M.MhkError):
+        M.footprint(prm, b2, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    with pytest.raises(M.MhkError):
+        M.footprint(prm, w.boundary, w.volume, None, on_surface=False)
+    b3 = dict(w.boundary)
+    b3["curve_panel_ofs"] = np.array([0, 5])
+    with pytest.raises(M.MhkError):
+        M.footprint(prm, b3, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
