@@ -38,6 +38,10 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -52,6 +56,7 @@ def main():
     t0 = time.time()
     w = synth.multibody()
     gen_s = time.time() - t0
+    log(f"workload {w.name} generated in {gen_s:.1f} s")
     alphas = [float(x) for x in a.alphas.split(",")]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -65,12 +70,14 @@ def main():
         torch.cuda.synchronize()
         plan_s.append(time.time() - t1)
         plans.append(p)
+        log(f"plan alpha={al}: {plan_s[-1]:.1f} s, grid {p.info()['n_fine']}, {p.info()['device_bytes'] / 1e9:.2f} GB")
     n_out = plans[0].n_out
     outs = [p.eval(sigma, mu, fv, ft) for p in plans]
     for _ in range(a.warmup):
         for p, o in zip(plans, outs):
             p.eval(sigma, mu, fv, ft, out=o)
     torch.cuda.synchronize()
+    log("warmup done")
     for p in plans:
         p.set_timing(True)
     stage = {k: [0.0] * len(plans) for k in ("ms_spread", "ms_fft", "ms_multiply", "ms_interp", "ms_levels",
@@ -101,6 +108,7 @@ def main():
     dom = max(tot, key=tot.get)
     roof = roofline(dom, stage, infos, w, plans)
 
+    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step")
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(w, infos, alphas, a.cpu_sample)

@@ -112,6 +112,7 @@ typedef struct {
     int64_t device_bytes; /* device memory owned by the plan                         */
     /* milliseconds of the last eval per stage (0 unless timing was enabled)       */
     double ms_spread, ms_fft, ms_multiply, ms_interp, ms_levels, ms_local, ms_total;
+    int history_truncated; /* 1: smoothly truncated history kernel, tabulated spectrum */
 } mhk_info;
 
 typedef struct mhk_plan mhk_plan;

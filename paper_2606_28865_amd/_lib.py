@@ -49,7 +49,7 @@ class Info(C.Structure):
                 ("n_out", C.c_int64), ("device_bytes", C.c_int64),
                 ("ms_spread", C.c_double), ("ms_fft", C.c_double), ("ms_multiply", C.c_double),
                 ("ms_interp", C.c_double), ("ms_levels", C.c_double), ("ms_local", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("history_truncated", C.c_int)]
 
     def as_dict(self):
         d = {}

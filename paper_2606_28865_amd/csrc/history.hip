@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
 // Fourier multiplier on the half spectrum [n][n/2+1] of each field.
 __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t field, double *grid,
                                                   const double *__restrict__ fac, double c, double alpha2,
-                                                  double dk)
+                                                  double dk, const double *__restrict__ mtab, int lmax)
 {
     const int64_t nh = n / 2 + 1;
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -151,9 +151,15 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
     const size_t fs = (size_t)B * field / 2;                  // complex values per field group
     double2 *F = reinterpret_cast<double2 *>(grid) + (size_t)b * (field / 2) + ly * nh + lx;
     double2 zS = {0, 0}, zV = {0, 0}, zD = {0, 0};
-    if (ax != 0.0 && ay != 0.0) {
+    double M = 0.0;
+    if (mtab) {
+        if (lx <= lmax && fy >= -lmax && fy <= lmax) M = mtab[(fy + lmax) * (lmax + 1) + lx];
+    } else if (ax != 0.0 && ay != 0.0) {
         const double kx = dk * lx, ky = dk * fy;
-        const double M = c * ax * ay / (alpha2 + kx * kx + ky * ky);
+        M = c * ax * ay / (alpha2 + kx * kx + ky * ky);
+    }
+    if (M != 0.0) {
+        const double kx = dk * lx, ky = dk * fy;
         const double2 s = F[0], v = F[fs], gx = F[2 * fs], gy = F[3 * fs];
         zS = make_double2(M * s.x, M * s.y);
         zV = make_double2(M * v.x, M * v.y);
@@ -228,6 +234,88 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs A)
     }
 }
 
+// History kernel G^H(r) = int_delta^inf H(t, r) dt (eq. (sl_sh)) by composite
+// 16-point Gauss-Legendre in u with t = delta e^{-u}, u in (-inf, 0]:
+//   G^H = (1/4pi) int exp(-a e^u - b e^{-u}) du,  a = r^2/(4 delta), b = alpha^2 delta,
+// truncated where the exponent is below -700; panels narrower than the
+// width 1/sqrt(2 sqrt(ab)) of the integrand's peak.
+__device__ double history_kernel(double r, double alpha, double delta, const double *__restrict__ gt,
+                                 const double *__restrict__ gw)
+{
+    const double a = r * r / (4.0 * delta), b = alpha * alpha * delta;
+    double lo = log(b / 700.0), hi = 0.0;
+    if (a > 0.0) hi = fmin(hi, log(700.0 / a));
+    if (!(hi > lo)) return 0.0;
+    const double width = 1.0 / sqrt(1.0 + 2.0 * sqrt(a * b));
+    int m = (int)ceil((hi - lo) / (0.5 * width));
+    m = max(1, min(m, 2000));
+    const double hp = (hi - lo) / m;
+    double s = 0.0;
+    for (int p = 0; p < m; ++p) {
+        const double c = lo + (p + 0.5) * hp;
+        double ps = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            const double u = c + 0.5 * hp * gt[q];
+            ps = fma(gw[q], exp(-a * exp(u) - b * exp(-u)), ps);
+        }
+        s += ps;
+    }
+    return s * 0.5 * hp / (4.0 * M_PI);
+}
+
+// Samples h^2 G^H(r) chi(r) of the smoothly truncated history kernel on a
+// centred periodic grid of 2n x 2n points of step h (rows padded to 2n+2),
+// chi(r) = erfc((r - rmid) slope)/2, zero beyond rcut.
+__global__ void __launch_bounds__(256) k_trunc_samples(double *buf, int64_t n2, double h, double alpha,
+                                                       double delta, double rcut, double rmid, double slope,
+                                                       const double *__restrict__ gt,
+                                                       const double *__restrict__ gw)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n2 * n2) return;
+    const int64_t iy = id / n2, ix = id % n2;
+    const double x = (ix < n2 / 2 ? ix : ix - n2) * h, y = (iy < n2 / 2 ? iy : iy - n2) * h;
+    const double r = sqrt(x * x + y * y);
+    double v = 0.0;
+    if (r < rcut) v = h * h * history_kernel(r, alpha, delta, gt, gw) * 0.5 * erfc((r - rmid) * slope);
+    buf[iy * (n2 + 2) + ix] = v;
+}
+
+// Multiplier table on the kept modes from the spectrum of the samples: the
+// transform of the even kernel is real; mode l of the period-P grid is mode
+// 2l of the period-2P sample grid.
+__global__ void __launch_bounds__(256) k_trunc_table(const double *__restrict__ spec, int64_t n2, int lmax,
+                                                     const double *__restrict__ phi2inv, double c,
+                                                     double *__restrict__ mtab)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = lmax + 1;
+    if (id >= (2 * (int64_t)lmax + 1) * w) return;
+    const int64_t lx = id % w, fy = id / w - lmax;
+    const int64_t ky2 = ((2 * fy) % n2 + n2) % n2, kx2 = 2 * lx;
+    const double re = spec[2 * (ky2 * (n2 / 2 + 1) + kx2)];
+    mtab[id] = c * re * phi2inv[lx] * phi2inv[fy < 0 ? -fy : fy];
+}
+
+hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,
+                                       double rmid, double slope, const double *gl_t, const double *gl_w,
+                                       hipStream_t s)
+{
+    const int64_t tot = n2 * n2;
+    hipLaunchKernelGGL(k_trunc_samples, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, buf, n2, h, alpha,
+                       delta, rcut, rmid, slope, gl_t, gl_w);
+    return hipGetLastError();
+}
+
+hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const double *phi2inv, double c,
+                              double *mtab, hipStream_t s)
+{
+    const int64_t tot = (2 * (int64_t)lmax + 1) * (lmax + 1);
+    hipLaunchKernelGGL(k_trunc_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, spec, n2, lmax, phi2inv,
+                       c, mtab);
+    return hipGetLastError();
+}
+
 template <int W>
 static hipError_t spread_w(mhk_plan *P, const SpreadArgs &A)
 {
@@ -289,7 +377,8 @@ hipError_t launch_multiply(mhk_plan *P)
     const History &G = P->hist;
     const int64_t tot = G.n * (G.n / 2 + 1) * P->p.batch;
     hipLaunchKernelGGL(k_multiply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, G.n, P->p.batch,
-                       G.field, G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha, 2.0 * M_PI / G.period);
+                       G.field, G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha, 2.0 * M_PI / G.period,
+                       G.trunc ? G.mtab : nullptr, G.lmax);
     return hipGetLastError();
 }
 

@@ -85,6 +85,13 @@ struct History {
     // multiplier factors A[l] = exp(-delta k_l^2)/phihat(k_l)^2, 0 beyond kcut
     double *fac = nullptr;                        // [n/2+1]
     double mult_c = 0;                            // h^4/P^2 exp(-delta alpha^2)
+    // truncated-kernel mode: the history kernel is cut off smoothly beyond the
+    // largest source-target distance and its spectrum tabulated on the kept
+    // modes |l_x|, |l_y| <= lmax (already divided by phihat^2, times h^4/P^2)
+    bool trunc = false;
+    int lmax = 0;
+    double *mtab = nullptr;                       // [2 lmax + 1][lmax + 1]
+    double trunc_d = 0, trunc_w = 0;              // separation bound D, transition width
     // grids
     double *grid = nullptr;                       // [4][batch][field]
     void *work = nullptr;
@@ -144,5 +151,10 @@ hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, con
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,
+                                       double rmid, double slope, const double *gl_t, const double *gl_w,
+                                       hipStream_t s);
+hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const double *phi2inv, double c,
+                              double *mtab, hipStream_t s);
 
 }  // namespace mhk

@@ -644,6 +644,116 @@ double window_ft(double k, double half_width, double beta, const std::vector<dou
     return (double)(s * half_width);
 }
 
+// Multiplier table of the smoothly truncated history kernel g_T(r) =
+// G^H(r) chi(r), chi = 1 up to the separation bound D and 0 beyond D + trans:
+// samples on a 2n x 2n grid of the same step (period 2P, which holds the
+// support of g_T without overlap), one real-to-complex FFT, and the even
+// modes, which are the modes of the period-P grid.
+mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const std::vector<double> &qw)
+{
+    History &G = P->hist;
+    const double rmid = G.trunc_d + 0.5 * G.trunc_w, slope = 11.8 / G.trunc_w;
+    const double rcut = G.trunc_d + G.trunc_w;
+    const int64_t n2 = 2 * G.n;
+    G.lmax = (int)floor(G.kcut * G.period / (2 * M_PI));
+    if (2 * G.lmax > n2 / 2) {
+        set_error("truncated-kernel table: too many modes for the grid");
+        return MHK_EUNSUPPORTED;
+    }
+    std::vector<double> t16, w16;
+    gauss_legendre(16, t16, w16);
+    double *buf = nullptr, *gt = nullptr, *gw = nullptr, *phi = nullptr, *work = nullptr;
+    size_t bytes = sizeof(double) * (size_t)n2 * (size_t)(n2 + 2);
+    if (hipMalloc((void **)&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("truncated-kernel table: allocation of the sample grid failed");
+        return MHK_ENOMEM;
+    }
+    mhk_status st = MHK_OK;
+    rocfft_plan plan = nullptr;
+    rocfft_execution_info ex = nullptr;
+    rocfft_plan_description d = nullptr;
+    std::vector<double> phi2inv(G.lmax + 1);
+    for (int l = 0; l <= G.lmax; ++l) {
+        double k = 2 * M_PI * l / G.period;
+        double ph = window_ft(k, 0.5 * G.w * G.h, G.beta, qt, qw);
+        phi2inv[l] = 1.0 / (ph * ph);
+    }
+    do {
+        if (hipMalloc((void **)&gt, 16 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&gw, 16 * sizeof(double)) != hipSuccess ||
+            hipMalloc((void **)&phi, (G.lmax + 1) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("truncated-kernel table: allocation failed");
+            st = MHK_ENOMEM;
+            break;
+        }
+        if (hipMemcpy(gt, t16.data(), 16 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(gw, w16.data(), 16 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(phi, phi2inv.data(), (G.lmax + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("truncated-kernel table: copy failed");
+            st = MHK_EHIP;
+            break;
+        }
+        if (launch_trunc_kernel_samples(buf, n2, G.h, P->p.alpha, P->delta, rcut, rmid, slope, gt, gw, P->stream) !=
+            hipSuccess) {
+            set_error("truncated-kernel sample launch failed");
+            st = MHK_EHIP;
+            break;
+        }
+        size_t len[2] = {(size_t)n2, (size_t)n2};
+        size_t rstr[2] = {1, (size_t)n2 + 2}, cstr[2] = {1, (size_t)(n2 / 2 + 1)};
+        if (rocfft_plan_description_create(&d) != rocfft_status_success ||
+            rocfft_plan_description_set_data_layout(d, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
+                                                    nullptr, nullptr, 2, rstr, (size_t)n2 * (n2 + 2), 2, cstr,
+                                                    (size_t)n2 * (n2 / 2 + 1)) != rocfft_status_success ||
+            rocfft_plan_create(&plan, rocfft_placement_inplace, rocfft_transform_type_real_forward,
+                               rocfft_precision_double, 2, len, 1, d) != rocfft_status_success ||
+            rocfft_execution_info_create(&ex) != rocfft_status_success) {
+            set_error("truncated-kernel table: rocFFT plan failed");
+            st = MHK_EHIP;
+            break;
+        }
+        size_t wb = 0;
+        rocfft_plan_get_work_buffer_size(plan, &wb);
+        if (wb) {
+            if (hipMalloc((void **)&work, wb) != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("truncated-kernel table: work buffer allocation failed");
+                st = MHK_ENOMEM;
+                break;
+            }
+            rocfft_execution_info_set_work_buffer(ex, work, wb);
+        }
+        rocfft_execution_info_set_stream(ex, P->stream);
+        void *io[1] = {buf};
+        if (rocfft_execute(plan, io, nullptr, ex) != rocfft_status_success) {
+            set_error("truncated-kernel table: FFT failed");
+            st = MHK_EHIP;
+            break;
+        }
+        const int64_t nt = (2 * (int64_t)G.lmax + 1) * (G.lmax + 1);
+        st = dalloc(P, &G.mtab, nt);
+        if (st != MHK_OK) break;
+        const double c = pow(G.h, 4) / (G.period * G.period);   // samples carry h^2: spectrum ~ transform
+        if (launch_trunc_table(buf, n2, G.lmax, phi, c, G.mtab, P->stream) != hipSuccess ||
+            hipStreamSynchronize(P->stream) != hipSuccess) {
+            set_error("truncated-kernel table kernel failed");
+            st = MHK_EHIP;
+            break;
+        }
+    } while (0);
+    if (ex) rocfft_execution_info_destroy(ex);
+    if (plan) rocfft_plan_destroy(plan);
+    if (d) rocfft_plan_description_destroy(d);
+    (void)hipFree(buf);
+    if (gt) (void)hipFree(gt);
+    if (gw) (void)hipFree(gw);
+    if (phi) (void)hipFree(phi);
+    if (work) (void)hipFree(work);
+    return st;
+}
+
 mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, const std::vector<double> &tgy)
 {
     History &G = P->hist;
@@ -663,7 +773,19 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     double R = 1.0 / alpha;
     while (sqrt(M_PI / (2 * alpha * R)) * exp(-alpha * R) / (2 * M_PI) > thr) R *= 1.02;
     G.h = M_PI / (G.ups * G.kcut);
-    double need = L + R + (G.w + 6) * G.h;
+    // Two ways to make the periodic images harmless: a period longer than the
+    // extent plus the decay length R of the kernel, or a kernel cut off
+    // smoothly beyond the largest source-target distance D (its spectrum
+    // then tabulated by FFT, in the spirit of the truncated-kernel method
+    // of Vico, Greengard and Ferrando the paper cites for small alpha).
+    // The cut-off erfc((r - r_mid) 11.8/trans)/2 smears the spectrum by a
+    // Gaussian of width ~23.6/trans: it must stay narrow against both the
+    // multiplier's own width 1/sqrt(delta) and the cut-off k_max.
+    const double Dsep = sqrt(Lx * Lx + Ly * Ly);
+    const double trans = std::max({0.25 * Dsep, 110.0 * sqrt(delta), 120.0 / G.kcut});
+    const double per_periodic = L + R, per_trunc = L + Dsep + trans;
+    G.trunc = per_trunc < 0.9 * per_periodic;
+    double need = (G.trunc ? per_trunc : per_periodic) + (G.w + 6) * G.h;
     int64_t nmin = (int64_t)ceil(need / G.h);
     if (nmin > 60000) {
         set_error("history grid too large (" + std::to_string(nmin) + "^2)");
@@ -676,8 +798,15 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     G.ox = H.xmin - (G.w / 2 + 3) * G.h;
     G.oy = H.ymin - (G.w / 2 + 3) * G.h;
     G.beta = 0.97 * M_PI * (1.0 - 0.5 / G.ups) * G.w;
+    G.trunc_d = Dsep;
+    G.trunc_w = trans;
+    if (!g_rocfft_ready) {
+        MHK_FFT(rocfft_setup());
+        g_rocfft_ready = true;
+    }
     P->info.period = G.period;
     P->info.n_fine = G.n;
+    P->info.history_truncated = G.trunc ? 1 : 0;
 
     // multiplier factors
     std::vector<double> qt, qw;
@@ -695,6 +824,7 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     }
     G.mult_c = pow(G.h, 4) / (G.period * G.period) * exp(-delta * alpha * alpha);
     TRY(upload(P, &G.fac, fac.data(), nh));
+    if (G.trunc) TRY(build_trunc_table(P, qt, qw));
 
     const int64_t nt2 = (int64_t)G.ntile * G.ntile;
     auto tile_of = [&](double x, double y) -> int64_t {
@@ -1066,7 +1196,10 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         double R = 1.0 / a;
         while (sqrt(M_PI / (2 * a * R)) * exp(-a * R) / (2 * M_PI) > thr) R *= 1.02;
         double h = M_PI / (p.upsamp * I.kmax);
-        int64_t n = good_fft_size((int64_t)ceil((L + R + (I.wspread + 6) * h) / h));
+        double Dsep = hypot(x1 - x0, y1 - y0);
+        double trans = std::max({0.25 * Dsep, 110.0 * sqrt(d), 120.0 / I.kmax});
+        double per = std::min(L + R, L + Dsep + trans);
+        int64_t n = good_fft_size((int64_t)ceil((per + (I.wspread + 6) * h) / h));
         s += 4 * B * n * (n + 2) * 8 + 2 * B * n * (n + 2) * 8;   // grids + FFT work estimate
         s += (nb + nv) * (8 * 3 + 4);
     }

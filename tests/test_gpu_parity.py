@@ -84,10 +84,10 @@ def test_config0_parts(cfg0, parts):
         assert err < TOL, (name, err)
 
 
-@pytest.mark.parametrize("alpha", [3.0, 30.0, 300.0])
+@pytest.mark.parametrize("alpha", [1.0, 3.0, 30.0, 300.0])
 def test_config0_alphas(cfg0, alpha):
-    """Other alpha: small (large history grid), large (history vanishes at
-    300 since delta alpha^2 > ln(1/eps), Section 5.2)."""
+    """Other alpha: small (truncated history kernel, tabulated spectrum),
+    large (at 300 the history is below 1e-12 of its peak, Section 5.2)."""
     w = cfg0
     print(f"case config0 alpha={alpha}", flush=True)
     plan = _plan(w, alpha)
@@ -95,7 +95,8 @@ def test_config0_alphas(cfg0, alpha):
     S, D, V = _run(plan, w)
     So, Do, Vo = oracle_eval(w, alpha, info["delta"], 3)
     errs = [rel_err(S, So), rel_err(D, Do), rel_err(V, Vo)]
-    print(f"alpha {alpha} kmax {info['kmax']:.1f} n {info['n_fine']} errs {errs}", flush=True)
+    print(f"alpha {alpha} kmax {info['kmax']:.1f} n {info['n_fine']} trunc {info['history_truncated']} "
+          f"errs {errs}", flush=True)
     assert max(errs) < TOL
 
 
@@ -160,14 +161,17 @@ def test_edge_cases(cfg0):
     assert rel_err(S.cpu().numpy(), So) < TOL
 
 
-def test_multibody_sampled():
+@pytest.mark.parametrize("alpha,trunc", [(1.0, 1), (30.0, 0)])
+def test_multibody_sampled(alpha, trunc):
     """Small multi-body workload (3 bodies, 2048 boundary nodes, ~40k volume
-    nodes, 6000 targets), alpha = 10, oracle on a stratified target sample."""
+    nodes, 6000 targets) with the fine split delta = 2e-5 of the bench
+    workload, oracle on a stratified target sample.  At alpha = 1 the history
+    uses the smoothly truncated kernel, at alpha = 30 the periodic one."""
     w = small_multibody()
-    alpha = 10.0
-    print(f"case multibody nb={w.n_b} nv={w.n_v} nt={w.n_t}", flush=True)
-    plan = _plan(w, alpha)
+    print(f"case multibody alpha={alpha} nb={w.n_b} nv={w.n_v} nt={w.n_t}", flush=True)
+    plan = _plan(w, alpha, delta=2e-5)
     info = plan.info()
+    assert info["history_truncated"] == trunc
     S, D, V = _run(plan, w)
     sub = stratified_subset(w, info["band_volume"])
     So, Do, Vo = oracle_eval(w, alpha, info["delta"], 3, subset=sub)
