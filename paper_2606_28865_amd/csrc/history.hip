@@ -23,6 +23,8 @@
 
 namespace mhk {
 
+
+template <typename T>
 struct SpreadArgs {
     int64_t n, field, nb, nv;
     int ntile, B;
@@ -31,31 +33,35 @@ struct SpreadArgs {
     const int32_t *bidx, *btile;
     const double *vgx, *vgy, *vw;
     const int32_t *vidx, *vtile;
-    const double *sigma, *mu, *f_vol;
-    double *grid;          // [4][B][field]: S, V, Dx, Dy sources
+    const T *sigma, *mu, *f_vol;
+    T *grid;               // [4][B][field]: S, V, Dx, Dy sources
 };
 
-template <int W>
-__device__ inline void window_weights(double g, double beta, int &m0, double *wt)
+// Window values phi(z_k), z_k = (m0 + k - g) 2/W, at the W grid points from
+// m0 = ceil(g - W/2).  The offset m0 - g is formed in FP64; in the FP32 path
+// the window itself is evaluated in FP32.
+template <int W, typename T>
+__device__ inline void window_weights(double g, double beta, int &m0, T *wt)
 {
     m0 = (int)ceil(g - 0.5 * W);
-    const double sc = 2.0 / W;
+    const T off = (T)((double)m0 - g);
+    const T sc = (T)2 / (T)W, bt = (T)beta;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const double z = (m0 + k - g) * sc;
-        const double z2 = 1.0 - z * z;
-        wt[k] = (z2 > 0.0) ? exp(beta * (sqrt(z2) - 1.0)) : 0.0;
+        const T z = (off + (T)k) * sc;
+        const T z2 = (T)1 - z * z;
+        wt[k] = (z2 > (T)0) ? exp(bt * (sqrt(z2) - (T)1)) : (T)0;
     }
 }
 
-template <int W>
-__global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
+template <int W, typename T>
+__global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
 {
-    __shared__ double tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
+    __shared__ T tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
     const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const int tx = tile % A.ntile, ty = tile / A.ntile;
     const int x0 = tx * TILE, y0 = ty * TILE;
-    for (int i = tid; i < TILE * TILE; i += 256) tileS[i] = tileV[i] = tileX[i] = tileY[i] = 0.0;
+    for (int i = tid; i < TILE * TILE; i += 256) tileS[i] = tileV[i] = tileX[i] = tileY[i] = (T)0;
     __syncthreads();
     const bool has_b = A.sigma || A.mu;
     for (int dty = -1; dty <= 1; ++dty) {
@@ -67,16 +73,16 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
             for (int s = s0 + tid; s < s1; s += 256) {
                 const double gx = A.bgx[s], gy = A.bgy[s];
                 int mx0, my0;
-                double wx[W], wy[W];
-                window_weights<W>(gx, A.beta, mx0, wx);
-                window_weights<W>(gy, A.beta, my0, wy);
+                T wx[W], wy[W];
+                window_weights<W, T>(gx, A.beta, mx0, wx);
+                window_weights<W, T>(gy, A.beta, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
                 if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
                 const int i = A.bidx[s];
-                const double qs = A.sigma ? A.bw[s] * A.sigma[(size_t)b * A.nb + i] : 0.0;
-                const double m = A.mu ? A.mu[(size_t)b * A.nb + i] : 0.0;
-                const double qx = A.bwx[s] * m, qy = A.bwy[s] * m;
+                const T qs = A.sigma ? (T)(A.bw[s] * (double)A.sigma[(size_t)b * A.nb + i]) : (T)0;
+                const double m = A.mu ? (double)A.mu[(size_t)b * A.nb + i] : 0.0;
+                const T qx = (T)(A.bwx[s] * m), qy = (T)(A.bwy[s] * m);
 #pragma unroll
                 for (int ky = 0; ky < W; ++ky) {
                     const int my = my0 + ky;
@@ -85,7 +91,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
                     for (int kx = 0; kx < W; ++kx) {
                         const int mx = mx0 + kx;
                         if (mx < 0 || mx >= TILE) continue;
-                        const double v = wx[kx] * wy[ky];
+                        const T v = wx[kx] * wy[ky];
                         const int o = my * TILE + mx;
                         if (A.sigma) atomicAdd(&tileS[o], qs * v);
                         if (A.mu) {
@@ -101,18 +107,18 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
             for (int s = s0 + tid; s < s1; s += 256) {
                 const double gx = A.vgx[s], gy = A.vgy[s];
                 int mx0, my0;
-                double wx[W], wy[W];
-                window_weights<W>(gx, A.beta, mx0, wx);
-                window_weights<W>(gy, A.beta, my0, wy);
+                T wx[W], wy[W];
+                window_weights<W, T>(gx, A.beta, mx0, wx);
+                window_weights<W, T>(gy, A.beta, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
                 if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
-                const double q = A.vw[s] * A.f_vol[(size_t)b * A.nv + A.vidx[s]];
+                const T q = (T)(A.vw[s] * (double)A.f_vol[(size_t)b * A.nv + A.vidx[s]]);
 #pragma unroll
                 for (int ky = 0; ky < W; ++ky) {
                     const int my = my0 + ky;
                     if (my < 0 || my >= TILE) continue;
-                    const double qy = q * wy[ky];
+                    const T qy = q * wy[ky];
 #pragma unroll
                     for (int kx = 0; kx < W; ++kx) {
                         const int mx = mx0 + kx;
@@ -125,7 +131,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
     }
     __syncthreads();
     const size_t fs = (size_t)A.B * A.field;
-    double *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
+    T *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
     for (int i = tid; i < TILE * TILE; i += 256) {
         const size_t o = (size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE);
         gS[o] = tileS[i];
@@ -135,8 +141,11 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs A)
     }
 }
 
-// Fourier multiplier on the half spectrum [n][n/2+1] of each field.
-__global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t field, double *grid,
+// Fourier multiplier on the half spectrum [n][n/2+1] of each field; the
+// multiplier is formed in FP64 in both precision paths (it peaks at 1/alpha^2
+// near k = 0).
+template <typename T>
+__global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t field, T *grid,
                                                   const double *__restrict__ fac, double c, double alpha2,
                                                   double dk, const double *__restrict__ mtab, int lmax)
 {
@@ -149,8 +158,9 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
     const int64_t fy = ly <= n / 2 ? ly : ly - n;
     const double ax = fac[lx], ay = fac[fy < 0 ? -fy : fy];
     const size_t fs = (size_t)B * field / 2;                  // complex values per field group
-    double2 *F = reinterpret_cast<double2 *>(grid) + (size_t)b * (field / 2) + ly * nh + lx;
-    double2 zS = {0, 0}, zV = {0, 0}, zD = {0, 0};
+    typedef typename Vec2<T>::type T2;
+    T2 *F = reinterpret_cast<T2 *>(grid) + (size_t)b * (field / 2) + ly * nh + lx;
+    T2 zS = {0, 0}, zV = {0, 0}, zD = {0, 0};
     double M = 0.0;
     if (mtab) {
         if (lx <= lmax && fy >= -lmax && fy <= lmax) M = mtab[(fy + lmax) * (lmax + 1) + lx];
@@ -160,63 +170,64 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
     }
     if (M != 0.0) {
         const double kx = dk * lx, ky = dk * fy;
-        const double2 s = F[0], v = F[fs], gx = F[2 * fs], gy = F[3 * fs];
-        zS = make_double2(M * s.x, M * s.y);
-        zV = make_double2(M * v.x, M * v.y);
+        const T2 s = F[0], v = F[fs], gx = F[2 * fs], gy = F[3 * fs];
+        zS.x = (T)(M * s.x); zS.y = (T)(M * s.y);
+        zV.x = (T)(M * v.x); zV.y = (T)(M * v.y);
         // -i (kx Gx + ky Gy)
         const double re = kx * gx.x + ky * gy.x, im = kx * gx.y + ky * gy.y;
-        zD = make_double2(M * im, -M * re);
+        zD.x = (T)(M * im); zD.y = (T)(-M * re);
     }
     F[0] = zS;
     F[fs] = zV;
     F[2 * fs] = zD;
 }
 
+template <typename T>
 struct InterpArgs {
     int64_t n, field, nout;
     int ntile, B;
     double beta, ox, oy, h;
     const int32_t *tile_xy, *tile_rng;
     const double *tx, *ty;
-    const double *grid;    // [3][B][field]: S, V, D results
-    double *acc;           // [3][B][nout]: S, D, V
+    const T *grid;         // [3][B][field]: S, V, D results
+    T *acc;                // [3][B][nout]: S, D, V
     int want_s, want_d, want_v;
 };
 
-template <int W>
-__global__ void __launch_bounds__(256) k_interp(InterpArgs A)
+template <int W, typename T>
+__global__ void __launch_bounds__(256) k_interp(InterpArgs<T> A)
 {
     constexpr int RS = TILE + W + 2;
-    __shared__ double reg[3][RS * RS];
+    __shared__ T reg[3][RS * RS];
     const int t = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const int tile = A.tile_xy[t];
     const int tx = tile % A.ntile, ty = tile / A.ntile;
     const int rx0 = tx * TILE - W / 2 - 1, ry0 = ty * TILE - W / 2 - 1;
     const size_t fs = (size_t)A.B * A.field;
-    const double *g0 = A.grid + (size_t)b * A.field;
+    const T *g0 = A.grid + (size_t)b * A.field;
     for (int i = tid; i < RS * RS; i += 256) {
         int gy = ry0 + i / RS, gx = rx0 + i % RS;
         gy = (int)(((int64_t)gy % A.n + A.n) % A.n);
         gx = (int)(((int64_t)gx % A.n + A.n) % A.n);
         const size_t o = (size_t)gy * (A.n + 2) + gx;
-        reg[0][i] = A.want_s ? g0[o] : 0.0;
-        reg[1][i] = A.want_v ? g0[fs + o] : 0.0;
-        reg[2][i] = A.want_d ? g0[2 * fs + o] : 0.0;
+        reg[0][i] = A.want_s ? g0[o] : (T)0;
+        reg[1][i] = A.want_v ? g0[fs + o] : (T)0;
+        reg[2][i] = A.want_d ? g0[2 * fs + o] : (T)0;
     }
     __syncthreads();
     const int s0 = A.tile_rng[t], s1 = A.tile_rng[t + 1];
     for (int s = s0 + tid; s < s1; s += 256) {
         const double gx = (A.tx[s] - A.ox) / A.h, gy = (A.ty[s] - A.oy) / A.h;
         int mx0, my0;
-        double wx[W], wy[W];
-        window_weights<W>(gx, A.beta, mx0, wx);
-        window_weights<W>(gy, A.beta, my0, wy);
+        T wx[W], wy[W];
+        window_weights<W, T>(gx, A.beta, mx0, wx);
+        window_weights<W, T>(gy, A.beta, my0, wy);
         const int lx = min(max(mx0 - rx0, 0), RS - W), ly = min(max(my0 - ry0, 0), RS - W);
-        double uS = 0, uV = 0, uD = 0;
+        T uS = 0, uV = 0, uD = 0;
 #pragma unroll 1
         for (int ky = 0; ky < W; ++ky) {
             const int o = (ly + ky) * RS + lx;
-            double rS = 0, rV = 0, rD = 0;
+            T rS = 0, rV = 0, rD = 0;
 #pragma unroll
             for (int kx = 0; kx < W; ++kx) {
                 rS = fma(wx[kx], reg[0][o + kx], rS);
@@ -316,45 +327,46 @@ hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const do
     return hipGetLastError();
 }
 
-template <int W>
-static hipError_t spread_w(mhk_plan *P, const SpreadArgs &A)
+template <int W, typename T>
+static hipError_t spread_w(mhk_plan *P, const SpreadArgs<T> &A)
 {
     dim3 grid((unsigned)(A.ntile * A.ntile), (unsigned)A.B);
-    hipLaunchKernelGGL(k_spread<W>, grid, dim3(256), 0, P->stream, A);
+    hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(256), 0, P->stream, A);
     return hipGetLastError();
 }
 
-template <int W>
-static hipError_t interp_w(mhk_plan *P, const InterpArgs &A)
+template <int W, typename T>
+static hipError_t interp_w(mhk_plan *P, const InterpArgs<T> &A)
 {
     if (P->hist.n_ttiles == 0) return hipSuccess;
     dim3 grid((unsigned)P->hist.n_ttiles, (unsigned)A.B);
-    hipLaunchKernelGGL(k_interp<W>, grid, dim3(256), 0, P->stream, A);
+    hipLaunchKernelGGL((k_interp<W, T>), grid, dim3(256), 0, P->stream, A);
     return hipGetLastError();
 }
 
-#define MHK_W_SWITCH(w, F, ...)              \
-    switch (w) {                             \
-    case 4: return F<4>(__VA_ARGS__);        \
-    case 5: return F<5>(__VA_ARGS__);        \
-    case 6: return F<6>(__VA_ARGS__);        \
-    case 7: return F<7>(__VA_ARGS__);        \
-    case 8: return F<8>(__VA_ARGS__);        \
-    case 9: return F<9>(__VA_ARGS__);        \
-    case 10: return F<10>(__VA_ARGS__);      \
-    case 11: return F<11>(__VA_ARGS__);      \
-    case 12: return F<12>(__VA_ARGS__);      \
-    case 13: return F<13>(__VA_ARGS__);      \
-    case 14: return F<14>(__VA_ARGS__);      \
-    case 15: return F<15>(__VA_ARGS__);      \
-    case 16: return F<16>(__VA_ARGS__);      \
-    default: return hipErrorInvalidValue;    \
+#define MHK_W_SWITCH(w, F, T, ...)              \
+    switch (w) {                                \
+    case 4: return F<4, T>(__VA_ARGS__);        \
+    case 5: return F<5, T>(__VA_ARGS__);        \
+    case 6: return F<6, T>(__VA_ARGS__);        \
+    case 7: return F<7, T>(__VA_ARGS__);        \
+    case 8: return F<8, T>(__VA_ARGS__);        \
+    case 9: return F<9, T>(__VA_ARGS__);        \
+    case 10: return F<10, T>(__VA_ARGS__);      \
+    case 11: return F<11, T>(__VA_ARGS__);      \
+    case 12: return F<12, T>(__VA_ARGS__);      \
+    case 13: return F<13, T>(__VA_ARGS__);      \
+    case 14: return F<14, T>(__VA_ARGS__);      \
+    case 15: return F<15, T>(__VA_ARGS__);      \
+    case 16: return F<16, T>(__VA_ARGS__);      \
+    default: return hipErrorInvalidValue;       \
     }
 
-hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, const double *f_vol)
+template <typename T>
+static hipError_t spread_t(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol)
 {
     const History &G = P->hist;
-    SpreadArgs A;
+    SpreadArgs<T> A;
     A.n = G.n;
     A.field = G.field;
     A.nb = P->nb;
@@ -365,27 +377,39 @@ hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, con
     A.bgx = G.bgx; A.bgy = G.bgy; A.bw = G.bw; A.bwx = G.bwx; A.bwy = G.bwy;
     A.bidx = G.bidx; A.btile = G.btile;
     A.vgx = G.vgx; A.vgy = G.vgy; A.vw = G.vw; A.vidx = G.vidx; A.vtile = G.vtile;
-    A.sigma = sigma;
-    A.mu = mu;
-    A.f_vol = f_vol;
-    A.grid = G.grid;
-    MHK_W_SWITCH(G.w, spread_w, P, A);
+    A.sigma = (const T *)sigma;
+    A.mu = (const T *)mu;
+    A.f_vol = (const T *)f_vol;
+    A.grid = (T *)G.grid;
+    MHK_W_SWITCH(G.w, spread_w, T, P, A);
+}
+
+hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol)
+{
+    return P->p.prec == MHK_FP64 ? spread_t<double>(P, sigma, mu, f_vol) : spread_t<float>(P, sigma, mu, f_vol);
+}
+
+template <typename T>
+static hipError_t multiply_t(mhk_plan *P)
+{
+    const History &G = P->hist;
+    const int64_t tot = G.n * (G.n / 2 + 1) * P->p.batch;
+    hipLaunchKernelGGL(k_multiply<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, G.n,
+                       P->p.batch, G.field, (T *)G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha,
+                       2.0 * M_PI / G.period, G.trunc ? G.mtab : nullptr, G.lmax);
+    return hipGetLastError();
 }
 
 hipError_t launch_multiply(mhk_plan *P)
 {
-    const History &G = P->hist;
-    const int64_t tot = G.n * (G.n / 2 + 1) * P->p.batch;
-    hipLaunchKernelGGL(k_multiply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, G.n, P->p.batch,
-                       G.field, G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha, 2.0 * M_PI / G.period,
-                       G.trunc ? G.mtab : nullptr, G.lmax);
-    return hipGetLastError();
+    return P->p.prec == MHK_FP64 ? multiply_t<double>(P) : multiply_t<float>(P);
 }
 
-hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v)
+template <typename T>
+static hipError_t interp_t(mhk_plan *P, bool want_s, bool want_d, bool want_v)
 {
     const History &G = P->hist;
-    InterpArgs A;
+    InterpArgs<T> A;
     A.n = G.n;
     A.field = G.field;
     A.nout = P->nout;
@@ -399,12 +423,18 @@ hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v)
     A.tile_rng = G.ttile_rng;
     A.tx = P->tx;
     A.ty = P->ty;
-    A.grid = G.grid;
-    A.acc = P->acc;
+    A.grid = (const T *)G.grid;
+    A.acc = (T *)P->acc;
     A.want_s = want_s;
     A.want_d = want_d;
     A.want_v = want_v;
-    MHK_W_SWITCH(G.w, interp_w, P, A);
+    MHK_W_SWITCH(G.w, interp_w, T, P, A);
+}
+
+hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v)
+{
+    return P->p.prec == MHK_FP64 ? interp_t<double>(P, want_s, want_d, want_v)
+                                 : interp_t<float>(P, want_s, want_d, want_v);
 }
 
 }  // namespace mhk

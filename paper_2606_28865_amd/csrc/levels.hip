@@ -8,11 +8,20 @@
 // pairs with a >= a_max are below the requested accuracy and skipped.
 //
 // Work decomposition: a workgroup owns 256 consecutive targets of the Morton
-// order, takes the bounding box of their cells (cells of side R_j) and walks
-// the sources of the 3x3-extended box row by row.  Sources are staged through
-// LDS in blocks of 256 and read back by broadcast, so every source is loaded
-// from HBM once per workgroup, and each lane keeps its target's sums in
-// registers: no atomics, deterministic summation order.
+// order.  At plan time the union of its targets' cell neighbourhoods (cells
+// of side R_j/2, +-2 cells) is turned into a short list of ranges of the
+// cell-sorted sources.  Sources are staged through LDS in blocks of 256 and
+// read back by broadcast, so every candidate source is loaded once per
+// workgroup, and each lane keeps its target's sums in registers: no atomics,
+// deterministic summation order.  The kernel table sits in LDS with a padded
+// segment stride so that the per-lane gathers of different segments spread
+// over the LDS banks.
+//
+// Precision: T = double (FP64 path) or float (FP32 path).  In the FP32 path
+// the separation x - x_q is formed in FP64 from FP64 positions and rounded
+// once, so that its relative error is that of one rounding even when the
+// separation is far smaller than the coordinates; the table (degree 7), the
+// kernel evaluation and the accumulation are FP32.
 #include "mhk_internal.h"
 
 namespace mhk {
@@ -20,15 +29,16 @@ namespace mhk {
 // Child-node strengths of level j for the current densities: q_S = w sigma,
 // q_Dx = w nu_x mu, q_Dy = w nu_y mu, with sigma, mu at the child node
 // interpolated from the parent panel's 16 nodal values.
+template <typename T>
 __global__ void __launch_bounds__(256) k_level_q(int64_t n_src, int nch, int B, int64_t nb,
                                                  const int32_t *__restrict__ code,
-                                                 const double *__restrict__ T,
+                                                 const double *__restrict__ Tm,
                                                  const double *__restrict__ sw,
                                                  const double *__restrict__ swx,
                                                  const double *__restrict__ swy,
-                                                 const double *__restrict__ sigma,
-                                                 const double *__restrict__ mu,
-                                                 double *__restrict__ q)
+                                                 const T *__restrict__ sigma,
+                                                 const T *__restrict__ mu,
+                                                 T *__restrict__ q)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_src) return;
@@ -37,57 +47,56 @@ __global__ void __launch_bounds__(256) k_level_q(int64_t n_src, int nch, int B, 
     int pc = c / NGL;
     int child = pc % nch;
     int64_t panel = pc / nch;
-    const double *row = T + ((size_t)child * NGL + k) * NGL;
+    const double *row = Tm + ((size_t)child * NGL + k) * NGL;
     double r[NGL];
 #pragma unroll
     for (int i = 0; i < NGL; ++i) r[i] = row[i];
     const double w = sw[s], wx = swx[s], wy = swy[s];
     for (int b = 0; b < B; ++b) {
         if (sigma) {
-            const double *f = sigma + (size_t)b * nb + panel * NGL;
+            const T *f = sigma + (size_t)b * nb + panel * NGL;
             double v = 0;
 #pragma unroll
-            for (int i = 0; i < NGL; ++i) v = fma(r[i], f[i], v);
-            q[((size_t)0 * B + b) * n_src + s] = w * v;
+            for (int i = 0; i < NGL; ++i) v = fma(r[i], (double)f[i], v);
+            q[((size_t)0 * B + b) * n_src + s] = (T)(w * v);
         }
         if (mu) {
-            const double *f = mu + (size_t)b * nb + panel * NGL;
+            const T *f = mu + (size_t)b * nb + panel * NGL;
             double v = 0;
 #pragma unroll
-            for (int i = 0; i < NGL; ++i) v = fma(r[i], f[i], v);
-            q[((size_t)1 * B + b) * n_src + s] = wx * v;
-            q[((size_t)2 * B + b) * n_src + s] = wy * v;
+            for (int i = 0; i < NGL; ++i) v = fma(r[i], (double)f[i], v);
+            q[((size_t)1 * B + b) * n_src + s] = (T)(wx * v);
+            q[((size_t)2 * B + b) * n_src + s] = (T)(wy * v);
         }
     }
 }
 
+template <typename T>
 struct LevelArgs {
     int64_t nout, n_src;
     const double *tx, *ty;
-    double ox, oy, cell, inv4d, a_max, seg_inv;
-    int ncx, ncy, nseg, B, b0, nbh;
-    const int32_t *cell_start;
-    const double *sx, *sy, *q, *tab;
-    double *acc_s, *acc_d;     // [B][nout] each (sorted order)
+    double inv4d, a_max, seg_inv;
+    int nseg, B, b0, nbh;
+    const int32_t *blk_ofs, *blk_rng;
+    const double *sx, *sy;
+    const T *q, *tab;
+    T *acc_s, *acc_d;     // [B][nout] each (sorted order)
     int want_s, want_d;
 };
 
-template <int BCH>
-__global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs A)
+
+template <int BCH, typename T, int NC, int STRIDE>
+__global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
+    typedef typename Vec2<T>::type T2;
     extern __shared__ double lds[];
-    double *s_tab = lds;                                  // [nseg][TAB_NC][2]
-    double *s_x = lds + (size_t)A.nseg * TAB_NC * 2;      // [LV_BLOCK]
+    double *s_x = lds;                                    // [LV_BLOCK]
     double *s_y = s_x + LV_BLOCK;
-    double *s_q = s_y + LV_BLOCK;                         // [3*BCH][LV_BLOCK]
-    __shared__ int bbox[4];
+    T *s_q = reinterpret_cast<T *>(s_y + LV_BLOCK);       // [3*BCH][LV_BLOCK]
+    T *s_tab = s_q + 3 * BCH * LV_BLOCK;                  // [nseg][STRIDE][2]
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < A.nseg * TAB_NC * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
-    if (tid == 0) {
-        bbox[0] = 0x7fffffff; bbox[1] = -1; bbox[2] = 0x7fffffff; bbox[3] = -1;
-    }
-    __syncthreads();
+    for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
 
     const int64_t t = (int64_t)blockIdx.x * LV_BLOCK + tid;
     const bool active = t < A.nout;
@@ -95,26 +104,15 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs A)
     if (active) {
         x = A.tx[t];
         y = A.ty[t];
-        int cx = (int)floor((x - A.ox) / A.cell);
-        int cy = (int)floor((y - A.oy) / A.cell);
-        cx = min(max(cx, 0), A.ncx - 1);
-        cy = min(max(cy, 0), A.ncy - 1);
-        atomicMin(&bbox[0], cx);
-        atomicMax(&bbox[1], cx);
-        atomicMin(&bbox[2], cy);
-        atomicMax(&bbox[3], cy);
     }
-    __syncthreads();
-    const int x0 = max(bbox[0] - 1, 0), x1 = min(bbox[1] + 1, A.ncx - 1);
-    const int y0 = max(bbox[2] - 1, 0), y1 = min(bbox[3] + 1, A.ncy - 1);
-
-    double S[BCH], D[BCH];
+    const T inv4d = (T)A.inv4d, a_max = (T)A.a_max, seg_inv = (T)A.seg_inv;
+    T S[BCH], D[BCH];
 #pragma unroll
-    for (int b = 0; b < BCH; ++b) S[b] = D[b] = 0.0;
+    for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
 
-    for (int cy = y0; cy <= y1; ++cy) {
-        const int s0 = A.cell_start[(int64_t)cy * A.ncx + x0];
-        const int s1 = A.cell_start[(int64_t)cy * A.ncx + x1 + 1];
+    const int r0 = A.blk_ofs[blockIdx.x], r1 = A.blk_ofs[blockIdx.x + 1];
+    for (int r = r0; r < r1; ++r) {
+        const int s0 = A.blk_rng[2 * r], s1 = A.blk_rng[2 * r + 1];
         for (int c0 = s0; c0 < s1; c0 += LV_BLOCK) {
             const int m = min(LV_BLOCK, s1 - c0);
             __syncthreads();
@@ -126,26 +124,26 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs A)
                 for (int b = 0; b < BCH; ++b) {
                     if (b < A.nbh) {
                         const int bb = A.b0 + b;
-                        s_q[(0 * BCH + b) * LV_BLOCK + tid] = A.want_s ? A.q[((size_t)0 * A.B + bb) * A.n_src + s] : 0.0;
-                        s_q[(1 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)1 * A.B + bb) * A.n_src + s] : 0.0;
-                        s_q[(2 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)2 * A.B + bb) * A.n_src + s] : 0.0;
+                        s_q[(0 * BCH + b) * LV_BLOCK + tid] = A.want_s ? A.q[((size_t)0 * A.B + bb) * A.n_src + s] : (T)0;
+                        s_q[(1 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)1 * A.B + bb) * A.n_src + s] : (T)0;
+                        s_q[(2 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)2 * A.B + bb) * A.n_src + s] : (T)0;
                     }
                 }
             }
             __syncthreads();
             if (active) {
                 for (int i = 0; i < m; ++i) {
-                    const double dx = x - s_x[i], dy = y - s_y[i];
-                    const double a = (dx * dx + dy * dy) * A.inv4d;
-                    if (a < A.a_max) {
-                        const double f = a * A.seg_inv;
+                    const T dx = (T)(x - s_x[i]), dy = (T)(y - s_y[i]);
+                    const T a = (dx * dx + dy * dy) * inv4d;
+                    if (a < a_max) {
+                        const T f = a * seg_inv;
                         const int sg = (int)f;
-                        const double v = 2.0 * (f - sg) - 1.0;
-                        const double2 *c = reinterpret_cast<const double2 *>(s_tab) + sg * TAB_NC;
-                        double2 cc = c[TAB_NC - 1];
-                        double ks = cc.x, kd = cc.y;
+                        const T v = (T)2 * (f - (T)sg) - (T)1;
+                        const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
+                        T2 cc = c[NC - 1];
+                        T ks = cc.x, kd = cc.y;
 #pragma unroll
-                        for (int k = TAB_NC - 2; k >= 0; --k) {
+                        for (int k = NC - 2; k >= 0; --k) {
                             cc = c[k];
                             ks = fma(ks, v, cc.x);
                             kd = fma(kd, v, cc.y);
@@ -153,8 +151,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs A)
 #pragma unroll
                         for (int b = 0; b < BCH; ++b) {
                             S[b] = fma(s_q[(0 * BCH + b) * LV_BLOCK + i], ks, S[b]);
-                            const double nd = fma(s_q[(1 * BCH + b) * LV_BLOCK + i], dx,
-                                                  s_q[(2 * BCH + b) * LV_BLOCK + i] * dy);
+                            const T nd = fma(s_q[(1 * BCH + b) * LV_BLOCK + i], dx,
+                                             s_q[(2 * BCH + b) * LV_BLOCK + i] * dy);
                             D[b] = fma(nd, kd, D[b]);
                         }
                     }
@@ -174,57 +172,68 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs A)
     }
 }
 
-hipError_t launch_level_densities(mhk_plan *P, int j, const double *sigma, const double *mu)
+template <typename T>
+static hipError_t level_q(mhk_plan *P, int j, const void *sigma, const void *mu)
 {
     Level &L = P->lev[j - 1];
     const int64_t n = L.n_src;
     dim3 grid((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(k_level_q, grid, dim3(256), 0, P->stream, n, L.nchild, P->p.batch, P->nb, L.code,
-                       L.interp, L.sw, L.swx, L.swy, sigma, mu, L.q);
+    hipLaunchKernelGGL(k_level_q<T>, grid, dim3(256), 0, P->stream, n, L.nchild, P->p.batch, P->nb, L.code,
+                       L.interp, L.sw, L.swx, L.swy, (const T *)sigma, (const T *)mu, (T *)L.q);
     return hipGetLastError();
 }
 
-hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
+hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu)
+{
+    return P->p.prec == MHK_FP64 ? level_q<double>(P, j, sigma, mu) : level_q<float>(P, j, sigma, mu);
+}
+
+template <typename T, int NC, int STRIDE>
+static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
 {
     Level &L = P->lev[j - 1];
     const int B = P->p.batch;
-    LevelArgs A;
+    LevelArgs<T> A;
     A.nout = P->nout;
     A.n_src = L.n_src;
     A.tx = P->tx;
     A.ty = P->ty;
-    A.ox = L.ox;
-    A.oy = L.oy;
-    A.cell = L.cell;
     A.inv4d = L.inv4d;
     A.a_max = L.a_max;
     A.seg_inv = L.seg_inv;
-    A.ncx = L.ncx;
-    A.ncy = L.ncy;
     A.nseg = L.nseg;
     A.B = B;
-    A.cell_start = L.cell_start;
+    A.blk_ofs = L.blk_ofs;
+    A.blk_rng = L.blk_rng;
     A.sx = L.sx;
     A.sy = L.sy;
-    A.q = L.q;
-    A.tab = L.tab;
-    A.acc_s = P->acc;                                  // component 0: S
-    A.acc_d = P->acc + (size_t)B * P->nout;            // component 1: D
+    A.q = (const T *)L.q;
+    A.tab = (const T *)L.tab_dev;
+    A.acc_s = (T *)P->acc;                                  // component 0: S
+    A.acc_d = (T *)P->acc + (size_t)B * P->nout;            // component 1: D
     A.want_s = want_s;
     A.want_d = want_d;
-    const size_t lds = sizeof(double) * ((size_t)L.nseg * TAB_NC * 2 + (2 + 3 * LV_BCH) * LV_BLOCK);
     dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK));
     for (int b0 = 0; b0 < B; b0 += LV_BCH) {
         A.b0 = b0;
         A.nbh = min(LV_BCH, B - b0);
-        if (A.nbh == 1)
-            hipLaunchKernelGGL(k_level_sums<1>, grid, dim3(LV_BLOCK), lds, P->stream, A);
+        const int bch = A.nbh == 1 ? 1 : LV_BCH;
+        const size_t lds = sizeof(double) * 2 * LV_BLOCK + sizeof(T) * (3 * (size_t)bch * LV_BLOCK +
+                                                                       (size_t)L.nseg * STRIDE * 2);
+        if (bch == 1)
+            hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
         else
-            hipLaunchKernelGGL(k_level_sums<LV_BCH>, grid, dim3(LV_BLOCK), lds, P->stream, A);
+            hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
+{
+    if (P->p.prec == MHK_FP64) return level_sums<double, TAB_NC, TAB_STRIDE>(P, j, want_s, want_d);
+    return level_sums<float, TABF_NC, TABF_STRIDE>(P, j, want_s, want_d);
 }
 
 }  // namespace mhk

@@ -1,6 +1,6 @@
 // Local asymptotic part (Section 4.1) and the closest boundary point
-// (Section 3.2), in FP64, plus the final scatter of the accumulated
-// potentials to the caller's target order.
+// (Section 3.2), in FP64 in both precision paths, plus the final scatter of
+// the accumulated potentials to the caller's target order.
 //
 // For an off-surface target x the nearest boundary node is found in a cell
 // list (cells larger than the widest band plus the largest node gap, so the
@@ -15,10 +15,11 @@
 
 namespace mhk {
 
-// Legendre coefficients of sigma and mu on every panel: c = Leg * f.
+// Legendre coefficients of sigma and mu on every panel: c = Leg * f (FP64).
+template <typename T>
 __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const double *__restrict__ leg,
-                                                      const double *__restrict__ sigma,
-                                                      const double *__restrict__ mu,
+                                                      const T *__restrict__ sigma,
+                                                      const T *__restrict__ mu,
                                                       double *__restrict__ cs, double *__restrict__ cm)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -28,17 +29,17 @@ __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const
     int64_t pb = id / NGL;                 // b * npan + p
     const double *row = leg + k * NGL;
     if (sigma) {
-        const double *f = sigma + pb * NGL;
+        const T *f = sigma + pb * NGL;
         double v = 0;
 #pragma unroll
-        for (int i = 0; i < NGL; ++i) v = fma(row[i], f[i], v);
+        for (int i = 0; i < NGL; ++i) v = fma(row[i], (double)f[i], v);
         cs[id] = v;
     }
     if (mu) {
-        const double *f = mu + pb * NGL;
+        const T *f = mu + pb * NGL;
         double v = 0;
 #pragma unroll
-        for (int i = 0; i < NGL; ++i) v = fma(row[i], f[i], v);
+        for (int i = 0; i < NGL; ++i) v = fma(row[i], (double)f[i], v);
         cm[id] = v;
     }
 }
@@ -82,6 +83,7 @@ __device__ inline double leg1(const double *__restrict__ c, double t)
     return v;
 }
 
+template <typename T>
 struct LocalArgs {
     int64_t nout, nt, nb, npan;
     int B;
@@ -90,19 +92,20 @@ struct LocalArgs {
     const int8_t *tin;
     const int32_t *tidx;
     const double *bx, *by, *bk;
-    const double *sigma, *mu, *f_trg;
+    const T *sigma, *mu, *f_trg;
     const double *cs, *cm;
     const double *pcx, *pcy, *pck, *ends, *gl_t;
     const int32_t *prev, *next, *node, *cell_start;
     double cell, ox, oy;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
-    const double *acc;     // [3][B][nout]: S, D, V in sorted order
-    double *out_s, *out_d, *out_v;
+    const T *acc;          // [3][B][nout]: S, D, V in sorted order
+    T *out_s, *out_d, *out_v;
 };
 
 // Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p.
-__device__ inline void panel_min(const LocalArgs &A, int p, double px, double py, double &tbest, double &d2best)
+template <typename T>
+__device__ inline void panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
 {
     const double *cx = A.pcx + (size_t)p * NGL, *cy = A.pcy + (size_t)p * NGL;
     // start: best of the 16 nodes and the two end points
@@ -137,7 +140,8 @@ __device__ inline void panel_min(const LocalArgs &A, int p, double px, double py
     else { tbest = ts; d2best = ds; }
 }
 
-__global__ void __launch_bounds__(256) k_local(LocalArgs A)
+template <typename T>
+__global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nout) return;
@@ -229,24 +233,24 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs A)
         const size_t ob = (size_t)b * A.nout + idx;
         const size_t ab = (size_t)b * A.nout + s;
         if (ws) {
-            double v = A.acc[(size_t)0 * A.B * A.nout + ab];
+            double v = (double)A.acc[(size_t)0 * A.B * A.nout + ab];
             if (do_local) {
                 if (on) {
                     const int64_t i = idx - A.nt;
-                    v += sq * A.sigma[(size_t)b * A.nb + i] * erf(c2) / (2.0 * c2);        // Cor. 4.4
+                    v += sq * (double)A.sigma[(size_t)b * A.nb + i] * erf(c2) / (2.0 * c2);        // Cor. 4.4
                 } else if (near_s) {
                     const double sg = leg1(A.cs + ((size_t)b * A.npan + pbest) * NGL, tbest);
                     v += sq * sg * P0 * 0.25 + A.dstar * rho * kap * sg * P1 * 0.125;     // Lemma 4.1
                 }
             }
-            A.out_s[ob] = v;
+            A.out_s[ob] = (T)v;
         }
         if (wd) {
-            double v = A.acc[(size_t)1 * A.B * A.nout + ab];
+            double v = (double)A.acc[(size_t)1 * A.B * A.nout + ab];
             if (do_local) {
                 if (on) {
                     const int64_t i = idx - A.nt;
-                    v -= sq * A.bk[i] * A.mu[(size_t)b * A.nb + i] * erf(c2) / (4.0 * c2);  // Cor. 4.7
+                    v -= sq * A.bk[i] * (double)A.mu[(size_t)b * A.nb + i] * erf(c2) / (4.0 * c2);  // Cor. 4.7
                 } else if (near_s) {
                     const double *cm = A.cm + ((size_t)b * A.npan + pbest) * NGL;
                     double m0, m1, m2, z0, z1, z2;
@@ -256,41 +260,49 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs A)
                          - A.dstar * (rho * mss * P1 * 0.125 + 3.0 * rho * kap * kap * m0 * (P1 + U2) / 32.0);
                 }
             }
-            A.out_d[ob] = v;
+            A.out_d[ob] = (T)v;
         }
         if (wv) {
-            double v = A.acc[(size_t)2 * A.B * A.nout + ab];
-            if (do_local) v += A.delta * A.f_trg[ob] * vfac;
-            A.out_v[ob] = v;
+            double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
+            if (do_local) v += A.delta * (double)A.f_trg[ob] * vfac;
+            A.out_v[ob] = (T)v;
         }
     }
 }
 
-__global__ void k_fill(double *p, int64_t n, double v)
+__global__ void k_zero(uint32_t *p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i < n) p[i] = 0u;
 }
 
-hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s)
+hipError_t launch_fill(mhk_plan *P, void *p, int64_t n)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    const int64_t words = n * (int64_t)P->es / 4;
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, P->stream, (uint32_t *)p, words);
     return hipGetLastError();
 }
 
-hipError_t launch_panel_coeffs(mhk_plan *P, const double *sigma, const double *mu)
+template <typename T>
+static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu)
 {
     const int64_t tot = P->npan * NGL * P->p.batch;
-    hipLaunchKernelGGL(k_panel_coeffs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
-                       P->p.batch, P->loc.leg, sigma, mu, P->loc.csig, P->loc.cmu);
+    hipLaunchKernelGGL(k_panel_coeffs<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
+                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, P->loc.csig, P->loc.cmu);
     return hipGetLastError();
 }
 
-hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const double *mu, const double *f_trg,
-                        double *out_s, double *out_d, double *out_v)
+hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu)
 {
-    LocalArgs A;
+    return P->p.prec == MHK_FP64 ? panel_coeffs<double>(P, sigma, mu) : panel_coeffs<float>(P, sigma, mu);
+}
+
+template <typename T>
+static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
+                          void *out_s, void *out_d, void *out_v)
+{
+    LocalArgs<T> A;
     A.nout = P->nout;
     A.nt = P->nt;
     A.nb = P->nb;
@@ -304,9 +316,9 @@ hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const doubl
     A.bx = P->bx;
     A.by = P->by;
     A.bk = P->bk;
-    A.sigma = sigma;
-    A.mu = mu;
-    A.f_trg = f_trg;
+    A.sigma = (const T *)sigma;
+    A.mu = (const T *)mu;
+    A.f_trg = (const T *)f_trg;
     A.cs = P->loc.csig;
     A.cm = P->loc.cmu;
     A.pcx = P->loc.cx;
@@ -328,12 +340,19 @@ hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const doubl
     A.dstar = P->dstar;
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
-    A.acc = P->acc;
-    A.out_s = out_s;
-    A.out_d = out_d;
-    A.out_v = out_v;
-    hipLaunchKernelGGL(k_local, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A);
+    A.acc = (const T *)P->acc;
+    A.out_s = (T *)out_s;
+    A.out_d = (T *)out_d;
+    A.out_v = (T *)out_v;
+    hipLaunchKernelGGL(k_local<T>, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A);
     return hipGetLastError();
+}
+
+hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
+                        void *out_s, void *out_d, void *out_v)
+{
+    if (P->p.prec == MHK_FP64) return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v);
+    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v);
 }
 
 }  // namespace mhk

@@ -32,11 +32,19 @@ constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
 constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
 constexpr int TAB_NC = 12;       // coefficients per table segment (degree 11)
+constexpr int TAB_STRIDE = 13;   // double2 slots per segment in LDS (padded against bank conflicts)
+constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
+constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
+constexpr int LV_CDIV = 2;       // level cells are R_j / LV_CDIV wide; neighbourhood +-LV_CDIV cells
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
 constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
 
 void set_error(const std::string &msg);
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double2 type; };
+template <> struct Vec2<float> { typedef float2 type; };
 
 struct Level {
     double delta_j = 0;          // delta / 4^(j-1): upper end of the level's time interval
@@ -55,9 +63,16 @@ struct Level {
     double *sw = nullptr;                         // w
     int32_t *code = nullptr;                      // (panel * nchild + child) * 16 + node
     int32_t *cell_start = nullptr;                // [ncx*ncy + 1]
+    // per block of LV_BLOCK sorted targets: ranges of sorted sources covering
+    // the union of the targets' cell neighbourhoods
+    int32_t *blk_ofs = nullptr;                   // [n_blocks + 1]
+    int32_t *blk_rng = nullptr;                   // [n_ranges][2]
+    int64_t n_ranges = 0;
     double *interp = nullptr;                     // [nchild][16][16] parent -> child values
-    double *tab = nullptr;                        // [nseg][TAB_NC][2] (S, D interleaved)
-    double *q = nullptr;                          // per eval: [3][batch][n_src]
+    double *tab = nullptr;                        // [nseg][TAB_STRIDE][2] (S, D interleaved)
+    float *tabf = nullptr;                        // FP32 path: [nseg][TABF_STRIDE][2]
+    void *tab_dev = nullptr;                      // the table of the plan's precision
+    void *q = nullptr;                            // per eval: [3][batch][n_src], plan precision
     double tab_err = 0;                           // measured max table error / K(0)
 };
 
@@ -93,7 +108,7 @@ struct History {
     double *mtab = nullptr;                       // [2 lmax + 1][lmax + 1]
     double trunc_d = 0, trunc_w = 0;              // separation bound D, transition width
     // grids
-    double *grid = nullptr;                       // [4][batch][field]
+    void *grid = nullptr;                         // [4][batch][field], plan precision
     void *work = nullptr;
     size_t work_bytes = 0;
     rocfft_plan fwd = nullptr, inv = nullptr;
@@ -110,7 +125,7 @@ struct Local {
     double *ends = nullptr;                       // [n_panels][4]: x(-1), y(-1), x(1), y(1)
     double *gl_t = nullptr;                       // [16] Gauss-Legendre abscissae
     int32_t *prev = nullptr, *next = nullptr;     // panel neighbours within each curve
-    double *csig = nullptr, *cmu = nullptr;       // per eval: [batch][n_panels][16]
+    double *csig = nullptr, *cmu = nullptr;       // per eval: [batch][n_panels][16] (FP64)
 };
 
 }  // namespace mhk
@@ -129,8 +144,9 @@ struct mhk_plan {
     double *tx = nullptr, *ty = nullptr;
     int8_t *tin = nullptr;
     int32_t *tidx = nullptr;
-    // accumulators in sorted target order: [3][batch][n_out] (S, D, V)
-    double *acc = nullptr;
+    // accumulators in sorted target order: [3][batch][n_out] (S, D, V), plan precision
+    void *acc = nullptr;
+    size_t es = 8;                               // bytes per value of the plan precision
     mhk::Level lev[mhk::MAXJ];
     mhk::History hist;
     mhk::Local loc;
@@ -141,16 +157,17 @@ struct mhk_plan {
 
 namespace mhk {
 
-// kernels launchers (defined in the .hip files)
-hipError_t launch_level_densities(mhk_plan *P, int j, const double *sigma, const double *mu);
+// kernels launchers (defined in the .hip files); density and output pointers
+// are of the plan's precision
+hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu);
 hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d);
-hipError_t launch_panel_coeffs(mhk_plan *P, const double *sigma, const double *mu);
-hipError_t launch_local(mhk_plan *P, int parts, const double *sigma, const double *mu,
-                        const double *f_trg, double *out_s, double *out_d, double *out_v);
-hipError_t launch_spread(mhk_plan *P, const double *sigma, const double *mu, const double *f_vol);
+hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu);
+hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
+                        const void *f_trg, void *out_s, void *out_d, void *out_v);
+hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
-hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
 hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,
                                        double rmid, double slope, const double *gl_t, const double *gl_w,
                                        hipStream_t s);

@@ -5,6 +5,7 @@
 // and tile order, the history grid and its FFT plans.  mhk_eval only enqueues
 // device work on the plan's stream.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -202,6 +203,10 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
     }
     if (p.prec != MHK_FP64 && p.prec != MHK_FP32) {
         set_error("prec must be MHK_FP64 or MHK_FP32");
+        return MHK_EINVAL;
+    }
+    if (p.prec == MHK_FP32 && p.tol < 1e-7) {
+        set_error("the FP32 path needs tol >= 1e-7");
         return MHK_EINVAL;
     }
     if (p.J < 0) p.J = 3;
@@ -465,7 +470,7 @@ void host_common(Host &H)
 // the 16-point Gauss-Legendre nodes of each child interval, with geometry
 // interpolated by the parent's degree-15 polynomial, normals renormalised,
 // and weights w_GL,child * speed * 2^-j.
-mhk_status build_level(mhk_plan *P, Host &H, int j)
+mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &tgx, const std::vector<double> &tgy)
 {
     Level &L = P->lev[j - 1];
     const mhk_boundary *b = H.b;
@@ -510,8 +515,8 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
                 cwy[q] = wq * ny / nn;
             }
     }
-    // cells of side R_j over the bounding box of sources and targets
-    L.cell = L.radius;
+    // cells of side R_j / LV_CDIV over the bounding box of sources and targets
+    L.cell = L.radius / LV_CDIV;
     L.ox = H.xmin - 1e-9;
     L.oy = H.ymin - 1e-9;
     int64_t ncx = (int64_t)floor((H.xmax - L.ox) / L.cell) + 1;
@@ -545,19 +550,75 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
     TRY(upload(P, &L.code, code.data(), L.n_src));
     TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
-    TRY(dalloc(P, &L.q, 3 * (int64_t)P->p.batch * L.n_src));
+    // per target block: the union of the targets' (2 LV_CDIV + 1)^2 cell
+    // neighbourhoods as row intervals, mapped to ranges of sorted sources
+    {
+        const int64_t nout = (int64_t)tgx.size();
+        const int64_t nblk = (nout + LV_BLOCK - 1) / LV_BLOCK;
+        std::vector<int32_t> bofs(nblk + 1, 0), rng;
+        std::vector<int64_t> cells;
+        std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
+        for (int64_t b = 0; b < nblk; ++b) {
+            cells.clear();
+            for (int64_t t = b * LV_BLOCK; t < std::min(nout, (b + 1) * LV_BLOCK); ++t) {
+                int64_t ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((tgx[t] - L.ox) / L.cell)));
+                int64_t iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((tgy[t] - L.oy) / L.cell)));
+                cells.push_back(iy * ncx + ix);
+            }
+            std::sort(cells.begin(), cells.end());
+            cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+            iv.clear();
+            for (int64_t c : cells) {
+                int64_t cy = c / ncx, cx = c % ncx;
+                for (int64_t r = std::max<int64_t>(0, cy - LV_CDIV); r <= std::min<int64_t>(ncy - 1, cy + LV_CDIV); ++r)
+                    iv.push_back({r, std::max<int64_t>(0, cx - LV_CDIV), std::min<int64_t>(ncx - 1, cx + LV_CDIV)});
+            }
+            std::sort(iv.begin(), iv.end());
+            int64_t last_end = -1;
+            for (size_t i = 0; i < iv.size();) {
+                int64_t r = iv[i][0], x0 = iv[i][1], x1 = iv[i][2];
+                size_t k = i + 1;
+                while (k < iv.size() && iv[k][0] == r && iv[k][1] <= x1 + 1) {
+                    x1 = std::max(x1, iv[k][2]);
+                    ++k;
+                }
+                int32_t s0 = start[r * ncx + x0], s1 = start[r * ncx + x1 + 1];
+                if (s1 > s0) {
+                    if ((int64_t)s0 == last_end && !rng.empty()) {
+                        rng.back() = s1;           // contiguous with the previous range
+                    } else {
+                        rng.push_back(s0);
+                        rng.push_back(s1);
+                    }
+                    last_end = s1;
+                }
+                i = k;
+            }
+            bofs[b + 1] = (int32_t)(rng.size() / 2);
+        }
+        L.n_ranges = (int64_t)rng.size() / 2;
+        TRY(upload(P, &L.blk_ofs, bofs.data(), nblk + 1));
+        TRY(upload(P, &L.blk_rng, rng.data(), std::max<int64_t>(2, (int64_t)rng.size())));
+    }
+    {
+        char *q = nullptr;
+        TRY(dalloc(P, &q, 3 * (int64_t)P->p.batch * L.n_src * (int64_t)P->es));
+        L.q = q;
+    }
 
     // Kernel table: piecewise polynomials in a = r^2/(4 delta_j) on segments of
     // width 1/4, each in the local variable v in [-1, 1]; coefficients from
-    // Chebyshev interpolation converted to monomials in v.
+    // Chebyshev interpolation converted to monomials in v.  FP64 path: degree
+    // 11; FP32 path: degree 7, stored as floats.
     LevelQuad Q;
     const double seg_w = 0.25;
     L.seg_inv = 1.0 / seg_w;
     L.nseg = (int)ceil(L.a_max / seg_w) + 1;
     const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
     const double cS = 1.0 / (4.0 * M_PI), cD = 1.0 / (8.0 * M_PI * L.delta_j);
-    std::vector<double> tab((size_t)L.nseg * TAB_NC * 2);
-    const int nc = TAB_NC;
+    const bool fp64 = P->p.prec == MHK_FP64;
+    const int nc = fp64 ? TAB_NC : TABF_NC, stride = fp64 ? TAB_STRIDE : TABF_STRIDE;
+    std::vector<double> tab((size_t)L.nseg * stride * 2, 0.0);
     std::vector<double> node(nc);
     for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
     for (int sgi = 0; sgi < L.nseg; ++sgi) {
@@ -575,17 +636,16 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
             // Chebyshev coefficients
             std::vector<long double> ch(nc, 0);
             for (int m = 0; m < nc; ++m) {
-                long double s = 0;
-                for (int i = 0; i < nc; ++i) s += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
-                ch[m] = s * (m == 0 ? 1.0L : 2.0L) / nc;
+                long double sacc = 0;
+                for (int i = 0; i < nc; ++i) sacc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
+                ch[m] = sacc * (m == 0 ? 1.0L : 2.0L) / nc;
             }
             // T_m(v) -> monomials in v
             std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
             tprev[0] = 1;       // T0
             tcur[1] = 1;        // T1
             for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
-            if (nc > 1)
-                for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
+            for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
             for (int m = 2; m < nc; ++m) {
                 std::fill(tnext.begin(), tnext.end(), 0.0L);
                 for (int k = 0; k < nc; ++k) {
@@ -596,7 +656,7 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
                 tprev = tcur;
                 tcur = tnext;
             }
-            for (int k = 0; k < nc; ++k) tab[((size_t)sgi * nc + k) * 2 + kind] = (double)mono[k];
+            for (int k = 0; k < nc; ++k) tab[((size_t)sgi * stride + k) * 2 + kind] = (double)mono[k];
         }
     }
     // accuracy check of the table against direct quadrature
@@ -614,19 +674,26 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
             double v = 2.0 * (a * L.seg_inv - sgi) - 1.0;
             double pS = 0, pD = 0;
             for (int k = nc - 1; k >= 0; --k) {
-                pS = pS * v + tab[((size_t)sgi * nc + k) * 2];
-                pD = pD * v + tab[((size_t)sgi * nc + k) * 2 + 1];
+                pS = pS * v + tab[((size_t)sgi * stride + k) * 2];
+                pD = pD * v + tab[((size_t)sgi * stride + k) * 2 + 1];
             }
             emax = std::max(emax, fabs(pS - i0 * cS) / k0S);
             emax = std::max(emax, fabs(pD - i1 * cD) / k0D);
         }
         L.tab_err = emax;
-        if (emax > 1e-13) {
+        if (emax > (fp64 ? 1e-13 : 1e-8)) {
             set_error("level kernel table not accurate: " + std::to_string(emax));
             return MHK_EUNSUPPORTED;
         }
     }
+    if (!fp64) {
+        std::vector<float> tf(tab.begin(), tab.end());
+        TRY(upload(P, &L.tabf, tf.data(), (int64_t)tf.size()));
+        L.tab_dev = L.tabf;
+        return MHK_OK;
+    }
     TRY(upload(P, &L.tab, tab.data(), (int64_t)tab.size()));
+    L.tab_dev = L.tab;
     return MHK_OK;
 }
 
@@ -901,7 +968,12 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         TRY(upload(P, &G.ttile_rng, rng.data(), (int64_t)rng.size()));
     }
     // grids and FFT plans
-    TRY(dalloc(P, &G.grid, 4 * (int64_t)P->p.batch * G.field));
+    {
+        char *g = nullptr;
+        TRY(dalloc(P, &g, 4 * (int64_t)P->p.batch * G.field * (int64_t)P->es));
+        G.grid = g;
+    }
+    const rocfft_precision fprec = P->p.prec == MHK_FP64 ? rocfft_precision_double : rocfft_precision_single;
     if (!g_rocfft_ready) {
         MHK_FFT(rocfft_setup());
         g_rocfft_ready = true;
@@ -914,12 +986,12 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
                                                     nullptr, nullptr, 2, rstr, rdist, 2, cstr, cdist));
     MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward,
-                               rocfft_precision_double, 2, len, 4 * (size_t)P->p.batch, df));
+                               fprec, 2, len, 4 * (size_t)P->p.batch, df));
     MHK_FFT(rocfft_plan_description_create(&di));
     MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real,
                                                     nullptr, nullptr, 2, cstr, cdist, 2, rstr, rdist));
     MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse,
-                               rocfft_precision_double, 2, len, 3 * (size_t)P->p.batch, di));
+                               fprec, 2, len, 3 * (size_t)P->p.batch, di));
     rocfft_plan_description_destroy(df);
     rocfft_plan_description_destroy(di);
     size_t w1 = 0, w2 = 0;
@@ -1036,10 +1108,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
 {
     TRY(check_inputs(params, b, v, t));
     TRY(resolve(params, &P->info, &P->p));
-    if (P->p.prec != MHK_FP64) {
-        set_error("FP32 evaluation is not available in this build");
-        return MHK_EUNSUPPORTED;
-    }
+    P->es = P->p.prec == MHK_FP64 ? sizeof(double) : sizeof(float);
     P->stream = (hipStream_t)stream;
     P->J = P->p.J;
     P->delta = P->info.delta;
@@ -1111,10 +1180,14 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
         tgx.swap(sx);
         tgy.swap(sy);
     }
-    for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j));
+    for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j, tgx, tgy));
     TRY(build_history(P, H, tgx, tgy));
     TRY(build_local(P, H));
-    TRY(dalloc(P, &P->acc, 3 * (int64_t)P->p.batch * P->nout));
+    {
+        char *a = nullptr;
+        TRY(dalloc(P, &a, 3 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
+        P->acc = a;
+    }
     for (auto &e : P->ev) MHK_HIP(hipEventCreate(&e));
     P->info.n_boundary = P->nb;
     P->info.n_volume = P->nv;
@@ -1247,9 +1320,8 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void
         set_error("invalid parts mask");
         return MHK_EINVAL;
     }
-    const double *sigma = (const double *)sigma_, *mu = (const double *)mu_;
-    const double *f_vol = (const double *)f_vol_, *f_trg = (const double *)f_trg_;
-    double *out_s = (double *)out_s_, *out_d = (double *)out_d_, *out_v = (double *)out_v_;
+    const void *sigma = sigma_, *mu = mu_, *f_vol = f_vol_, *f_trg = f_trg_;
+    void *out_s = out_s_, *out_d = out_d_, *out_v = out_v_;
     const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if ((sigma && !out_s) || (mu && !out_d) || (f_vol && !out_v)) {
         set_error("an input density was given without its output array");
@@ -1282,7 +1354,7 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[4], st));
         MHK_HIP(launch_interp(P, ws, wd, wv));
     } else {
-        MHK_HIP(launch_fill(P->acc, 3 * (int64_t)B * nout, 0.0, st));
+        MHK_HIP(launch_fill(P, P->acc, 3 * (int64_t)B * nout));
         if (P->timing)
             for (int e = 1; e <= 4; ++e) MHK_HIP(hipEventRecord(P->ev[e], st));
     }

@@ -67,7 +67,8 @@ def test_bands_and_levels():
                                 dict(alpha=1.0, tol=1e-6, delta=1e-3, batch=0),
                                 dict(alpha=1.0, tol=1e-6, delta=1e-3, prec=3),
                                 dict(alpha=1.0, tol=1e-6, delta=1e-3, wspread=2),
-                                dict(alpha=float("nan"), tol=1e-6, delta=1e-3)])
+                                dict(alpha=float("nan"), tol=1e-6, delta=1e-3),
+                                dict(alpha=10.0, tol=1e-10, prec=1, delta=1e-3)])
 def test_invalid_params_rejected(kw):
     with pytest.raises(M.MhkError) as e:
         M.resolve_params(**kw)

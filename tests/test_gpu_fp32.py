@@ -1,0 +1,65 @@
+"""FP32 path (spreading, FFT, interpolation and level sums in FP32, local
+part and Fourier multiplier in FP64) against the FP64 oracle: relative
+max-norm error below 1e-6 per potential at tol = 1e-6."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from helpers import oracle_eval, rel_err, small_multibody, stratified_subset
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-6
+
+
+def _f32(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _plan(w, alpha, tol=TOL32, **kw):
+    import paper_2606_28865_amd as M
+    prm = M.make_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, dx=w.dx, **kw)
+    return M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+
+
+def _run(plan, w, parts=7):
+    out = plan.eval(_f32(w.sigma), _f32(w.mu), _f32(w.f_vol), _f32(w.f_trg), parts=parts)
+    torch.cuda.synchronize()
+    for o in out:
+        assert o.dtype == torch.float32
+    return [o.cpu().numpy().astype(np.float64).ravel() for o in out]
+
+
+@pytest.mark.parametrize("alpha", [3.0, 10.0, 30.0])
+def test_fp32_config0(alpha):
+    w = synth.config0()
+    print(f"case fp32 config0 alpha={alpha}", flush=True)
+    plan = _plan(w, alpha)
+    info = plan.info()
+    S, D, V = _run(plan, w)
+    # the oracle in FP64 on the FP32 inputs (the data the GPU saw)
+    r = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    So, Do, Vo = oracle_eval(w, alpha, info["delta"], 3, sigma=r(w.sigma), mu=r(w.mu), f_vol=r(w.f_vol),
+                             f_trg=r(w.f_trg))
+    errs = [rel_err(S, So), rel_err(D, Do), rel_err(V, Vo)]
+    print(f"fp32 config0 alpha {alpha}: errs S {errs[0]:.2e} D {errs[1]:.2e} V {errs[2]:.2e}", flush=True)
+    assert max(errs) < TOL32
+
+
+def test_fp32_multibody_sampled():
+    """3-body workload at alpha = 30 with the tol = 1e-6 split rule."""
+    w = small_multibody()
+    alpha = 30.0
+    print("case fp32 multibody", flush=True)
+    plan = _plan(w, alpha)
+    info = plan.info()
+    S, D, V = _run(plan, w)
+    sub = stratified_subset(w, info["band_volume"])
+    r = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    So, Do, Vo = oracle_eval(w, alpha, info["delta"], 3, subset=sub, sigma=r(w.sigma), mu=r(w.mu),
+                             f_vol=r(w.f_vol), f_trg=r(w.f_trg))
+    errs = [rel_err(S[sub], So), rel_err(D[sub], Do), rel_err(V[sub], Vo)]
+    print(f"fp32 multibody errs {errs} n {info['n_fine']} w {info['wspread']}", flush=True)
+    assert max(errs) < TOL32
