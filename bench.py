@@ -35,7 +35,28 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-sample", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB device-to-device 4 times (calibrates HBM byte counters)")
+    ap.add_argument("--workload", default="multibody", choices=["multibody", "precision", "batched", "serve"],
+                    help="multibody: the default throughput line; precision: FP32 vs FP64 at tol 1e-6 on "
+                         "64k boundary / 4M volume / 4M targets; batched: 64 densities per call under a "
+                         "captured HIP graph; serve: Poisson stream of Rothe-step requests")
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=120)
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device copy of known size: 256 MiB read + 256 MiB written per
+    dispatch; the FETCH_SIZE / WRITE_SIZE counters of this dispatch give the
+    scale factor of the counters on this GPU."""
+    import torch
+    a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "dispatches": 4}), flush=True)
 
 
 def log(msg):
@@ -44,10 +65,16 @@ def log(msg):
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); the per-GPU "
               "throughput at N=1 is the figure this workload reports.", file=sys.stderr)
         sys.exit(2)
+    if a.workload != "multibody":
+        {"precision": run_precision, "batched": run_batched, "serve": run_serve}[a.workload](a)
+        return
     import torch
 
     import paper_2606_28865_amd as M
@@ -146,14 +173,17 @@ def roofline(dom, stage, infos, w, plans):
     measured HIP-event time."""
     name = dom[3:]
     if name == "levels":
-        # pairs within the level radii, counted from the plan geometry on the host
+        # algorithmic flops of the three level launches of every plan over
+        # their HIP-event time (the stage also holds the small k_level_q)
         flops = 0.0
         for info in infos:
             flops += level_flops(w, info)
         t = sum(stage[dom]) * 1e-3
         ach = flops / t / 1e12
+        launches = sum(i["J"] for i in infos)
         return {"kernel": "k_level_sums", "bound": "alu", "achieved": ach, "peak": FP64_PEAK,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": None}
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": None,
+                "flops_per_launch": flops / launches, "ms_per_launch": sum(stage[dom]) / launches}
     if name in ("fft", "spread", "multiply", "interp"):
         byts = 0.0
         for info in infos:
@@ -178,7 +208,29 @@ def roofline(dom, stage, infos, w, plans):
             "frac": None, "traffic": None}
 
 
-LEVEL_FLOPS_PER_PAIR = 64.0   # distance 5, compare 1, segment 4, 2 x 11 FMA table (44), S 2, D 4, misc 4
+# Flops the level sum spends on one (target, child node) pair with r < R_j:
+# separation 2, a = (dx^2 + dy^2)/(4 delta_j) 3, segment and local variable 3,
+# two degree-9 Horner recurrences 36, S accumulation 2, nu.(x - x_q) 3 and D
+# accumulation 2.
+LEVEL_FLOPS_PER_PAIR = 53.0
+
+
+def child_nodes(w, j):
+    """Positions of the level-j child nodes (every panel bisected j times, 16
+    Gauss-Legendre nodes per child), from the analytic curves."""
+    import synth
+    tg, _ = synth.gauss_legendre()
+    xs = []
+    ofs = w.boundary["curve_panel_ofs"]
+    for c, cv in enumerate(w.curves):
+        M = int(ofs[c + 1] - ofs[c])
+        edges = np.linspace(0.0, 2 * np.pi, M + 1)
+        nch = 1 << j
+        h = (edges[1] - edges[0]) / nch
+        t = (edges[:-1, None, None] + h * (np.arange(nch)[None, :, None] + 0.5 * (1 + tg[None, None, :]))).ravel()
+        g, _, _ = cv.eval(t)
+        xs.append(np.stack([g.real, g.imag], 1))
+    return np.concatenate(xs)
 
 
 def level_flops(w, info):
@@ -186,15 +238,11 @@ def level_flops(w, info):
     the flops the level sum spends on one pair."""
     from scipy.spatial import cKDTree
     tg = np.concatenate([np.stack([w.tx, w.ty], 1), np.stack([w.boundary["x"], w.boundary["y"]], 1)])
-    b = w.boundary
-    pairs = 0
+    pairs = 0.0
     for j in range(1, info["J"] + 1):
-        R = info["level_radius"][j - 1]
-        # child nodes: the level sum's sources lie on the same curves as the
-        # panel nodes with 2^j times the density; count with the parent nodes
-        tree = cKDTree(np.stack([b["x"], b["y"]], 1))
-        cnt = tree.query_ball_point(tg, R, return_length=True)
-        pairs += float(np.sum(cnt)) * (1 << j)
+        tree = cKDTree(child_nodes(w, j))
+        cnt = tree.query_ball_point(tg, info["level_radius"][j - 1], return_length=True, workers=-1)
+        pairs += float(np.sum(cnt))
     return pairs * LEVEL_FLOPS_PER_PAIR
 
 
@@ -214,6 +262,215 @@ def cpu_baseline(w, infos, alphas, n_sample):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_sample / dt, "unit": "target-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{n_sample} random targets of the same workload at alpha={alphas[i]}, {dt:.1f} s"}
+
+
+# ---------------------------------------------------------------------------
+# Other workloads (one JSON line each)
+# ---------------------------------------------------------------------------
+def _sample_errors(w, info, alpha, outs, n_sample=32, seed=3):
+    """Relative max-norm error of (S, D, V) against the oracle on a random
+    sample of targets (FP64 oracle on the same inputs)."""
+    import oracle as O
+    g = np.random.default_rng(seed)
+    sub = np.sort(g.choice(w.n_t + w.n_b, n_sample, replace=False)).astype(np.int64)
+    P = O.Problem(alpha, info["delta"], info["J"], w.boundary, volume=w.volume, targets=(w.tx, w.ty),
+                  inside=w.inside, on_surface=True, sigma=w.sigma, mu=w.mu, f_vol=w.f_vol, f_trg=w.f_trg)
+    t0 = time.perf_counter()
+    ref = P.eval(sub)
+    dt = time.perf_counter() - t0
+    errs = []
+    for o, r in zip(outs, ref):
+        o = o.double().cpu().numpy().ravel()[sub]
+        errs.append(float(np.abs(o - r).max() / np.abs(r).max()))
+    return errs, dt
+
+
+def run_precision(a):
+    """FP32 vs FP64 at tol 1e-6 on the multi-body generator at 65536
+    boundary nodes, ~4M volume nodes and 4M targets, alpha = 30."""
+    import torch
+
+    import paper_2606_28865_amd as M
+    import synth
+    t0 = time.time()
+    w = synth.multibody(cfg=2, n_boundary=65536, n_volume=4_000_000, n_targets=4_000_000, alphas=(30.0,), tol=1e-6)
+    log(f"workload {w.name} generated in {time.time() - t0:.1f} s")
+    alpha, tol = 30.0, 1e-6
+    res = {}
+    for prec, dt, name in ((M.MHK_FP32, torch.float32, "fp32"), (M.MHK_FP64, torch.float64, "fp64")):
+        t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+        ins = (t(w.sigma), t(w.mu), t(w.f_vol), t(w.f_trg))
+        p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=prec, dx=w.dx), w.boundary, w.volume,
+                   (w.tx, w.ty, w.inside), on_surface=True)
+        out = p.eval(*ins)
+        for _ in range(a.warmup):
+            p.eval(*ins, out=out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            p.eval(*ins, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        p.set_timing(True)
+        p.eval(*ins, out=out)
+        info = p.info()
+        errs, odt = _sample_errors(w, info, alpha, out)
+        res[name] = {"ms_per_eval": ms, "target_evals_per_s": p.n_out / (ms * 1e-3),
+                     "rel_err_vs_oracle": {"S": errs[0], "D": errs[1], "V": errs[2]},
+                     "stage_ms": {k: round(info[k], 4) for k in info if k.startswith("ms_")},
+                     "grid": info["n_fine"], "wspread": info["wspread"]}
+        log(f"{name}: {ms:.2f} ms, errs {errs}")
+        p.close()
+        del ins, out
+        torch.cuda.empty_cache()
+    line = {"metric": "target evals/s at tol 1e-6, FP32 vs FP64", "value": res["fp32"]["target_evals_per_s"],
+            "unit": "target-evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": res["fp32"]["ms_per_eval"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "multibody-precision", "n_boundary": w.n_b, "n_volume": w.n_v,
+                       "n_targets": w.n_t, "alpha": alpha, "tol": tol},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def run_batched(a):
+    """64 densities per call on one 65536-node multi-body geometry (~1M volume
+    nodes, 1M targets + boundary nodes), evaluated by replaying a captured HIP
+    graph; grid parameters from the autotuner; alpha in {3, 30}, FP32 and FP64."""
+    import torch
+
+    import paper_2606_28865_amd as M
+    from paper_2606_28865_amd import autotune
+    import synth
+    t0 = time.time()
+    w = synth.multibody(cfg=3, n_boundary=65536, n_volume=1_000_000, n_targets=1_000_000, alphas=(3.0, 30.0))
+    log(f"workload {w.name} generated in {time.time() - t0:.1f} s")
+    B = a.batch
+    g = np.random.default_rng(7)
+    # B densities and sources with the config-0 spectra: rescaled copies
+    # with seeded random mode amplitudes per density
+    tt = w.boundary["t"]
+    k = np.arange(9)
+    sc = 1.0 / np.maximum(1, k) ** 2
+    def dens():
+        a_, b_ = g.standard_normal(9) * sc, g.standard_normal(9) * sc
+        return (a_[None, :] * np.cos(np.outer(tt, k)) + b_[None, :] * np.sin(np.outer(tt, k))).sum(1)
+    sig = np.stack([dens() for _ in range(B)])
+    mu = np.stack([dens() for _ in range(B)])
+    amp = g.standard_normal(B)
+    fv = amp[:, None] * w.f_vol[None, :]
+    ft = amp[:, None] * w.f_trg[None, :]
+    geometry = {"boundary": w.boundary, "volume": w.volume, "targets": (w.tx, w.ty, w.inside), "on_surface": True}
+    res = {}
+    for alpha in (3.0, 30.0):
+        for prec, dt, name, tol in ((M.MHK_FP32, torch.float32, "fp32", 1e-6), (M.MHK_FP64, torch.float64, "fp64", 1e-10)):
+            tun = autotune.tune(geometry, alpha, tol, prec, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx, batch=1,
+                                cache=None, log=log)
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+                ins = (t(sig), t(mu), t(fv), t(ft))
+                p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=prec, delta=tun["delta"], batch=B,
+                                         upsamp=tun["upsamp"], wspread=tun["wspread"]),
+                           w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=stream)
+                out = p.capture(*ins)
+                for _ in range(a.warmup):
+                    p.replay()
+                stream.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(a.steps):
+                    p.replay()
+                e1.record(stream)
+                stream.synchronize()
+            ms = e0.elapsed_time(e1) / a.steps
+            evals = B * p.n_out
+            key = f"{name}_alpha{alpha:g}"
+            res[key] = {"ms_per_replay": ms, "target_evals_per_s": evals / (ms * 1e-3), "batch": B,
+                        "upsamp": tun["upsamp"], "wspread": tun["wspread"], "grid": p.info()["n_fine"],
+                        "autotune": [{k2: v for k2, v in c.items() if k2 != "sigma_eff"} for c in tun["table"]]}
+            log(f"{key}: {ms:.1f} ms per replay of {B} densities -> {evals / (ms * 1e-3):.3e} target-evals/s")
+            p.close()
+            del ins, out
+            torch.cuda.empty_cache()
+    best = max(v["target_evals_per_s"] for v in res.values())
+    line = {"metric": "target evals/s, 64 densities per call under a captured HIP graph", "value": best,
+            "unit": "target-evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "multibody-batched", "n_boundary": w.n_b, "n_volume": w.n_v,
+                       "n_targets": w.n_t, "batch": B},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(a):
+    """Poisson stream of Rothe-step requests from several concurrent
+    simulations (1-50 bodies, 1k-128k boundary nodes, 10k-2M volume nodes,
+    alpha log-uniform in [1, 300], tol 1e-6 (FP32) or 1e-10 (FP64))."""
+    import torch
+
+    import synth
+    from paper_2606_28865_amd.serve import Geometry, Request, Server, latency_stats
+    g = np.random.default_rng(4)
+    sims = []
+    t0 = time.time()
+    sizes = [(3, 2048, 20_000), (12, 8192, 150_000), (1, 1024, 10_000), (30, 32768, 600_000),
+             (50, 131072, 2_000_000), (6, 4096, 60_000)]
+    for si, (nbod, nb, nv) in enumerate(sizes):
+        w = synth.multibody(cfg=100 + si, n_bodies=nbod, n_boundary=nb, n_volume=nv, n_targets=nv // 2,
+                            box=1.0 if nbod < 30 else 1.4)
+        alpha = float(np.exp(g.uniform(np.log(1.0), np.log(300.0))))
+        tol = 1e-6 if g.uniform() < 0.5 else 1e-10
+        geo = Geometry(f"sim{si}", w.boundary, w.volume, (w.tx, w.ty, w.inside), True)
+        sims.append((w, geo, alpha, tol))
+        log(f"sim {si}: {nbod} bodies, nb {w.n_b}, nv {w.n_v}, alpha {alpha:.1f}, tol {tol:g}")
+    log(f"generated in {time.time() - t0:.1f} s")
+
+    def make_req(rid, si, arrival):
+        w, geo, alpha, tol = sims[si]
+        s = 1.0 + 0.1 * g.standard_normal()
+        return Request(rid, geo, alpha, tol, 1 if tol >= 1e-6 else 0, w.sigma * s, w.mu * s, w.f_vol * s,
+                       w.f_trg * s, arrival=arrival, dx=w.dx)
+
+    srv = Server(budget_bytes=int(torch.cuda.mem_get_info()[0] * 0.7), max_inflight=8)
+    # warm-up: one request per simulation (plan creation), also gives service times
+    warm = [make_req(-1 - i, i, 0.0) for i in range(len(sims))]
+    srv.run(warm)
+    svc = {}
+    for r in warm:
+        svc[r.geometry.key] = r.done - r.admitted
+    srv.finished.clear()
+    # measured service time per request when run alone
+    alone = []
+    for i in range(len(sims)):
+        r = make_req(-100 - i, i, 0.0)
+        srv.run([r])
+        alone.append(r.done - r.admitted)
+    srv.finished.clear()
+    mean_svc = float(np.mean(alone))
+    lam = 0.7 / mean_svc                      # ~70% of one-at-a-time capacity
+    t = 0.0
+    reqs = []
+    for rid in range(a.requests):
+        t += g.exponential(1.0 / lam)
+        reqs.append(make_req(rid, int(g.integers(len(sims))), t))
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    span = time.perf_counter() - t0
+    st = latency_stats(done)
+    evals = sum(r.geometry.n_out for r in done)
+    srv.close()
+    line = {"metric": "served target evals/s with p50/p99 request latency", "value": evals / span,
+            "unit": "target-evals/s", "n_gpus": 1, "steps": len(done), "warmup": len(warm),
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "rothe-serving", "simulations": len(sims), "requests": a.requests,
+                       "arrival_rate_per_s": lam, "sizes": sizes},
+            "latency": st, "alone_service_ms": [round(x * 1e3, 3) for x in alone], "span_s": span}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -154,6 +154,18 @@ mhk_status mhk_eval_parts(mhk_plan *plan, int parts, const void *sigma, const vo
                           const void *f_vol, const void *f_trg, void *out_S, void *out_D,
                           void *out_V);
 
+/* Record one evaluation (the arguments of mhk_eval_parts) into a HIP graph
+ * owned by the plan, bound to these device pointers, without running it; the
+ * plan's stream is synchronised first.  mhk_plan_launch_graph then replays
+ * the whole evaluation (every stage, all densities of the batch) with one
+ * launch on the plan's stream; the caller refreshes the contents of the
+ * input buffers between replays and keeps every bound buffer alive.  A new
+ * capture replaces the previous graph. */
+mhk_status mhk_plan_capture(mhk_plan *plan, int parts, const void *sigma, const void *mu,
+                            const void *f_vol, const void *f_trg, void *out_S, void *out_D,
+                            void *out_V);
+mhk_status mhk_plan_launch_graph(mhk_plan *plan);
+
 /* Enable (1) or disable (0) per-stage timing with HIP events; when enabled,
  * each eval synchronises its stream at the end and fills the ms_* fields. */
 mhk_status mhk_plan_set_timing(mhk_plan *plan, int enable);

@@ -60,8 +60,8 @@ class Info(C.Structure):
 
 
 EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
-           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_set_timing", "mhk_plan_info",
-           "mhk_plan_destroy", "mhk_last_error"]
+           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_capture", "mhk_plan_launch_graph",
+           "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error"]
 
 _lib = None
 
@@ -81,13 +81,15 @@ def lib():
         L.mhk_eval_D.argtypes = [C.c_void_p] * 3
         L.mhk_eval_V.argtypes = [C.c_void_p] * 4
         L.mhk_eval_parts.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        L.mhk_plan_capture.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        L.mhk_plan_launch_graph.argtypes = [C.c_void_p]
         L.mhk_plan_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.mhk_plan_info.argtypes = [C.c_void_p, P(Info)]
         L.mhk_plan_destroy.argtypes = [C.c_void_p]
         L.mhk_plan_destroy.restype = None
         L.mhk_last_error.restype = C.c_char_p
-        for name in EXPORTS[:-2] + ["mhk_plan_info"]:
-            if name != "mhk_plan_destroy":
+        for name in EXPORTS:
+            if name not in ("mhk_plan_destroy", "mhk_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -214,6 +216,27 @@ class Plan:
         if t.numel() != self.batch * n:
             raise ValueError(f"expected {self.batch} x {n} values, got {t.numel()}")
         return t
+
+    def capture(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None):
+        """Record one evaluation bound to these tensors into a HIP graph;
+        returns the output tensors the graph writes.  replay() runs it."""
+        import torch
+        sigma = self._dev(sigma, self.nb)
+        mu = self._dev(mu, self.nb)
+        f_vol = self._dev(f_vol, self.nv)
+        f_trg = self._dev(f_trg, self.n_out)
+        shape = (self.batch, self.n_out)
+        if out is None:
+            out = tuple(torch.empty(shape, dtype=self.dtype, device="cuda") if x is not None else None
+                        for x in (sigma, mu, f_vol))
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        _check(lib().mhk_plan_capture(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
+                                      ptr(out[0]), ptr(out[1]), ptr(out[2])))
+        self._bound = (sigma, mu, f_vol, f_trg, out)
+        return out
+
+    def replay(self):
+        _check(lib().mhk_plan_launch_graph(self._h))
 
     def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None):
         """Returns (S, D, V) device tensors [batch, n_out] (None where not requested)."""

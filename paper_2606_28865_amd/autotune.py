@@ -1,0 +1,116 @@
+"""Autotuner for the history grid: oversampling factor and window width.
+
+For one geometry, alpha, tolerance and precision, each candidate (upsamp,
+wspread) is built as a plan with the same split delta, timed on the device
+with HIP events over a few evaluations, and checked against a reference
+evaluation of the same inputs by a more accurate plan (FP64, the tolerance
+/ 1000, the default grid): a candidate is admissible when its relative
+max-norm difference to the reference is below the tolerance for S, D and V.
+The fastest admissible candidate wins.  Results are cached in a JSON file
+keyed by the problem's sizes and parameters.
+
+Everything runs through the library (no CPU fallback); the reference is the
+library's own FP64 path, whose agreement with the oracle is what the parity
+tests establish.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import _lib as L
+
+DEFAULT_CANDIDATES = [(2.0, 0), (1.75, 0), (1.5, 0), (2.0, -1), (1.5, 1), (1.25, 2)]
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mhk_autotune.json")
+
+
+def _key(geometry, alpha, tol, prec, batch):
+    b, v, t = geometry["boundary"], geometry.get("volume"), geometry["targets"]
+    return f"nb{len(b['x'])}-nv{0 if v is None else len(v['x'])}-nt{len(t[0])}-a{alpha:g}-t{tol:g}-p{prec}-b{batch}"
+
+
+def _rel(a, b):
+    a = a.double().cpu().numpy().ravel()
+    b = b.double().cpu().numpy().ravel()
+    m = np.isfinite(b)
+    s = np.abs(b[m]).max()
+    return float(np.abs(a[m] - b[m]).max() / (s if s > 0 else 1.0))
+
+
+def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, candidates=None, reps=3,
+         cache=CACHE, log=None):
+    """geometry: dict(boundary=..., volume=..., targets=(x, y, inside), on_surface=bool);
+    densities: (sigma, mu, f_vol, f_trg) host arrays of one density.
+    Returns dict(upsamp, wspread, ms, err, table)."""
+    import torch
+    key = _key(geometry, alpha, tol, prec, batch)
+    if cache and os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+            if key in db:
+                return db[key]
+        except (OSError, ValueError):
+            pass
+    cands = candidates or DEFAULT_CANDIDATES
+    if delta <= 0:
+        delta = L.resolve_params(alpha=alpha, tol=tol, prec=prec, dx=dx)["delta"]
+    geo = (geometry["boundary"], geometry.get("volume"), geometry["targets"])
+    on = geometry.get("on_surface", True)
+    dt = torch.float64 if prec == L.MHK_FP64 else torch.float32
+
+    def dev(a, d):
+        a = np.ascontiguousarray(a)
+        a = np.broadcast_to(a, (batch,) + a.shape).copy()
+        return torch.as_tensor(a, dtype=d, device="cuda")
+
+    ref_plan = L.Plan(L.make_params(alpha=alpha, tol=max(1e-13, tol * 1e-3), delta=delta, batch=1), *geo,
+                      on_surface=on)
+    ref = ref_plan.eval(*(dev(x, torch.float64)[:1] for x in densities))
+    torch.cuda.synchronize()
+    ref_plan.close()
+    ins = [dev(x, dt) for x in densities]
+    w0 = L.resolve_params(alpha=alpha, tol=tol, prec=prec, delta=delta)["wspread"]
+    table = []
+    for ups, dw in cands:
+        ws = max(4, min(16, w0 + dw))
+        try:
+            p = L.Plan(L.make_params(alpha=alpha, tol=tol, prec=prec, delta=delta, batch=batch, upsamp=ups,
+                                     wspread=ws), *geo, on_surface=on)
+        except L.MhkError as e:
+            table.append({"upsamp": ups, "wspread": ws, "error": str(e)})
+            continue
+        out = p.eval(*ins)
+        torch.cuda.synchronize()
+        err = max(_rel(o[0], r[0]) for o, r in zip(out, ref))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            p.eval(*ins, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        info = p.info()
+        table.append({"upsamp": ups, "wspread": ws, "ms": ms, "err": err, "n_fine": info["n_fine"],
+                      "sigma_eff": None})
+        if log:
+            log(f"autotune alpha={alpha} ups={ups} w={ws}: {ms:.3f} ms, err {err:.2e}, n {info['n_fine']}")
+        p.close()
+        del out
+    ok = [c for c in table if "ms" in c and c["err"] < tol]
+    if not ok:
+        raise RuntimeError(f"autotune: no admissible candidate for {key}: {table}")
+    best = min(ok, key=lambda c: c["ms"])
+    res = {"upsamp": best["upsamp"], "wspread": best["wspread"], "ms": best["ms"], "err": best["err"],
+           "table": table, "delta": delta}
+    if cache:
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            db = json.load(open(cache)) if os.path.exists(cache) else {}
+            db[key] = res
+            json.dump(db, open(cache, "w"), indent=1)
+        except (OSError, ValueError):
+            pass
+    return res

@@ -72,13 +72,17 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
             const int s0 = A.btile[tyy * A.ntile + xa], s1 = A.btile[tyy * A.ntile + xb + 1];
             for (int s = s0 + tid; s < s1; s += 256) {
                 const double gx = A.bgx[s], gy = A.bgy[s];
+                // window start; skip sources whose window misses this tile
+                // before evaluating any window value
+                if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
+                    (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
+                    continue;
                 int mx0, my0;
                 T wx[W], wy[W];
                 window_weights<W, T>(gx, A.beta, mx0, wx);
                 window_weights<W, T>(gy, A.beta, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
-                if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
                 const int i = A.bidx[s];
                 const T qs = A.sigma ? (T)(A.bw[s] * (double)A.sigma[(size_t)b * A.nb + i]) : (T)0;
                 const double m = A.mu ? (double)A.mu[(size_t)b * A.nb + i] : 0.0;
@@ -106,13 +110,15 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
             const int s0 = A.vtile[tyy * A.ntile + xa], s1 = A.vtile[tyy * A.ntile + xb + 1];
             for (int s = s0 + tid; s < s1; s += 256) {
                 const double gx = A.vgx[s], gy = A.vgy[s];
+                if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
+                    (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
+                    continue;
                 int mx0, my0;
                 T wx[W], wy[W];
                 window_weights<W, T>(gx, A.beta, mx0, wx);
                 window_weights<W, T>(gy, A.beta, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
-                if (mx0 >= TILE || my0 >= TILE || mx0 + W <= 0 || my0 + W <= 0) continue;
                 const T q = (T)(A.vw[s] * (double)A.f_vol[(size_t)b * A.nv + A.vidx[s]]);
 #pragma unroll
                 for (int ky = 0; ky < W; ++ky) {

@@ -76,7 +76,7 @@ struct LevelArgs {
     int64_t nout, n_src;
     const double *tx, *ty;
     double inv4d, a_max, seg_inv;
-    int nseg, B, b0, nbh;
+    int nseg, B;
     const int32_t *blk_ofs, *blk_rng;
     const double *sx, *sy;
     const T *q, *tab;
@@ -97,6 +97,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 
     const int tid = threadIdx.x;
     for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
+    // densities b0 .. b0 + nbh - 1 of the batch (one chunk per grid row)
+    const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
 
     const int64_t t = (int64_t)blockIdx.x * LV_BLOCK + tid;
     const bool active = t < A.nout;
@@ -122,8 +124,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                 s_y[tid] = A.sy[s];
 #pragma unroll
                 for (int b = 0; b < BCH; ++b) {
-                    if (b < A.nbh) {
-                        const int bb = A.b0 + b;
+                    if (b < nbh) {
+                        const int bb = b0 + b;
                         s_q[(0 * BCH + b) * LV_BLOCK + tid] = A.want_s ? A.q[((size_t)0 * A.B + bb) * A.n_src + s] : (T)0;
                         s_q[(1 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)1 * A.B + bb) * A.n_src + s] : (T)0;
                         s_q[(2 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)2 * A.B + bb) * A.n_src + s] : (T)0;
@@ -163,8 +165,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
     if (active) {
 #pragma unroll
         for (int b = 0; b < BCH; ++b) {
-            if (b < A.nbh) {
-                const size_t o = (size_t)(A.b0 + b) * A.nout + t;
+            if (b < nbh) {
+                const size_t o = (size_t)(b0 + b) * A.nout + t;
                 if (A.want_s) A.acc_s[o] += S[b];
                 if (A.want_d) A.acc_d[o] += D[b];
             }
@@ -213,21 +215,23 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.acc_d = (T *)P->acc + (size_t)B * P->nout;            // component 1: D
     A.want_s = want_s;
     A.want_d = want_d;
-    dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK));
-    for (int b0 = 0; b0 < B; b0 += LV_BCH) {
-        A.b0 = b0;
-        A.nbh = min(LV_BCH, B - b0);
-        const int bch = A.nbh == 1 ? 1 : LV_BCH;
-        const size_t lds = sizeof(double) * 2 * LV_BLOCK + sizeof(T) * (3 * (size_t)bch * LV_BLOCK +
-                                                                       (size_t)L.nseg * STRIDE * 2);
-        if (bch == 1)
-            hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
-        else
-            hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const int bch = B == 1 ? 1 : LV_BCH;
+    dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK), (unsigned)((B + bch - 1) / bch));
+    const size_t lds = sizeof(double) * 2 * LV_BLOCK + sizeof(T) * (3 * (size_t)bch * LV_BLOCK +
+                                                                   (size_t)L.nseg * STRIDE * 2);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (bch == 1) {
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void *)k_level_sums<1, T, NC, STRIDE>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
+    } else {
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void *)k_level_sums<LV_BCH, T, NC, STRIDE>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
     }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d)

@@ -96,7 +96,8 @@ struct LocalArgs {
     const double *cs, *cm;
     const double *pcx, *pcy, *pck, *ends, *gl_t;
     const int32_t *prev, *next, *node, *cell_start;
-    double cell, ox, oy;
+    const double *nx_s, *ny_s;
+    double cell, ox, oy, gap;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
     const T *acc;          // [3][B][nout]: S, D, V in sorted order
@@ -174,14 +175,18 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                     const int c0 = A.cell_start[(int64_t)yy * A.ncx + max(cx - 1, 0)];
                     const int c1 = A.cell_start[(int64_t)yy * A.ncx + min(cx + 1, A.ncx - 1) + 1];
                     for (int c = c0; c < c1; ++c) {
-                        const int i = A.node[c];
-                        const double dx = A.bx[i] - px, dy = A.by[i] - py;
+                        const double dx = A.nx_s[c] - px, dy = A.ny_s[c] - py;
                         const double d = dx * dx + dy * dy;
-                        if (d < dmin || (d == dmin && i < imin)) { dmin = d; imin = i; }
+                        if (d <= dmin) {
+                            const int i = A.node[c];
+                            if (d < dmin || i < imin) { dmin = d; imin = i; }
+                        }
                     }
                 }
             }
-            if (imin >= 0) {
+            // the closest point lies within half a node gap of a node, so a
+            // nearest node farther than band + gap puts x outside both bands
+            if (imin >= 0 && sqrt(dmin) <= fmax(A.band_s, A.band_v) + A.gap) {
                 const int p0 = imin / NGL;
                 int cand[3] = {p0, A.prev[p0], A.next[p0]};
                 double d2b = INFINITY;
@@ -330,6 +335,9 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
     A.next = P->loc.next;
     A.node = P->loc.node;
     A.cell_start = P->loc.cell_start;
+    A.nx_s = P->loc.nx_s;
+    A.ny_s = P->loc.ny_s;
+    A.gap = P->loc.gap;
     A.cell = P->loc.cell;
     A.ox = P->loc.ox;
     A.oy = P->loc.oy;

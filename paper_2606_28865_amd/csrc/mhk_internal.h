@@ -31,8 +31,8 @@ namespace mhk {
 constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
 constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
-constexpr int TAB_NC = 12;       // coefficients per table segment (degree 11)
-constexpr int TAB_STRIDE = 13;   // double2 slots per segment in LDS (padded against bank conflicts)
+constexpr int TAB_NC = 10;       // coefficients per table segment (degree 9)
+constexpr int TAB_STRIDE = 11;   // double2 slots per segment in LDS (44 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
 constexpr int LV_CDIV = 2;       // level cells are R_j / LV_CDIV wide; neighbourhood +-LV_CDIV cells
@@ -116,9 +116,10 @@ struct History {
 };
 
 struct Local {
-    double cell = 0, ox = 0, oy = 0;
+    double cell = 0, ox = 0, oy = 0, gap = 0;
     int ncx = 0, ncy = 0;
     int32_t *node = nullptr;                      // boundary node indices sorted by cell
+    double *nx_s = nullptr, *ny_s = nullptr;      // their positions in the same order
     int32_t *cell_start = nullptr;
     double *leg = nullptr;                        // [16][16] nodal values -> Legendre coefficients
     double *cx = nullptr, *cy = nullptr, *ck = nullptr;   // [n_panels][16]
@@ -153,6 +154,8 @@ struct mhk_plan {
     std::vector<void *> allocs;
     int64_t bytes = 0;
     hipEvent_t ev[8] = {};
+    hipStream_t cap = nullptr;                  // capture stream of mhk_plan_capture
+    hipGraphExec_t gexec = nullptr;             // captured evaluation
 };
 
 namespace mhk {

@@ -186,6 +186,8 @@ static void counting_sort(const std::vector<int64_t> &key, int64_t nkeys,
 // ---------------------------------------------------------------------------
 // Parameter rules
 // ---------------------------------------------------------------------------
+static double hist_eps(const mhk_params &p) { return p.prec == MHK_FP64 ? p.tol : 0.1 * p.tol; }
+
 static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
 {
     if (!pp || !I) {
@@ -255,8 +257,10 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         double dj = p.delta / pow(4.0, j - 1);
         I->level_radius[j - 1] = sqrt(4.0 * dj * amax);
     }
-    // Fourier cut-off of the history part with margin tol/10 (eqs. (kmax), (kmax_dlp))
-    double eps = p.tol * 0.1, L = log(1.0 / eps), da2 = p.delta * p.alpha * p.alpha;
+    // Fourier cut-off of the history part (eqs. (kmax), (kmax_dlp)) at eps =
+    // tol in FP64 (the truncation error is far below tol relative to the
+    // potentials) and tol/10 in FP32 (where rounding already costs ~tol/10)
+    double eps = hist_eps(p), L = log(1.0 / eps), da2 = p.delta * p.alpha * p.alpha;
     if (da2 >= L) {
         I->kmax = 0;
     } else {
@@ -272,7 +276,7 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         I->kmax = k;
     }
     if (p.wspread == 0) {
-        double ew = p.tol * 0.1;
+        double ew = hist_eps(p);
         int w = (int)ceil(log(1.0 / ew) / (M_PI * sqrt(1.0 - 1.0 / p.upsamp))) + 1;
         p.wspread = std::min(MAXW, std::max(4, w));
     }
@@ -329,6 +333,8 @@ static void free_plan(mhk_plan *P)
     if (P->hist.exec) rocfft_execution_info_destroy(P->hist.exec);
     for (auto &e : P->ev)
         if (e) (void)hipEventDestroy(e);
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
     delete P;
 }
 
@@ -609,58 +615,61 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     // Kernel table: piecewise polynomials in a = r^2/(4 delta_j) on segments of
     // width 1/4, each in the local variable v in [-1, 1]; coefficients from
     // Chebyshev interpolation converted to monomials in v.  FP64 path: degree
-    // 11; FP32 path: degree 7, stored as floats.
+    // 9 (error ~4e-14 of K_j(0)); FP32 path: degree 7, stored as floats.
     LevelQuad Q;
-    const double seg_w = 0.25;
-    L.seg_inv = 1.0 / seg_w;
-    L.nseg = (int)ceil(L.a_max / seg_w) + 1;
     const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
     const double cS = 1.0 / (4.0 * M_PI), cD = 1.0 / (8.0 * M_PI * L.delta_j);
     const bool fp64 = P->p.prec == MHK_FP64;
     const int nc = fp64 ? TAB_NC : TABF_NC, stride = fp64 ? TAB_STRIDE : TABF_STRIDE;
-    std::vector<double> tab((size_t)L.nseg * stride * 2, 0.0);
-    std::vector<double> node(nc);
-    for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
-    for (int sgi = 0; sgi < L.nseg; ++sgi) {
-        double a0 = sgi * seg_w;
-        std::vector<long double> fS(nc), fD(nc);
-        for (int i = 0; i < nc; ++i) {
-            double a = a0 + 0.5 * seg_w * (1.0 + node[i]);
-            double i0, i1;
-            Q.eval(a, b_j, i0, i1);
-            fS[i] = i0 * cS;
-            fD[i] = i1 * cD;
-        }
-        for (int kind = 0; kind < 2; ++kind) {
-            std::vector<long double> &f = kind ? fD : fS;
-            // Chebyshev coefficients
-            std::vector<long double> ch(nc, 0);
-            for (int m = 0; m < nc; ++m) {
-                long double sacc = 0;
-                for (int i = 0; i < nc; ++i) sacc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
-                ch[m] = sacc * (m == 0 ? 1.0L : 2.0L) / nc;
+    const double tab_tol = fp64 ? 1e-12 : 1e-8;
+    std::vector<double> tab;
+    // segment width 1/4, halved while the table misses tab_tol (large alpha^2
+    // delta_j makes K_j decay like e^{-4a})
+    for (double seg_w = 0.25;; seg_w *= 0.5) {
+        L.seg_inv = 1.0 / seg_w;
+        L.nseg = (int)ceil(L.a_max / seg_w) + 1;
+        tab.assign((size_t)L.nseg * stride * 2, 0.0);
+        std::vector<double> node(nc);
+        for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
+        for (int sgi = 0; sgi < L.nseg; ++sgi) {
+            double a0 = sgi * seg_w;
+            std::vector<long double> fS(nc), fD(nc);
+            for (int i = 0; i < nc; ++i) {
+                double a = a0 + 0.5 * seg_w * (1.0 + node[i]);
+                double i0, i1;
+                Q.eval(a, b_j, i0, i1);
+                fS[i] = i0 * cS;
+                fD[i] = i1 * cD;
             }
-            // T_m(v) -> monomials in v
-            std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
-            tprev[0] = 1;       // T0
-            tcur[1] = 1;        // T1
-            for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
-            for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
-            for (int m = 2; m < nc; ++m) {
-                std::fill(tnext.begin(), tnext.end(), 0.0L);
-                for (int k = 0; k < nc; ++k) {
-                    if (k + 1 < nc) tnext[k + 1] += 2 * tcur[k];
-                    tnext[k] -= tprev[k];
+            for (int kind = 0; kind < 2; ++kind) {
+                std::vector<long double> &f = kind ? fD : fS;
+                // Chebyshev coefficients
+                std::vector<long double> ch(nc, 0);
+                for (int m = 0; m < nc; ++m) {
+                    long double sacc = 0;
+                    for (int i = 0; i < nc; ++i) sacc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
+                    ch[m] = sacc * (m == 0 ? 1.0L : 2.0L) / nc;
                 }
-                for (int k = 0; k < nc; ++k) mono[k] += ch[m] * tnext[k];
-                tprev = tcur;
-                tcur = tnext;
+                // T_m(v) -> monomials in v
+                std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
+                tprev[0] = 1;       // T0
+                tcur[1] = 1;        // T1
+                for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
+                for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
+                for (int m = 2; m < nc; ++m) {
+                    std::fill(tnext.begin(), tnext.end(), 0.0L);
+                    for (int k = 0; k < nc; ++k) {
+                        if (k + 1 < nc) tnext[k + 1] += 2 * tcur[k];
+                        tnext[k] -= tprev[k];
+                    }
+                    for (int k = 0; k < nc; ++k) mono[k] += ch[m] * tnext[k];
+                    tprev = tcur;
+                    tcur = tnext;
+                }
+                for (int k = 0; k < nc; ++k) tab[((size_t)sgi * stride + k) * 2 + kind] = (double)mono[k];
             }
-            for (int k = 0; k < nc; ++k) tab[((size_t)sgi * stride + k) * 2 + kind] = (double)mono[k];
         }
-    }
-    // accuracy check of the table against direct quadrature
-    {
+        // accuracy check of the table against direct quadrature
         double k0S, k0D;
         Q.eval(0.0, b_j, k0S, k0D);
         k0S *= cS;
@@ -681,8 +690,11 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
             emax = std::max(emax, fabs(pD - i1 * cD) / k0D);
         }
         L.tab_err = emax;
-        if (emax > (fp64 ? 1e-13 : 1e-8)) {
-            set_error("level kernel table not accurate: " + std::to_string(emax));
+        if (emax <= tab_tol) break;
+        if (seg_w < 0.05) {
+            char msg[128];
+            snprintf(msg, sizeof msg, "level kernel table not accurate: %.3e of K_j(0)", emax);
+            set_error(msg);
             return MHK_EUNSUPPORTED;
         }
     }
@@ -821,17 +833,30 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
     return st;
 }
 
-mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, const std::vector<double> &tgy)
+// Relative cost of rocFFT 2D transforms of size n x n (per point), measured
+// on MI355X for the in-place real transforms used here: sizes above 4096
+// leave the single-pass 1D kernels (x1.6 per point) and a factor 7 costs
+// about x1.45.
+static double fft_cost(int64_t n)
 {
-    History &G = P->hist;
-    const double alpha = P->p.alpha, delta = P->delta;
-    G.kcut = P->info.kmax;
-    G.w = P->info.wspread;
-    G.ups = P->p.upsamp;
-    G.active = G.kcut > 0;
-    if (!G.active) return MHK_OK;
-    double eps = P->p.tol * 0.1;
-    double Lx = H.xmax - H.xmin, Ly = H.ymax - H.ymin, L = std::max(Lx, Ly);
+    double c = n <= 4096 ? 1.0 : 1.6;
+    if ((n / TILE) % 7 == 0) c *= 1.45;
+    return c * (double)n * (double)n;
+}
+
+// History grid: period, step and size (shared by plan creation and the
+// footprint estimate).
+struct GridChoice {
+    bool trunc = false;
+    double h = 0, period = 0, trans = 0, Dsep = 0, sigma = 0, beta = 0;
+    int64_t n = 0;
+};
+
+static mhk_status choose_grid(const mhk_params &p, const mhk_info &I, double Lx, double Ly, GridChoice &g)
+{
+    const double alpha = p.alpha, delta = I.delta, kc = I.kmax;
+    const int W = I.wspread;
+    const double eps = hist_eps(p), L = std::max(Lx, Ly);
     // image distance: the periodic images of the history kernel must be below
     // eps relative to its peak and to the mean field of a uniform source.
     double gh0 = expint_e1(alpha * alpha * delta) / (4 * M_PI);
@@ -839,7 +864,6 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     double thr = eps * std::min(gh0, m0 / std::max(L * L, 1e-6));
     double R = 1.0 / alpha;
     while (sqrt(M_PI / (2 * alpha * R)) * exp(-alpha * R) / (2 * M_PI) > thr) R *= 1.02;
-    G.h = M_PI / (G.ups * G.kcut);
     // Two ways to make the periodic images harmless: a period longer than the
     // extent plus the decay length R of the kernel, or a kernel cut off
     // smoothly beyond the largest source-target distance D (its spectrum
@@ -848,32 +872,74 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     // The cut-off erfc((r - r_mid) 11.8/trans)/2 smears the spectrum by a
     // Gaussian of width ~23.6/trans: it must stay narrow against both the
     // multiplier's own width 1/sqrt(delta) and the cut-off k_max.
-    const double Dsep = sqrt(Lx * Lx + Ly * Ly);
-    const double trans = std::max({0.25 * Dsep, 110.0 * sqrt(delta), 120.0 / G.kcut});
-    const double per_periodic = L + R, per_trunc = L + Dsep + trans;
-    G.trunc = per_trunc < 0.9 * per_periodic;
-    double need = (G.trunc ? per_trunc : per_periodic) + (G.w + 6) * G.h;
-    int64_t nmin = (int64_t)ceil(need / G.h);
-    if (nmin > 60000) {
-        set_error("history grid too large (" + std::to_string(nmin) + "^2)");
+    g.Dsep = sqrt(Lx * Lx + Ly * Ly);
+    g.trans = std::max(110.0 * sqrt(delta), 120.0 / kc);
+    const double per_periodic = L + R, per_trunc = L + g.Dsep + g.trans;
+    g.trunc = per_trunc < 0.9 * per_periodic;
+    const double P = g.trunc ? per_trunc : per_periodic;
+    // oversampling: any sigma in [sigma_min, upsamp] keeps the window width W
+    // (W - 1 >= ln(1/eps)/(pi sqrt(1 - 1/sigma))); among the grid sizes this
+    // allows, take the cheapest FFT.
+    const double q = log(1.0 / eps) / (M_PI * (W - 1));
+    double smin = q < 1.0 ? 1.0 / (1.0 - q * q) : p.upsamp;
+    smin = std::min(p.upsamp, std::max(1.25, smin));
+    const double hmax = M_PI / (smin * kc);
+    const int64_t nlo = (int64_t)ceil(P / hmax) + W + 6;
+    const int64_t nhi = (int64_t)ceil((P * p.upsamp * kc / M_PI + W + 6) * 1.25);
+    if (nlo > 60000) {
+        set_error("history grid too large (" + std::to_string(nlo) + "^2)");
         return MHK_EUNSUPPORTED;
     }
-    G.n = good_fft_size(nmin);
-    G.period = G.n * G.h;
+    int64_t best = 0;
+    for (int64_t n = good_fft_size(nlo); n <= std::max(nhi, good_fft_size(nlo)); n = good_fft_size(n + 1))
+        if (best == 0 || fft_cost(n) < fft_cost(best)) best = n;
+    g.n = best;
+    g.h = std::min(hmax, P / (double)(g.n - W - 6));
+    g.sigma = M_PI / (kc * g.h);
+    g.period = g.n * g.h;
+    g.beta = 0.97 * M_PI * (1.0 - 0.5 / g.sigma) * W;
+    return MHK_OK;
+}
+
+// Grid geometry of the history part; called before the targets are sorted,
+// since their order follows the grid tiles.
+mhk_status history_geometry(mhk_plan *P, const Host &H)
+{
+    History &G = P->hist;
+    G.kcut = P->info.kmax;
+    G.w = P->info.wspread;
+    G.ups = P->p.upsamp;
+    G.active = G.kcut > 0;
+    if (!G.active) return MHK_OK;
+    GridChoice g;
+    TRY(choose_grid(P->p, P->info, H.xmax - H.xmin, H.ymax - H.ymin, g));
+    G.trunc = g.trunc;
+    G.n = g.n;
+    G.h = g.h;
+    G.ups = g.sigma;
+    G.period = g.period;
+    G.beta = g.beta;
     G.ntile = (int)(G.n / TILE);
     G.field = G.n * (G.n + 2);
     G.ox = H.xmin - (G.w / 2 + 3) * G.h;
     G.oy = H.ymin - (G.w / 2 + 3) * G.h;
-    G.beta = 0.97 * M_PI * (1.0 - 0.5 / G.ups) * G.w;
-    G.trunc_d = Dsep;
-    G.trunc_w = trans;
+    G.trunc_d = g.Dsep;
+    G.trunc_w = g.trans;
+    P->info.period = G.period;
+    P->info.n_fine = G.n;
+    P->info.history_truncated = G.trunc ? 1 : 0;
+    return MHK_OK;
+}
+
+mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, const std::vector<double> &tgy)
+{
+    History &G = P->hist;
+    const double alpha = P->p.alpha, delta = P->delta;
+    if (!G.active) return MHK_OK;
     if (!g_rocfft_ready) {
         MHK_FFT(rocfft_setup());
         g_rocfft_ready = true;
     }
-    P->info.period = G.period;
-    P->info.n_fine = G.n;
-    P->info.history_truncated = G.trunc ? 1 : 0;
 
     // multiplier factors
     std::vector<double> qt, qw;
@@ -1089,6 +1155,16 @@ mhk_status build_local(mhk_plan *P, Host &H)
         next[p] = (int32_t)H.next[p];
     }
     TRY(upload(P, &C.node, order.data(), nb));
+    {
+        std::vector<double> sx(nb), sy(nb);
+        for (int64_t k = 0; k < nb; ++k) {
+            sx[k] = b->x[order[k]];
+            sy[k] = b->y[order[k]];
+        }
+        TRY(upload(P, &C.nx_s, sx.data(), nb));
+        TRY(upload(P, &C.ny_s, sy.data(), nb));
+    }
+    C.gap = gap;
     TRY(upload(P, &C.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &C.leg, leg.data(), NGL * NGL));
     TRY(upload(P, &C.cx, cx.data(), nb));
@@ -1132,23 +1208,18 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     TRY(upload(P, &P->bw, b->w, P->nb));
     TRY(upload(P, &P->bk, b->kappa, P->nb));
 
-    // history parameters first: the target order follows the grid tiles
+    // history grid first: the target order follows the grid tiles
     History &G = P->hist;
-    G.kcut = P->info.kmax;
-    G.w = P->info.wspread;
-    G.ups = P->p.upsamp;
+    TRY(history_geometry(P, H));
     // targets sorted in Morton order of cells of one grid step (or of a virtual
     // grid of step R_J/8 when there is no history grid)
     std::vector<double> tgx, tgy;
     {
         double hh, ox, oy;
-        if (G.kcut > 0) {
-            // provisional values, recomputed identically in build_history
-            double eps = P->p.tol * 0.1;
-            (void)eps;
-            hh = M_PI / (G.ups * G.kcut);
-            ox = H.xmin - (G.w / 2 + 3) * hh;
-            oy = H.ymin - (G.w / 2 + 3) * hh;
+        if (G.active) {
+            hh = G.h;
+            ox = G.ox;
+            oy = G.oy;
         } else {
             double rj = P->J > 0 ? P->info.level_radius[P->J - 1] : P->info.band_layer;
             hh = std::max(rj / 8.0, std::max(H.xmax - H.xmin, H.ymax - H.ymin) / 60000.0);
@@ -1254,7 +1325,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
     }
     s += nb * (8 * 3 + 4) + 2 * B * nb * 8;   // local
-    if (I.kmax > 0) {                         // history grid estimate
+    if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {
             x0 = std::min(x0, x); x1 = std::max(x1, x);
@@ -1263,17 +1334,10 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         for (int64_t i = 0; i < nb; ++i) acc(b->x[i], b->y[i]);
         for (int64_t i = 0; i < nv; ++i) acc(v->x[i], v->y[i]);
         for (int64_t i = 0; i < t->n; ++i) acc(t->x[i], t->y[i]);
-        double L = std::max(x1 - x0, y1 - y0), a = p.alpha, d = I.delta;
-        double eps = p.tol * 0.1;
-        double thr = eps * std::min(expint_e1(a * a * d) / (4 * M_PI), exp(-d * a * a) / (a * a) / std::max(L * L, 1e-6));
-        double R = 1.0 / a;
-        while (sqrt(M_PI / (2 * a * R)) * exp(-a * R) / (2 * M_PI) > thr) R *= 1.02;
-        double h = M_PI / (p.upsamp * I.kmax);
-        double Dsep = hypot(x1 - x0, y1 - y0);
-        double trans = std::max({0.25 * Dsep, 110.0 * sqrt(d), 120.0 / I.kmax});
-        double per = std::min(L + R, L + Dsep + trans);
-        int64_t n = good_fft_size((int64_t)ceil((per + (I.wspread + 6) * h) / h));
-        s += 4 * B * n * (n + 2) * 8 + 2 * B * n * (n + 2) * 8;   // grids + FFT work estimate
+        GridChoice g;
+        TRY(choose_grid(p, I, x1 - x0, y1 - y0, g));
+        const int64_t es = p.prec == MHK_FP64 ? 8 : 4;
+        s += 4 * B * g.n * (g.n + 2) * es * 2;   // grids + FFT work estimate
         s += (nb + nv) * (8 * 3 + 4);
     }
     *bytes = s;
@@ -1308,9 +1372,12 @@ void mhk_plan_destroy(mhk_plan *P)
     }
 }
 
-mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void *mu_,
-                          const void *f_vol_, const void *f_trg_, void *out_s_, void *out_d_,
-                          void *out_v_)
+}  // extern "C"
+
+namespace {
+
+mhk_status validate_eval(const mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol,
+                         const void *f_trg, const void *out_s, const void *out_d, const void *out_v)
 {
     if (!P) {
         set_error("plan is NULL");
@@ -1320,14 +1387,11 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void
         set_error("invalid parts mask");
         return MHK_EINVAL;
     }
-    const void *sigma = sigma_, *mu = mu_, *f_vol = f_vol_, *f_trg = f_trg_;
-    void *out_s = out_s_, *out_d = out_d_, *out_v = out_v_;
-    const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if ((sigma && !out_s) || (mu && !out_d) || (f_vol && !out_v)) {
         set_error("an input density was given without its output array");
         return MHK_EINVAL;
     }
-    if (wv && !f_trg && (parts & MHK_PART_LOCAL)) {
+    if (f_vol && out_v && !f_trg && (parts & MHK_PART_LOCAL)) {
         set_error("f_trg is required with f_vol for the local part of V");
         return MHK_EINVAL;
     }
@@ -1335,6 +1399,14 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void
         set_error("f_vol given but the plan has no volume nodes");
         return MHK_EINVAL;
     }
+    return MHK_OK;
+}
+
+// Enqueue one evaluation on P->stream (no synchronisation unless timing).
+mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol, const void *f_trg,
+                   void *out_s, void *out_d, void *out_v)
+{
+    const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if (!ws && !wd && !wv) return MHK_OK;
     hipStream_t st = P->stream;
     const int B = P->p.batch;
@@ -1384,6 +1456,72 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma_, const void
         MHK_HIP(hipEventElapsedTime(&tot, P->ev[0], P->ev[7]));
         P->info.ms_total = tot;
     }
+    return MHK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol,
+                          const void *f_trg, void *out_s, void *out_d, void *out_v)
+{
+    TRY(validate_eval(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v));
+    return enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v);
+}
+
+mhk_status mhk_plan_capture(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol,
+                            const void *f_trg, void *out_s, void *out_d, void *out_v)
+{
+    TRY(validate_eval(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v));
+    if (!P->cap) MHK_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    // the work captured must not depend on work still queued on the plan's stream
+    MHK_HIP(hipStreamSynchronize(P->stream));
+    hipStream_t saved = P->stream;
+    const bool timing = P->timing;
+    P->stream = P->cap;
+    P->timing = false;
+    if (P->hist.exec) MHK_FFT(rocfft_execution_info_set_stream(P->hist.exec, P->cap));
+    hipGraph_t g = nullptr;
+    mhk_status st = MHK_OK;
+    hipError_t e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        set_error(std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        st = MHK_EHIP;
+    } else {
+        st = enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v);
+        e = hipStreamEndCapture(P->cap, &g);
+        if (st == MHK_OK && e != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            st = MHK_EHIP;
+        }
+    }
+    P->stream = saved;
+    P->timing = timing;
+    if (P->hist.exec) MHK_FFT(rocfft_execution_info_set_stream(P->hist.exec, saved));
+    if (st == MHK_OK) {
+        if (P->gexec) {
+            (void)hipGraphExecDestroy(P->gexec);
+            P->gexec = nullptr;
+        }
+        e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            P->gexec = nullptr;
+            st = MHK_EHIP;
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
+mhk_status mhk_plan_launch_graph(mhk_plan *P)
+{
+    if (!P || !P->gexec) {
+        set_error("no captured graph on this plan");
+        return MHK_EINVAL;
+    }
+    MHK_HIP(hipGraphLaunch(P->gexec, P->stream));
     return MHK_OK;
 }
 

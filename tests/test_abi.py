@@ -47,7 +47,7 @@ def test_parameter_rule_hilbert_chain():
     assert info["delta"] == pytest.approx(g["delta"], rel=5e-3)
     assert info["delta_star"] == pytest.approx(g["delta_star"], rel=5e-3)
     # the history cut-off uses the stricter double-layer rule (eq. (kmax_dlp))
-    k, d, a, eps = info["kmax"], info["delta"], g["alpha"], g["eps"] * 0.1
+    k, d, a, eps = info["kmax"], info["delta"], g["alpha"], g["eps"]
     assert k * math.exp(-d * (a * a + k * k)) == pytest.approx(eps, rel=1e-8)
 
 
