@@ -12,8 +12,8 @@
 //   FFT       rocFFT complex-to-real, in place;
 //   interp    u(x) = sum_m phi(x - x_m) U_m.
 //
-// Spreading: one workgroup owns one 32x32 tile of the fine grid and one
-// density of the batch.  It visits the sources of the 3x3 neighbouring tiles
+// Spreading: one workgroup (1024 threads) owns one 32x32 tile of the fine
+// grid and one density of the batch.  It visits the sources of the 3x3 neighbouring tiles
 // (sorted by tile at plan time), adds the part of each source's w x w window
 // that falls in its own tile into LDS with LDS atomics, and writes the tile
 // once: every grid value is written exactly once, with no global atomics.
@@ -23,6 +23,9 @@
 
 namespace mhk {
 
+// threads per spreading / interpolation workgroup: the sources (targets) sit
+// in a few hundred busy tiles, so each tile gets 16 wavefronts
+constexpr int HB = 1024;
 
 template <typename T>
 struct SpreadArgs {
@@ -34,34 +37,37 @@ struct SpreadArgs {
     const double *vgx, *vgy, *vw;
     const int32_t *vidx, *vtile;
     const T *sigma, *mu, *f_vol;
+    const T *wcoef;
     T *grid;               // [4][B][field]: S, V, Dx, Dy sources
 };
 
 // Window values phi(z_k), z_k = (m0 + k - g) 2/W, at the W grid points from
-// m0 = ceil(g - W/2).  The offset m0 - g is formed in FP64; in the FP32 path
-// the window itself is evaluated in FP32.
+// m0 = ceil(g - W/2), from the per-point polynomials in t = 2(m0 - g + W/2) - 1
+// (degree W + 3, Horner; the coefficients are the same for every lane and are
+// read as scalars).  The offset is formed in FP64.
 template <int W, typename T>
-__device__ inline void window_weights(double g, double beta, int &m0, T *wt)
+__device__ inline void window_weights(double g, const T *__restrict__ cf, int &m0, T *wt)
 {
+    constexpr int D = W + 3;
     m0 = (int)ceil(g - 0.5 * W);
-    const T off = (T)((double)m0 - g);
-    const T sc = (T)2 / (T)W, bt = (T)beta;
+    const T t = (T)(2.0 * ((double)m0 - g + 0.5 * W) - 1.0);
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        const T z = (off + (T)k) * sc;
-        const T z2 = (T)1 - z * z;
-        wt[k] = (z2 > (T)0) ? exp(bt * (sqrt(z2) - (T)1)) : (T)0;
+        T p = cf[k * (D + 1) + D];
+#pragma unroll
+        for (int j = D - 1; j >= 0; --j) p = fma(p, t, cf[k * (D + 1) + j]);
+        wt[k] = p;
     }
 }
 
 template <int W, typename T>
-__global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
+__global__ void __launch_bounds__(HB) k_spread(SpreadArgs<T> A)
 {
     __shared__ T tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
     const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const int tx = tile % A.ntile, ty = tile / A.ntile;
     const int x0 = tx * TILE, y0 = ty * TILE;
-    for (int i = tid; i < TILE * TILE; i += 256) tileS[i] = tileV[i] = tileX[i] = tileY[i] = (T)0;
+    for (int i = tid; i < TILE * TILE; i += HB) tileS[i] = tileV[i] = tileX[i] = tileY[i] = (T)0;
     __syncthreads();
     const bool has_b = A.sigma || A.mu;
     for (int dty = -1; dty <= 1; ++dty) {
@@ -70,7 +76,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
         const int xa = max(tx - 1, 0), xb = min(tx + 1, A.ntile - 1);
         if (has_b) {
             const int s0 = A.btile[tyy * A.ntile + xa], s1 = A.btile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += 256) {
+            for (int s = s0 + tid; s < s1; s += HB) {
                 const double gx = A.bgx[s], gy = A.bgy[s];
                 // window start; skip sources whose window misses this tile
                 // before evaluating any window value
@@ -79,8 +85,8 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
                     continue;
                 int mx0, my0;
                 T wx[W], wy[W];
-                window_weights<W, T>(gx, A.beta, mx0, wx);
-                window_weights<W, T>(gy, A.beta, my0, wy);
+                window_weights<W, T>(gx, A.wcoef, mx0, wx);
+                window_weights<W, T>(gy, A.wcoef, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
                 const int i = A.bidx[s];
@@ -108,15 +114,15 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
         }
         if (A.f_vol) {
             const int s0 = A.vtile[tyy * A.ntile + xa], s1 = A.vtile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += 256) {
+            for (int s = s0 + tid; s < s1; s += HB) {
                 const double gx = A.vgx[s], gy = A.vgy[s];
                 if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
                     (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
                     continue;
                 int mx0, my0;
                 T wx[W], wy[W];
-                window_weights<W, T>(gx, A.beta, mx0, wx);
-                window_weights<W, T>(gy, A.beta, my0, wy);
+                window_weights<W, T>(gx, A.wcoef, mx0, wx);
+                window_weights<W, T>(gy, A.wcoef, my0, wy);
                 mx0 -= x0;
                 my0 -= y0;
                 const T q = (T)(A.vw[s] * (double)A.f_vol[(size_t)b * A.nv + A.vidx[s]]);
@@ -138,7 +144,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T> A)
     __syncthreads();
     const size_t fs = (size_t)A.B * A.field;
     T *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
-    for (int i = tid; i < TILE * TILE; i += 256) {
+    for (int i = tid; i < TILE * TILE; i += HB) {
         const size_t o = (size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE);
         gS[o] = tileS[i];
         gV[o] = tileV[i];
@@ -196,12 +202,13 @@ struct InterpArgs {
     const int32_t *tile_xy, *tile_rng;
     const double *tx, *ty;
     const T *grid;         // [3][B][field]: S, V, D results
+    const T *wcoef;
     T *acc;                // [3][B][nout]: S, D, V
     int want_s, want_d, want_v;
 };
 
 template <int W, typename T>
-__global__ void __launch_bounds__(256) k_interp(InterpArgs<T> A)
+__global__ void __launch_bounds__(HB) k_interp(InterpArgs<T> A)
 {
     constexpr int RS = TILE + W + 2;
     __shared__ T reg[3][RS * RS];
@@ -211,7 +218,7 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T> A)
     const int rx0 = tx * TILE - W / 2 - 1, ry0 = ty * TILE - W / 2 - 1;
     const size_t fs = (size_t)A.B * A.field;
     const T *g0 = A.grid + (size_t)b * A.field;
-    for (int i = tid; i < RS * RS; i += 256) {
+    for (int i = tid; i < RS * RS; i += HB) {
         int gy = ry0 + i / RS, gx = rx0 + i % RS;
         gy = (int)(((int64_t)gy % A.n + A.n) % A.n);
         gx = (int)(((int64_t)gx % A.n + A.n) % A.n);
@@ -222,12 +229,12 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T> A)
     }
     __syncthreads();
     const int s0 = A.tile_rng[t], s1 = A.tile_rng[t + 1];
-    for (int s = s0 + tid; s < s1; s += 256) {
+    for (int s = s0 + tid; s < s1; s += HB) {
         const double gx = (A.tx[s] - A.ox) / A.h, gy = (A.ty[s] - A.oy) / A.h;
         int mx0, my0;
         T wx[W], wy[W];
-        window_weights<W, T>(gx, A.beta, mx0, wx);
-        window_weights<W, T>(gy, A.beta, my0, wy);
+        window_weights<W, T>(gx, A.wcoef, mx0, wx);
+        window_weights<W, T>(gy, A.wcoef, my0, wy);
         const int lx = min(max(mx0 - rx0, 0), RS - W), ly = min(max(my0 - ry0, 0), RS - W);
         T uS = 0, uV = 0, uD = 0;
 #pragma unroll 1
@@ -337,7 +344,7 @@ template <int W, typename T>
 static hipError_t spread_w(mhk_plan *P, const SpreadArgs<T> &A)
 {
     dim3 grid((unsigned)(A.ntile * A.ntile), (unsigned)A.B);
-    hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(256), 0, P->stream, A);
+    hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(HB), 0, P->stream, A);
     return hipGetLastError();
 }
 
@@ -346,7 +353,7 @@ static hipError_t interp_w(mhk_plan *P, const InterpArgs<T> &A)
 {
     if (P->hist.n_ttiles == 0) return hipSuccess;
     dim3 grid((unsigned)P->hist.n_ttiles, (unsigned)A.B);
-    hipLaunchKernelGGL((k_interp<W, T>), grid, dim3(256), 0, P->stream, A);
+    hipLaunchKernelGGL((k_interp<W, T>), grid, dim3(HB), 0, P->stream, A);
     return hipGetLastError();
 }
 
@@ -387,6 +394,7 @@ static hipError_t spread_t(mhk_plan *P, const void *sigma, const void *mu, const
     A.mu = (const T *)mu;
     A.f_vol = (const T *)f_vol;
     A.grid = (T *)G.grid;
+    A.wcoef = (const T *)G.wcoef;
     MHK_W_SWITCH(G.w, spread_w, T, P, A);
 }
 
@@ -430,6 +438,7 @@ static hipError_t interp_t(mhk_plan *P, bool want_s, bool want_d, bool want_v)
     A.tx = P->tx;
     A.ty = P->ty;
     A.grid = (const T *)G.grid;
+    A.wcoef = (const T *)G.wcoef;
     A.acc = (T *)P->acc;
     A.want_s = want_s;
     A.want_d = want_d;

@@ -7,15 +7,16 @@
 // read from a piecewise-polynomial table in a = r^2/(4 delta_j) held in LDS;
 // pairs with a >= a_max are below the requested accuracy and skipped.
 //
-// Work decomposition: a workgroup owns 256 consecutive targets of the Morton
+// Work decomposition: a wavefront owns 64 consecutive targets of the Morton
 // order.  At plan time the union of its targets' cell neighbourhoods (cells
 // of side R_j/2, +-2 cells) is turned into a short list of ranges of the
-// cell-sorted sources.  Sources are staged through LDS in blocks of 256 and
-// read back by broadcast, so every candidate source is loaded once per
-// workgroup, and each lane keeps its target's sums in registers: no atomics,
-// deterministic summation order.  The kernel table sits in LDS with a padded
-// segment stride so that the per-lane gathers of different segments spread
-// over the LDS banks.
+// cell-sorted sources.  The wavefront walks these ranges with wave-uniform
+// indices, so each source is read once per wavefront with scalar loads and
+// broadcast to the lanes; each lane keeps its target's sums in registers: no
+// atomics, no barriers in the loop, deterministic summation order.  The
+// kernel table sits in LDS (shared by the 4 wavefronts of a workgroup) with a
+// padded segment stride so that the per-lane gathers of different segments
+// spread over the LDS banks.
 //
 // Precision: T = double (FP64 path) or float (FP32 path).  In the FP32 path
 // the separation x - x_q is formed in FP64 from FP64 positions and rounded
@@ -77,7 +78,7 @@ struct LevelArgs {
     const double *tx, *ty;
     double inv4d, a_max, seg_inv;
     int nseg, B;
-    const int32_t *blk_ofs, *blk_rng;
+    const int32_t *blk_ofs, *blk_rng, *wave_order;
     const double *sx, *sy;
     const T *q, *tab;
     T *acc_s, *acc_d;     // [B][nout] each (sorted order)
@@ -90,76 +91,100 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
     typedef typename Vec2<T>::type T2;
     extern __shared__ double lds[];
-    double *s_x = lds;                                    // [LV_BLOCK]
-    double *s_y = s_x + LV_BLOCK;
-    T *s_q = reinterpret_cast<T *>(s_y + LV_BLOCK);       // [3*BCH][LV_BLOCK]
-    T *s_tab = s_q + 3 * BCH * LV_BLOCK;                  // [nseg][STRIDE][2]
-
+    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg][STRIDE][2]
     const int tid = threadIdx.x;
     for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
-    // densities b0 .. b0 + nbh - 1 of the batch (one chunk per grid row)
-    const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
+    __syncthreads();
 
-    const int64_t t = (int64_t)blockIdx.x * LV_BLOCK + tid;
+    // one wavefront = LV_WAVE consecutive targets with their own source ranges;
+    // every index below derived from the wave number is wave-uniform, so the
+    // source data is read with scalar loads and broadcast to the lanes
+    const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (LV_BLOCK / LV_WAVE) + tid / LV_WAVE]);
+    const int64_t t = (int64_t)wave * LV_WAVE + (tid % LV_WAVE);
     const bool active = t < A.nout;
     double x = 0, y = 0;
     if (active) {
         x = A.tx[t];
         y = A.ty[t];
     }
+    const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
     const T inv4d = (T)A.inv4d, a_max = (T)A.a_max, seg_inv = (T)A.seg_inv;
     T S[BCH], D[BCH];
 #pragma unroll
     for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
+    const T *qs[BCH], *qx[BCH], *qy[BCH];
+#pragma unroll
+    for (int b = 0; b < BCH; ++b) {
+        const int bb = b0 + min(b, nbh - 1);
+        qs[b] = A.q + ((size_t)0 * A.B + bb) * A.n_src;
+        qx[b] = A.q + ((size_t)1 * A.B + bb) * A.n_src;
+        qy[b] = A.q + ((size_t)2 * A.B + bb) * A.n_src;
+    }
 
-    const int r0 = A.blk_ofs[blockIdx.x], r1 = A.blk_ofs[blockIdx.x + 1];
+    // one source pair-evaluation
+    auto pair = [&](double sxv, double syv, const T *qsv, const T *qxv, const T *qyv) {
+        const T dx = (T)(x - sxv), dy = (T)(y - syv);
+        const T a = (dx * dx + dy * dy) * inv4d;
+        if (a < a_max) {
+            const T f = a * seg_inv;
+            const int sg = (int)f;
+            const T v = (T)2 * (f - (T)sg) - (T)1;
+            const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
+            T2 cc = c[NC - 1];
+            T ks = cc.x, kd = cc.y;
+#pragma unroll
+            for (int k = NC - 2; k >= 0; --k) {
+                cc = c[k];
+                ks = fma(ks, v, cc.x);
+                kd = fma(kd, v, cc.y);
+            }
+#pragma unroll
+            for (int b = 0; b < BCH; ++b) {
+                S[b] = fma(qsv[b], ks, S[b]);
+                D[b] = fma(fma(qxv[b], dx, qyv[b] * dy), kd, D[b]);
+            }
+        }
+    };
+    // sources are fetched PF at a time, one batch ahead of their use
+    constexpr int PF = 4;
+    const int r0 = A.blk_ofs[wave], r1 = A.blk_ofs[wave + 1];
     for (int r = r0; r < r1; ++r) {
         const int s0 = A.blk_rng[2 * r], s1 = A.blk_rng[2 * r + 1];
-        for (int c0 = s0; c0 < s1; c0 += LV_BLOCK) {
-            const int m = min(LV_BLOCK, s1 - c0);
-            __syncthreads();
-            if (tid < m) {
-                const int64_t s = c0 + tid;
-                s_x[tid] = A.sx[s];
-                s_y[tid] = A.sy[s];
+        double nx[PF], ny[PF];
+        T nqs[PF][BCH], nqx[PF][BCH], nqy[PF][BCH];
+        auto fetch = [&](int base) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int s = min(base + k, s1 - 1);
+                nx[k] = A.sx[s];
+                ny[k] = A.sy[s];
 #pragma unroll
                 for (int b = 0; b < BCH; ++b) {
-                    if (b < nbh) {
-                        const int bb = b0 + b;
-                        s_q[(0 * BCH + b) * LV_BLOCK + tid] = A.want_s ? A.q[((size_t)0 * A.B + bb) * A.n_src + s] : (T)0;
-                        s_q[(1 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)1 * A.B + bb) * A.n_src + s] : (T)0;
-                        s_q[(2 * BCH + b) * LV_BLOCK + tid] = A.want_d ? A.q[((size_t)2 * A.B + bb) * A.n_src + s] : (T)0;
-                    }
+                    nqs[k][b] = A.want_s ? qs[b][s] : (T)0;
+                    nqx[k][b] = A.want_d ? qx[b][s] : (T)0;
+                    nqy[k][b] = A.want_d ? qy[b][s] : (T)0;
                 }
             }
-            __syncthreads();
-            if (active) {
-                for (int i = 0; i < m; ++i) {
-                    const T dx = (T)(x - s_x[i]), dy = (T)(y - s_y[i]);
-                    const T a = (dx * dx + dy * dy) * inv4d;
-                    if (a < a_max) {
-                        const T f = a * seg_inv;
-                        const int sg = (int)f;
-                        const T v = (T)2 * (f - (T)sg) - (T)1;
-                        const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
-                        T2 cc = c[NC - 1];
-                        T ks = cc.x, kd = cc.y;
+        };
+        fetch(s0);
+        for (int s = s0; s < s1; s += PF) {
+            double cx[PF], cy[PF];
+            T cqs[PF][BCH], cqx[PF][BCH], cqy[PF][BCH];
 #pragma unroll
-                        for (int k = NC - 2; k >= 0; --k) {
-                            cc = c[k];
-                            ks = fma(ks, v, cc.x);
-                            kd = fma(kd, v, cc.y);
-                        }
+            for (int k = 0; k < PF; ++k) {
+                cx[k] = nx[k];
+                cy[k] = ny[k];
 #pragma unroll
-                        for (int b = 0; b < BCH; ++b) {
-                            S[b] = fma(s_q[(0 * BCH + b) * LV_BLOCK + i], ks, S[b]);
-                            const T nd = fma(s_q[(1 * BCH + b) * LV_BLOCK + i], dx,
-                                             s_q[(2 * BCH + b) * LV_BLOCK + i] * dy);
-                            D[b] = fma(nd, kd, D[b]);
-                        }
-                    }
+                for (int b = 0; b < BCH; ++b) {
+                    cqs[k][b] = nqs[k][b];
+                    cqx[k][b] = nqx[k][b];
+                    cqy[k][b] = nqy[k][b];
                 }
             }
+            if (s + PF < s1) fetch(s + PF);
+#pragma unroll
+            for (int k = 0; k < PF; ++k)
+                if (s + k < s1) pair(cx[k], cy[k], cqs[k], cqx[k], cqy[k]);
         }
     }
     if (active) {
@@ -207,6 +232,7 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.B = B;
     A.blk_ofs = L.blk_ofs;
     A.blk_rng = L.blk_rng;
+    A.wave_order = L.wave_order;
     A.sx = L.sx;
     A.sy = L.sy;
     A.q = (const T *)L.q;
@@ -217,8 +243,7 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.want_d = want_d;
     const int bch = B == 1 ? 1 : LV_BCH;
     dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK), (unsigned)((B + bch - 1) / bch));
-    const size_t lds = sizeof(double) * 2 * LV_BLOCK + sizeof(T) * (3 * (size_t)bch * LV_BLOCK +
-                                                                   (size_t)L.nseg * STRIDE * 2);
+    const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE * 2;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (bch == 1) {
         if (lds > 64 * 1024)

@@ -44,8 +44,12 @@ __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const
     }
 }
 
-// Value and first two t-derivatives of two Legendre series at t, using
-// P_{k+1} = ((2k+1) t P_k - k P_{k-1})/(k+1), P'_{k+1} = P'_{k-1} + (2k+1) P_k,
+// Legendre recurrence P_{k+1} = A_k t P_k - B_k P_{k-1}, A_k = (2k+1)/(k+1),
+// B_k = k/(k+1): with the loops unrolled, k is a constant and both
+// coefficients fold to literals (no division on the device).
+
+// Value and first two t-derivatives of two Legendre series at t, using the
+// recurrence above with P'_{k+1} = P'_{k-1} + (2k+1) P_k and
 // P''_{k+1} = P''_{k-1} + (2k+1) P'_k.
 __device__ inline void leg2(const double *__restrict__ ca, const double *__restrict__ cb, double t,
                             double &a0, double &a1, double &a2, double &b0, double &b1, double &b2)
@@ -59,7 +63,7 @@ __device__ inline void leg2(const double *__restrict__ ca, const double *__restr
     b2 = 0.0;
 #pragma unroll
     for (int k = 1; k < NGL - 1; ++k) {
-        const double pn = ((2 * k + 1) * t * p - k * pm) / (k + 1);
+        const double pn = ((2.0 * k + 1.0) / (k + 1.0)) * t * p - ((double)k / (k + 1.0)) * pm;
         const double dn = dm + (2 * k + 1) * p;
         const double en = em + (2 * k + 1) * d;
         pm = p; p = pn;
@@ -76,7 +80,7 @@ __device__ inline double leg1(const double *__restrict__ c, double t)
     double pm = 1.0, p = t, v = c[0] + c[1] * t;
 #pragma unroll
     for (int k = 1; k < NGL - 1; ++k) {
-        const double pn = ((2 * k + 1) * t * p - k * pm) / (k + 1);
+        const double pn = ((2.0 * k + 1.0) / (k + 1.0)) * t * p - ((double)k / (k + 1.0)) * pm;
         pm = p; p = pn;
         v = fma(c[k + 1], p, v);
     }
@@ -190,6 +194,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                 const int p0 = imin / NGL;
                 int cand[3] = {p0, A.prev[p0], A.next[p0]};
                 double d2b = INFINITY;
+#pragma unroll 1
                 for (int c = 0; c < 3; ++c) {
                     double t, d2;
                     panel_min(A, cand[c], px, py, t, d2);

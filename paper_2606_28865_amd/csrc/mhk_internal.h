@@ -31,13 +31,14 @@ namespace mhk {
 constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
 constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
-constexpr int TAB_NC = 10;       // coefficients per table segment (degree 9)
-constexpr int TAB_STRIDE = 11;   // double2 slots per segment in LDS (44 dwords: spreads segments over the banks)
+constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
+constexpr int TAB_STRIDE = 9;    // double2 slots per segment in LDS (36 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
 constexpr int LV_CDIV = 2;       // level cells are R_j / LV_CDIV wide; neighbourhood +-LV_CDIV cells
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
+constexpr int LV_WAVE = 64;      // targets per level-sum wavefront (one source range list each)
 constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
 
 void set_error(const std::string &msg);
@@ -66,6 +67,7 @@ struct Level {
     // per block of LV_BLOCK sorted targets: ranges of sorted sources covering
     // the union of the targets' cell neighbourhoods
     int32_t *blk_ofs = nullptr;                   // [n_blocks + 1]
+    int32_t *wave_order = nullptr;                // wavefronts in decreasing order of candidate work
     int32_t *blk_rng = nullptr;                   // [n_ranges][2]
     int64_t n_ranges = 0;
     double *interp = nullptr;                     // [nchild][16][16] parent -> child values
@@ -97,6 +99,10 @@ struct History {
     int n_ttiles = 0;
     int32_t *ttile_xy = nullptr;                  // [n_ttiles] tile index ty*ntile+tx
     int32_t *ttile_rng = nullptr;                 // [n_ttiles + 1]
+    // window phi_k(t), k = 0..w-1, as monomials of degree w+3 in t = 2u - 1,
+    // u = m0 - g + w/2 in [0, 1): [w][w+4] in the plan precision
+    void *wcoef = nullptr;
+    double wfit_err = 0;
     // multiplier factors A[l] = exp(-delta k_l^2)/phihat(k_l)^2, 0 beyond kcut
     double *fac = nullptr;                        // [n/2+1]
     double mult_c = 0;                            // h^4/P^2 exp(-delta alpha^2)

@@ -556,17 +556,18 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     TRY(upload(P, &L.code, code.data(), L.n_src));
     TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
-    // per target block: the union of the targets' (2 LV_CDIV + 1)^2 cell
-    // neighbourhoods as row intervals, mapped to ranges of sorted sources
+    // per wavefront of LV_WAVE targets: the union of the targets'
+    // (2 LV_CDIV + 1)^2 cell neighbourhoods as row intervals, mapped to ranges
+    // of sorted sources (waves past the last target get no ranges)
     {
         const int64_t nout = (int64_t)tgx.size();
-        const int64_t nblk = (nout + LV_BLOCK - 1) / LV_BLOCK;
+        const int64_t nblk = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
         std::vector<int32_t> bofs(nblk + 1, 0), rng;
         std::vector<int64_t> cells;
         std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
         for (int64_t b = 0; b < nblk; ++b) {
             cells.clear();
-            for (int64_t t = b * LV_BLOCK; t < std::min(nout, (b + 1) * LV_BLOCK); ++t) {
+            for (int64_t t = b * LV_WAVE; t < std::min(nout, (b + 1) * LV_WAVE); ++t) {
                 int64_t ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((tgx[t] - L.ox) / L.cell)));
                 int64_t iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((tgy[t] - L.oy) / L.cell)));
                 cells.push_back(iy * ncx + ix);
@@ -603,6 +604,19 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
             bofs[b + 1] = (int32_t)(rng.size() / 2);
         }
         L.n_ranges = (int64_t)rng.size() / 2;
+        // schedule the wavefronts heaviest first (candidate sources x targets),
+        // so that the long ones start early and each workgroup holds four
+        // wavefronts of similar work
+        std::vector<int64_t> work(nblk, 0);
+        for (int64_t b = 0; b < nblk; ++b) {
+            int64_t nt_w = std::max<int64_t>(0, std::min(nout, (b + 1) * LV_WAVE) - b * LV_WAVE);
+            for (int32_t r = bofs[b]; r < bofs[b + 1]; ++r) work[b] += (int64_t)(rng[2 * r + 1] - rng[2 * r]);
+            work[b] *= (nt_w > 0 ? 1 : 0);
+        }
+        std::vector<int32_t> worder(nblk);
+        std::iota(worder.begin(), worder.end(), 0);
+        std::stable_sort(worder.begin(), worder.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
+        TRY(upload(P, &L.wave_order, worder.data(), nblk));
         TRY(upload(P, &L.blk_ofs, bofs.data(), nblk + 1));
         TRY(upload(P, &L.blk_rng, rng.data(), std::max<int64_t>(2, (int64_t)rng.size())));
     }
@@ -615,7 +629,8 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     // Kernel table: piecewise polynomials in a = r^2/(4 delta_j) on segments of
     // width 1/4, each in the local variable v in [-1, 1]; coefficients from
     // Chebyshev interpolation converted to monomials in v.  FP64 path: degree
-    // 9 (error ~4e-14 of K_j(0)); FP32 path: degree 7, stored as floats.
+    // 7 on segments of 1/8 (error ~4e-13 of K_j(0)); FP32 path: degree 7 on
+    // segments of 1/4, stored as floats.
     LevelQuad Q;
     const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
     const double cS = 1.0 / (4.0 * M_PI), cD = 1.0 / (8.0 * M_PI * L.delta_j);
@@ -623,9 +638,10 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     const int nc = fp64 ? TAB_NC : TABF_NC, stride = fp64 ? TAB_STRIDE : TABF_STRIDE;
     const double tab_tol = fp64 ? 1e-12 : 1e-8;
     std::vector<double> tab;
-    // segment width 1/4, halved while the table misses tab_tol (large alpha^2
-    // delta_j makes K_j decay like e^{-4a})
-    for (double seg_w = 0.25;; seg_w *= 0.5) {
+    // segment width 1/8 (FP64, degree 7) or 1/4 (FP32, degree 7), halved
+    // while the table misses tab_tol (large alpha^2 delta_j makes K_j decay
+    // like e^{-4a})
+    for (double seg_w = fp64 ? 0.125 : 0.25;; seg_w *= 0.5) {
         L.seg_inv = 1.0 / seg_w;
         L.nseg = (int)ceil(L.a_max / seg_w) + 1;
         tab.assign((size_t)L.nseg * stride * 2, 0.0);
@@ -941,6 +957,68 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         g_rocfft_ready = true;
     }
 
+    // window polynomials: phi at grid point m0 + k of a source at g, as a
+    // function of t = 2(m0 - g + w/2) - 1 in [-1, 1), fitted by Chebyshev
+    // interpolation and converted to monomials (Horner form, as in the
+    // spreading of Barnett, Magland and af Klinteberg)
+    {
+        const int W = G.w, D = W + 3, nfit = 4 * (D + 1);
+        std::vector<double> cf((size_t)W * (D + 1));
+        double emax = 0;
+        auto phi = [&](long double z) -> long double {
+            return fabsl(z) < 1 ? expl((long double)G.beta * (sqrtl(1 - z * z) - 1)) : 0.0L;
+        };
+        for (int k = 0; k < W; ++k) {
+            std::vector<long double> f(nfit), ch(D + 1, 0);
+            for (int i = 0; i < nfit; ++i) {
+                long double t = cosl(M_PIl * (i + 0.5L) / nfit);
+                f[i] = phi(((t + 1) / 2 - W / 2.0L + k) * 2 / W);
+            }
+            for (int m = 0; m <= D; ++m) {
+                long double acc = 0;
+                for (int i = 0; i < nfit; ++i) acc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nfit);
+                ch[m] = acc * (m == 0 ? 1.0L : 2.0L) / nfit;
+            }
+            std::vector<long double> mono(D + 1, 0), tp(D + 1, 0), tc(D + 1, 0), tn(D + 1, 0);
+            tp[0] = 1;
+            tc[1] = 1;
+            for (int j = 0; j <= D; ++j) mono[j] += ch[0] * tp[j] + ch[1] * tc[j];
+            for (int m = 2; m <= D; ++m) {
+                std::fill(tn.begin(), tn.end(), 0.0L);
+                for (int j = 0; j <= D; ++j) {
+                    if (j + 1 <= D) tn[j + 1] += 2 * tc[j];
+                    tn[j] -= tp[j];
+                }
+                for (int j = 0; j <= D; ++j) mono[j] += ch[m] * tn[j];
+                tp = tc;
+                tc = tn;
+            }
+            for (int j = 0; j <= D; ++j) cf[(size_t)k * (D + 1) + j] = (double)mono[j];
+            for (int i = 0; i <= 400; ++i) {
+                double t = -1.0 + 2.0 * i / 400.0;
+                double pv = 0;
+                for (int j = D; j >= 0; --j) pv = pv * t + cf[(size_t)k * (D + 1) + j];
+                emax = std::max(emax, fabs(pv - (double)phi(((t + 1) / 2 - W / 2.0L + k) * 2 / W)));
+            }
+        }
+        G.wfit_err = emax;
+        if (emax > std::max(P->p.prec == MHK_FP64 ? 1e-11 : 1e-6, 0.5 * P->p.tol)) {
+            char msg[128];
+            snprintf(msg, sizeof msg, "window polynomial fit error %.3e too large", emax);
+            set_error(msg);
+            return MHK_EUNSUPPORTED;
+        }
+        if (P->p.prec == MHK_FP64) {
+            double *d = nullptr;
+            TRY(upload(P, &d, cf.data(), (int64_t)cf.size()));
+            G.wcoef = d;
+        } else {
+            std::vector<float> cff(cf.begin(), cf.end());
+            float *d = nullptr;
+            TRY(upload(P, &d, cff.data(), (int64_t)cff.size()));
+            G.wcoef = d;
+        }
+    }
     // multiplier factors
     std::vector<double> qt, qw;
     gauss_legendre(160, qt, qw);
