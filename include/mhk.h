@@ -174,6 +174,77 @@ mhk_status mhk_plan_info(const mhk_plan *plan, mhk_info *info);
 void mhk_plan_destroy(mhk_plan *plan);
 const char *mhk_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Boundary integral equations (Section 3.2)
+ *
+ * The Dirichlet problem (-Lap + alpha^2) u = f in Omega, u = g on the
+ * boundary, is solved through u = V[f] + D[mu] (eq. (sol_dirichlet)) and the
+ * second-kind equation -mu/2 + D[mu] = g - V[f] on the boundary (eq.
+ * (bie_dir)); the Neumann problem (du/dnu = g) through u = V[f] + S[g] -
+ * D[u] (eq. (sol_neumann)) and u/2 + D[u] = V[f] + S[g] (eq. (bie_neu)).  On
+ * the boundary nodes the double-layer operator is discretised by the
+ * Nystrom method with the smooth panel rule (the matrix K of Section 3.2:
+ * K_ij = w_j alpha/(2 pi) K_1(alpha r_ij) (x_i - x_j).nu_j / r_ij, i != j;
+ * K_ii = -w_i kappa_i/(4 pi), eq. (dlp_diag_limit)), and the discrete
+ * systems (eqs. (dirichlet-discrete), (neumann-discrete)) are solved by
+ * restarted GMRES on the device.  All vectors of these calls are DEVICE
+ * pointers of doubles.
+ * ------------------------------------------------------------------------ */
+typedef struct mhk_nystrom mhk_nystrom;
+
+typedef struct {
+    int64_t n;            /* N_B                                                    */
+    double alpha;
+    int64_t device_bytes; /* K (8 N_B^2 bytes) plus GMRES and solve workspace      */
+    double ms_assemble;   /* time to build K on the device                         */
+} mhk_nys_info;
+
+typedef struct {
+    int iters;            /* GMRES iterations (matrix-vector products in the Krylov loop) */
+    int converged;        /* 1 if |b - A x| <= tol |b| at exit                      */
+    double resid;         /* final true relative residual                           */
+    double ms_eval, ms_gmres, ms_total;  /* potential evaluations / GMRES / total   */
+} mhk_solve_info;
+
+/* Assemble K on the device for the boundary (host arrays as for
+ * mhk_plan_create; N_B <= 2^20, K needs 8 N_B^2 bytes of device memory).
+ * Later calls run on the given stream (NULL: default stream).  *out is NULL
+ * on error (MHK_ENOMEM when K does not fit). */
+mhk_status mhk_nystrom_create(double alpha, const mhk_boundary *boundary, void *hip_stream, mhk_nystrom **out);
+
+/* y = shift x + K x, x and y device arrays of N_B doubles (y must not alias x);
+ * asynchronous on the object's stream. */
+mhk_status mhk_nystrom_apply(mhk_nystrom *nys, double shift, const double *x, double *y);
+
+/* Solve (shift I + K) x = rhs by GMRES(restart), x = 0 initially, until the
+ * relative residual is <= tol or maxit iterations were made; synchronises the
+ * object's stream (the Arnoldi coefficients are reduced on the host).
+ * 0 < tol < 1, 1 <= restart <= 1000, maxit >= 1.  Not converging is not an
+ * error: check info->converged. */
+mhk_status mhk_nystrom_solve(mhk_nystrom *nys, double shift, const double *rhs, double *x, double tol,
+                             int restart, int maxit, mhk_solve_info *info);
+
+/* Dirichlet problem with data g [N_B] and optional source (f_vol [N_V] at
+ * the volume nodes and f_trg [n_out] at the outputs, both or neither):
+ * mu [N_B] receives the layer density, u [n_out] the solution at every
+ * output of the plan (targets, then boundary nodes, where u is the interior
+ * limit V + D[mu] - mu/2 of eq. (jumprel)).  The plan must be FP64 with batch
+ * 1, on-surface targets, the same boundary and alpha as nys; the work runs on
+ * the plan's stream and ends synchronised. */
+mhk_status mhk_solve_dirichlet(mhk_plan *plan, mhk_nystrom *nys, const double *g, const double *f_vol,
+                               const double *f_trg, double tol, int restart, int maxit, double *mu, double *u,
+                               mhk_solve_info *info);
+
+/* Neumann problem with data g = du/dnu [N_B] (outward normal): u_b [N_B]
+ * receives the boundary values, u [n_out] the solution at every output (u_b
+ * on the boundary nodes).  Same requirements as mhk_solve_dirichlet. */
+mhk_status mhk_solve_neumann(mhk_plan *plan, mhk_nystrom *nys, const double *g, const double *f_vol,
+                             const double *f_trg, double tol, int restart, int maxit, double *u_b, double *u,
+                             mhk_solve_info *info);
+
+mhk_status mhk_nystrom_info(const mhk_nystrom *nys, mhk_nys_info *info);
+void mhk_nystrom_destroy(mhk_nystrom *nys);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,17 +25,24 @@ from scipy.special import k1
 from . import PART_ALL, Problem
 
 
-def nystrom_matrix(boundary, alpha):
+def nystrom_rows(boundary, alpha, rows):
+    """Rows `rows` of the Nystrom matrix."""
+    rows = np.asarray(rows, dtype=np.int64)
     x, y = np.asarray(boundary["x"], float), np.asarray(boundary["y"], float)
     nx, ny = np.asarray(boundary["nx"], float), np.asarray(boundary["ny"], float)
     w, kap = np.asarray(boundary["w"], float), np.asarray(boundary["kappa"], float)
-    dx = x[:, None] - x[None, :]
-    dy = y[:, None] - y[None, :]
+    dx = x[rows, None] - x[None, :]
+    dy = y[rows, None] - y[None, :]
     r = np.hypot(dx, dy)
-    np.fill_diagonal(r, 1.0)
+    diag = rows[:, None] == np.arange(len(x))[None, :]
+    r[diag] = 1.0
     K = w[None, :] * (alpha / (2.0 * np.pi)) * k1(alpha * r) * (dx * nx[None, :] + dy * ny[None, :]) / r
-    np.fill_diagonal(K, -w * kap / (4.0 * np.pi))
+    K[diag] = (-w * kap / (4.0 * np.pi))[rows]
     return K
+
+
+def nystrom_matrix(boundary, alpha):
+    return nystrom_rows(boundary, alpha, np.arange(len(boundary["x"])))
 
 
 def _problem(alpha, delta, J, boundary, volume, targets, inside, sigma, mu, f_vol, f_trg):

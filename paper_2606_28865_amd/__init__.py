@@ -1,7 +1,10 @@
 """MI355X-native evaluation of the kernel-split layer and volume potentials
-of the 2D modified Helmholtz equation (HIP library libmhk.so + binding)."""
+of the 2D modified Helmholtz equation (HIP library libmhk.so + binding), and
+the boundary integral equation solves built on it."""
 from ._lib import (MHK_FP32, MHK_FP64, PART_ALL, PART_HISTORY, PART_LEVELS, PART_LOCAL, Info, MhkError,
-                   Params, Plan, footprint, lib, make_params, resolve_params)
+                   Nystrom, Params, Plan, footprint, lib, make_params, resolve_params, solve_dirichlet,
+                   solve_neumann)
 
 __all__ = ["MHK_FP32", "MHK_FP64", "PART_ALL", "PART_HISTORY", "PART_LEVELS", "PART_LOCAL", "Info",
-           "MhkError", "Params", "Plan", "footprint", "lib", "make_params", "resolve_params"]
+           "MhkError", "Nystrom", "Params", "Plan", "footprint", "lib", "make_params", "resolve_params",
+           "solve_dirichlet", "solve_neumann"]

@@ -59,9 +59,24 @@ class Info(C.Structure):
         return d
 
 
+class NysInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("alpha", C.c_double), ("device_bytes", C.c_int64), ("ms_assemble", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("resid", C.c_double), ("ms_eval", C.c_double),
+                ("ms_gmres", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
            "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_capture", "mhk_plan_launch_graph",
-           "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error"]
+           "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error",
+           "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_solve_dirichlet",
+           "mhk_solve_neumann", "mhk_nystrom_info", "mhk_nystrom_destroy"]
+_VOID = ("mhk_plan_destroy", "mhk_last_error", "mhk_nystrom_destroy")
 
 _lib = None
 
@@ -88,8 +103,17 @@ def lib():
         L.mhk_plan_destroy.argtypes = [C.c_void_p]
         L.mhk_plan_destroy.restype = None
         L.mhk_last_error.restype = C.c_char_p
+        d, vp, i = C.c_double, C.c_void_p, C.c_int
+        L.mhk_nystrom_create.argtypes = [d, P(Boundary), vp, P(vp)]
+        L.mhk_nystrom_apply.argtypes = [vp, d, vp, vp]
+        L.mhk_nystrom_solve.argtypes = [vp, d, vp, vp, d, i, i, P(SolveInfo)]
+        L.mhk_solve_dirichlet.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
+        L.mhk_solve_neumann.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
+        L.mhk_nystrom_info.argtypes = [vp, P(NysInfo)]
+        L.mhk_nystrom_destroy.argtypes = [vp]
+        L.mhk_nystrom_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("mhk_plan_destroy", "mhk_last_error"):
+            if name not in _VOID:
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -254,3 +278,86 @@ class Plan:
         _check(lib().mhk_eval_parts(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
                                     ptr(out[0]), ptr(out[1]), ptr(out[2])))
         return out
+
+
+def _f64_dev(t, n, what):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{what} must be a contiguous float64 device tensor")
+    if t.numel() != n:
+        raise ValueError(f"{what}: expected {n} values, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Nystrom:
+    """The dense Nystrom matrix K of the double-layer operator on the boundary
+    nodes, resident on the device, with its product and GMRES solve."""
+
+    def __init__(self, alpha, boundary, stream=None):
+        import torch
+        keep = _Keep()
+        B, _, _ = _structs(boundary, None, None, False, keep)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.alpha = float(alpha)
+        self.n = int(B.n_panels) * NGL
+        h = C.c_void_p()
+        _check(lib().mhk_nystrom_create(self.alpha, C.byref(B), C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mhk_nystrom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = NysInfo()
+        _check(lib().mhk_nystrom_info(self._h, C.byref(i)))
+        return {name: getattr(i, name) for name, _ in i._fields_}
+
+    def apply(self, x, shift=0.0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(lib().mhk_nystrom_apply(self._h, float(shift), _f64_dev(x, self.n, "x"), _f64_dev(out, self.n, "y")))
+        return out
+
+    def solve(self, rhs, shift, tol=1e-12, restart=60, maxit=500, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        info = SolveInfo()
+        _check(lib().mhk_nystrom_solve(self._h, float(shift), _f64_dev(rhs, self.n, "rhs"),
+                                       _f64_dev(out, self.n, "x"), float(tol), int(restart), int(maxit),
+                                       C.byref(info)))
+        return out, info.as_dict()
+
+
+def _solve(kind, plan, nys, g, f_vol, f_trg, tol, restart, maxit):
+    import torch
+    dens = torch.empty(plan.nb, dtype=torch.float64, device="cuda")
+    u = torch.empty(plan.n_out, dtype=torch.float64, device="cuda")
+    fv = None if f_vol is None else _f64_dev(f_vol, plan.nv, "f_vol")
+    ft = None if f_trg is None else _f64_dev(f_trg, plan.n_out, "f_trg")
+    info = SolveInfo()
+    fn = lib().mhk_solve_dirichlet if kind == "dirichlet" else lib().mhk_solve_neumann
+    _check(fn(plan._h, nys._h, _f64_dev(g, plan.nb, "g"), fv, ft, float(tol), int(restart), int(maxit),
+              C.c_void_p(dens.data_ptr()), C.c_void_p(u.data_ptr()), C.byref(info)))
+    return dens, u, info.as_dict()
+
+
+def solve_dirichlet(plan, nys, g, f_vol=None, f_trg=None, tol=1e-12, restart=60, maxit=500):
+    """Returns (mu, u, info): layer density and u at every output of the plan."""
+    return _solve("dirichlet", plan, nys, g, f_vol, f_trg, tol, restart, maxit)
+
+
+def solve_neumann(plan, nys, g, f_vol=None, f_trg=None, tol=1e-12, restart=60, maxit=500):
+    """Returns (u_b, u, info): boundary values and u at every output of the plan."""
+    return _solve("neumann", plan, nys, g, f_vol, f_trg, tol, restart, maxit)

@@ -3,11 +3,15 @@
 For one geometry, alpha, tolerance and precision, each candidate (upsamp,
 wspread) is built as a plan with the same split delta, timed on the device
 with HIP events over a few evaluations, and checked against a reference
-evaluation of the same inputs by a more accurate plan (FP64, the tolerance
-/ 1000, the default grid): a candidate is admissible when its relative
-max-norm difference to the reference is below the tolerance for S, D and V.
-The fastest admissible candidate wins.  Results are cached in a JSON file
-keyed by the problem's sizes and parameters.
+evaluation by a more accurate plan (FP64, the tolerance / 1000, the default
+grid) of the same inputs as the candidate sees them (for an FP32 candidate,
+the densities rounded to FP32: the grid is tuned for the numerical error of
+the evaluation, not for the rounding of its inputs, which the local layer
+terms amplify through the density's second derivative): a candidate is
+admissible when its relative max-norm difference to the reference is below
+the tolerance for S, D and V.  The fastest admissible candidate wins.
+Results are cached in a JSON file keyed by the problem's sizes and
+parameters.
 
 Everything runs through the library (no CPU fallback); the reference is the
 library's own FP64 path, whose agreement with the oracle is what the parity
@@ -68,7 +72,7 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
 
     ref_plan = L.Plan(L.make_params(alpha=alpha, tol=max(1e-13, tol * 1e-3), delta=delta, batch=1), *geo,
                       on_surface=on)
-    ref = ref_plan.eval(*(dev(x, torch.float64)[:1] for x in densities))
+    ref = ref_plan.eval(*(dev(x, dt)[:1].to(torch.float64) for x in densities))
     torch.cuda.synchronize()
     ref_plan.close()
     ins = [dev(x, dt) for x in densities]

@@ -91,3 +91,26 @@ def test_footprint_and_input_validation():
     b3["curve_panel_ofs"] = np.array([0, 5])
     with pytest.raises(M.MhkError):
         M.footprint(prm, b3, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+
+
+def test_nystrom_argument_validation():
+    """Argument checks of the boundary-integral entry points happen on the host
+    before any device call."""
+    import ctypes as C
+    from paper_2606_28865_amd import _lib
+    w = synth.config0()
+    keep = _lib._Keep()
+    B, _, _ = _lib._structs(w.boundary, None, None, False, keep)
+    L = M.lib()
+    h = C.c_void_p()
+    for alpha in (0.0, -1.0, float("nan")):
+        assert L.mhk_nystrom_create(alpha, C.byref(B), None, C.byref(h)) == -1
+        assert not h.value
+    assert L.mhk_nystrom_create(10.0, None, None, C.byref(h)) == -1
+    assert L.mhk_nystrom_create(10.0, C.byref(B), None, None) == -1
+    info = _lib.SolveInfo()
+    assert L.mhk_nystrom_solve(None, 0.5, None, None, 1e-10, 30, 100, C.byref(info)) == -1
+    assert L.mhk_nystrom_apply(None, 0.5, None, None) == -1
+    assert L.mhk_solve_dirichlet(None, None, None, None, None, 1e-10, 30, 100, None, None, C.byref(info)) == -1
+    assert L.mhk_solve_neumann(None, None, None, None, None, 1e-10, 30, 100, None, None, C.byref(info)) == -1
+    L.mhk_nystrom_destroy(None)
