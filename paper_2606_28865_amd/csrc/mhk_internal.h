@@ -35,7 +35,7 @@ constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
 constexpr int TAB_STRIDE = 9;    // double2 slots per segment in LDS (36 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
-constexpr int LV_CDIV = 2;       // level cells are R_j / LV_CDIV wide; neighbourhood +-LV_CDIV cells
+constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
 constexpr int LV_WAVE = 64;      // targets per level-sum wavefront (one source range list each)

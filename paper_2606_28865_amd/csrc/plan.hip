@@ -556,29 +556,34 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     TRY(upload(P, &L.code, code.data(), L.n_src));
     TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
-    // per wavefront of LV_WAVE targets: the union of the targets'
-    // (2 LV_CDIV + 1)^2 cell neighbourhoods as row intervals, mapped to ranges
-    // of sorted sources (waves past the last target get no ranges)
+    // per wavefront of LV_WAVE targets: for every cell row, the cells that
+    // can hold a source within R_j of one of the wave's targets (row gap g to
+    // the target, half-width sqrt(R_j^2 - g^2) in x), merged into row
+    // intervals and mapped to ranges of sorted sources (waves past the last
+    // target get no ranges)
     {
         const int64_t nout = (int64_t)tgx.size();
         const int64_t nblk = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
+        const double R = L.radius;
         std::vector<int32_t> bofs(nblk + 1, 0), rng;
-        std::vector<int64_t> cells;
         std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
+        auto col = [&](double x) {
+            return std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((x - L.ox) / L.cell)));
+        };
+        auto row = [&](double y) {
+            return std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((y - L.oy) / L.cell)));
+        };
         for (int64_t b = 0; b < nblk; ++b) {
-            cells.clear();
-            for (int64_t t = b * LV_WAVE; t < std::min(nout, (b + 1) * LV_WAVE); ++t) {
-                int64_t ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((tgx[t] - L.ox) / L.cell)));
-                int64_t iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((tgy[t] - L.oy) / L.cell)));
-                cells.push_back(iy * ncx + ix);
-            }
-            std::sort(cells.begin(), cells.end());
-            cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
             iv.clear();
-            for (int64_t c : cells) {
-                int64_t cy = c / ncx, cx = c % ncx;
-                for (int64_t r = std::max<int64_t>(0, cy - LV_CDIV); r <= std::min<int64_t>(ncy - 1, cy + LV_CDIV); ++r)
-                    iv.push_back({r, std::max<int64_t>(0, cx - LV_CDIV), std::min<int64_t>(ncx - 1, cx + LV_CDIV)});
+            for (int64_t t = b * LV_WAVE; t < std::min(nout, (b + 1) * LV_WAVE); ++t) {
+                const double tx = tgx[t], ty = tgy[t];
+                for (int64_t r = row(ty - R); r <= row(ty + R); ++r) {
+                    const double ylo = L.oy + r * L.cell, yhi = ylo + L.cell;
+                    const double g = std::max(0.0, std::max(ylo - ty, ty - yhi));
+                    if (g > R) continue;
+                    const double hw = sqrt(R * R - g * g);
+                    iv.push_back({r, col(tx - hw), col(tx + hw)});
+                }
             }
             std::sort(iv.begin(), iv.end());
             int64_t last_end = -1;
