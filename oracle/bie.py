@@ -84,3 +84,16 @@ def solve_neumann(alpha, delta, J, boundary, volume, targets, inside, g, f_vol=N
     u = V + S - D
     u[nt:] = ub
     return ub, u
+
+
+def heat_step(alpha, delta, J, boundary, volume, u_n, g_next, F=None):
+    """One implicit-Euler step of u_t = Lap u + F with time step 1/alpha^2
+    (elliptic marching, Section 1): (-Lap + alpha^2) u^{n+1} = alpha^2 u^n +
+    F^{n+1} with u^{n+1} = g_next on the boundary, solved as the Dirichlet
+    problem above with the volume nodes as targets.  u_n and F are given at
+    the outputs (volume nodes, then boundary nodes); returns (mu, u^{n+1})."""
+    f = alpha ** 2 * np.asarray(u_n, float) + (0.0 if F is None else np.asarray(F, float))
+    nv = len(volume["x"])
+    targets = (volume["x"], volume["y"])
+    inside = np.ones(nv, np.int8)
+    return solve_dirichlet(alpha, delta, J, boundary, volume, targets, inside, g_next, f[:nv], f)

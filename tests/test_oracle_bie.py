@@ -111,3 +111,25 @@ def test_dirichlet_with_volume_source():
     ue = np.concatenate([ue_f(tx, ty), gD])
     e = np.abs(uh - ue) / np.abs(ue).max()
     assert e[:nt].max() < 5e-6 and e[nt:].max() < 1e-4, (e[:nt].max(), e[nt:].max())
+
+
+def test_heat_step_closed_form():
+    """One implicit-Euler step of the heat equation (elliptic marching,
+    Section 1) from u0 = sin(k(x+a)) sin(k(y+b)): (-Lap + alpha^2) u1 =
+    alpha^2 u0 has the solution u1 = alpha^2/(alpha^2 + 2k^2) u0, so with that
+    boundary data the step must return it at every volume node and boundary
+    node, up to the split's local error, which falls with delta."""
+    cv = synth.Curve(r0=0.5, a=0.1, l1=3)
+    b = synth.discretize([cv], 24)
+    k, alpha = np.pi, 3.0
+    u0 = lambda x, y: np.sin(k * (x + 0.3)) * np.sin(k * (y + 0.2))
+    c = alpha ** 2 / (alpha ** 2 + 2 * k * k)
+    errs = []
+    for nr, nth, delta in ((24, 96, 2e-3), (32, 128, 1e-3)):
+        vol = synth.polar_volume(cv, nr, nth)
+        X = np.concatenate([vol["x"], b["x"]])
+        Y = np.concatenate([vol["y"], b["y"]])
+        _, u1 = bie.heat_step(alpha, delta, 3, b, vol, u0(X, Y), c * u0(b["x"], b["y"]))
+        errs.append(np.abs(u1 - c * u0(X, Y)).max() / np.abs(c * u0(X, Y)).max())
+    assert errs[0] / errs[1] > 2, errs
+    assert errs[1] < 1e-3, errs
