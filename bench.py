@@ -37,10 +37,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="multibody", choices=["multibody", "precision", "batched", "serve"],
+    ap.add_argument("--workload", default="multibody",
+                    choices=["multibody", "precision", "batched", "serve", "bie", "heat"],
                     help="multibody: the default throughput line; precision: FP32 vs FP64 at tol 1e-6 on "
                          "64k boundary / 4M volume / 4M targets; batched: 64 densities per call under a "
-                         "captured HIP graph; serve: Poisson stream of Rothe-step requests")
+                         "captured HIP graph; serve: Poisson stream of Rothe-step requests; bie: Dirichlet "
+                         "solve (Nystrom matrix, GMRES) on the 10-body geometry; heat: implicit-Euler "
+                         "heat steps with the volume nodes as targets")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--requests", type=int, default=120)
     return ap.parse_args()
@@ -73,7 +76,8 @@ def main():
               "throughput at N=1 is the figure this workload reports.", file=sys.stderr)
         sys.exit(2)
     if a.workload != "multibody":
-        {"precision": run_precision, "batched": run_batched, "serve": run_serve}[a.workload](a)
+        {"precision": run_precision, "batched": run_batched, "serve": run_serve, "bie": run_bie,
+         "heat": run_heat}[a.workload](a)
         return
     import torch
 
@@ -505,6 +509,131 @@ def run_serve(a):
                        "sizes": sizes},
             "latency": st, "sweep": sweep, "alone_service_ms": [round(x * 1e3, 3) for x in alone]}
     print(json.dumps(line), flush=True)
+
+
+def run_bie(a):
+    """Dirichlet problem on the 10-body geometry (16384 boundary nodes, ~1M
+    volume nodes, 1M targets + boundary nodes), alpha = 10, FP64, tol 1e-10
+    for the potentials and 1e-12 for GMRES: Nystrom assembly, the product's
+    HBM roofline, GMRES iterations and the whole solve (right-hand side V at
+    the boundary, GMRES, u = V + D[mu] at every output)."""
+    import torch
+
+    import paper_2606_28865_amd as M
+    import synth
+    from oracle import bie as OB
+    w = synth.multibody()
+    alpha = 10.0
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    plan = M.Plan(M.make_params(alpha=alpha, tol=1e-10, dx=w.dx), w.boundary, w.volume, (w.tx, w.ty, w.inside),
+                  on_surface=True)
+    nys = M.Nystrom(alpha, w.boundary)
+    ninfo = nys.info()
+    n = w.n_b
+    x = dev(np.random.default_rng(5).standard_normal(n))
+    y = torch.empty_like(x)
+    for _ in range(3):
+        nys.apply(x, -0.5, out=y)
+    torch.cuda.synchronize()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        nys.apply(x, -0.5, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_prod = e0.elapsed_time(e1) / reps
+    bytes_prod = 8.0 * n * (n + n % 2) + 16.0 * n       # K once, x and y
+    g, fv, ft = dev(w.sigma), dev(w.f_vol), dev(w.f_trg)
+    M.solve_dirichlet(plan, nys, g, fv, ft, tol=1e-12)
+    torch.cuda.synchronize()
+    times, infos = [], []
+    for _ in range(a.steps):
+        t0 = time.perf_counter()
+        mu, u, info = M.solve_dirichlet(plan, nys, g, fv, ft, tol=1e-12)
+        times.append(time.perf_counter() - t0)
+        infos.append(info)
+    ms_solve = 1e3 * float(np.mean(times))
+    log(f"product {ms_prod:.3f} ms ({bytes_prod / ms_prod / 1e6:.0f} GB/s), solve {ms_solve:.1f} ms, {infos[-1]}")
+    # CPU oracle: rows of the Nystrom matrix times x on a bounded sample
+    rows = np.arange(0, n, max(1, n // 512))
+    xh = x.cpu().numpy()
+    t0 = time.perf_counter()
+    _ = OB.nystrom_rows(w.boundary, alpha, rows) @ xh
+    cpu_rows_s = len(rows) / (time.perf_counter() - t0)
+    line = {"metric": "Dirichlet solves/s (V at the boundary, GMRES to 1e-12, u = V + D at all outputs)",
+            "value": 1e3 / ms_solve, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
+            "ms_per_step": ms_solve, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "multibody-dirichlet", "n_boundary": n, "n_volume": w.n_v, "n_targets": w.n_t,
+                       "alpha": alpha},
+            "gmres_iters": infos[-1]["iters"], "resid": infos[-1]["resid"],
+            "ms_gmres": infos[-1]["ms_gmres"], "ms_eval": infos[-1]["ms_eval"],
+            "ms_assemble": ninfo["ms_assemble"], "nystrom_bytes": ninfo["device_bytes"],
+            "roofline": {"kernel": "k_gemv", "bound": "hbm", "achieved": bytes_prod / ms_prod / 1e6,
+                         "peak": 8000.0, "unit": "GB/s", "frac": bytes_prod / ms_prod / 1e6 / 8000.0,
+                         "traffic": None, "ms_per_launch": ms_prod},
+            "cpu_baseline": {"value": cpu_rows_s / n, "unit": "Nystrom products/s", "cores": os.cpu_count(),
+                             "kind": "oracle", "sample": f"{len(rows)} rows of K times x (numpy, scipy K1)"}}
+    print(json.dumps(line), flush=True)
+    plan.close()
+    nys.close()
+
+
+def run_heat(a):
+    """Elliptic marching of the heat equation on the 10-body geometry (16384
+    boundary nodes, ~1M volume nodes carrying u), alpha = 10 (time step
+    0.01), FP64: each step is a Dirichlet solve with the source alpha^2 u^n
+    evaluated at every volume node.  u0 = sin(pi(x+0.3)) sin(pi(y+0.2)) with
+    boundary data c^n u0, c = alpha^2/(alpha^2 + 2 pi^2), whose steps are
+    exactly c^n u0: the error against that is reported."""
+    import torch
+
+    import paper_2606_28865_amd as M
+    import synth
+    w = synth.multibody(n_targets=10)
+    vol = w.volume
+    nv, nb = len(vol["x"]), w.n_b
+    alpha = 10.0
+    plan = M.Plan(M.make_params(alpha=alpha, tol=1e-10, dx=w.dx), w.boundary, vol,
+                  (vol["x"], vol["y"], np.ones(nv, np.int8)), on_surface=True)
+    nys = M.Nystrom(alpha, w.boundary)
+    k = np.pi
+    X = np.concatenate([vol["x"], w.boundary["x"]])
+    Y = np.concatenate([vol["y"], w.boundary["y"]])
+    u0 = np.sin(k * (X + 0.3)) * np.sin(k * (Y + 0.2))
+    c = alpha ** 2 / (alpha ** 2 + 2 * k * k)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    gb = u0[nv:]
+    nsteps = max(2, a.steps)
+    gs = [dev(c ** n * gb) for n in range(1, nsteps + 2)]
+    u = dev(u0)
+    bufs = [torch.empty_like(u), torch.empty_like(u)]
+    u1, _, info = M.heat_step(plan, nys, u, gs[0], tol=1e-12, out=bufs[0])        # warm-up step
+    torch.cuda.synchronize()
+    u = dev(u0)
+    iters = []
+    t0 = time.perf_counter()
+    for n in range(nsteps):
+        u, _, info = M.heat_step(plan, nys, u, gs[n], tol=1e-12, out=bufs[n % 2])
+        iters.append(info["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ex = c ** nsteps * u0
+    err = float(np.abs(u.cpu().numpy() - ex).max() / np.abs(ex).max())
+    ms = 1e3 * dt / nsteps
+    log(f"heat: {ms:.1f} ms per step, GMRES iterations {iters}, error vs c^n u0 {err:.2e}")
+    line = {"metric": "heat steps/s (implicit Euler, Dirichlet solve with V at 1M volume nodes)",
+            "value": nsteps / dt, "unit": "steps/s", "n_gpus": 1, "steps": nsteps, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "multibody-heat", "n_boundary": nb, "n_volume": nv, "alpha": alpha,
+                       "time_step": 1.0 / alpha ** 2},
+            "node_updates_per_s": (nv + nb) * nsteps / dt, "gmres_iters": iters,
+            "ms_eval": info["ms_eval"], "ms_gmres": info["ms_gmres"], "rel_err_vs_closed_form": err}
+    print(json.dumps(line), flush=True)
+    plan.close()
+    nys.close()
 
 
 if __name__ == "__main__":

@@ -242,6 +242,21 @@ mhk_status mhk_solve_neumann(mhk_plan *plan, mhk_nystrom *nys, const double *g, 
                              const double *f_trg, double tol, int restart, int maxit, double *u_b, double *u,
                              mhk_solve_info *info);
 
+/* One step of elliptic marching (Rothe's method, Section 1) for the heat
+ * equation u_t = Lap u + F in Omega, u = g on the boundary: the implicit
+ * Euler step with time step 1/alpha^2 is the modified Helmholtz problem
+ * (-Lap + alpha^2) u^{n+1} = alpha^2 u^n + F^{n+1} (eq. (mod_helm)), solved
+ * as the Dirichlet problem above.  The plan's targets must be its volume
+ * nodes, in the same order (checked at plan creation), with on-surface
+ * targets; u_n, F (may be NULL) and u_next are [n_out] device arrays over
+ * the volume nodes then the boundary nodes (u_n there is g^n), g_next [N_B]
+ * the boundary data of the new step, mu [N_B] receives the layer density.
+ * u_next must not alias u_n.  Same requirements and synchronisation as
+ * mhk_solve_dirichlet. */
+mhk_status mhk_heat_step(mhk_plan *plan, mhk_nystrom *nys, const double *u_n, const double *F,
+                         const double *g_next, double tol, int restart, int maxit, double *u_next, double *mu,
+                         mhk_solve_info *info);
+
 mhk_status mhk_nystrom_info(const mhk_nystrom *nys, mhk_nys_info *info);
 void mhk_nystrom_destroy(mhk_nystrom *nys);
 

@@ -2,9 +2,9 @@
 of the 2D modified Helmholtz equation (HIP library libmhk.so + binding), and
 the boundary integral equation solves built on it."""
 from ._lib import (MHK_FP32, MHK_FP64, PART_ALL, PART_HISTORY, PART_LEVELS, PART_LOCAL, Info, MhkError,
-                   Nystrom, Params, Plan, footprint, lib, make_params, resolve_params, solve_dirichlet,
-                   solve_neumann)
+                   Nystrom, Params, Plan, footprint, heat_step, lib, make_params, resolve_params,
+                   solve_dirichlet, solve_neumann)
 
 __all__ = ["MHK_FP32", "MHK_FP64", "PART_ALL", "PART_HISTORY", "PART_LEVELS", "PART_LOCAL", "Info",
-           "MhkError", "Nystrom", "Params", "Plan", "footprint", "lib", "make_params", "resolve_params",
+           "MhkError", "Nystrom", "Params", "Plan", "footprint", "heat_step", "lib", "make_params", "resolve_params",
            "solve_dirichlet", "solve_neumann"]

@@ -75,7 +75,7 @@ EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_e
            "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_capture", "mhk_plan_launch_graph",
            "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error",
            "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_solve_dirichlet",
-           "mhk_solve_neumann", "mhk_nystrom_info", "mhk_nystrom_destroy"]
+           "mhk_solve_neumann", "mhk_heat_step", "mhk_nystrom_info", "mhk_nystrom_destroy"]
 _VOID = ("mhk_plan_destroy", "mhk_last_error", "mhk_nystrom_destroy")
 
 _lib = None
@@ -109,6 +109,7 @@ def lib():
         L.mhk_nystrom_solve.argtypes = [vp, d, vp, vp, d, i, i, P(SolveInfo)]
         L.mhk_solve_dirichlet.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
         L.mhk_solve_neumann.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
+        L.mhk_heat_step.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
         L.mhk_nystrom_info.argtypes = [vp, P(NysInfo)]
         L.mhk_nystrom_destroy.argtypes = [vp]
         L.mhk_nystrom_destroy.restype = None
@@ -361,3 +362,19 @@ def solve_dirichlet(plan, nys, g, f_vol=None, f_trg=None, tol=1e-12, restart=60,
 def solve_neumann(plan, nys, g, f_vol=None, f_trg=None, tol=1e-12, restart=60, maxit=500):
     """Returns (u_b, u, info): boundary values and u at every output of the plan."""
     return _solve("neumann", plan, nys, g, f_vol, f_trg, tol, restart, maxit)
+
+
+def heat_step(plan, nys, u_n, g_next, F=None, tol=1e-12, restart=60, maxit=500, out=None):
+    """One implicit-Euler step of the heat equation with time step
+    1/alpha^2 (the plan's targets are its volume nodes).  u_n, F: [n_out]
+    over the volume nodes then the boundary nodes; g_next: [N_B].  Returns
+    (u_next, mu, info)."""
+    import torch
+    u = torch.empty(plan.n_out, dtype=torch.float64, device="cuda") if out is None else out
+    mu = torch.empty(plan.nb, dtype=torch.float64, device="cuda")
+    info = SolveInfo()
+    _check(lib().mhk_heat_step(plan._h, nys._h, _f64_dev(u_n, plan.n_out, "u_n"),
+                               None if F is None else _f64_dev(F, plan.n_out, "F"),
+                               _f64_dev(g_next, plan.nb, "g_next"), float(tol), int(restart), int(maxit),
+                               _f64_dev(u, plan.n_out, "u_next"), C.c_void_p(mu.data_ptr()), C.byref(info)))
+    return u, mu, info.as_dict()

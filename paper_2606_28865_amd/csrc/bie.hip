@@ -248,6 +248,15 @@ __global__ void __launch_bounds__(BT) k_neumann_u(int64_t nt, int64_t nout, cons
     u[s] = s < nt ? u[s] + sg[s] - d[s] : ub[s - nt];
 }
 
+// f = alpha^2 u + F (F may be NULL): the source of one implicit-Euler step
+__global__ void __launch_bounds__(BT) k_heat_source(int64_t n, double a2, const double *__restrict__ u,
+                                                    const double *__restrict__ F, double *__restrict__ f)
+{
+    const int64_t s = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (s >= n) return;
+    f[s] = a2 * u[s] + (F ? F[s] : 0.0);
+}
+
 // rhs[i] = a * p[off + i] + b * q[off + i]  (q may be NULL)
 __global__ void __launch_bounds__(BT) k_rhs(int64_t n, int64_t off, double a, const double *p, double b,
                                             const double *q, double *rhs)
@@ -698,6 +707,30 @@ mhk_status mhk_solve_neumann(mhk_plan *plan, mhk_nystrom *nys, const double *g, 
                              mhk_solve_info *info)
 {
     return solve_common(plan, nys, 1, g, f_vol, f_trg, tol, restart, maxit, u_b, u, info);
+}
+
+mhk_status mhk_heat_step(mhk_plan *P, mhk_nystrom *N, const double *u_n, const double *F, const double *g_next,
+                         double tol, int restart, int maxit, double *u_next, double *mu, mhk_solve_info *info)
+{
+    if (!P || !N || !u_n || !u_next || u_n == u_next) {
+        set_error("null plan, Nystrom matrix or state, or u_n aliases u_next");
+        return MHK_EINVAL;
+    }
+    if (!P->targets_are_volume) {
+        set_error("the heat step needs a plan whose targets are its volume nodes, in the same order");
+        return MHK_EINVAL;
+    }
+    BIE_TRY(check_solve(P, N, g_next, u_n, u_n, tol, restart, maxit, mu, u_next));
+    const int64_t nout = P->nout;
+    BIE_TRY(nys_scratch(N, nout));
+    // f at the outputs (volume nodes, then boundary nodes) in the first
+    // scratch half, which the Dirichlet solve leaves untouched; its first N_V
+    // entries are f at the volume nodes
+    double *f = N->work;
+    hipLaunchKernelGGL(k_heat_source, dim3(nb_of(nout)), dim3(BT), 0, P->stream, nout, P->p.alpha * P->p.alpha,
+                       u_n, F, f);
+    BIE_HIP(hipGetLastError());
+    return solve_common(P, N, 0, g_next, f, f, tol, restart, maxit, mu, u_next, info);
 }
 
 void mhk_nystrom_destroy(mhk_nystrom *N)

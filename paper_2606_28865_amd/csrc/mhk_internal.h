@@ -143,6 +143,7 @@ struct mhk_plan {
     hipStream_t stream = nullptr;
     bool timing = false;
     int64_t nb = 0, npan = 0, nv = 0, nt = 0, nout = 0;
+    bool targets_are_volume = false;            // targets == volume nodes, same order
     int J = 3;
     double delta = 0, dstar = 0;
     // boundary (caller order)

@@ -1277,6 +1277,11 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     P->nv = v ? v->n : 0;
     P->nt = t->n;
     P->nout = t->n + (t->on_surface ? P->nb : 0);
+    // targets that are exactly the volume nodes, in the same order (the
+    // setting of elliptic marching, where u is carried at the nodes)
+    P->targets_are_volume = P->nv > 0 && P->nt == P->nv &&
+                            memcmp(t->x, v->x, sizeof(double) * P->nv) == 0 &&
+                            memcmp(t->y, v->y, sizeof(double) * P->nv) == 0;
     Host H;
     H.b = b;
     H.v = (v && v->n > 0) ? v : nullptr;
