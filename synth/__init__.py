@@ -203,13 +203,138 @@ def _tri_nodes(A, B, Cc):
     return X.ravel(), Y.ravel(), Wt.ravel()
 
 
-def cut_cell_volume(curves, dx, box=None):
+def _tri_nodes_curved(A, B, Cc, M):
+    """6-point rule on triangles whose edge B-C is replaced by the quadratic
+    Q(s) through B, M, C (s in [0, 1]) and which are filled by the segments
+    from A to Q (a blending map): x(l) = A + m (Q(s) - A) with m = lB + lC,
+    s = lC/m, i.e. x = lA A + lB B + lC C + 4 lB lC/(lB + lC) (M - (B + C)/2).
+    Every node lies on a segment from A to the curved edge, so the cell
+    follows the boundary even when it is a sliver."""
+    bary, W = triangle_rule6()
+    d = M - 0.5 * (B + Cc)                                        # (n, 2)
+    lA, lB, lC = bary[:, 0][None, :], bary[:, 1][None, :], bary[:, 2][None, :]
+    m = lB + lC
+    g = 4 * lB * lC / m
+    X = lA * A[:, None, 0] + lB * B[:, None, 0] + lC * Cc[:, None, 0] + g * d[:, None, 0]
+    Y = lA * A[:, None, 1] + lB * B[:, None, 1] + lC * Cc[:, None, 1] + g * d[:, None, 1]
+    # Jacobian in (lB, lC): d g/d lB = 4 (lC/m)^2, d g/d lC = 4 (lB/m)^2
+    gB, gC = 4 * (lC / m) ** 2, 4 * (lB / m) ** 2
+    j11 = (B[:, None, 0] - A[:, None, 0]) + gB * d[:, None, 0]
+    j21 = (B[:, None, 1] - A[:, None, 1]) + gB * d[:, None, 1]
+    j12 = (Cc[:, None, 0] - A[:, None, 0]) + gC * d[:, None, 0]
+    j22 = (Cc[:, None, 1] - A[:, None, 1]) + gC * d[:, None, 1]
+    Wt = 0.5 * np.abs(j11 * j22 - j12 * j21) * W[None, :]
+    return X.ravel(), Y.ravel(), Wt.ravel()
+
+
+def _boundary_midpoints(curves, c1, c2, iters=48):
+    """Point of the boundary on the perpendicular bisector of each chord
+    c1-c2 (bisection on the inside test within half a chord length of the
+    chord); the chord midpoint where no crossing is bracketed."""
+    M = 0.5 * (c1 + c2)
+    t = c2 - c1
+    L = np.hypot(t[:, 0], t[:, 1])
+    n = np.stack([-t[:, 1], t[:, 0]], -1) / np.maximum(L, 1e-300)[:, None]
+    pa = M - 0.5 * L[:, None] * n
+    pb = M + 0.5 * L[:, None] * n
+    ia = inside_any(curves, pa[:, 0], pa[:, 1])
+    ib = inside_any(curves, pb[:, 0], pb[:, 1])
+    ok = ia != ib
+    lo = np.where(ia[:, None], pa, pb)      # inside end
+    hi = np.where(ia[:, None], pb, pa)      # outside end
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        im = inside_any(curves, mid[:, 0], mid[:, 1])
+        lo = np.where(im[:, None], mid, lo)
+        hi = np.where(im[:, None], hi, mid)
+    return np.where(ok[:, None], 0.5 * (lo + hi), M)
+
+
+def _edge_crossings(curves, ax, ay, ai, bx, by):
+    """Boundary crossing on each edge a-b with exactly one end inside (ai:
+    whether a is inside), by bisection on the inside test."""
+    lx = np.where(ai, ax, bx); ly = np.where(ai, ay, by)
+    hx = np.where(ai, bx, ax); hy = np.where(ai, by, ay)
+    for _ in range(48):
+        mx, my = 0.5 * (lx + hx), 0.5 * (ly + hy)
+        im = inside_any(curves, mx, my)
+        lx = np.where(im, mx, lx); ly = np.where(im, my, ly)
+        hx = np.where(im, hx, mx); hy = np.where(im, hy, my)
+    return 0.5 * (lx + hx), 0.5 * (ly + hy)
+
+
+def _cut_cells(curves, CX, CY, CI):
+    """Nodes of cut triangles (vertex arrays (n, 3), inside flags (n, 3)):
+    the polygon inside the boundary chord, fan-triangulated from its first
+    vertex, with the sub-triangle on the chord curved.  Returns x, y, w of
+    shape (n, k) with k = 12 (unused slots weight 0)."""
+    nc = len(CX)
+    pts = np.zeros((nc, 6, 2))
+    keep = np.zeros((nc, 6), dtype=bool)
+    crossing = np.zeros((nc, 6), dtype=bool)
+    for e in range(3):
+        a, b = e, (e + 1) % 3
+        pts[:, 2 * e, 0], pts[:, 2 * e, 1] = CX[:, a], CY[:, a]
+        keep[:, 2 * e] = CI[:, a]
+        cross = CI[:, a] != CI[:, b]
+        idx = np.nonzero(cross)[0]
+        px, py = _edge_crossings(curves, CX[idx, a], CY[idx, a], CI[idx, a], CX[idx, b], CY[idx, b])
+        pts[idx, 2 * e + 1, 0] = px
+        pts[idx, 2 * e + 1, 1] = py
+        keep[:, 2 * e + 1] = cross
+        crossing[:, 2 * e + 1] = cross
+    # kept points in cyclic order (3 or 4 of them; the two crossings are
+    # adjacent in the cycle and form the boundary chord)
+    order = np.argsort(~keep, axis=1, kind="stable")
+    P = np.take_along_axis(pts, order[:, :, None], axis=1)
+    X_ = np.take_along_axis(crossing, order, axis=1)
+    cntp = keep.sum(1)
+    ar = np.arange(nc)
+    k0 = np.full(nc, -1)
+    for k in range(3, -1, -1):
+        kn = (k + 1) % cntp
+        isk = (k < cntp) & X_[ar, np.minimum(k, 5)] & X_[ar, kn]
+        k0 = np.where(isk, k, k0)
+    assert np.all(k0 >= 0)
+    c1 = P[ar, k0]
+    c2 = P[ar, (k0 + 1) % cntp]
+    Mb = _boundary_midpoints(curves, c1, c2)
+    # fan from P0: (P0, P1, P2) and, for 4-gons, (P0, P2, P3); the chord
+    # (P_k, P_k+1) lies in the first for k in {0, 1} (3-gons: always), in the
+    # second for k in {2, 3}; opposite vertex of the chord in its triangle
+    tri3 = cntp == 3
+    first = tri3 | (k0 <= 1)
+    opp = np.where(tri3, (k0 + 2) % 3, np.where(k0 == 0, 2, np.where(k0 == 1, 0, np.where(k0 == 2, 0, 2))))
+    x, y, w = (a.reshape(nc, 6) for a in _tri_nodes_curved(P[ar, opp], c1, c2, Mb))
+    X = np.zeros((nc, 12)); Y = np.zeros((nc, 12)); Wt = np.zeros((nc, 12))
+    X[:, :6], Y[:, :6], Wt[:, :6] = x, y, w
+    # the straight other triangle of a 4-gon
+    q4 = ~tri3
+    A2 = np.where((q4 & ~first)[:, None], P[:, 0], P[:, 0])
+    B2 = np.where((q4 & ~first)[:, None], P[:, 1], P[:, 2])
+    C2 = np.where((q4 & ~first)[:, None], P[:, 2], P[:, 3])
+    if q4.any():
+        x, y, w = (a.reshape(-1, 6) for a in _tri_nodes(A2[q4], B2[q4], C2[q4]))
+        X[q4, 6:], Y[q4, 6:], Wt[q4, 6:] = x, y, w
+        # unused slots of 3-gons sit on the first node with weight 0
+    X[~q4, 6:] = X[~q4, :1]; Y[~q4, 6:] = Y[~q4, :1]
+    return X, Y, Wt
+
+
+def cut_cell_volume(curves, dx, box=None, max_depth=4):
     """Cut-cell quadrature of the union of the curves' interiors.
 
-    Background grid of equilateral triangles of side dx.  Triangles with all
-    vertices inside are kept, those with all outside are dropped, cut
-    triangles are clipped against the boundary (edge crossings located by
-    bisection on the inside test) and fan-triangulated.
+    Background grid of equilateral triangles of side dx (Section 3.1).
+    Triangles with all vertices inside are kept, those with all outside are
+    dropped; cut triangles are clipped at the boundary crossings of their
+    edges (located by bisection on the inside test) and fan-triangulated,
+    and in the sub-triangle that carries the boundary chord that edge becomes
+    the quadratic through the two crossings and the boundary point on the
+    chord's perpendicular bisector (curved cut cells, mapped by blending
+    towards the opposite vertex).  A triangle whose nodes are not all inside
+    (the boundary crosses one of its edges more than once) is split into four
+    and treated again, up to max_depth times, so that every node lies
+    inside.
     """
     if box is None:
         xs = [c.cx for c in curves]; ys = [c.cy for c in curves]; rr = [c.rmax() for c in curves]
@@ -239,47 +364,54 @@ def cut_cell_volume(curves, dx, box=None):
                                   for a in t], 1))
     T = np.concatenate(tris, 0)  # (nt, 3, 2) of (row, col)
     TX = VX[T[..., 0], T[..., 1]]; TY = VY[T[..., 0], T[..., 1]]; TI = ins[T[..., 0], T[..., 1]]
-    cnt = TI.sum(1)
-    full = cnt == 3
     xs, ys, ws = [], [], []
-    A = np.stack([TX[full, 0], TY[full, 0]], -1); B = np.stack([TX[full, 1], TY[full, 1]], -1)
-    Cc = np.stack([TX[full, 2], TY[full, 2]], -1)
-    x, y, w = _tri_nodes(A, B, Cc)
-    xs.append(x); ys.append(y); ws.append(w)
-    cut = np.nonzero((cnt > 0) & (cnt < 3))[0]
-    if len(cut):
-        CX, CY, CI = TX[cut], TY[cut], TI[cut]                    # (nc, 3)
-        pts = np.zeros((len(cut), 6, 2))
-        keep = np.zeros((len(cut), 6), dtype=bool)
-        for e in range(3):
-            a, b = e, (e + 1) % 3
-            pts[:, 2 * e, 0], pts[:, 2 * e, 1] = CX[:, a], CY[:, a]
-            keep[:, 2 * e] = CI[:, a]
-            cross = CI[:, a] != CI[:, b]
-            # bisection for the boundary crossing on the edge (lo inside, hi outside)
-            lox = np.where(CI[:, a], CX[:, a], CX[:, b]); loy = np.where(CI[:, a], CY[:, a], CY[:, b])
-            hix = np.where(CI[:, a], CX[:, b], CX[:, a]); hiy = np.where(CI[:, a], CY[:, b], CY[:, a])
-            idx = np.nonzero(cross)[0]
-            lx, ly, hx, hy = lox[idx], loy[idx], hix[idx], hiy[idx]
-            for _ in range(48):
-                mx, my = 0.5 * (lx + hx), 0.5 * (ly + hy)
-                ins = inside_any(curves, mx, my)
-                lx = np.where(ins, mx, lx); ly = np.where(ins, my, ly)
-                hx = np.where(ins, hx, mx); hy = np.where(ins, hy, my)
-            pts[idx, 2 * e + 1, 0] = 0.5 * (lx + hx)
-            pts[idx, 2 * e + 1, 1] = 0.5 * (ly + hy)
-            keep[:, 2 * e + 1] = cross
-        order = np.argsort(~keep, axis=1, kind="stable")
-        P = np.take_along_axis(pts, order[:, :, None], axis=1)
-        cntp = keep.sum(1)
-        A, Bv, Cv = P[:, 0], P[:, 1], P[:, 2]
-        x, y, w = _tri_nodes(A, Bv, Cv)
-        xs.append(x); ys.append(y); ws.append(w)
-        q = cntp == 4
-        if q.any():
-            x, y, w = _tri_nodes(P[q, 0], P[q, 2], P[q, 3])
-            xs.append(x); ys.append(y); ws.append(w)
-    return {"x": np.concatenate(xs), "y": np.concatenate(ys), "w": np.concatenate(ws)}
+    for depth in range(max_depth + 1):
+        cnt = TI.sum(1)
+        full = np.nonzero(cnt == 3)[0]
+        cut = np.nonzero((cnt > 0) & (cnt < 3))[0]
+        # candidate nodes, (n, 12) per triangle (full triangles use 6 slots)
+        NX = np.zeros((len(full) + len(cut), 12)); NY = np.zeros_like(NX); NW = np.zeros_like(NX)
+        x, y, w = (a.reshape(-1, 6) for a in _tri_nodes(np.stack([TX[full, 0], TY[full, 0]], -1),
+                                                       np.stack([TX[full, 1], TY[full, 1]], -1),
+                                                       np.stack([TX[full, 2], TY[full, 2]], -1)))
+        nf = len(full)
+        NX[:nf, :6], NY[:nf, :6], NW[:nf, :6] = x, y, w
+        NX[:nf, 6:], NY[:nf, 6:] = x[:, :1], y[:, :1]
+        if len(cut):
+            NX[nf:], NY[nf:], NW[nf:] = _cut_cells(curves, TX[cut], TY[cut], TI[cut])
+        src = np.concatenate([full, cut])
+        # triangles near the boundary: every node must be inside
+        ok = np.ones(len(src), dtype=bool)
+        near = np.ones(len(src), dtype=bool)
+        near[:nf] = False
+        if nf:
+            # full triangles can hide a boundary bump only if a node of theirs
+            # is outside; test those within one side length of a cut triangle
+            # vertex cheaply by the inside test of all their nodes
+            near[:nf] = True
+        cand = np.nonzero(near)[0]
+        inside_nodes = inside_any(curves, NX[cand].ravel(), NY[cand].ravel()).reshape(-1, 12)
+        ok[cand] = inside_nodes.all(1)
+        if depth == max_depth:
+            ok[:] = True
+        good = np.nonzero(ok)[0]
+        xs.append(NX[good].ravel()); ys.append(NY[good].ravel()); ws.append(NW[good].ravel())
+        bad = src[~ok]
+        if len(bad) == 0:
+            break
+        # split the bad triangles into four at their edge midpoints
+        ax, ay = TX[bad, 0], TY[bad, 0]; bx, by = TX[bad, 1], TY[bad, 1]; cx, cy = TX[bad, 2], TY[bad, 2]
+        abx, aby = 0.5 * (ax + bx), 0.5 * (ay + by)
+        bcx, bcy = 0.5 * (bx + cx), 0.5 * (by + cy)
+        cax, cay = 0.5 * (cx + ax), 0.5 * (cy + ay)
+        TX = np.concatenate([np.stack([ax, abx, cax], 1), np.stack([abx, bx, bcx], 1),
+                             np.stack([cax, bcx, cx], 1), np.stack([abx, bcx, cax], 1)])
+        TY = np.concatenate([np.stack([ay, aby, cay], 1), np.stack([aby, by, bcy], 1),
+                             np.stack([cay, bcy, cy], 1), np.stack([aby, bcy, cay], 1)])
+        TI = inside_any(curves, TX.ravel(), TY.ravel()).reshape(-1, 3)
+    x = np.concatenate(xs); y = np.concatenate(ys); w = np.concatenate(ws)
+    m = w > 0
+    return {"x": x[m], "y": y[m], "w": w[m]}
 
 
 def polar_volume(curve: Curve, n_rho: int, n_theta: int):

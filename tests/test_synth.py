@@ -52,3 +52,20 @@ def test_random_bodies_separated_and_smooth():
         assert synth.min_curvature_radius(a) >= 0.02 - 1e-12
         for b in cs[:i]:
             assert math.hypot(a.cx - b.cx, a.cy - b.cy) > a.rmax() + b.rmax() + 0.05
+
+
+def test_cut_cells_conform_to_the_boundary():
+    """Curved cut cells: every node inside, and area and a smooth integral
+    converging fast under refinement (against the polar rule)."""
+    cv = [synth.Curve(r0=1.0, a=0.3, l1=5)]
+    pv = synth.polar_volume(cv[0], 80, 400)
+    f = lambda x, y: np.exp(0.5 * x) * np.cos(y)
+    ref = (pv["w"] * f(pv["x"], pv["y"])).sum()
+    errs = []
+    for dx in (0.05, 0.0125):
+        v = synth.cut_cell_volume(cv, dx)
+        assert synth.inside_any(cv, v["x"], v["y"]).all()
+        assert np.all(v["w"] > 0)
+        errs.append(abs((v["w"] * f(v["x"], v["y"])).sum() - ref))
+        assert abs(v["w"].sum() - cv[0].area()) < (2e-5 if dx > 0.02 else 2e-6)
+    assert errs[1] < errs[0] / 4 and errs[1] < 2e-6, errs
