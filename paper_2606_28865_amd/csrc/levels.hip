@@ -8,15 +8,15 @@
 // pairs with a >= a_max are below the requested accuracy and skipped.
 //
 // Work decomposition: a wavefront owns 64 consecutive targets of the Morton
-// order.  At plan time the union of its targets' cell neighbourhoods (cells
-// of side R_j/2, +-2 cells) is turned into a short list of ranges of the
-// cell-sorted sources.  The wavefront walks these ranges with wave-uniform
-// indices, so each source is read once per wavefront with scalar loads and
-// broadcast to the lanes; each lane keeps its target's sums in registers: no
-// atomics, no barriers in the loop, deterministic summation order.  The
-// kernel table sits in LDS (shared by the 4 wavefronts of a workgroup) with a
-// padded segment stride so that the per-lane gathers of different segments
-// spread over the LDS banks.
+// order.  At plan time the cells (side R_j/4) that can hold a source within
+// R_j of one of its targets are turned into a short list of ranges of the
+// cell-sorted sources.  The wavefront reads its ranges and then, range by
+// range, 64 sources at a time with vector loads (lane l holds source l) and
+// hands each source to all lanes with readlane; each lane keeps its target's
+// sums in registers: no atomics, no barriers in the loop, deterministic
+// summation order.  The kernel table sits in LDS (shared by the wavefronts of
+// a workgroup) with a padded segment stride so that the per-lane gathers of
+// different segments spread over the LDS banks.
 //
 // Precision: T = double (FP64 path) or float (FP32 path).  In the FP32 path
 // the separation x - x_q is formed in FP64 from FP64 positions and rounded
@@ -86,6 +86,18 @@ struct LevelArgs {
 };
 
 
+// Value of lane k (wave-uniform k) for the whole wave.
+__device__ inline double bcast(double v, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float bcast(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
 template <int BCH, typename T, int NC, int STRIDE>
 __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
@@ -96,9 +108,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
     for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
     __syncthreads();
 
-    // one wavefront = LV_WAVE consecutive targets with their own source ranges;
-    // every index below derived from the wave number is wave-uniform, so the
-    // source data is read with scalar loads and broadcast to the lanes
+    // one wavefront = LV_WAVE consecutive targets with their own source ranges
+    // (the wave number is wave-uniform)
     const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (LV_BLOCK / LV_WAVE) + tid / LV_WAVE]);
     const int64_t t = (int64_t)wave * LV_WAVE + (tid % LV_WAVE);
     const bool active = t < A.nout;
@@ -145,46 +156,44 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
             }
         }
     };
-    // sources are fetched PF at a time, one batch ahead of their use
-    constexpr int PF = 4;
+    // The wave's ranges and, per range, its sources 64 at a time are read
+    // with vector loads, lane l holding item l, and handed to the whole wave
+    // one by one with readlane: no scalar loads are in flight in the loop,
+    // so the waits for the kernel-table reads from LDS (which share their
+    // counter with scalar loads) never wait for source data.
+    const int lane = tid % LV_WAVE;
     const int r0 = A.blk_ofs[wave], r1 = A.blk_ofs[wave + 1];
-    for (int r = r0; r < r1; ++r) {
-        const int s0 = A.blk_rng[2 * r], s1 = A.blk_rng[2 * r + 1];
-        double nx[PF], ny[PF];
-        T nqs[PF][BCH], nqx[PF][BCH], nqy[PF][BCH];
-        auto fetch = [&](int base) {
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                const int s = min(base + k, s1 - 1);
-                nx[k] = A.sx[s];
-                ny[k] = A.sy[s];
-#pragma unroll
-                for (int b = 0; b < BCH; ++b) {
-                    nqs[k][b] = A.want_s ? qs[b][s] : (T)0;
-                    nqx[k][b] = A.want_d ? qx[b][s] : (T)0;
-                    nqy[k][b] = A.want_d ? qy[b][s] : (T)0;
-                }
-            }
-        };
-        fetch(s0);
-        for (int s = s0; s < s1; s += PF) {
-            double cx[PF], cy[PF];
-            T cqs[PF][BCH], cqx[PF][BCH], cqy[PF][BCH];
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                cx[k] = nx[k];
-                cy[k] = ny[k];
+    for (int rb = r0; rb < r1; rb += LV_WAVE) {
+        int my_s0 = 0, my_s1 = 0;
+        if (rb + lane < r1) {
+            my_s0 = A.blk_rng[2 * (rb + lane)];
+            my_s1 = A.blk_rng[2 * (rb + lane) + 1];
+        }
+        const int rcnt = min(LV_WAVE, r1 - rb);
+        for (int ri = 0; ri < rcnt; ++ri) {
+            const int s0 = __builtin_amdgcn_readlane(my_s0, ri), s1 = __builtin_amdgcn_readlane(my_s1, ri);
+            for (int base = s0; base < s1; base += LV_WAVE) {
+                const int sl = min(base + lane, s1 - 1);
+                const double lx = A.sx[sl], ly = A.sy[sl];
+                T lqs[BCH], lqx[BCH], lqy[BCH];
 #pragma unroll
                 for (int b = 0; b < BCH; ++b) {
-                    cqs[k][b] = nqs[k][b];
-                    cqx[k][b] = nqx[k][b];
-                    cqy[k][b] = nqy[k][b];
+                    lqs[b] = A.want_s ? qs[b][sl] : (T)0;
+                    lqx[b] = A.want_d ? qx[b][sl] : (T)0;
+                    lqy[b] = A.want_d ? qy[b][sl] : (T)0;
+                }
+                const int cnt = min(LV_WAVE, s1 - base);
+                for (int k = 0; k < cnt; ++k) {
+                    T cqs[BCH], cqx[BCH], cqy[BCH];
+#pragma unroll
+                    for (int b = 0; b < BCH; ++b) {
+                        cqs[b] = bcast(lqs[b], k);
+                        cqx[b] = bcast(lqx[b], k);
+                        cqy[b] = bcast(lqy[b], k);
+                    }
+                    pair(bcast(lx, k), bcast(ly, k), cqs, cqx, cqy);
                 }
             }
-            if (s + PF < s1) fetch(s + PF);
-#pragma unroll
-            for (int k = 0; k < PF; ++k)
-                if (s + k < s1) pair(cx[k], cy[k], cqs[k], cqx[k], cqy[k]);
         }
     }
     if (active) {
