@@ -34,7 +34,11 @@
  *  - dyadic level j uses every panel bisected j times, geometry and density
  *    at the child nodes interpolated with the parent's degree-15 polynomial;
  *  - V at exterior targets closer than sqrt(delta)(12+2 alpha sqrt(delta))
- *    to the boundary has no formula in the paper and is returned as NaN.
+ *    to the boundary has no formula in the paper (Lemma 4.8 holds inside);
+ *    it is taken from the complement domain, which contains the target:
+ *    V_L = delta f0 [(1 - e^{-c2^2})/c2^2 - W0/4] with f0 the value of f at
+ *    the closest boundary point (panel interpolation of f at the boundary
+ *    nodes, the on-surface entries of f_trg); NaN when those are not given.
  */
 #include <math.h>
 #include <stdint.h>
@@ -464,19 +468,26 @@ static or_sd or_local_layer_on(double ds, double alpha, double kappa0, double si
 }
 
 /* Volume local part with delta (Lemma 4.8 / Cor. 4.10 / Cor. 4.11).
- * where: 0 interior off-surface, 1 on-surface, 2 exterior off-surface. */
+ * where: 0 interior off-surface, 1 on-surface, 2 exterior off-surface.
+ * Exterior targets (the paper's lemma holds inside Omega): the local
+ * integral over Omega is the whole-plane integral minus the one over the
+ * complement, and the complement is a domain that contains x, so Lemma 4.8
+ * applies to it; to first order, with f taken at the closest boundary
+ * point (f0; the difference to f(x) is of the neglected order),
+ * V_L = delta f0 [(1 - e^{-c2^2})/c2^2 - W0(c1, c2)/4].  f0 is NaN when f on
+ * the boundary is unknown. */
 static double or_local_vol(double r, int where, double delta, double alpha, double f)
 {
     __float128 sq = sqrtq((__float128)delta), c2 = alpha * sq;
     double band = (double)(sq * (12 + 2 * c2));
     if (where == 1)
         return (double)(delta * f * (-expm1q(-c2 * c2)) / (2 * c2 * c2));
-    if (where == 2)
-        return (r >= band) ? 0.0 : NAN;
     if (r >= band)
-        return (double)(delta * f * (-expm1q(-c2 * c2)) / (c2 * c2));
+        return where == 2 ? 0.0 : (double)(delta * f * (-expm1q(-c2 * c2)) / (c2 * c2));
     double c[17];
     or_local_coeffs(r / (double)sq, (double)c2, c);
+    if (where == 2)
+        return delta * f * ((double)(-expm1q(-c2 * c2) / (c2 * c2)) - c[15] / 4.0);
     return delta * f * c[15] / 4.0;
 }
 
@@ -501,13 +512,17 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
         for (int j = 1; j <= P->J; ++j) or_refine(P, j, &lev[j - 1]);
     }
     /* panel Legendre coefficients of sigma, mu, kappa for local terms */
-    double *cs = NULL, *cm = NULL, *ck = NULL;
+    double *cs = NULL, *cm = NULL, *ck = NULL, *cf = NULL;
+    /* f on the boundary nodes: the on-surface entries of f_trg */
+    const double *fb = (P->on_surface && P->f_trg) ? P->f_trg + P->n_trg : NULL;
     if (P->parts & 4) {
         cs = calloc(nb, sizeof(double)); cm = calloc(nb, sizeof(double)); ck = calloc(nb, sizeof(double));
+        cf = calloc(nb, sizeof(double));
         for (int64_t p = 0; p < P->n_panels; ++p) {
             if (P->sigma) or_coeffs(P->sigma + p * OR_NGL, 1, cs + p * OR_NGL);
             if (P->mu) or_coeffs(P->mu + p * OR_NGL, 1, cm + p * OR_NGL);
             or_coeffs(P->bkappa + p * OR_NGL, 1, ck + p * OR_NGL);
+            if (fb) or_coeffs(fb + p * OR_NGL, 1, cf + p * OR_NGL);
         }
     }
 
@@ -588,6 +603,17 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
                     s += l.S; d += l.D;
                 }
                 if (P->f_trg) {
+                    if (!inside) {
+                        /* f at the closest boundary point (exterior targets) */
+                        double f0 = NAN;
+                        if (fb) {
+                            double P_[OR_NGL], dP[OR_NGL], ddP[OR_NGL];
+                            or_legendre_all(cp.t, P_, dP, ddP);
+                            f0 = 0.0;
+                            for (int q = 0; q < OR_NGL; ++q) f0 += cf[cp.panel * OR_NGL + q] * P_[q];
+                        }
+                        fx = f0;
+                    }
                     v += or_local_vol(cp.r, inside ? 0 : 2, delta, alpha, fx);
                 }
             }
@@ -595,6 +621,6 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
         S[o] = s; D[o] = d; V[o] = v;
     }
     if (lev) { for (int j = 0; j < P->J; ++j) or_level_free(&lev[j]); free(lev); }
-    free(cs); free(cm); free(ck);
+    free(cs); free(cm); free(ck); free(cf);
     return 0;
 }

@@ -236,6 +236,65 @@ def test_circle_closed_forms_full_split():
     assert e[2, 0] < 5e-8 and e[2, 1] < 2e-7, e
 
 
+def test_local_volume_exterior_disk():
+    """Exterior targets near a disk (the complement-domain reading of Lemma
+    4.8): V_L = int_0^delta int_disk H dt dx' for f = 1 against the first-
+    order formula delta f0 [(1 - e^{-c2^2})/c2^2 - W0/4], converging at order
+    3/2; the next term of Lemma 4.8 for the complement (curvature -kappa)
+    accounts for the error."""
+    R, alpha = 0.5, 10.0
+    bnd = synth.discretize([synth.Curve(r0=R)], 32)
+    nb = len(bnd["x"])
+
+    def mass(t, rho):
+        f = lambda s: s / (2 * t) * math.exp(-(s - rho) ** 2 / (4 * t)) * sp.ive(0, s * rho / (2 * t))
+        lo, hi = max(0.0, rho - 40 * math.sqrt(t)), min(R, rho + 40 * math.sqrt(t))
+        return integrate.quad(f, lo, hi, epsabs=0, epsrel=1e-12, limit=200)[0] if hi > lo else 0.0
+
+    errs, nxt = [], []
+    for d in (1e-3, 2.5e-4, 6.25e-5):
+        rho = R + 1.2 * math.sqrt(d)
+        ref = integrate.quad(lambda t: math.exp(-alpha ** 2 * t) * mass(t, rho), 0, d, epsabs=0, epsrel=1e-11,
+                             limit=200)[0]
+        # f on the boundary nodes comes from the on-surface entries of f_trg;
+        # the exterior target's own entry is not used
+        P = O.Problem(alpha, d, 0, bnd, targets=(np.array([rho]), np.array([0.0])), inside=np.array([0]),
+                      on_surface=True, f_trg=np.concatenate([[7.0], np.ones(nb)]), parts=O.PART_LOCAL)
+        _, _, V = P.eval()
+        errs.append(abs(V[0] - ref))
+        q0 = O.local_coeffs(1.2, alpha * math.sqrt(d))["Q0"]
+        nxt.append(abs(V[0] - d ** 1.5 * (1 / R) * q0 / 8 - ref))
+    assert errs[0] / errs[2] > 30, errs
+    assert errs[2] < 2e-7, errs
+    assert all(n < e / 10 for n, e in zip(nxt, errs)), (nxt, errs)
+    # without f on the boundary the exterior local part is unknown: NaN
+    P = O.Problem(alpha, 1e-3, 0, bnd, targets=(np.array([R + 0.01]), np.array([0.0])), inside=np.array([0]),
+                  f_trg=np.array([1.0]), parts=O.PART_LOCAL)
+    assert np.isnan(P.eval()[2][0])
+
+
+def test_disk_volume_exterior_closed_form():
+    """V[1] outside a disk, (R/a) I1(a R) K0(a r): history + exterior local
+    part (polar volume rule) within the band converging at order 3/2 in
+    delta, and exact beyond the band (history part alone)."""
+    R, alpha = 0.5, 10.0
+    cv = synth.Curve(r0=R)
+    b = synth.discretize([cv], 16)
+    nb = len(b["x"])
+    vol = synth.polar_volume(cv, 80, 400)
+    rr = R + np.array([0.001, 0.01, 0.3])
+    ex = R * sp.i1(alpha * R) * sp.k0(alpha * rr) / alpha
+    e = []
+    for d in (8e-4, 5e-5):
+        P = O.Problem(alpha, d, 3, b, volume=vol, targets=(rr, np.zeros(3)), inside=np.zeros(3), on_surface=True,
+                      f_vol=np.ones(len(vol["x"])), f_trg=np.ones(3 + nb), parts=O.PART_HISTORY | O.PART_LOCAL)
+        _, _, V = P.eval()
+        e.append(np.abs(V[:3] - ex) / np.abs(ex).max())
+    e = np.array(e)
+    assert np.all(e[0, :2] / e[1, :2] > 30), e           # 16x delta: order 3/2 gives 64
+    assert e[1, :2].max() < 5e-5 and e[1, 2] < 1e-14, e
+
+
 def test_disk_volume_closed_form():
     """V[1] inside a disk: (1 - a R K1(a R) I0(a r))/a^2 (history + local,
     polar volume rule), at targets farther than sqrt(delta)(12 + 2 a sqrt(delta))
