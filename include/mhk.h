@@ -36,9 +36,12 @@
  *  - Target outputs: the N_T off-surface targets first, then, if
  *    targets.on_surface is set, the N_B boundary nodes as on-surface targets
  *    (D there is the direct value, i.e. the principal value of eq. (jumprel)).
- *    V has no local formula at exterior targets closer to the boundary than
- *    sqrt(delta)(12 + 2 alpha sqrt(delta)) (Lemma 4.8 holds for x in Omega);
- *    those entries are NaN.
+ *    At exterior targets closer to the boundary than sqrt(delta)(12 + 2 alpha
+ *    sqrt(delta)) the local part of V comes from the complement domain
+ *    (Lemma 4.8 holds for x in Omega; the complement contains x): first
+ *    order, with f at the closest boundary point interpolated from f at the
+ *    boundary nodes, i.e. the on-surface entries of f_trg.  Without
+ *    on-surface targets those entries are NaN.
  */
 #ifndef MHK_H
 #define MHK_H

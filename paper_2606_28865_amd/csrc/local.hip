@@ -15,12 +15,16 @@
 
 namespace mhk {
 
-// Legendre coefficients of sigma and mu on every panel: c = Leg * f (FP64).
+// Legendre coefficients of sigma, mu and (for the exterior volume part) f
+// at the boundary nodes on every panel: c = Leg * f (FP64).  f at the
+// boundary nodes is the on-surface part of f_trg ([B][nout], entries nt..).
 template <typename T>
 __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const double *__restrict__ leg,
                                                       const T *__restrict__ sigma,
                                                       const T *__restrict__ mu,
-                                                      double *__restrict__ cs, double *__restrict__ cm)
+                                                      const T *__restrict__ f_trg, int64_t nout, int64_t nt,
+                                                      double *__restrict__ cs, double *__restrict__ cm,
+                                                      double *__restrict__ cf)
 {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t tot = npan * NGL * B;
@@ -41,6 +45,14 @@ __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const
 #pragma unroll
         for (int i = 0; i < NGL; ++i) v = fma(row[i], (double)f[i], v);
         cm[id] = v;
+    }
+    if (f_trg) {
+        const int64_t b = pb / npan, p = pb % npan;
+        const T *f = f_trg + b * nout + nt + p * NGL;
+        double v = 0;
+#pragma unroll
+        for (int i = 0; i < NGL; ++i) v = fma(row[i], (double)f[i], v);
+        cf[id] = v;
     }
 }
 
@@ -98,6 +110,7 @@ struct LocalArgs {
     const double *bx, *by, *bk;
     const T *sigma, *mu, *f_trg;
     const double *cs, *cm;
+    const double *cf;      // Legendre coefficients of f on the boundary, or NULL
     const double *pcx, *pcy, *pck, *ends, *gl_t;
     const int32_t *prev, *next, *node, *cell_start;
     const double *nx_s, *ny_s;
@@ -166,6 +179,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
     double tbest = 0.0;
     double P0 = 0, P1 = 0, U0 = 0, U1 = 0, U2 = 0, kap = 0, mss_fac1 = 0, mss_fac2 = 0;
     double vfac = 0.0;             // V local = delta * f * vfac (or NaN)
+    bool v_ext = false;            // exterior target in the band: f at the closest point
     if (do_local) {
         if (on) {
             vfac = -expm1(-c2v * c2v) / (2.0 * c2v * c2v);          // Cor. 4.10
@@ -202,20 +216,28 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                 }
                 r = sqrt(d2b);
             }
-            // volume part (Lemma 4.8 first order inside the band, Cor. 4.11 beyond)
-            if (inside) {
-                if (r < A.band_v) {
-                    const double c1v = r / sv, a = 0.5 * c1v;
-                    const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
-                    const double pre = exp(-a * a - c2v * c2v);
-                    // W0 = (4 - 4 e^{-c2^2} + 2 lambda - Phi_+)/c2^2, lambda = e^{-c2^2} erfc(c1/2)
-                    const double W0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
+            // volume part (Lemma 4.8 first order inside the band, Cor. 4.11
+            // beyond).  Exterior targets in the band: the local integral over
+            // Omega is the whole-plane one minus the one over the complement,
+            // a domain that contains x, so V_L = delta f0 [(1 - e^{-c2^2})/c2^2
+            // - W0/4] with f0 = f at the closest boundary point, from the
+            // panel expansion of f at the boundary nodes (NaN without them).
+            if (r < A.band_v) {
+                const double c1v = r / sv, a = 0.5 * c1v;
+                const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
+                const double pre = exp(-a * a - c2v * c2v);
+                // W0 = (4 - 4 e^{-c2^2} + 2 lambda - Phi_+)/c2^2, lambda = e^{-c2^2} erfc(c1/2)
+                const double W0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
+                if (inside) {
                     vfac = 0.25 * W0;
+                } else if (A.cf && pbest >= 0) {
+                    vfac = -expm1(-c2v * c2v) / (c2v * c2v) - 0.25 * W0;
+                    v_ext = true;
                 } else {
-                    vfac = -expm1(-c2v * c2v) / (c2v * c2v);
+                    vfac = NAN;
                 }
             } else {
-                vfac = (r < A.band_v) ? NAN : 0.0;
+                vfac = inside ? -expm1(-c2v * c2v) / (c2v * c2v) : 0.0;
             }
             if (r < A.band_s && pbest >= 0) {
                 near_s = true;
@@ -274,7 +296,11 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
         }
         if (wv) {
             double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
-            if (do_local) v += A.delta * (double)A.f_trg[ob] * vfac;
+            if (do_local) {
+                const double f = v_ext ? leg1(A.cf + ((size_t)b * A.npan + pbest) * NGL, tbest)
+                                       : (double)A.f_trg[ob];
+                v += A.delta * f * vfac;
+            }
             A.out_v[ob] = (T)v;
         }
     }
@@ -295,22 +321,24 @@ hipError_t launch_fill(mhk_plan *P, void *p, int64_t n)
 }
 
 template <typename T>
-static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu)
+static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd)
 {
     const int64_t tot = P->npan * NGL * P->p.batch;
     hipLaunchKernelGGL(k_panel_coeffs<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
-                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, P->loc.csig, P->loc.cmu);
+                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, (const T *)f_bnd, P->nout, P->nt,
+                       P->loc.csig, P->loc.cmu, P->loc.cf);
     return hipGetLastError();
 }
 
-hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu)
+hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd)
 {
-    return P->p.prec == MHK_FP64 ? panel_coeffs<double>(P, sigma, mu) : panel_coeffs<float>(P, sigma, mu);
+    return P->p.prec == MHK_FP64 ? panel_coeffs<double>(P, sigma, mu, f_bnd)
+                                 : panel_coeffs<float>(P, sigma, mu, f_bnd);
 }
 
 template <typename T>
 static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                          void *out_s, void *out_d, void *out_v)
+                          void *out_s, void *out_d, void *out_v, bool have_fb)
 {
     LocalArgs<T> A;
     A.nout = P->nout;
@@ -331,6 +359,7 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
     A.f_trg = (const T *)f_trg;
     A.cs = P->loc.csig;
     A.cm = P->loc.cmu;
+    A.cf = have_fb ? P->loc.cf : nullptr;
     A.pcx = P->loc.cx;
     A.pcy = P->loc.cy;
     A.pck = P->loc.ck;
@@ -362,10 +391,10 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
 }
 
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                        void *out_s, void *out_d, void *out_v)
+                        void *out_s, void *out_d, void *out_v, bool have_fb)
 {
-    if (P->p.prec == MHK_FP64) return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v);
-    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v);
+    if (P->p.prec == MHK_FP64) return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb);
+    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb);
 }
 
 }  // namespace mhk

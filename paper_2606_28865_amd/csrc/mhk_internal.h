@@ -133,6 +133,7 @@ struct Local {
     double *gl_t = nullptr;                       // [16] Gauss-Legendre abscissae
     int32_t *prev = nullptr, *next = nullptr;     // panel neighbours within each curve
     double *csig = nullptr, *cmu = nullptr;       // per eval: [batch][n_panels][16] (FP64)
+    double *cf = nullptr;                         // f at the boundary nodes, same layout
 };
 
 }  // namespace mhk
@@ -171,9 +172,9 @@ namespace mhk {
 // are of the plan's precision
 hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu);
 hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d);
-hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu);
+hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd);
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
-                        const void *f_trg, void *out_s, void *out_d, void *out_v);
+                        const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);

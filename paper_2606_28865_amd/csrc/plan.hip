@@ -1259,6 +1259,7 @@ mhk_status build_local(mhk_plan *P, Host &H)
     TRY(upload(P, &C.next, next.data(), npan));
     TRY(dalloc(P, &C.csig, (int64_t)P->p.batch * nb));
     TRY(dalloc(P, &C.cmu, (int64_t)P->p.batch * nb));
+    TRY(dalloc(P, &C.cf, (int64_t)P->p.batch * nb));
     return MHK_OK;
 }
 
@@ -1412,7 +1413,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         int64_t ns = nb << j;
         s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
     }
-    s += nb * (8 * 3 + 4) + 2 * B * nb * 8;   // local
+    s += nb * (8 * 3 + 4) + 3 * B * nb * 8;   // local
     if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {
@@ -1526,9 +1527,13 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
         }
     }
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], st));
-    if ((parts & MHK_PART_LOCAL) && (ws || wd)) MHK_HIP(launch_panel_coeffs(P, ws ? sigma : nullptr, wd ? mu : nullptr));
+    // f at the boundary nodes (the on-surface entries of f_trg) gives the
+    // local volume part at exterior targets near the boundary
+    const bool have_fb = wv && (parts & MHK_PART_LOCAL) && P->nout > P->nt;
+    if ((parts & MHK_PART_LOCAL) && (ws || wd || have_fb))
+        MHK_HIP(launch_panel_coeffs(P, ws ? sigma : nullptr, wd ? mu : nullptr, have_fb ? f_trg : nullptr));
     MHK_HIP(launch_local(P, parts, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_trg : nullptr,
-                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr));
+                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb));
     if (P->timing) {
         MHK_HIP(hipEventRecord(P->ev[7], st));
         MHK_HIP(hipEventSynchronize(P->ev[7]));

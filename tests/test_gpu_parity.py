@@ -178,3 +178,38 @@ def test_multibody_sampled(alpha, trunc):
     errs = [rel_err(S[0][sub], So), rel_err(D[0][sub], Do), rel_err(V[0][sub], Vo)]
     print(f"multibody errs {errs} n {info['n_fine']}", flush=True)
     assert max(errs) < TOL
+
+
+def test_exterior_volume_targets():
+    """V at exterior targets near the boundary (complement-domain form of the
+    local part, f taken at the closest boundary point from f at the boundary
+    nodes), with two densities of different sources per call: targets along
+    the outward normals of config 0's starfish at distances 1e-4 .. 0.3."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    print("case exterior V targets config0 batch 2", flush=True)
+    t0 = np.linspace(0.05, 2 * np.pi, 40, endpoint=False)
+    g, g1, _ = w.curves[0].eval(t0)
+    nrm = (g1.imag - 1j * g1.real) / np.abs(g1)
+    z = np.concatenate([g + h * nrm for h in (1e-4, 1e-3, 1e-2, 0.05, 0.3)])
+    tx, ty = z.real, z.imag
+    ins = np.zeros(len(tx), np.int8)
+    prm = M.make_params(alpha=10.0, tol=TOL, dx=w.dx, batch=2)
+    plan = M.Plan(prm, w.boundary, w.volume, (tx, ty, ins), on_surface=True)
+    info = plan.info()
+    fsrc2 = synth.gauss_source(np.random.default_rng(3), np.array([0.2, -0.3]), np.array([0.1, 0.4]))
+    X = np.concatenate([tx, w.boundary["x"]]); Y = np.concatenate([ty, w.boundary["y"]])
+    fv = np.stack([w.f_vol, fsrc2(w.volume["x"], w.volume["y"])])
+    ft = np.stack([w.meta["fsrc"](X, Y), fsrc2(X, Y)])
+    z0 = np.zeros((2, w.n_b))
+    out = plan.eval(None, None, _dev(fv), _dev(ft))
+    torch.cuda.synchronize()
+    V = out[2].cpu().numpy()
+    for b in range(2):
+        P = O.Problem(10.0, info["delta"], 3, w.boundary, volume=w.volume, targets=(tx, ty), inside=ins,
+                      on_surface=True, sigma=z0[b], mu=z0[b], f_vol=fv[b], f_trg=ft[b])
+        _, _, Vo = P.eval()
+        e = rel_err(V[b], Vo)
+        print(f"exterior V batch {b}: err {e:.2e}, finite {np.isfinite(Vo).all()}", flush=True)
+        assert np.isfinite(Vo).all()
+        assert e < TOL
