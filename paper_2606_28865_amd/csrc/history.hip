@@ -26,6 +26,7 @@ namespace mhk {
 // threads per spreading / interpolation workgroup: the sources (targets) sit
 // in a few hundred busy tiles, so each tile gets 16 wavefronts
 constexpr int HB = 1024;
+constexpr int SB = 1024;   // threads per spreading workgroup
 
 template <typename T>
 struct SpreadArgs {
@@ -61,13 +62,13 @@ __device__ inline void window_weights(double g, const T *__restrict__ cf, int &m
 }
 
 template <int W, typename T>
-__global__ void __launch_bounds__(HB) k_spread(SpreadArgs<T> A)
+__global__ void __launch_bounds__(SB) k_spread(SpreadArgs<T> A)
 {
     __shared__ T tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
     const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const int tx = tile % A.ntile, ty = tile / A.ntile;
     const int x0 = tx * TILE, y0 = ty * TILE;
-    for (int i = tid; i < TILE * TILE; i += HB) tileS[i] = tileV[i] = tileX[i] = tileY[i] = (T)0;
+    for (int i = tid; i < TILE * TILE; i += SB) tileS[i] = tileV[i] = tileX[i] = tileY[i] = (T)0;
     __syncthreads();
     const bool has_b = A.sigma || A.mu;
     for (int dty = -1; dty <= 1; ++dty) {
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(HB) k_spread(SpreadArgs<T> A)
         const int xa = max(tx - 1, 0), xb = min(tx + 1, A.ntile - 1);
         if (has_b) {
             const int s0 = A.btile[tyy * A.ntile + xa], s1 = A.btile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += HB) {
+            for (int s = s0 + tid; s < s1; s += SB) {
                 const double gx = A.bgx[s], gy = A.bgy[s];
                 // window start; skip sources whose window misses this tile
                 // before evaluating any window value
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(HB) k_spread(SpreadArgs<T> A)
         }
         if (A.f_vol) {
             const int s0 = A.vtile[tyy * A.ntile + xa], s1 = A.vtile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += HB) {
+            for (int s = s0 + tid; s < s1; s += SB) {
                 const double gx = A.vgx[s], gy = A.vgy[s];
                 if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
                     (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(HB) k_spread(SpreadArgs<T> A)
     __syncthreads();
     const size_t fs = (size_t)A.B * A.field;
     T *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
-    for (int i = tid; i < TILE * TILE; i += HB) {
+    for (int i = tid; i < TILE * TILE; i += SB) {
         const size_t o = (size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE);
         gS[o] = tileS[i];
         gV[o] = tileV[i];
@@ -299,9 +300,11 @@ __global__ void __launch_bounds__(256) k_trunc_samples(double *buf, int64_t n2, 
     if (id >= n2 * n2) return;
     const int64_t iy = id / n2, ix = id % n2;
     const double x = (ix < n2 / 2 ? ix : ix - n2) * h, y = (iy < n2 / 2 ? iy : iy - n2) * h;
-    const double r = sqrt(x * x + y * y);
+    const double ax = fabs(x), ay = fabs(y);
     double v = 0.0;
-    if (r < rcut) v = h * h * history_kernel(r, alpha, delta, gt, gw) * 0.5 * erfc((r - rmid) * slope);
+    if (ax < rcut && ay < rcut)
+        v = h * h * history_kernel(sqrt(x * x + y * y), alpha, delta, gt, gw) * 0.25 * erfc((ax - rmid) * slope) *
+            erfc((ay - rmid) * slope);
     buf[iy * (n2 + 2) + ix] = v;
 }
 
@@ -344,7 +347,7 @@ template <int W, typename T>
 static hipError_t spread_w(mhk_plan *P, const SpreadArgs<T> &A)
 {
     dim3 grid((unsigned)(A.ntile * A.ntile), (unsigned)A.B);
-    hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(HB), 0, P->stream, A);
+    hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(SB), 0, P->stream, A);
     return hipGetLastError();
 }
 

@@ -108,21 +108,27 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
     for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
     __syncthreads();
 
-    // one wavefront = LV_WAVE consecutive targets with their own source ranges
-    // (the wave number is wave-uniform)
+    // one wavefront = LV_TPW consecutive targets with their own source ranges
+    // (the wave number is wave-uniform); lane l holds targets l, l + 64, ...
     const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (LV_BLOCK / LV_WAVE) + tid / LV_WAVE]);
-    const int64_t t = (int64_t)wave * LV_WAVE + (tid % LV_WAVE);
-    const bool active = t < A.nout;
-    double x = 0, y = 0;
-    if (active) {
-        x = A.tx[t];
-        y = A.ty[t];
+    double x[LV_TPL], y[LV_TPL];
+    int64_t t[LV_TPL];
+#pragma unroll
+    for (int i = 0; i < LV_TPL; ++i) {
+        t[i] = (int64_t)wave * LV_TPW + i * LV_WAVE + (tid % LV_WAVE);
+        x[i] = y[i] = 0.0;
+        if (t[i] < A.nout) {
+            x[i] = A.tx[t[i]];
+            y[i] = A.ty[t[i]];
+        }
     }
     const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
     const T inv4d = (T)A.inv4d, a_max = (T)A.a_max, seg_inv = (T)A.seg_inv;
-    T S[BCH], D[BCH];
+    T S[LV_TPL][BCH], D[LV_TPL][BCH];
 #pragma unroll
-    for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
+    for (int i = 0; i < LV_TPL; ++i)
+#pragma unroll
+        for (int b = 0; b < BCH; ++b) S[i][b] = D[i][b] = (T)0;
     const T *qs[BCH], *qx[BCH], *qy[BCH];
 #pragma unroll
     for (int b = 0; b < BCH; ++b) {
@@ -132,27 +138,30 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
         qy[b] = A.q + ((size_t)2 * A.B + bb) * A.n_src;
     }
 
-    // one source pair-evaluation
+    // one source against the lane's targets
     auto pair = [&](double sxv, double syv, const T *qsv, const T *qxv, const T *qyv) {
-        const T dx = (T)(x - sxv), dy = (T)(y - syv);
-        const T a = (dx * dx + dy * dy) * inv4d;
-        if (a < a_max) {
-            const T f = a * seg_inv;
-            const int sg = (int)f;
-            const T v = (T)2 * (f - (T)sg) - (T)1;
-            const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
-            T2 cc = c[NC - 1];
-            T ks = cc.x, kd = cc.y;
 #pragma unroll
-            for (int k = NC - 2; k >= 0; --k) {
-                cc = c[k];
-                ks = fma(ks, v, cc.x);
-                kd = fma(kd, v, cc.y);
-            }
+        for (int i = 0; i < LV_TPL; ++i) {
+            const T dx = (T)(x[i] - sxv), dy = (T)(y[i] - syv);
+            const T a = (dx * dx + dy * dy) * inv4d;
+            if (a < a_max) {
+                const T f = a * seg_inv;
+                const int sg = (int)f;
+                const T v = (T)2 * (f - (T)sg) - (T)1;
+                const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
+                T2 cc = c[NC - 1];
+                T ks = cc.x, kd = cc.y;
 #pragma unroll
-            for (int b = 0; b < BCH; ++b) {
-                S[b] = fma(qsv[b], ks, S[b]);
-                D[b] = fma(fma(qxv[b], dx, qyv[b] * dy), kd, D[b]);
+                for (int k = NC - 2; k >= 0; --k) {
+                    cc = c[k];
+                    ks = fma(ks, v, cc.x);
+                    kd = fma(kd, v, cc.y);
+                }
+#pragma unroll
+                for (int b = 0; b < BCH; ++b) {
+                    S[i][b] = fma(qsv[b], ks, S[i][b]);
+                    D[i][b] = fma(fma(qxv[b], dx, qyv[b] * dy), kd, D[i][b]);
+                }
             }
         }
     };
@@ -196,13 +205,16 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
             }
         }
     }
-    if (active) {
 #pragma unroll
-        for (int b = 0; b < BCH; ++b) {
-            if (b < nbh) {
-                const size_t o = (size_t)(b0 + b) * A.nout + t;
-                if (A.want_s) A.acc_s[o] += S[b];
-                if (A.want_d) A.acc_d[o] += D[b];
+    for (int i = 0; i < LV_TPL; ++i) {
+        if (t[i] < A.nout) {
+#pragma unroll
+            for (int b = 0; b < BCH; ++b) {
+                if (b < nbh) {
+                    const size_t o = (size_t)(b0 + b) * A.nout + t[i];
+                    if (A.want_s) A.acc_s[o] += S[i][b];
+                    if (A.want_d) A.acc_d[o] += D[i][b];
+                }
             }
         }
     }
@@ -251,7 +263,7 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.want_s = want_s;
     A.want_d = want_d;
     const int bch = B == 1 ? 1 : LV_BCH;
-    dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK), (unsigned)((B + bch - 1) / bch));
+    dim3 grid((unsigned)((P->nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)), (unsigned)((B + bch - 1) / bch));
     const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE * 2;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (bch == 1) {

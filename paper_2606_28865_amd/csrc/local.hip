@@ -87,6 +87,26 @@ __device__ inline void leg2(const double *__restrict__ ca, const double *__restr
     }
 }
 
+// Value and first two t-derivatives of one Legendre series at t.
+__device__ inline void leg2s(const double *__restrict__ c, double t, double &v0, double &v1, double &v2)
+{
+    double pm = 1.0, p = t, dm = 0.0, d = 1.0, em = 0.0, e = 0.0;
+    v0 = c[0] + c[1] * t;
+    v1 = c[1];
+    v2 = 0.0;
+#pragma unroll
+    for (int k = 1; k < NGL - 1; ++k) {
+        const double pn = ((2.0 * k + 1.0) / (k + 1.0)) * t * p - ((double)k / (k + 1.0)) * pm;
+        const double dn = dm + (2 * k + 1) * p;
+        const double en = em + (2 * k + 1) * d;
+        pm = p; p = pn;
+        dm = d; d = dn;
+        em = e; e = en;
+        const double A = c[k + 1];
+        v0 = fma(A, p, v0); v1 = fma(A, d, v1); v2 = fma(A, e, v2);
+    }
+}
+
 __device__ inline double leg1(const double *__restrict__ c, double t)
 {
     double pm = 1.0, p = t, v = c[0] + c[1] * t;
@@ -111,6 +131,9 @@ struct LocalArgs {
     const T *sigma, *mu, *f_trg;
     const double *cs, *cm;
     const double *cf;      // Legendre coefficients of f on the boundary, or NULL
+    const double *geo;     // per-plan local geometry (k_local_geom)
+    const int32_t *gpan;
+    const uint8_t *gflag;
     const double *pcx, *pcy, *pck, *ends, *gl_t;
     const int32_t *prev, *next, *node, *cell_start;
     const double *nx_s, *ny_s;
@@ -158,8 +181,17 @@ __device__ inline void panel_min(const LocalArgs<T> &A, int p, double px, double
     else { tbest = ts; d2best = ds; }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
+// Geometry of the local part, once per plan (targets and boundary are
+// fixed): closest point, the density-independent coefficients of Lemmas
+// 4.1, 4.5 and the factor of Lemma 4.8 / Cor. 4.10 / 4.11 per sorted
+// target, so that an evaluation only combines them with the densities.
+// Stored per sorted target s: pan[s] (closest panel or -1), flag[s] (bit 0:
+// inside the layer band with a closest point; bit 1: exterior target inside
+// the volume band) and geo[k * nout + s] for k = GEO_T, GEO_P0, ... GEO_VFAC.
+enum { GEO_T, GEO_P0, GEO_P1, GEO_U0, GEO_U1, GEO_U2, GEO_KAP, GEO_MF1, GEO_MF2, GEO_VFAC, GEO_N };
+
+__global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double *__restrict__ geo,
+                                                    int32_t *__restrict__ pan, uint8_t *__restrict__ flag)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nout) return;
@@ -167,100 +199,140 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
     const double px = A.tx[s], py = A.ty[s];
     const bool inside = A.tin[s] != 0;
     const bool on = idx >= A.nt;
-    const bool do_local = (A.parts & MHK_PART_LOCAL) != 0;
-    const bool ws = A.out_s != nullptr, wd = A.out_d != nullptr, wv = A.out_v != nullptr;
-
-    // geometry of the local part (shared by the batch)
     const double sq = sqrt(A.dstar), c2 = A.alpha * sq;
     const double sv = sqrt(A.delta), c2v = A.alpha * sv;
-    bool near_s = false;           // inside the layer band with a closest point
-    double r = INFINITY, rho = inside ? 1.0 : -1.0;
+    bool near_s = false, ext = false;
+    double r = INFINITY;
     int pbest = -1;
     double tbest = 0.0;
     double P0 = 0, P1 = 0, U0 = 0, U1 = 0, U2 = 0, kap = 0, mss_fac1 = 0, mss_fac2 = 0;
-    double vfac = 0.0;             // V local = delta * f * vfac (or NaN)
-    bool v_ext = false;            // exterior target in the band: f at the closest point
-    if (do_local) {
-        if (on) {
-            vfac = -expm1(-c2v * c2v) / (2.0 * c2v * c2v);          // Cor. 4.10
-        } else {
-            // nearest boundary node (lowest index on ties)
-            int cx = (int)floor((px - A.ox) / A.cell), cy = (int)floor((py - A.oy) / A.cell);
-            double dmin = INFINITY;
-            int imin = -1;
-            if (cx >= -1 && cx <= A.ncx && cy >= -1 && cy <= A.ncy) {
-                for (int yy = max(cy - 1, 0); yy <= min(cy + 1, A.ncy - 1); ++yy) {
-                    const int c0 = A.cell_start[(int64_t)yy * A.ncx + max(cx - 1, 0)];
-                    const int c1 = A.cell_start[(int64_t)yy * A.ncx + min(cx + 1, A.ncx - 1) + 1];
-                    for (int c = c0; c < c1; ++c) {
-                        const double dx = A.nx_s[c] - px, dy = A.ny_s[c] - py;
-                        const double d = dx * dx + dy * dy;
-                        if (d <= dmin) {
-                            const int i = A.node[c];
-                            if (d < dmin || i < imin) { dmin = d; imin = i; }
-                        }
+    double vfac = 0.0;             // V local = delta * f * vfac
+    if (on) {
+        vfac = -expm1(-c2v * c2v) / (2.0 * c2v * c2v);          // Cor. 4.10
+    } else {
+        // nearest boundary node (lowest index on ties)
+        int cx = (int)floor((px - A.ox) / A.cell), cy = (int)floor((py - A.oy) / A.cell);
+        double dmin = INFINITY;
+        int imin = -1;
+        if (cx >= -1 && cx <= A.ncx && cy >= -1 && cy <= A.ncy) {
+            for (int yy = max(cy - 1, 0); yy <= min(cy + 1, A.ncy - 1); ++yy) {
+                const int c0 = A.cell_start[(int64_t)yy * A.ncx + max(cx - 1, 0)];
+                const int c1 = A.cell_start[(int64_t)yy * A.ncx + min(cx + 1, A.ncx - 1) + 1];
+                for (int c = c0; c < c1; ++c) {
+                    const double dx = A.nx_s[c] - px, dy = A.ny_s[c] - py;
+                    const double d = dx * dx + dy * dy;
+                    if (d <= dmin) {
+                        const int i = A.node[c];
+                        if (d < dmin || i < imin) { dmin = d; imin = i; }
                     }
                 }
             }
-            // the closest point lies within half a node gap of a node, so a
-            // nearest node farther than band + gap puts x outside both bands
-            if (imin >= 0 && sqrt(dmin) <= fmax(A.band_s, A.band_v) + A.gap) {
-                const int p0 = imin / NGL;
-                int cand[3] = {p0, A.prev[p0], A.next[p0]};
-                double d2b = INFINITY;
+        }
+        // the closest point lies within half a node gap of a node, so a
+        // nearest node farther than band + gap puts x outside both bands
+        if (imin >= 0 && sqrt(dmin) <= fmax(A.band_s, A.band_v) + A.gap) {
+            const int p0 = imin / NGL;
+            int cand[3] = {p0, A.prev[p0], A.next[p0]};
+            double d2b = INFINITY;
 #pragma unroll 1
-                for (int c = 0; c < 3; ++c) {
-                    double t, d2;
-                    panel_min(A, cand[c], px, py, t, d2);
-                    if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; }
-                }
-                r = sqrt(d2b);
+            for (int c = 0; c < 3; ++c) {
+                double t, d2;
+                panel_min(A, cand[c], px, py, t, d2);
+                if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; }
             }
-            // volume part (Lemma 4.8 first order inside the band, Cor. 4.11
-            // beyond).  Exterior targets in the band: the local integral over
-            // Omega is the whole-plane one minus the one over the complement,
-            // a domain that contains x, so V_L = delta f0 [(1 - e^{-c2^2})/c2^2
-            // - W0/4] with f0 = f at the closest boundary point, from the
-            // panel expansion of f at the boundary nodes (NaN without them).
-            if (r < A.band_v) {
-                const double c1v = r / sv, a = 0.5 * c1v;
-                const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
-                const double pre = exp(-a * a - c2v * c2v);
-                // W0 = (4 - 4 e^{-c2^2} + 2 lambda - Phi_+)/c2^2, lambda = e^{-c2^2} erfc(c1/2)
-                const double W0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
-                if (inside) {
-                    vfac = 0.25 * W0;
-                } else if (A.cf && pbest >= 0) {
-                    vfac = -expm1(-c2v * c2v) / (c2v * c2v) - 0.25 * W0;
-                    v_ext = true;
-                } else {
-                    vfac = NAN;
-                }
+            r = sqrt(d2b);
+        }
+        // volume part (Lemma 4.8 first order inside the band, Cor. 4.11
+        // beyond).  Exterior targets in the band: the local integral over
+        // Omega is the whole-plane one minus the one over the complement, a
+        // domain that contains x, so V_L = delta f0 [(1 - e^{-c2^2})/c2^2 -
+        // W0/4] with f0 = f at the closest boundary point, from the panel
+        // expansion of f at the boundary nodes (NaN without them).
+        if (r < A.band_v) {
+            const double c1v = r / sv, a = 0.5 * c1v;
+            const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
+            const double pre = exp(-a * a - c2v * c2v);
+            // W0 = (4 - 4 e^{-c2^2} + 2 lambda - Phi_+)/c2^2, lambda = e^{-c2^2} erfc(c1/2)
+            const double W0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
+            if (inside) {
+                vfac = 0.25 * W0;
             } else {
-                vfac = inside ? -expm1(-c2v * c2v) / (c2v * c2v) : 0.0;
+                vfac = -expm1(-c2v * c2v) / (c2v * c2v) - 0.25 * W0;
+                ext = true;
             }
-            if (r < A.band_s && pbest >= 0) {
-                near_s = true;
-                const double c1 = r / sq, a = 0.5 * c1;
-                const double em = erfcx(a - c2), ep = erfcx(a + c2);
-                const double pre = exp(-a * a - c2 * c2);
-                const double phim = pre * (em - ep), phip = pre * (em + ep);
-                P0 = phim / c2;
-                P1 = c1 * P0;
-                U0 = phip;
-                U1 = c1 * U0;
-                U2 = c1 * U1;
-                kap = leg1(A.pck + (size_t)pbest * NGL, tbest);
-                double x0, x1, x2, y0, y1, y2;
-                leg2(A.pcx + (size_t)pbest * NGL, A.pcy + (size_t)pbest * NGL, tbest, x0, x1, x2, y0, y1, y2);
-                const double sp2 = x1 * x1 + y1 * y1;
-                // d^2/ds^2 = (d^2/dt^2 - (gamma'.gamma''/|gamma'|^2) d/dt)/|gamma'|^2
-                mss_fac2 = 1.0 / sp2;
-                mss_fac1 = -(x1 * x2 + y1 * y2) / (sp2 * sp2);
-            }
+        } else {
+            vfac = inside ? -expm1(-c2v * c2v) / (c2v * c2v) : 0.0;
+        }
+        if (r < A.band_s && pbest >= 0) {
+            near_s = true;
+            const double c1 = r / sq, a = 0.5 * c1;
+            const double em = erfcx(a - c2), ep = erfcx(a + c2);
+            const double pre = exp(-a * a - c2 * c2);
+            const double phim = pre * (em - ep), phip = pre * (em + ep);
+            P0 = phim / c2;
+            P1 = c1 * P0;
+            U0 = phip;
+            U1 = c1 * U0;
+            U2 = c1 * U1;
+            kap = leg1(A.pck + (size_t)pbest * NGL, tbest);
+            double x0, x1, x2, y0, y1, y2;
+            leg2(A.pcx + (size_t)pbest * NGL, A.pcy + (size_t)pbest * NGL, tbest, x0, x1, x2, y0, y1, y2);
+            const double sp2 = x1 * x1 + y1 * y1;
+            // d^2/ds^2 = (d^2/dt^2 - (gamma'.gamma''/|gamma'|^2) d/dt)/|gamma'|^2
+            mss_fac2 = 1.0 / sp2;
+            mss_fac1 = -(x1 * x2 + y1 * y2) / (sp2 * sp2);
+        }
+    }
+    const int64_t n = A.nout;
+    geo[GEO_T * n + s] = tbest;
+    geo[GEO_P0 * n + s] = P0;
+    geo[GEO_P1 * n + s] = P1;
+    geo[GEO_U0 * n + s] = U0;
+    geo[GEO_U1 * n + s] = U1;
+    geo[GEO_U2 * n + s] = U2;
+    geo[GEO_KAP * n + s] = kap;
+    geo[GEO_MF1 * n + s] = mss_fac1;
+    geo[GEO_MF2 * n + s] = mss_fac2;
+    geo[GEO_VFAC * n + s] = vfac;
+    pan[s] = pbest;
+    flag[s] = (uint8_t)((near_s ? 1 : 0) | (ext ? 2 : 0));
+}
+
+// Local part of an evaluation from the per-plan geometry, added to the
+// accumulated history and level sums, and the scatter to the caller's order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nout) return;
+    const int64_t idx = A.tidx[s];
+    const bool inside = A.tin[s] != 0;
+    const bool on = idx >= A.nt;
+    const bool do_local = (A.parts & MHK_PART_LOCAL) != 0;
+    const bool ws = A.out_s != nullptr, wd = A.out_d != nullptr, wv = A.out_v != nullptr;
+    const double sq = sqrt(A.dstar), c2 = A.alpha * sq;
+    const double rho = inside ? 1.0 : -1.0;
+    const int64_t n = A.nout;
+    const uint8_t fl = A.gflag[s];
+    const bool near_s = (fl & 1) != 0, ext = (fl & 2) != 0;
+    const int pbest = A.gpan[s];
+    const double vfac = do_local && wv ? A.geo[GEO_VFAC * n + s] : 0.0;
+    double tbest = 0.0, P0 = 0, P1 = 0, U0 = 0, U1 = 0, U2 = 0, kap = 0, mss_fac1 = 0, mss_fac2 = 0;
+    if (do_local && (near_s || ext)) tbest = A.geo[GEO_T * n + s];
+    if (do_local && near_s && (ws || wd)) {
+        P0 = A.geo[GEO_P0 * n + s];
+        P1 = A.geo[GEO_P1 * n + s];
+        kap = A.geo[GEO_KAP * n + s];
+        if (wd) {
+            U0 = A.geo[GEO_U0 * n + s];
+            U1 = A.geo[GEO_U1 * n + s];
+            U2 = A.geo[GEO_U2 * n + s];
+            mss_fac1 = A.geo[GEO_MF1 * n + s];
+            mss_fac2 = A.geo[GEO_MF2 * n + s];
         }
     }
 
+#pragma unroll 1
     for (int b = 0; b < A.B; ++b) {
         const size_t ob = (size_t)b * A.nout + idx;
         const size_t ab = (size_t)b * A.nout + s;
@@ -284,9 +356,8 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                     const int64_t i = idx - A.nt;
                     v -= sq * A.bk[i] * (double)A.mu[(size_t)b * A.nb + i] * erf(c2) / (4.0 * c2);  // Cor. 4.7
                 } else if (near_s) {
-                    const double *cm = A.cm + ((size_t)b * A.npan + pbest) * NGL;
-                    double m0, m1, m2, z0, z1, z2;
-                    leg2(cm, cm, tbest, m0, m1, m2, z0, z1, z2);
+                    double m0, m1, m2;
+                    leg2s(A.cm + ((size_t)b * A.npan + pbest) * NGL, tbest, m0, m1, m2);
                     const double mss = mss_fac2 * m2 + mss_fac1 * m1;
                     v += -rho * m0 * U0 * 0.25 - sq * kap * m0 * (P0 + U1) * 0.125                // Lemma 4.5
                          - A.dstar * (rho * mss * P1 * 0.125 + 3.0 * rho * kap * kap * m0 * (P1 + U2) / 32.0);
@@ -297,8 +368,11 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
         if (wv) {
             double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
             if (do_local) {
-                const double f = v_ext ? leg1(A.cf + ((size_t)b * A.npan + pbest) * NGL, tbest)
-                                       : (double)A.f_trg[ob];
+                double f;
+                if (ext)
+                    f = A.cf ? leg1(A.cf + ((size_t)b * A.npan + pbest) * NGL, tbest) : NAN;
+                else
+                    f = (double)A.f_trg[ob];
                 v += A.delta * f * vfac;
             }
             A.out_v[ob] = (T)v;
@@ -337,16 +411,14 @@ hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, c
 }
 
 template <typename T>
-static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                          void *out_s, void *out_d, void *out_v, bool have_fb)
+static void fill_args(mhk_plan *P, LocalArgs<T> &A)
 {
-    LocalArgs<T> A;
     A.nout = P->nout;
     A.nt = P->nt;
     A.nb = P->nb;
     A.npan = P->npan;
     A.B = P->p.batch;
-    A.parts = parts;
+    A.parts = MHK_PART_ALL;
     A.tx = P->tx;
     A.ty = P->ty;
     A.tin = P->tin;
@@ -354,12 +426,15 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
     A.bx = P->bx;
     A.by = P->by;
     A.bk = P->bk;
-    A.sigma = (const T *)sigma;
-    A.mu = (const T *)mu;
-    A.f_trg = (const T *)f_trg;
+    A.sigma = nullptr;
+    A.mu = nullptr;
+    A.f_trg = nullptr;
     A.cs = P->loc.csig;
     A.cm = P->loc.cmu;
-    A.cf = have_fb ? P->loc.cf : nullptr;
+    A.cf = nullptr;
+    A.geo = P->loc.geo;
+    A.gpan = P->loc.gpan;
+    A.gflag = P->loc.gflag;
     A.pcx = P->loc.cx;
     A.pcy = P->loc.cy;
     A.pck = P->loc.ck;
@@ -383,6 +458,30 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
     A.acc = (const T *)P->acc;
+    A.out_s = A.out_d = A.out_v = nullptr;
+}
+
+hipError_t launch_local_geom(mhk_plan *P)
+{
+    if (P->nout == 0) return hipSuccess;
+    LocalArgs<double> A;
+    fill_args(P, A);
+    hipLaunchKernelGGL(k_local_geom, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A,
+                       P->loc.geo, P->loc.gpan, P->loc.gflag);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
+                          void *out_s, void *out_d, void *out_v, bool have_fb)
+{
+    LocalArgs<T> A;
+    fill_args(P, A);
+    A.parts = parts;
+    A.sigma = (const T *)sigma;
+    A.mu = (const T *)mu;
+    A.f_trg = (const T *)f_trg;
+    A.cf = have_fb ? P->loc.cf : nullptr;
     A.out_s = (T *)out_s;
     A.out_d = (T *)out_d;
     A.out_v = (T *)out_v;

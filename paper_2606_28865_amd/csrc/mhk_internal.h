@@ -38,7 +38,9 @@ constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
 constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
-constexpr int LV_WAVE = 64;      // targets per level-sum wavefront (one source range list each)
+constexpr int LV_WAVE = 64;      // lanes per level-sum wavefront
+constexpr int LV_TPL = 1;        // targets per lane of the level sums
+constexpr int LV_TPW = LV_WAVE * LV_TPL;   // targets per wavefront (one source range list each)
 constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
 
 void set_error(const std::string &msg);
@@ -134,6 +136,9 @@ struct Local {
     int32_t *prev = nullptr, *next = nullptr;     // panel neighbours within each curve
     double *csig = nullptr, *cmu = nullptr;       // per eval: [batch][n_panels][16] (FP64)
     double *cf = nullptr;                         // f at the boundary nodes, same layout
+    double *geo = nullptr;                        // per-plan local geometry [10][n_out] (sorted order)
+    int32_t *gpan = nullptr;                      // closest panel per sorted target (-1: none)
+    uint8_t *gflag = nullptr;                     // bit 0: in the layer band, bit 1: exterior in the volume band
 };
 
 }  // namespace mhk
@@ -173,6 +178,7 @@ namespace mhk {
 hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu);
 hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d);
 hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd);
+hipError_t launch_local_geom(mhk_plan *P);
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
                         const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);

@@ -556,14 +556,14 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     TRY(upload(P, &L.code, code.data(), L.n_src));
     TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
-    // per wavefront of LV_WAVE targets: for every cell row, the cells that
+    // per wavefront of LV_TPW targets: for every cell row, the cells that
     // can hold a source within R_j of one of the wave's targets (row gap g to
     // the target, half-width sqrt(R_j^2 - g^2) in x), merged into row
     // intervals and mapped to ranges of sorted sources (waves past the last
     // target get no ranges)
     {
         const int64_t nout = (int64_t)tgx.size();
-        const int64_t nblk = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
+        const int64_t nblk = ((nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)) * (LV_BLOCK / LV_WAVE);
         const double R = L.radius;
         std::vector<int32_t> bofs(nblk + 1, 0), rng;
         std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
@@ -575,7 +575,7 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
         };
         for (int64_t b = 0; b < nblk; ++b) {
             iv.clear();
-            for (int64_t t = b * LV_WAVE; t < std::min(nout, (b + 1) * LV_WAVE); ++t) {
+            for (int64_t t = b * LV_TPW; t < std::min(nout, (b + 1) * LV_TPW); ++t) {
                 const double tx = tgx[t], ty = tgy[t];
                 for (int64_t r = row(ty - R); r <= row(ty + R); ++r) {
                     const double ylo = L.oy + r * L.cell, yhi = ylo + L.cell;
@@ -614,7 +614,7 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
         // wavefronts of similar work
         std::vector<int64_t> work(nblk, 0);
         for (int64_t b = 0; b < nblk; ++b) {
-            int64_t nt_w = std::max<int64_t>(0, std::min(nout, (b + 1) * LV_WAVE) - b * LV_WAVE);
+            int64_t nt_w = std::max<int64_t>(0, std::min(nout, (b + 1) * LV_TPW) - b * LV_TPW);
             for (int32_t r = bofs[b]; r < bofs[b + 1]; ++r) work[b] += (int64_t)(rng[2 * r + 1] - rng[2 * r]);
             work[b] *= (nt_w > 0 ? 1 : 0);
         }
@@ -744,8 +744,9 @@ double window_ft(double k, double half_width, double beta, const std::vector<dou
     return (double)(s * half_width);
 }
 
-// Multiplier table of the smoothly truncated history kernel g_T(r) =
-// G^H(r) chi(r), chi = 1 up to the separation bound D and 0 beyond D + trans:
+// Multiplier table of the smoothly truncated history kernel g_T(x, y) =
+// G^H(r) chi(|x|) chi(|y|), chi = 1 up to the separation bound D and 0
+// beyond D + trans:
 // samples on a 2n x 2n grid of the same step (period 2P, which holds the
 // support of g_T without overlap), one real-to-complex FFT, and the even
 // modes, which are the modes of the period-P grid.
@@ -887,14 +888,19 @@ static mhk_status choose_grid(const mhk_params &p, const mhk_info &I, double Lx,
     while (sqrt(M_PI / (2 * alpha * R)) * exp(-alpha * R) / (2 * M_PI) > thr) R *= 1.02;
     // Two ways to make the periodic images harmless: a period longer than the
     // extent plus the decay length R of the kernel, or a kernel cut off
-    // smoothly beyond the largest source-target distance D (its spectrum
-    // then tabulated by FFT, in the spirit of the truncated-kernel method
-    // of Vico, Greengard and Ferrando the paper cites for small alpha).
-    // The cut-off erfc((r - r_mid) 11.8/trans)/2 smears the spectrum by a
-    // Gaussian of width ~23.6/trans: it must stay narrow against both the
-    // multiplier's own width 1/sqrt(delta) and the cut-off k_max.
-    g.Dsep = sqrt(Lx * Lx + Ly * Ly);
-    g.trans = std::max(110.0 * sqrt(delta), 120.0 / kc);
+    // smoothly beyond the largest source-target separation D per axis (its
+    // spectrum then tabulated by FFT, in the spirit of the truncated-kernel
+    // method of Vico, Greengard and Ferrando the paper cites for small
+    // alpha).  The cut-off is a product of one-dimensional ones in |x| and
+    // |y| (a square, not a disk: every separation has |dx| <= Lx, |dy| <= Ly,
+    // and images one period away then see a separation of at least P - L >=
+    // D + trans along an axis, so P = L + D + trans with D = max(Lx, Ly)
+    // rather than the diagonal).  Each factor erfc((s - s_mid) 11.8/trans)/2
+    // smears the spectrum by a Gaussian of width ~23.6/trans: it must stay
+    // narrow against both the multiplier's own width 1/sqrt(delta) and the
+    // cut-off k_max.
+    g.Dsep = std::max(Lx, Ly);
+    g.trans = std::max(140.0 * sqrt(delta), 160.0 / kc);
     const double per_periodic = L + R, per_trunc = L + g.Dsep + g.trans;
     g.trunc = per_trunc < 0.9 * per_periodic;
     const double P = g.trunc ? per_trunc : per_periodic;
@@ -1260,6 +1266,10 @@ mhk_status build_local(mhk_plan *P, Host &H)
     TRY(dalloc(P, &C.csig, (int64_t)P->p.batch * nb));
     TRY(dalloc(P, &C.cmu, (int64_t)P->p.batch * nb));
     TRY(dalloc(P, &C.cf, (int64_t)P->p.batch * nb));
+    // per-plan geometry of the local part (closest points and coefficients)
+    TRY(dalloc(P, &C.geo, 10 * std::max<int64_t>(P->nout, 1)));
+    TRY(dalloc(P, &C.gpan, std::max<int64_t>(P->nout, 1)));
+    TRY(dalloc(P, &C.gflag, std::max<int64_t>(P->nout, 1)));
     return MHK_OK;
 }
 
@@ -1343,6 +1353,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j, tgx, tgy));
     TRY(build_history(P, H, tgx, tgy));
     TRY(build_local(P, H));
+    MHK_HIP(launch_local_geom(P));
     {
         char *a = nullptr;
         TRY(dalloc(P, &a, 3 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
@@ -1414,6 +1425,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
     }
     s += nb * (8 * 3 + 4) + 3 * B * nb * 8;   // local
+    s += nout * (10 * 8 + 4 + 1);             // local geometry per target
     if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {
