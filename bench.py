@@ -186,7 +186,7 @@ def roofline(dom, stage, infos, w, plans):
         ach = flops / t / 1e12
         launches = sum(i["J"] for i in infos)
         return {"kernel": "k_level_sums", "bound": "alu", "achieved": ach, "peak": FP64_PEAK,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": LEVEL_SUMS_HBM_BYTES,
                 "flops_per_launch": flops / launches, "ms_per_launch": sum(stage[dom]) / launches}
     if name in ("fft", "spread", "multiply", "interp"):
         byts = 0.0
@@ -198,8 +198,7 @@ def roofline(dom, stage, infos, w, plans):
             if name == "fft":
                 byts += (4 + 4 + 3 + 3) * grid            # read + write per field, forward 4, inverse 3
             elif name == "multiply":
-                nf = min(1.0, 1.0 / 2.0)
-                byts += (4 + 3) * grid * 0.5 * 0 + (4 + 3) * grid * 0.5 + 0 * nf
+                byts += (4 + 3) * grid                    # half spectra: 4 read, 3 written
             elif name == "spread":
                 byts += 4 * grid + (w.n_v * 32 + w.n_b * 56)
             else:
@@ -217,6 +216,13 @@ def roofline(dom, stage, infos, w, plans):
 # two degree-7 Horner recurrences 28, S accumulation 2, nu.(x - x_q) 3 and D
 # accumulation 2.
 LEVEL_FLOPS_PER_PAIR = 45.0
+
+# HBM bytes per k_level_sums launch on this workload (mean over the levels and
+# plans): FETCH_SIZE 59.8 MB + WRITE_SIZE 16.3 MB per dispatch, each scaled by
+# the counter's reading for a 256 MiB device copy (profiles/
+# multibody_fp64_hbm_counters.md).  To be re-measured whenever the kernel
+# changes.
+LEVEL_SUMS_HBM_BYTES = 76.1e6
 
 
 def child_nodes(w, j):
