@@ -3,9 +3,12 @@
 // Level j sums, for every target x,
 //   S_j(x) = sum_q w_q sigma_q K_j^S(|x - x_q|),
 //   D_j(x) = sum_q w_q mu_q nu_q.(x - x_q) K_j^D(|x - x_q|),
-// over the child nodes q of the panels bisected j times.  The kernels are
-// read from a piecewise-polynomial table in a = r^2/(4 delta_j) held in LDS;
-// pairs with a >= a_max are below the requested accuracy and skipped.
+// over the child nodes q of the panels bisected j times.  The kernels come
+// from one piecewise-polynomial table of K_j^S in a = r^2/(4 delta_j) held in
+// LDS: Horner's rule gives the polynomial and its derivative together, and
+// K_j^D is a constant times dK_j^S/da, applied once per target at the end
+// (the table reads, which bound the loop, serve both kernels).  Pairs with
+// a >= a_max are below the requested accuracy and skipped.
 //
 // Work decomposition: a wavefront owns 64 consecutive targets of the Morton
 // order.  At plan time the cells (side R_j/4) that can hold a source within
@@ -76,7 +79,7 @@ template <typename T>
 struct LevelArgs {
     int64_t nout, n_src;
     const double *tx, *ty;
-    double inv4d, a_max, seg_inv;
+    double inv4d, a_max, seg_inv, d_scale;
     int nseg, B;
     const int32_t *blk_ofs, *blk_rng, *wave_order;
     const double *sx, *sy;
@@ -101,11 +104,10 @@ __device__ inline float bcast(float v, int k)
 template <int BCH, typename T, int NC, int STRIDE>
 __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
-    typedef typename Vec2<T>::type T2;
     extern __shared__ double lds[];
-    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg][STRIDE][2]
+    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg][STRIDE]
     const int tid = threadIdx.x;
-    for (int i = tid; i < A.nseg * STRIDE * 2; i += LV_BLOCK) s_tab[i] = A.tab[i];
+    for (int i = tid; i < A.nseg * STRIDE; i += LV_BLOCK) s_tab[i] = A.tab[i];
     __syncthreads();
 
     // one wavefront = LV_TPW consecutive targets with their own source ranges
@@ -148,14 +150,14 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                 const T f = a * seg_inv;
                 const int sg = (int)f;
                 const T v = (T)2 * (f - (T)sg) - (T)1;
-                const T2 *c = reinterpret_cast<const T2 *>(s_tab) + sg * STRIDE;
-                T2 cc = c[NC - 1];
-                T ks = cc.x, kd = cc.y;
+                const T *c = s_tab + sg * STRIDE;
+                // p(v) and p'(v) by Horner's rule (K_j^S and, up to the
+                // factor d_scale, K_j^D)
+                T ks = c[NC - 1], kd = (T)0;
 #pragma unroll
                 for (int k = NC - 2; k >= 0; --k) {
-                    cc = c[k];
-                    ks = fma(ks, v, cc.x);
-                    kd = fma(kd, v, cc.y);
+                    kd = fma(kd, v, ks);
+                    ks = fma(ks, v, c[k]);
                 }
 #pragma unroll
                 for (int b = 0; b < BCH; ++b) {
@@ -213,7 +215,7 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                 if (b < nbh) {
                     const size_t o = (size_t)(b0 + b) * A.nout + t[i];
                     if (A.want_s) A.acc_s[o] += S[i][b];
-                    if (A.want_d) A.acc_d[o] += D[i][b];
+                    if (A.want_d) A.acc_d[o] += D[i][b] * (T)A.d_scale;
                 }
             }
         }
@@ -249,6 +251,7 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.inv4d = L.inv4d;
     A.a_max = L.a_max;
     A.seg_inv = L.seg_inv;
+    A.d_scale = level_d_scale(L);
     A.nseg = L.nseg;
     A.B = B;
     A.blk_ofs = L.blk_ofs;
@@ -264,7 +267,7 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.want_d = want_d;
     const int bch = B == 1 ? 1 : LV_BCH;
     dim3 grid((unsigned)((P->nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)), (unsigned)((B + bch - 1) / bch));
-    const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE * 2;
+    const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (bch == 1) {
         if (lds > 64 * 1024)

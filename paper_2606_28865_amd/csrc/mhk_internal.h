@@ -32,9 +32,9 @@ constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
 constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
 constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
-constexpr int TAB_STRIDE = 9;    // double2 slots per segment in LDS (36 dwords: spreads segments over the banks)
+constexpr int TAB_STRIDE = 9;    // doubles per segment in LDS (18 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
-constexpr int TABF_STRIDE = 9;   // FP32 path: float2 slots per segment
+constexpr int TABF_STRIDE = 9;   // FP32 path: floats per segment
 constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
@@ -73,12 +73,17 @@ struct Level {
     int32_t *blk_rng = nullptr;                   // [n_ranges][2]
     int64_t n_ranges = 0;
     double *interp = nullptr;                     // [nchild][16][16] parent -> child values
-    double *tab = nullptr;                        // [nseg][TAB_STRIDE][2] (S, D interleaved)
-    float *tabf = nullptr;                        // FP32 path: [nseg][TABF_STRIDE][2]
+    double *tab = nullptr;                        // [nseg][TAB_STRIDE]: K_j^S per segment (K_j^D from its derivative)
+    float *tabf = nullptr;                        // FP32 path: [nseg][TABF_STRIDE]
     void *tab_dev = nullptr;                      // the table of the plan's precision
     void *q = nullptr;                            // per eval: [3][batch][n_src], plan precision
     double tab_err = 0;                           // measured max table error / K(0)
 };
+
+// Factor taking the v-derivative of a level's K_j^S polynomial to K_j^D:
+// K_j^D = -(1/(2 delta_j)) dK_j^S/da and da/dv = 1/(2 seg_inv), so
+// K_j^D = -(seg_inv/delta_j) dp/dv = -4 inv4d seg_inv dp/dv.
+inline double level_d_scale(const Level &L) { return -4.0 * L.inv4d * L.seg_inv; }
 
 struct History {
     bool active = false;

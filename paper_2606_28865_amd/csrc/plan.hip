@@ -631,11 +631,16 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
         L.q = q;
     }
 
-    // Kernel table: piecewise polynomials in a = r^2/(4 delta_j) on segments of
-    // width 1/4, each in the local variable v in [-1, 1]; coefficients from
-    // Chebyshev interpolation converted to monomials in v.  FP64 path: degree
-    // 7 on segments of 1/8 (error ~4e-13 of K_j(0)); FP32 path: degree 7 on
-    // segments of 1/4, stored as floats.
+    // Kernel table: piecewise polynomials in a = r^2/(4 delta_j), each in the
+    // local variable v in [-1, 1] of its segment; coefficients from Chebyshev
+    // interpolation converted to monomials in v.  Only K_j^S is tabulated:
+    // with K_j^S = cS I0(a) and K_j^D = cD I1(a), where I1 = -dI0/da (the
+    // a-derivative of exp(-a e^u) brings down -e^u), K_j^D = -(1/(2 delta_j))
+    // dK_j^S/da, which the level sums take from the derivative of the same
+    // polynomial (one LDS table read per coefficient serves both kernels).
+    // FP64 path: degree 7 on segments of 1/16 (S ~1e-15, D ~3e-13 of the
+    // kernels at a = 0); FP32 path: degree 7 on segments of 1/4, stored as
+    // floats.
     LevelQuad Q;
     const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
     const double cS = 1.0 / (4.0 * M_PI), cD = 1.0 / (8.0 * M_PI * L.delta_j);
@@ -643,58 +648,55 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     const int nc = fp64 ? TAB_NC : TABF_NC, stride = fp64 ? TAB_STRIDE : TABF_STRIDE;
     const double tab_tol = fp64 ? 1e-12 : 1e-8;
     std::vector<double> tab;
-    // segment width 1/8 (FP64, degree 7) or 1/4 (FP32, degree 7), halved
-    // while the table misses tab_tol (large alpha^2 delta_j makes K_j decay
-    // like e^{-4a})
-    for (double seg_w = fp64 ? 0.125 : 0.25;; seg_w *= 0.5) {
+    // segment width halved while the table (or its derivative) misses tab_tol
+    // (large alpha^2 delta_j makes K_j decay like e^{-4a})
+    for (double seg_w = fp64 ? 0.0625 : 0.25;; seg_w *= 0.5) {
         L.seg_inv = 1.0 / seg_w;
         L.nseg = (int)ceil(L.a_max / seg_w) + 1;
-        tab.assign((size_t)L.nseg * stride * 2, 0.0);
+        tab.assign((size_t)L.nseg * stride, 0.0);
         std::vector<double> node(nc);
         for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
         for (int sgi = 0; sgi < L.nseg; ++sgi) {
             double a0 = sgi * seg_w;
-            std::vector<long double> fS(nc), fD(nc);
+            std::vector<long double> f(nc);
             for (int i = 0; i < nc; ++i) {
                 double a = a0 + 0.5 * seg_w * (1.0 + node[i]);
                 double i0, i1;
                 Q.eval(a, b_j, i0, i1);
-                fS[i] = i0 * cS;
-                fD[i] = i1 * cD;
+                f[i] = i0 * cS;
             }
-            for (int kind = 0; kind < 2; ++kind) {
-                std::vector<long double> &f = kind ? fD : fS;
-                // Chebyshev coefficients
-                std::vector<long double> ch(nc, 0);
-                for (int m = 0; m < nc; ++m) {
-                    long double sacc = 0;
-                    for (int i = 0; i < nc; ++i) sacc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
-                    ch[m] = sacc * (m == 0 ? 1.0L : 2.0L) / nc;
-                }
-                // T_m(v) -> monomials in v
-                std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
-                tprev[0] = 1;       // T0
-                tcur[1] = 1;        // T1
-                for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
-                for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
-                for (int m = 2; m < nc; ++m) {
-                    std::fill(tnext.begin(), tnext.end(), 0.0L);
-                    for (int k = 0; k < nc; ++k) {
-                        if (k + 1 < nc) tnext[k + 1] += 2 * tcur[k];
-                        tnext[k] -= tprev[k];
-                    }
-                    for (int k = 0; k < nc; ++k) mono[k] += ch[m] * tnext[k];
-                    tprev = tcur;
-                    tcur = tnext;
-                }
-                for (int k = 0; k < nc; ++k) tab[((size_t)sgi * stride + k) * 2 + kind] = (double)mono[k];
+            // Chebyshev coefficients
+            std::vector<long double> ch(nc, 0);
+            for (int m = 0; m < nc; ++m) {
+                long double sacc = 0;
+                for (int i = 0; i < nc; ++i) sacc += f[i] * cosl(M_PIl * m * (i + 0.5L) / nc);
+                ch[m] = sacc * (m == 0 ? 1.0L : 2.0L) / nc;
             }
+            // T_m(v) -> monomials in v
+            std::vector<long double> mono(nc, 0), tprev(nc, 0), tcur(nc, 0), tnext(nc, 0);
+            tprev[0] = 1;       // T0
+            tcur[1] = 1;        // T1
+            for (int k = 0; k < nc; ++k) mono[k] += ch[0] * tprev[k];
+            for (int k = 0; k < nc; ++k) mono[k] += ch[1] * tcur[k];
+            for (int m = 2; m < nc; ++m) {
+                std::fill(tnext.begin(), tnext.end(), 0.0L);
+                for (int k = 0; k < nc; ++k) {
+                    if (k + 1 < nc) tnext[k + 1] += 2 * tcur[k];
+                    tnext[k] -= tprev[k];
+                }
+                for (int k = 0; k < nc; ++k) mono[k] += ch[m] * tnext[k];
+                tprev = tcur;
+                tcur = tnext;
+            }
+            for (int k = 0; k < nc; ++k) tab[(size_t)sgi * stride + k] = (double)mono[k];
         }
-        // accuracy check of the table against direct quadrature
+        // accuracy check of the table and of its derivative against direct
+        // quadrature, in the arithmetic of the device evaluation
         double k0S, k0D;
         Q.eval(0.0, b_j, k0S, k0D);
         k0S *= cS;
         k0D *= cD;
+        const double dscale = level_d_scale(L);
         double emax = 0;
         for (int i = 0; i < 997; ++i) {
             double a = L.a_max * (i + 0.37) / 997.0;
@@ -702,17 +704,18 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
             Q.eval(a, b_j, i0, i1);
             int sgi = (int)(a * L.seg_inv);
             double v = 2.0 * (a * L.seg_inv - sgi) - 1.0;
-            double pS = 0, pD = 0;
-            for (int k = nc - 1; k >= 0; --k) {
-                pS = pS * v + tab[((size_t)sgi * stride + k) * 2];
-                pD = pD * v + tab[((size_t)sgi * stride + k) * 2 + 1];
+            const double *c = &tab[(size_t)sgi * stride];
+            double pS = c[nc - 1], dS = 0;
+            for (int k = nc - 2; k >= 0; --k) {
+                dS = dS * v + pS;
+                pS = pS * v + c[k];
             }
             emax = std::max(emax, fabs(pS - i0 * cS) / k0S);
-            emax = std::max(emax, fabs(pD - i1 * cD) / k0D);
+            emax = std::max(emax, fabs(dS * dscale - i1 * cD) / k0D);
         }
         L.tab_err = emax;
         if (emax <= tab_tol) break;
-        if (seg_w < 0.05) {
+        if (seg_w < 0.01) {
             char msg[128];
             snprintf(msg, sizeof msg, "level kernel table not accurate: %.3e of K_j(0)", emax);
             set_error(msg);
