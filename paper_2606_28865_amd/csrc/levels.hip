@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
         }
     }
     const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
-    const T inv4d = (T)A.inv4d, a_max = (T)A.a_max, seg_inv = (T)A.seg_inv;
+    // segment coordinate f = a seg_inv = r^2 inv4d seg_inv in one product
+    const T fscale = (T)(A.inv4d * A.seg_inv), f_max = (T)(A.a_max * A.seg_inv);
     T S[LV_TPL][BCH], D[LV_TPL][BCH];
 #pragma unroll
     for (int i = 0; i < LV_TPL; ++i)
@@ -145,9 +146,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 #pragma unroll
         for (int i = 0; i < LV_TPL; ++i) {
             const T dx = (T)(x[i] - sxv), dy = (T)(y[i] - syv);
-            const T a = (dx * dx + dy * dy) * inv4d;
-            if (a < a_max) {
-                const T f = a * seg_inv;
+            const T f = (dx * dx + dy * dy) * fscale;
+            if (f < f_max) {
                 const int sg = (int)f;
                 const T v = (T)2 * (f - (T)sg) - (T)1;
                 const T *c = s_tab + sg * STRIDE;

@@ -251,8 +251,10 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
     // Remark 4.3: the local layer part is negligible beyond sqrt(d*)(12 + 2 alpha sqrt(d*))
     I->band_layer = sq * (12.0 + 2.0 * p.alpha * sq);
     I->band_volume = sv * (12.0 + 2.0 * p.alpha * sv);
-    // level cut-off: the difference kernel is below exp(-a_max) of its peak scale
-    double amax = std::min(40.5, log(1.0 / p.tol) + 9.0);
+    // level cut-off: K_j decays like exp(-a)/a, so the sources beyond a_max =
+    // ln(1/tol) + 3 add up to ~1e-3 tol of the level sum (measured on the
+    // 10-body workload at tol 1e-10: 1.3e-13 of max |S_j|)
+    double amax = std::min(40.5, log(1.0 / p.tol) + 3.0);
     for (int j = 1; j <= p.J; ++j) {
         double dj = p.delta / pow(4.0, j - 1);
         I->level_radius[j - 1] = sqrt(4.0 * dj * amax);
