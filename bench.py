@@ -218,11 +218,10 @@ def roofline(dom, stage, infos, w, plans):
 LEVEL_FLOPS_PER_PAIR = 45.0
 
 # HBM bytes per k_level_sums launch on this workload (mean over the levels and
-# plans): FETCH_SIZE 59.8 MB + WRITE_SIZE 16.3 MB per dispatch, each scaled by
-# the counter's reading for a 256 MiB device copy (profiles/
-# multibody_fp64_hbm_counters.md).  To be re-measured whenever the kernel
-# changes.
-LEVEL_SUMS_HBM_BYTES = 76.1e6
+# plans), FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by the counter's
+# reading for a 256 MiB device copy (profiles/multibody_fp64_hbm_counters.md).
+# None while the kernel has changed since the counters were taken.
+LEVEL_SUMS_HBM_BYTES = None
 
 
 def child_nodes(w, j):

@@ -12,21 +12,21 @@
 //   FFT       rocFFT complex-to-real, in place;
 //   interp    u(x) = sum_m phi(x - x_m) U_m.
 //
-// Spreading: one workgroup (1024 threads) owns one 32x32 tile of the fine
-// grid and one density of the batch.  It visits the sources of the 3x3 neighbouring tiles
-// (sorted by tile at plan time), adds the part of each source's w x w window
-// that falls in its own tile into LDS with LDS atomics, and writes the tile
-// once: every grid value is written exactly once, with no global atomics.
+// Spreading: one workgroup owns one 32x32 tile of the fine grid and one
+// density of the batch; it adds the windows of the sources that meet the
+// tile (listed per tile at plan time) into LDS with LDS atomics and writes
+// the tile once: every grid value is written exactly once, with no global
+// atomics.
 // Interpolation: one workgroup per non-empty target tile stages the tile plus
 // its window halo of the three result grids in LDS with coalesced row reads.
 #include "mhk_internal.h"
 
 namespace mhk {
 
-// threads per spreading / interpolation workgroup: the sources (targets) sit
-// in a few hundred busy tiles, so each tile gets 16 wavefronts
-constexpr int HB = 1024;
-constexpr int SB = 1024;   // threads per spreading workgroup
+// threads per spreading / interpolation workgroup: a busy tile holds a few
+// hundred sources (targets), one per thread
+constexpr int HB = 256;
+constexpr int SB = 256;
 
 template <typename T>
 struct SpreadArgs {
@@ -34,9 +34,9 @@ struct SpreadArgs {
     int ntile, B;
     double beta;
     const double *bgx, *bgy, *bw, *bwx, *bwy;
-    const int32_t *bidx, *btile;
+    const int32_t *bidx, *blofs, *blist;
     const double *vgx, *vgy, *vw;
-    const int32_t *vidx, *vtile;
+    const int32_t *vidx, *vlofs, *vlist;
     const T *sigma, *mu, *f_vol;
     const T *wcoef;
     T *grid;               // [4][B][field]: S, V, Dx, Dy sources
@@ -44,117 +44,128 @@ struct SpreadArgs {
 
 // Window values phi(z_k), z_k = (m0 + k - g) 2/W, at the W grid points from
 // m0 = ceil(g - W/2), from the per-point polynomials in t = 2(m0 - g + W/2) - 1
-// (degree W + 3, Horner; the coefficients are the same for every lane and are
-// read as scalars).  The offset is formed in FP64.
+// (degree W + 3; the offset is formed in FP64).
+// Window values at the W grid points of both axes of one source.  The
+// window is even, so point W-1-k at offset t is point k at -t: with the
+// polynomial of point k split into even and odd parts, p_k(t) = E(t^2) +
+// t O(t^2), the pair is E +- t O, and half the polynomials serve all W
+// points.  The coefficients are loaded with scalar loads inside the
+// caller's loop (the empty asm keeps the compiler from hoisting all of them
+// into vector registers), and each is used for both axes.
 template <int W, typename T>
-__device__ inline void window_weights(double g, const T *__restrict__ cf, int &m0, T *wt)
+__device__ inline void window_weights2(double gx, double gy, const T *__restrict__ cf, int &mx0, int &my0, T *wx,
+                                       T *wy)
 {
-    constexpr int D = W + 3;
-    m0 = (int)ceil(g - 0.5 * W);
-    const T t = (T)(2.0 * ((double)m0 - g + 0.5 * W) - 1.0);
+    constexpr int D = W + 3;           // degree
+    constexpr int NE = D / 2 + 1;      // even coefficients c_0, c_2, ...
+    constexpr int NO = (D + 1) / 2;    // odd coefficients c_1, c_3, ...
+    typedef const __attribute__((address_space(4))) T *ConstPtr;   // scalar-loadable
+    ConstPtr cc = (ConstPtr)cf;
+    asm volatile("" : "+s"(cc));
+    mx0 = (int)ceil(gx - 0.5 * W);
+    my0 = (int)ceil(gy - 0.5 * W);
+    const T tx = (T)(2.0 * ((double)mx0 - gx + 0.5 * W) - 1.0);
+    const T ty = (T)(2.0 * ((double)my0 - gy + 0.5 * W) - 1.0);
+    const T sx = tx * tx, sy = ty * ty;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        T p = cf[k * (D + 1) + D];
+    for (int k = 0; k < (W + 1) / 2; ++k) {
+        // the next point's coefficients are loaded only after this point's
+        // inputs exist, which keeps 16 (not 8 W) coefficients live in SGPRs
+        if (k > 0) asm volatile("" : "+s"(cc) : "v"(wx[k - 1]), "v"(wy[k - 1]));
+        ConstPtr c = cc + k * (D + 1);
+        T ex = c[2 * (NE - 1)], ey = ex;
 #pragma unroll
-        for (int j = D - 1; j >= 0; --j) p = fma(p, t, cf[k * (D + 1) + j]);
-        wt[k] = p;
+        for (int j = NE - 2; j >= 0; --j) {
+            ex = fma(ex, sx, c[2 * j]);
+            ey = fma(ey, sy, c[2 * j]);
+        }
+        T ox = c[2 * (NO - 1) + 1], oy = ox;
+#pragma unroll
+        for (int j = NO - 2; j >= 0; --j) {
+            ox = fma(ox, sx, c[2 * j + 1]);
+            oy = fma(oy, sy, c[2 * j + 1]);
+        }
+        wx[k] = fma(tx, ox, ex);
+        wy[k] = fma(ty, oy, ey);
+        if (W - 1 - k != k) {
+            wx[W - 1 - k] = fma(-tx, ox, ex);
+            wy[W - 1 - k] = fma(-ty, oy, ey);
+        }
     }
 }
 
+// One workgroup per (tile, density), four passes over one LDS buffer: V from
+// the volume sources, then S, D_x, D_y from the boundary sources.  Each pass
+// takes the plan's list of the sources whose window meets the tile (one
+// source per thread, every lane busy) and adds the part of its w x w window
+// inside the tile (row and column tests; the column tests are formed once
+// per source).  The buffer has a margin of w - 1 points around the tile, so
+// that every address is the source's window corner plus an immediate
+// offset; the tile's interior is then written once, so every grid value is
+// written exactly once, with no global atomics.  (Adding whole windows into
+// the margin instead of testing costs more: at w = 12 a listed source lies
+// ~45% outside the tile.)  The accumulators are FP64 at both precisions: LDS atomic adds of
+// FP64 run at more than twice the rate of FP32 ones, and the sums lose
+// nothing before the single rounding on the way out.
 template <int W, typename T>
 __global__ void __launch_bounds__(SB) k_spread(SpreadArgs<T> A)
 {
-    // The tile accumulators are FP64 at both precisions: LDS atomic adds of
-    // FP64 run at more than twice the rate of FP32 ones on this workload
-    // (spreading at tol 1e-6 on a 2560^2 grid: 0.59 against 1.31 ms), and
-    // the sums also lose nothing before the single rounding on the way out.
-    __shared__ double tileS[TILE * TILE], tileV[TILE * TILE], tileX[TILE * TILE], tileY[TILE * TILE];
+    constexpr int PAD = W - 1, PT = TILE + 2 * PAD;
+    __shared__ double acc[PT * PT];
     const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
-    const int tx = tile % A.ntile, ty = tile / A.ntile;
-    const int x0 = tx * TILE, y0 = ty * TILE;
-    for (int i = tid; i < TILE * TILE; i += SB) tileS[i] = tileV[i] = tileX[i] = tileY[i] = 0.0;
-    __syncthreads();
-    const bool has_b = A.sigma || A.mu;
-    for (int dty = -1; dty <= 1; ++dty) {
-        const int tyy = ty + dty;
-        if (tyy < 0 || tyy >= A.ntile) continue;
-        const int xa = max(tx - 1, 0), xb = min(tx + 1, A.ntile - 1);
-        if (has_b) {
-            const int s0 = A.btile[tyy * A.ntile + xa], s1 = A.btile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += SB) {
-                const double gx = A.bgx[s], gy = A.bgy[s];
-                // window start; skip sources whose window misses this tile
-                // before evaluating any window value
-                if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
-                    (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
-                    continue;
-                int mx0, my0;
-                T wx[W], wy[W];
-                window_weights<W, T>(gx, A.wcoef, mx0, wx);
-                window_weights<W, T>(gy, A.wcoef, my0, wy);
-                mx0 -= x0;
-                my0 -= y0;
-                const int i = A.bidx[s];
-                const T qs = A.sigma ? (T)(A.bw[s] * (double)A.sigma[(size_t)b * A.nb + i]) : (T)0;
-                const double m = A.mu ? (double)A.mu[(size_t)b * A.nb + i] : 0.0;
-                const T qx = (T)(A.bwx[s] * m), qy = (T)(A.bwy[s] * m);
-#pragma unroll
-                for (int ky = 0; ky < W; ++ky) {
-                    const int my = my0 + ky;
-                    if (my < 0 || my >= TILE) continue;
-#pragma unroll
-                    for (int kx = 0; kx < W; ++kx) {
-                        const int mx = mx0 + kx;
-                        if (mx < 0 || mx >= TILE) continue;
-                        const T v = wx[kx] * wy[ky];
-                        const int o = my * TILE + mx;
-                        if (A.sigma) atomicAdd(&tileS[o], (double)(qs * v));
-                        if (A.mu) {
-                            atomicAdd(&tileX[o], (double)(qx * v));
-                            atomicAdd(&tileY[o], (double)(qy * v));
-                        }
-                    }
-                }
-            }
-        }
-        if (A.f_vol) {
-            const int s0 = A.vtile[tyy * A.ntile + xa], s1 = A.vtile[tyy * A.ntile + xb + 1];
-            for (int s = s0 + tid; s < s1; s += SB) {
-                const double gx = A.vgx[s], gy = A.vgy[s];
-                if ((int)ceil(gx - 0.5 * W) - x0 >= TILE || (int)ceil(gy - 0.5 * W) - y0 >= TILE ||
-                    (int)ceil(gx - 0.5 * W) - x0 + W <= 0 || (int)ceil(gy - 0.5 * W) - y0 + W <= 0)
-                    continue;
-                int mx0, my0;
-                T wx[W], wy[W];
-                window_weights<W, T>(gx, A.wcoef, mx0, wx);
-                window_weights<W, T>(gy, A.wcoef, my0, wy);
-                mx0 -= x0;
-                my0 -= y0;
-                const T q = (T)(A.vw[s] * (double)A.f_vol[(size_t)b * A.nv + A.vidx[s]]);
-#pragma unroll
-                for (int ky = 0; ky < W; ++ky) {
-                    const int my = my0 + ky;
-                    if (my < 0 || my >= TILE) continue;
-                    const T qy = q * wy[ky];
-#pragma unroll
-                    for (int kx = 0; kx < W; ++kx) {
-                        const int mx = mx0 + kx;
-                        if (mx < 0 || mx >= TILE) continue;
-                        atomicAdd(&tileV[my * TILE + mx], (double)(qy * wx[kx]));
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
+    const int x0 = (tile % A.ntile) * TILE, y0 = (tile / A.ntile) * TILE;
     const size_t fs = (size_t)A.B * A.field;
     T *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
-    for (int i = tid; i < TILE * TILE; i += SB) {
-        const size_t o = (size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE);
-        gS[o] = (T)tileS[i];
-        gV[o] = (T)tileV[i];
-        gX[o] = (T)tileX[i];
-        gY[o] = (T)tileY[i];
+    for (int ph = 0; ph < 4; ++ph) {
+        T *out = ph == 0 ? gV : ph == 1 ? gS : ph == 2 ? gX : gY;
+        const bool vol = ph == 0;
+        const bool want = vol ? A.f_vol != nullptr : ph == 1 ? A.sigma != nullptr : A.mu != nullptr;
+        const int32_t *lofs = vol ? A.vlofs : A.blofs, *list = vol ? A.vlist : A.blist;
+        const int e0 = want ? lofs[tile] : 0, e1 = want ? lofs[tile + 1] : 0;
+        if (e0 == e1) {
+            for (int i = tid; i < TILE * TILE; i += SB)
+                out[(size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE)] = (T)0;
+            continue;
+        }
+        for (int i = tid; i < PT * PT; i += SB) acc[i] = 0.0;
+        __syncthreads();
+        for (int e = e0 + tid; e < e1; e += SB) {
+            const int s = list[e];
+            const double gx = vol ? A.vgx[s] : A.bgx[s], gy = vol ? A.vgy[s] : A.bgy[s];
+            int mx0, my0;
+            T wx[W], wy[W];
+            window_weights2<W, T>(gx, gy, A.wcoef, mx0, my0, wx, wy);
+            mx0 -= x0;
+            my0 -= y0;
+            // listed sources meet the tile; the test keeps every write inside
+            // the buffer whatever the list holds
+            if (mx0 <= -W || mx0 >= TILE || my0 <= -W || my0 >= TILE) continue;
+            T q;
+            if (vol) {
+                q = (T)(A.vw[s] * (double)A.f_vol[(size_t)b * A.nv + A.vidx[s]]);
+            } else {
+                const int i = A.bidx[s];
+                q = ph == 1 ? (T)(A.bw[s] * (double)A.sigma[(size_t)b * A.nb + i])
+                            : (T)((ph == 2 ? A.bwx[s] : A.bwy[s]) * (double)A.mu[(size_t)b * A.nb + i]);
+            }
+            double *base = acc + (my0 + PAD) * PT + (mx0 + PAD);
+            bool col[W];
+#pragma unroll
+            for (int kx = 0; kx < W; ++kx) col[kx] = (unsigned)(mx0 + kx) < (unsigned)TILE;
+#pragma unroll
+            for (int ky = 0; ky < W; ++ky) {
+                if ((unsigned)(my0 + ky) >= (unsigned)TILE) continue;
+                const T qy = q * wy[ky];
+#pragma unroll
+                for (int kx = 0; kx < W; ++kx)
+                    if (col[kx]) atomicAdd(base + ky * PT + kx, (double)(qy * wx[kx]));
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < TILE * TILE; i += SB)
+            out[(size_t)(y0 + i / TILE) * (A.n + 2) + x0 + (i % TILE)] =
+                (T)acc[(i / TILE + PAD) * PT + PAD + (i % TILE)];
+        __syncthreads();
     }
 }
 
@@ -224,9 +235,10 @@ __global__ void __launch_bounds__(HB) k_interp(InterpArgs<T> A)
     const size_t fs = (size_t)A.B * A.field;
     const T *g0 = A.grid + (size_t)b * A.field;
     for (int i = tid; i < RS * RS; i += HB) {
+        // the staged region exceeds the grid by less than one period
         int gy = ry0 + i / RS, gx = rx0 + i % RS;
-        gy = (int)(((int64_t)gy % A.n + A.n) % A.n);
-        gx = (int)(((int64_t)gx % A.n + A.n) % A.n);
+        gy += gy < 0 ? (int)A.n : gy >= A.n ? -(int)A.n : 0;
+        gx += gx < 0 ? (int)A.n : gx >= A.n ? -(int)A.n : 0;
         const size_t o = (size_t)gy * (A.n + 2) + gx;
         reg[0][i] = A.want_s ? g0[o] : (T)0;
         reg[1][i] = A.want_v ? g0[fs + o] : (T)0;
@@ -238,8 +250,7 @@ __global__ void __launch_bounds__(HB) k_interp(InterpArgs<T> A)
         const double gx = (A.tx[s] - A.ox) / A.h, gy = (A.ty[s] - A.oy) / A.h;
         int mx0, my0;
         T wx[W], wy[W];
-        window_weights<W, T>(gx, A.wcoef, mx0, wx);
-        window_weights<W, T>(gy, A.wcoef, my0, wy);
+        window_weights2<W, T>(gx, gy, A.wcoef, mx0, my0, wx, wy);
         const int lx = min(max(mx0 - rx0, 0), RS - W), ly = min(max(my0 - ry0, 0), RS - W);
         T uS = 0, uV = 0, uD = 0;
 #pragma unroll 1
@@ -395,8 +406,8 @@ static hipError_t spread_t(mhk_plan *P, const void *sigma, const void *mu, const
     A.B = P->p.batch;
     A.beta = G.beta;
     A.bgx = G.bgx; A.bgy = G.bgy; A.bw = G.bw; A.bwx = G.bwx; A.bwy = G.bwy;
-    A.bidx = G.bidx; A.btile = G.btile;
-    A.vgx = G.vgx; A.vgy = G.vgy; A.vw = G.vw; A.vidx = G.vidx; A.vtile = G.vtile;
+    A.bidx = G.bidx; A.blofs = G.blofs; A.blist = G.blist;
+    A.vgx = G.vgx; A.vgy = G.vgy; A.vw = G.vw; A.vidx = G.vidx; A.vlofs = G.vlofs; A.vlist = G.vlist;
     A.sigma = (const T *)sigma;
     A.mu = (const T *)mu;
     A.f_vol = (const T *)f_vol;

@@ -86,6 +86,7 @@ struct LevelArgs {
     const T *q, *tab;
     T *acc_s, *acc_d;     // [B][nout] each (sorted order)
     int want_s, want_d;
+    int init;             // store (first level) instead of add
 };
 
 
@@ -214,8 +215,9 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
             for (int b = 0; b < BCH; ++b) {
                 if (b < nbh) {
                     const size_t o = (size_t)(b0 + b) * A.nout + t[i];
-                    if (A.want_s) A.acc_s[o] += S[i][b];
-                    if (A.want_d) A.acc_d[o] += D[i][b] * (T)A.d_scale;
+                    const T s = S[i][b], d = D[i][b] * (T)A.d_scale;
+                    if (A.want_s) A.acc_s[o] = A.init ? s : A.acc_s[o] + s;
+                    if (A.want_d) A.acc_d[o] = A.init ? d : A.acc_d[o] + d;
                 }
             }
         }
@@ -223,23 +225,23 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 }
 
 template <typename T>
-static hipError_t level_q(mhk_plan *P, int j, const void *sigma, const void *mu)
+static hipError_t level_q(mhk_plan *P, hipStream_t st, int j, const void *sigma, const void *mu)
 {
     Level &L = P->lev[j - 1];
     const int64_t n = L.n_src;
     dim3 grid((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(k_level_q<T>, grid, dim3(256), 0, P->stream, n, L.nchild, P->p.batch, P->nb, L.code,
+    hipLaunchKernelGGL(k_level_q<T>, grid, dim3(256), 0, st, n, L.nchild, P->p.batch, P->nb, L.code,
                        L.interp, L.sw, L.swx, L.swy, (const T *)sigma, (const T *)mu, (T *)L.q);
     return hipGetLastError();
 }
 
-hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu)
+hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void *sigma, const void *mu)
 {
-    return P->p.prec == MHK_FP64 ? level_q<double>(P, j, sigma, mu) : level_q<float>(P, j, sigma, mu);
+    return P->p.prec == MHK_FP64 ? level_q<double>(P, st, j, sigma, mu) : level_q<float>(P, st, j, sigma, mu);
 }
 
 template <typename T, int NC, int STRIDE>
-static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
+static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
     Level &L = P->lev[j - 1];
     const int B = P->p.batch;
@@ -261,10 +263,11 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
     A.sy = L.sy;
     A.q = (const T *)L.q;
     A.tab = (const T *)L.tab_dev;
-    A.acc_s = (T *)P->acc;                                  // component 0: S
-    A.acc_d = (T *)P->acc + (size_t)B * P->nout;            // component 1: D
+    A.acc_s = (T *)P->acc_lev;                              // component 0: S
+    A.acc_d = (T *)P->acc_lev + (size_t)B * P->nout;        // component 1: D
     A.want_s = want_s;
     A.want_d = want_d;
+    A.init = init;
     const int bch = B == 1 ? 1 : LV_BCH;
     dim3 grid((unsigned)((P->nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)), (unsigned)((B + bch - 1) / bch));
     const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE;
@@ -273,20 +276,20 @@ static hipError_t level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void *)k_level_sums<1, T, NC, STRIDE>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
+        hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
     } else {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void *)k_level_sums<LV_BCH, T, NC, STRIDE>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, P->stream, A);
+        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d)
+hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
-    if (P->p.prec == MHK_FP64) return level_sums<double, TAB_NC, TAB_STRIDE>(P, j, want_s, want_d);
-    return level_sums<float, TABF_NC, TABF_STRIDE>(P, j, want_s, want_d);
+    if (P->p.prec == MHK_FP64) return level_sums<double, TAB_NC, TAB_STRIDE>(P, st, j, want_s, want_d, init);
+    return level_sums<float, TABF_NC, TABF_STRIDE>(P, st, j, want_s, want_d, init);
 }
 
 }  // namespace mhk

@@ -140,7 +140,8 @@ struct LocalArgs {
     double cell, ox, oy, gap;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
-    const T *acc;          // [3][B][nout]: S, D, V in sorted order
+    const T *acc;          // [3][B][nout]: S, D, V in sorted order (history part)
+    const T *lev;          // [2][B][nout]: S, D of the level sums, or null
     T *out_s, *out_d, *out_v;
 };
 
@@ -338,6 +339,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
         const size_t ab = (size_t)b * A.nout + s;
         if (ws) {
             double v = (double)A.acc[(size_t)0 * A.B * A.nout + ab];
+            if (A.lev) v += (double)A.lev[ab];
             if (do_local) {
                 if (on) {
                     const int64_t i = idx - A.nt;
@@ -351,6 +353,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
         }
         if (wd) {
             double v = (double)A.acc[(size_t)1 * A.B * A.nout + ab];
+            if (A.lev) v += (double)A.lev[(size_t)A.B * A.nout + ab];
             if (do_local) {
                 if (on) {
                     const int64_t i = idx - A.nt;
@@ -458,6 +461,7 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
     A.acc = (const T *)P->acc;
+    A.lev = nullptr;
     A.out_s = A.out_d = A.out_v = nullptr;
 }
 
@@ -473,10 +477,11 @@ hipError_t launch_local_geom(mhk_plan *P)
 
 template <typename T>
 static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                          void *out_s, void *out_d, void *out_v, bool have_fb)
+                          void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
 {
     LocalArgs<T> A;
     fill_args(P, A);
+    A.lev = have_lev ? (const T *)P->acc_lev : nullptr;
     A.parts = parts;
     A.sigma = (const T *)sigma;
     A.mu = (const T *)mu;
@@ -490,10 +495,11 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
 }
 
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                        void *out_s, void *out_d, void *out_v, bool have_fb)
+                        void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
 {
-    if (P->p.prec == MHK_FP64) return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb);
-    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb);
+    if (P->p.prec == MHK_FP64)
+        return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
 }
 
 }  // namespace mhk

@@ -98,10 +98,12 @@ struct History {
     double *bgx = nullptr, *bgy = nullptr;        // boundary nodes
     double *bw = nullptr, *bwx = nullptr, *bwy = nullptr;
     int32_t *bidx = nullptr;
-    int32_t *btile = nullptr;                     // [ntile*ntile + 1]
     double *vgx = nullptr, *vgy = nullptr, *vw = nullptr;
     int32_t *vidx = nullptr;
-    int32_t *vtile = nullptr;                     // [ntile*ntile + 1]
+    // per tile, the sorted sources whose w x w window meets the tile (a
+    // source is listed in up to 4 tiles): lists [*lofs[t], *lofs[t + 1])
+    int32_t *blofs = nullptr, *blist = nullptr;   // boundary: [ntile*ntile + 1], entries
+    int32_t *vlofs = nullptr, *vlist = nullptr;   // volume
     // targets by tile: list of non-empty tiles and their ranges in sorted order
     int n_ttiles = 0;
     int32_t *ttile_xy = nullptr;                  // [n_ttiles] tile index ty*ntile+tx
@@ -171,8 +173,14 @@ struct mhk_plan {
     mhk::Local loc;
     std::vector<void *> allocs;
     int64_t bytes = 0;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[9] = {};                      // stage timing (ev[8]: start of the level sums)
     hipStream_t cap = nullptr;                  // capture stream of mhk_plan_capture
+    // The level sums run on a second stream beside the history part (they
+    // share no data): they accumulate S and D into acc_lev, [2][batch][n_out],
+    // which the local part adds.
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    void *acc_lev = nullptr;
     hipGraphExec_t gexec = nullptr;             // captured evaluation
 };
 
@@ -180,12 +188,13 @@ namespace mhk {
 
 // kernels launchers (defined in the .hip files); density and output pointers
 // are of the plan's precision
-hipError_t launch_level_densities(mhk_plan *P, int j, const void *sigma, const void *mu);
-hipError_t launch_level_sums(mhk_plan *P, int j, bool want_s, bool want_d);
+hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void *sigma, const void *mu);
+// level j's sums into acc_lev on stream st: stored when init, else added
+hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init);
 hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd);
 hipError_t launch_local_geom(mhk_plan *P);
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
-                        const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb);
+                        const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);

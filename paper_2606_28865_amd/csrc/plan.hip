@@ -337,6 +337,9 @@ static void free_plan(mhk_plan *P)
         if (e) (void)hipEventDestroy(e);
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->cap) (void)hipStreamDestroy(P->cap);
+    if (P->fork_ev) (void)hipEventDestroy(P->fork_ev);
+    if (P->join_ev) (void)hipEventDestroy(P->join_ev);
+    if (P->side) (void)hipStreamDestroy(P->side);
     delete P;
 }
 
@@ -1054,6 +1057,47 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     if (G.trunc) TRY(build_trunc_table(P, qt, qw));
 
     const int64_t nt2 = (int64_t)G.ntile * G.ntile;
+    // per-tile lists of the sorted sources whose window [m0, m0 + w) (m0 =
+    // ceil(g - w/2), as the spreading kernel forms it) meets the tile in
+    // both axes; w <= 16 < TILE, so a window meets at most 2 tiles per axis
+    auto tile_lists = [&](const std::vector<double> &gx, const std::vector<double> &gy, int32_t **lofs,
+                          int32_t **list) -> mhk_status {
+        const int64_t ns = (int64_t)gx.size();
+        const int W = G.w;
+        auto span = [&](double g, int64_t &t0, int64_t &t1) {
+            const int64_t m0 = (int64_t)ceil(g - 0.5 * W);
+            t0 = std::max<int64_t>(0, (int64_t)floor((double)m0 / TILE));
+            t1 = std::min<int64_t>(G.ntile - 1, (int64_t)floor((double)(m0 + W - 1) / TILE));
+        };
+        std::vector<int32_t> ofs(nt2 + 1, 0);
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<int32_t> fill;
+            std::vector<int32_t> ent;
+            if (pass == 1) {
+                for (int64_t t = 0; t < nt2; ++t) ofs[t + 1] += ofs[t];
+                fill.assign(ofs.begin(), ofs.end() - 1);
+                ent.assign((size_t)std::max<int32_t>(1, ofs[nt2]), 0);
+            }
+            for (int64_t s = 0; s < ns; ++s) {
+                int64_t x0, x1, y0, y1;
+                span(gx[s], x0, x1);
+                span(gy[s], y0, y1);
+                for (int64_t ty = y0; ty <= y1; ++ty)
+                    for (int64_t tx = x0; tx <= x1; ++tx) {
+                        const int64_t t = ty * G.ntile + tx;
+                        if (pass == 0)
+                            ofs[t + 1]++;
+                        else
+                            ent[fill[t]++] = (int32_t)s;
+                    }
+            }
+            if (pass == 1) {
+                TRY(upload(P, list, ent.data(), (int64_t)ent.size()));
+                TRY(upload(P, lofs, ofs.data(), nt2 + 1));
+            }
+        }
+        return MHK_OK;
+    };
     auto tile_of = [&](double x, double y) -> int64_t {
         int64_t ix = (int64_t)floor((x - G.ox) / G.h) / TILE;
         int64_t iy = (int64_t)floor((y - G.oy) / G.h) / TILE;
@@ -1085,7 +1129,7 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         TRY(upload(P, &G.bwx, wx.data(), nb));
         TRY(upload(P, &G.bwy, wy.data(), nb));
         TRY(upload(P, &G.bidx, order.data(), nb));
-        TRY(upload(P, &G.btile, start.data(), nt2 + 1));
+        TRY(tile_lists(gx, gy, &G.blofs, &G.blist));
     }
     // volume sources
     {
@@ -1106,7 +1150,7 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         TRY(upload(P, &G.vgy, gy.data(), nv));
         TRY(upload(P, &G.vw, w.data(), nv));
         TRY(upload(P, &G.vidx, order.data(), nv));
-        TRY(upload(P, &G.vtile, start.data(), nt2 + 1));
+        TRY(tile_lists(gx, gy, &G.vlofs, &G.vlist));
     }
     // targets by tile (they are sorted with tiles contiguous)
     {
@@ -1363,8 +1407,14 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
         char *a = nullptr;
         TRY(dalloc(P, &a, 3 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
         P->acc = a;
+        char *l = nullptr;
+        TRY(dalloc(P, &l, 2 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
+        P->acc_lev = l;
     }
     for (auto &e : P->ev) MHK_HIP(hipEventCreate(&e));
+    MHK_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    MHK_HIP(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+    MHK_HIP(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
     P->info.n_boundary = P->nb;
     P->info.n_volume = P->nv;
     P->info.n_targets = P->nt;
@@ -1424,7 +1474,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
     int64_t s = 0;
     s += nb * 8 * 6;                          // boundary
     s += nout * (8 * 2 + 1 + 4);              // targets
-    s += 3 * B * nout * 8;                    // accumulators
+    s += 5 * B * nout * 8;                    // accumulators (history and levels)
     for (int j = 1; j <= p.J; ++j) {          // levels
         int64_t ns = nb << j;
         s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
@@ -1445,6 +1495,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         const int64_t es = p.prec == MHK_FP64 ? 8 : 4;
         s += 4 * B * g.n * (g.n + 2) * es * 2;   // grids + FFT work estimate
         s += (nb + nv) * (8 * 3 + 4);
+        s += (nb + nv) * 4 * 4 + 2 * (int64_t)(g.n / TILE) * (g.n / TILE) * 4;   // per-tile source lists
     }
     *bytes = s;
     return MHK_OK;
@@ -1518,6 +1569,22 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     const int B = P->p.batch;
     const int64_t nout = P->nout;
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[0], st));
+    // The level sums share no data with the history part: they run on the
+    // side stream, forked from and joined back into the plan's stream, so the
+    // two overlap (the level sums are bound by LDS and FP64 issue, the FFTs by
+    // memory).  They write acc_lev; the local part adds it.
+    const bool levels = (parts & MHK_PART_LEVELS) && (ws || wd) && P->J > 0;
+    if (levels) {
+        MHK_HIP(hipEventRecord(P->fork_ev, st));
+        MHK_HIP(hipStreamWaitEvent(P->side, P->fork_ev, 0));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[8], P->side));
+        for (int j = 1; j <= P->J; ++j) {
+            MHK_HIP(launch_level_densities(P, P->side, j, ws ? sigma : nullptr, wd ? mu : nullptr));
+            MHK_HIP(launch_level_sums(P, P->side, j, ws, wd, j == 1));
+        }
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], P->side));
+        MHK_HIP(hipEventRecord(P->join_ev, P->side));
+    }
     // history part writes the accumulators (or zeros them)
     bool hist = (parts & MHK_PART_HISTORY) && P->hist.active;
     if (hist) {
@@ -1537,25 +1604,29 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
             for (int e = 1; e <= 4; ++e) MHK_HIP(hipEventRecord(P->ev[e], st));
     }
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[5], st));
-    if ((parts & MHK_PART_LEVELS) && (ws || wd)) {
-        for (int j = 1; j <= P->J; ++j) {
-            MHK_HIP(launch_level_densities(P, j, ws ? sigma : nullptr, wd ? mu : nullptr));
-            MHK_HIP(launch_level_sums(P, j, ws, wd));
-        }
-    }
-    if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], st));
+    if (levels) MHK_HIP(hipStreamWaitEvent(st, P->join_ev, 0));
     // f at the boundary nodes (the on-surface entries of f_trg) gives the
     // local volume part at exterior targets near the boundary
     const bool have_fb = wv && (parts & MHK_PART_LOCAL) && P->nout > P->nt;
     if ((parts & MHK_PART_LOCAL) && (ws || wd || have_fb))
         MHK_HIP(launch_panel_coeffs(P, ws ? sigma : nullptr, wd ? mu : nullptr, have_fb ? f_trg : nullptr));
     MHK_HIP(launch_local(P, parts, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_trg : nullptr,
-                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb));
+                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb, levels));
     if (P->timing) {
         MHK_HIP(hipEventRecord(P->ev[7], st));
         MHK_HIP(hipEventSynchronize(P->ev[7]));
+        // history stages and the local part on the plan's stream; the level
+        // sums on the side stream (their span overlaps the history part)
         float ms[8] = {0};
-        for (int e = 1; e < 8; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
+        for (int e = 1; e <= 5; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
+        if (levels) MHK_HIP(hipEventElapsedTime(&ms[6], P->ev[8], P->ev[6]));
+        // the local part starts when both the history part and the levels are done
+        float t5 = 0, t6 = 0;
+        MHK_HIP(hipEventElapsedTime(&t5, P->ev[0], P->ev[5]));
+        if (levels) MHK_HIP(hipEventElapsedTime(&t6, P->ev[0], P->ev[6]));
+        float t7 = 0;
+        MHK_HIP(hipEventElapsedTime(&t7, P->ev[0], P->ev[7]));
+        ms[7] = t7 - std::max(t5, t6);
         P->info.ms_spread = ms[1];
         P->info.ms_fft = ms[2] + ms[4];
         P->info.ms_multiply = ms[3];
