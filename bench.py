@@ -109,20 +109,18 @@ def main():
             p.eval(sigma, mu, fv, ft, out=o)
     torch.cuda.synchronize()
     log("warmup done")
+    # stage events are recorded by the library on its streams during the timed
+    # steps and read after them (reading waits, so it stays outside the loop):
+    # the stage times are those of the last timed step
     for p in plans:
         p.set_timing(True)
-    stage = {k: [0.0] * len(plans) for k in ("ms_spread", "ms_fft", "ms_multiply", "ms_interp", "ms_levels",
-                                             "ms_local", "ms_total")}
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     wall0 = time.perf_counter()
     for _ in range(a.steps):
-        for i, (p, o) in enumerate(zip(plans, outs)):
+        for p, o in zip(plans, outs):
             p.eval(sigma, mu, fv, ft, out=o)
-            inf = p.info()
-            for k in stage:
-                stage[k][i] += inf[k]
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -130,9 +128,9 @@ def main():
     ms_step = ms / a.steps
     evals = n_out * len(plans)
     value = evals / (ms_step * 1e-3)
-    for k in stage:
-        stage[k] = [x / a.steps for x in stage[k]]
     infos = [p.info() for p in plans]
+    stage = {k: [inf[k] for inf in infos] for k in ("ms_spread", "ms_fft", "ms_multiply", "ms_interp",
+                                                     "ms_levels", "ms_local", "ms_total")}
 
     # dominant kernel: the one with the largest summed time over the step
     tot = {k: sum(v) for k, v in stage.items() if k != "ms_total"}

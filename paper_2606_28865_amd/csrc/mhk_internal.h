@@ -174,6 +174,7 @@ struct mhk_plan {
     std::vector<void *> allocs;
     int64_t bytes = 0;
     hipEvent_t ev[9] = {};                      // stage timing (ev[8]: start of the level sums)
+    bool t_pending = false, t_levels = false;   // stage events recorded, not read yet
     hipStream_t cap = nullptr;                  // capture stream of mhk_plan_capture
     // The level sums run on a second stream beside the history part (they
     // share no data): they accumulate S and D into acc_lev, [2][batch][n_out],

@@ -1424,6 +1424,8 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     return MHK_OK;
 }
 
+mhk_status collect_timing(mhk_plan *P);   // stage times of the last timed evaluation
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1517,6 +1519,7 @@ mhk_status mhk_plan_info(const mhk_plan *P, mhk_info *info)
         set_error("plan or info is NULL");
         return MHK_EINVAL;
     }
+    TRY(collect_timing(const_cast<mhk_plan *>(P)));
     *info = P->info;
     return MHK_OK;
 }
@@ -1559,7 +1562,36 @@ mhk_status validate_eval(const mhk_plan *P, int parts, const void *sigma, const 
     return MHK_OK;
 }
 
-// Enqueue one evaluation on P->stream (no synchronisation unless timing).
+// Stage times of the last timed evaluation, read when asked for (the
+// evaluation itself does not wait for them): history stages and the local
+// part on the plan's stream, the level sums on the side stream, whose span
+// overlaps the history part.
+mhk_status collect_timing(mhk_plan *P)
+{
+    if (!P->t_pending) return MHK_OK;
+    P->t_pending = false;
+    const bool levels = P->t_levels;
+    MHK_HIP(hipEventSynchronize(P->ev[7]));
+    float ms[8] = {0};
+    for (int e = 1; e <= 5; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
+    if (levels) MHK_HIP(hipEventElapsedTime(&ms[6], P->ev[8], P->ev[6]));
+    // the local part starts when both the history part and the levels are done
+    float t5 = 0, t6 = 0, t7 = 0;
+    MHK_HIP(hipEventElapsedTime(&t5, P->ev[0], P->ev[5]));
+    if (levels) MHK_HIP(hipEventElapsedTime(&t6, P->ev[0], P->ev[6]));
+    MHK_HIP(hipEventElapsedTime(&t7, P->ev[0], P->ev[7]));
+    ms[7] = t7 - std::max(t5, t6);
+    P->info.ms_spread = ms[1];
+    P->info.ms_fft = ms[2] + ms[4];
+    P->info.ms_multiply = ms[3];
+    P->info.ms_interp = ms[5];
+    P->info.ms_levels = ms[6];
+    P->info.ms_local = ms[7];
+    P->info.ms_total = t7;
+    return MHK_OK;
+}
+
+// Enqueue one evaluation on P->stream (no synchronisation).
 mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol, const void *f_trg,
                    void *out_s, void *out_d, void *out_v)
 {
@@ -1614,28 +1646,8 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
                          ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb, levels));
     if (P->timing) {
         MHK_HIP(hipEventRecord(P->ev[7], st));
-        MHK_HIP(hipEventSynchronize(P->ev[7]));
-        // history stages and the local part on the plan's stream; the level
-        // sums on the side stream (their span overlaps the history part)
-        float ms[8] = {0};
-        for (int e = 1; e <= 5; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
-        if (levels) MHK_HIP(hipEventElapsedTime(&ms[6], P->ev[8], P->ev[6]));
-        // the local part starts when both the history part and the levels are done
-        float t5 = 0, t6 = 0;
-        MHK_HIP(hipEventElapsedTime(&t5, P->ev[0], P->ev[5]));
-        if (levels) MHK_HIP(hipEventElapsedTime(&t6, P->ev[0], P->ev[6]));
-        float t7 = 0;
-        MHK_HIP(hipEventElapsedTime(&t7, P->ev[0], P->ev[7]));
-        ms[7] = t7 - std::max(t5, t6);
-        P->info.ms_spread = ms[1];
-        P->info.ms_fft = ms[2] + ms[4];
-        P->info.ms_multiply = ms[3];
-        P->info.ms_interp = ms[5];
-        P->info.ms_levels = ms[6];
-        P->info.ms_local = ms[7];
-        float tot = 0;
-        MHK_HIP(hipEventElapsedTime(&tot, P->ev[0], P->ev[7]));
-        P->info.ms_total = tot;
+        P->t_pending = true;
+        P->t_levels = levels;
     }
     return MHK_OK;
 }
