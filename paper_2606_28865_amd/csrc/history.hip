@@ -210,6 +210,244 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
     F[2 * fs] = zD;
 }
 
+// ---------------------------------------------------------------------------
+// Column transforms fused with the multiplier.  After the row transforms
+// (rocFFT, real-to-complex along x), every column l_x of the half spectrum is
+// an independent length-n sequence along y; the multiplier is applied between
+// the forward and the inverse column transforms, so one workgroup takes a
+// column from HBM into LDS, transforms it, multiplies, transforms back and
+// writes it: the 2D transforms' two column passes, their transposes and the
+// multiplier pass become one read and one write of each column.  Columns
+// with l_x beyond the multiplier's support are only written with zeros.
+//
+// Transforms: self-sorting (Stockham) passes of radix 2, 3, 4, 5 or 8 on the
+// LDS copy; each pass reads every butterfly's inputs into registers, waits,
+// and writes the outputs in place.  Twiddles e^{-2 pi i m/n} come from a
+// table (conjugated for the inverse); both directions are unnormalised, like
+// the rocFFT row transforms.
+// ---------------------------------------------------------------------------
+constexpr int CT = 512;            // threads per column workgroup
+
+template <typename T2>
+__device__ inline T2 c2(decltype(T2::x) x, decltype(T2::x) y)
+{
+    T2 r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+template <typename T2> __device__ inline T2 cadd(T2 a, T2 b) { return c2<T2>(a.x + b.x, a.y + b.y); }
+template <typename T2> __device__ inline T2 csub(T2 a, T2 b) { return c2<T2>(a.x - b.x, a.y - b.y); }
+template <typename T2> __device__ inline T2 cmul(T2 a, T2 b)
+{
+    return c2<T2>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T2> __device__ inline T2 cscale(T2 a, decltype(T2::x) s) { return c2<T2>(a.x * s, a.y * s); }
+// -i z (forward) or +i z (inverse)
+template <bool INV, typename T2> __device__ inline T2 rot(T2 z)
+{
+    return INV ? c2<T2>(-z.y, z.x) : c2<T2>(z.y, -z.x);
+}
+
+// DFT of R points, y_k = sum_t x_t e^{-+2 pi i t k / R}
+template <int R, bool INV, typename T2> __device__ inline void dft(T2 *x)
+{
+    typedef decltype(T2::x) T;
+    if constexpr (R == 2) {
+        const T2 a = x[0];
+        x[0] = cadd(a, x[1]);
+        x[1] = csub(a, x[1]);
+    } else if constexpr (R == 3) {
+        const T c = (T)-0.5, s = (T)0.86602540378443864676;
+        const T2 a = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+        const T2 r = cadd(x[0], cscale(a, c)), i = rot<INV>(cscale(d, s));
+        x[0] = cadd(x[0], a);
+        x[1] = cadd(r, i);
+        x[2] = csub(r, i);
+    } else if constexpr (R == 4) {
+        const T2 t0 = cadd(x[0], x[2]), t1 = csub(x[0], x[2]), t2 = cadd(x[1], x[3]), t3 = rot<INV>(csub(x[1], x[3]));
+        x[0] = cadd(t0, t2);
+        x[2] = csub(t0, t2);
+        x[1] = cadd(t1, t3);
+        x[3] = csub(t1, t3);
+    } else if constexpr (R == 8) {
+        // two DFTs of 4 on the even and odd points, combined with w8^k
+        T2 e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+        dft<4, INV>(e);
+        dft<4, INV>(o);
+        const T h = (T)0.70710678118654752440;
+        // w8^k o_k, w8 = e^{-+ i pi/4}
+        const T2 o1 = INV ? c2<T2>(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
+                          : c2<T2>(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+        const T2 o2 = rot<INV>(o[2]);
+        const T2 o3 = INV ? c2<T2>(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))
+                          : c2<T2>(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+        x[0] = cadd(e[0], o[0]);
+        x[4] = csub(e[0], o[0]);
+        x[1] = cadd(e[1], o1);
+        x[5] = csub(e[1], o1);
+        x[2] = cadd(e[2], o2);
+        x[6] = csub(e[2], o2);
+        x[3] = cadd(e[3], o3);
+        x[7] = csub(e[3], o3);
+    } else {
+        static_assert(R == 5, "radix");
+        const T c1 = (T)0.30901699437494742410, c2v = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        const T2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]), a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+        const T2 r1 = cadd(x[0], cadd(cscale(a1, c1), cscale(a2, c2v)));
+        const T2 r2 = cadd(x[0], cadd(cscale(a1, c2v), cscale(a2, c1)));
+        const T2 i1 = rot<INV>(cadd(cscale(b1, s1), cscale(b2, s2)));
+        const T2 i2 = rot<INV>(csub(cscale(b1, s2), cscale(b2, s1)));
+        x[0] = cadd(x[0], cadd(a1, a2));
+        x[1] = cadd(r1, i1);
+        x[4] = csub(r1, i1);
+        x[2] = cadd(r2, i2);
+        x[3] = csub(r2, i2);
+    }
+}
+
+// One radix-R pass of a length-N transform held in LDS; Ns = product of the
+// radices of the passes before it.
+template <int R, bool INV, typename T2>
+__device__ inline void col_pass(T2 *buf, const T2 *__restrict__ tw, int N, int Ns)
+{
+    typedef decltype(T2::x) T;
+    constexpr int MB = (COL_NMAX / R + CT - 1) / CT;
+    const int nb = N / R, step = N / (Ns * R);
+    T2 v[MB][R];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int j = threadIdx.x + i * CT;
+        if (j < nb) {
+            // one twiddle load per butterfly, issued before the LDS reads;
+            // w^t by repeated products
+            T2 w = c2<T2>((T)1, (T)0);
+            if (Ns > 1) {
+                w = tw[(j % Ns) * step];
+                if (INV) w.y = -w.y;
+            }
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[i][t] = buf[j + t * nb];
+            if (Ns > 1) {
+                T2 wt = w;
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    v[i][t] = cmul(v[i][t], wt);
+                    if (t + 1 < R) wt = cmul(wt, w);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int j = threadIdx.x + i * CT;
+        if (j < nb) {
+            dft<R, INV>(v[i]);
+            const int k = j % Ns, o = (j - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[o + t * Ns] = v[i][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool INV, typename T2>
+__device__ inline void col_fft(T2 *buf, const T2 *tw, int N, const int8_t *radix, int npass)
+{
+    int Ns = 1;
+    for (int p = 0; p < npass; ++p) {
+        const int r = radix[p];
+        if (r == 8) col_pass<8, INV>(buf, tw, N, Ns);
+        else if (r == 4) col_pass<4, INV>(buf, tw, N, Ns);
+        else if (r == 2) col_pass<2, INV>(buf, tw, N, Ns);
+        else if (r == 3) col_pass<3, INV>(buf, tw, N, Ns);
+        else col_pass<5, INV>(buf, tw, N, Ns);
+        Ns *= r;
+    }
+}
+
+template <typename T>
+struct ColArgs {
+    int64_t n, field;
+    int B, ncol, npass;
+    int8_t radix[COL_MAXPASS];
+    T *grid;
+    const typename Vec2<T>::type *tw;
+    const double *fac, *mtab;
+    double c, alpha2, dk;
+    int lmax;
+};
+
+// One workgroup per (column, density, output): 0 S, 1 V, 2 D (from the D_x
+// and D_y spectra: -i (k_x Gx + k_y Gy) M, as two transforms whose results
+// are added).
+template <typename T>
+__global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_columns(ColArgs<T> A)
+{
+    typedef typename Vec2<T>::type T2;
+    extern __shared__ double lds_col[];
+    T2 *buf = reinterpret_cast<T2 *>(lds_col);
+    const int n = (int)A.n, nh = n / 2 + 1;
+    // consecutive columns on one XCD (workgroups are dealt to the 8 XCDs in
+    // turn), so that neighbouring columns share the XCD's L2 lines
+    const int per = (nh + 7) / 8;
+    const int lx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (lx >= nh) return;
+    const int b = blockIdx.y, grp = blockIdx.z;
+    const size_t fs = (size_t)A.B * (A.field / 2);              // complex values per slot
+    T2 *base = reinterpret_cast<T2 *>(A.grid) + (size_t)b * (A.field / 2) + lx;
+    T2 *out = base + (size_t)grp * fs;
+    const T2 zero = c2<T2>((T)0, (T)0);
+    if (lx >= A.ncol) {
+        for (int y = threadIdx.x; y < n; y += CT) out[(size_t)y * nh] = zero;
+        return;
+    }
+    const double ax = A.fac[lx];
+    const double kx = A.dk * lx;
+    auto mult = [&](int ly) -> double {
+        const int fy = ly <= n / 2 ? ly : ly - n;
+        if (A.mtab) {
+            if (lx <= A.lmax && fy >= -A.lmax && fy <= A.lmax) return A.mtab[(fy + A.lmax) * (A.lmax + 1) + lx];
+            return 0.0;
+        }
+        const double ay = A.fac[fy < 0 ? -fy : fy];
+        if (ax == 0.0 || ay == 0.0) return 0.0;
+        const double ky = A.dk * fy;
+        return A.c * ax * ay / (A.alpha2 + kx * kx + ky * ky);
+    };
+    const int nparts = grp == 2 ? 2 : 1;
+    for (int part = 0; part < nparts; ++part) {
+        const T2 *in = base + (size_t)(grp == 2 ? 2 + part : grp) * fs;
+        for (int y = threadIdx.x; y < n; y += CT) buf[y] = in[(size_t)y * nh];
+        __syncthreads();
+        col_fft<false>(buf, A.tw, n, A.radix, A.npass);
+        for (int ly = threadIdx.x; ly < n; ly += CT) {
+            const double M = mult(ly);
+            const T2 z = buf[ly];
+            if (grp < 2) {
+                buf[ly] = c2<T2>((T)(M * z.x), (T)(M * z.y));
+            } else {
+                // -i k M z with k = k_x (part 0) or k_y (part 1)
+                const int fy = ly <= n / 2 ? ly : ly - n;
+                const double kM = (part == 0 ? kx : A.dk * fy) * M;
+                buf[ly] = c2<T2>((T)(kM * z.y), (T)(-kM * z.x));
+            }
+        }
+        __syncthreads();
+        col_fft<true>(buf, A.tw, n, A.radix, A.npass);
+        // part 0 of D writes its column, part 1 adds to it (same thread, same
+        // rows: no other thread touches these values)
+        for (int y = threadIdx.x; y < n; y += CT) {
+            T2 v = buf[y];
+            if (part == 1) v = cadd(out[(size_t)y * nh], v);
+            out[(size_t)y * nh] = v;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 struct InterpArgs {
     int64_t n, field, nout;
@@ -430,6 +668,39 @@ static hipError_t multiply_t(mhk_plan *P)
                        P->p.batch, G.field, (T *)G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha,
                        2.0 * M_PI / G.period, G.trunc ? G.mtab : nullptr, G.lmax);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t columns_t(mhk_plan *P)
+{
+    const History &G = P->hist;
+    ColArgs<T> A;
+    A.n = G.n;
+    A.field = G.field;
+    A.B = P->p.batch;
+    A.ncol = G.ncol;
+    A.npass = G.npass;
+    for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.radix[i];
+    A.grid = (T *)G.grid;
+    A.tw = (const typename Vec2<T>::type *)G.tw;
+    A.fac = G.fac;
+    A.mtab = G.trunc ? G.mtab : nullptr;
+    A.c = G.mult_c;
+    A.alpha2 = P->p.alpha * P->p.alpha;
+    A.dk = 2.0 * M_PI / G.period;
+    A.lmax = G.lmax;
+    const int64_t nh = G.n / 2 + 1;
+    const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)G.n;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_columns<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    dim3 grid((unsigned)(((nh + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
+    hipLaunchKernelGGL(k_columns<T>, grid, dim3(CT), lds, P->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_columns(mhk_plan *P)
+{
+    return P->p.prec == MHK_FP64 ? columns_t<double>(P) : columns_t<float>(P);
 }
 
 hipError_t launch_multiply(mhk_plan *P)

@@ -35,6 +35,8 @@ constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
 constexpr int TAB_STRIDE = 9;    // doubles per segment in LDS (18 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: floats per segment
+constexpr int COL_NMAX = 8192;   // longest history-grid column transformed in LDS
+constexpr int COL_MAXPASS = 16;  // radix passes of a column transform
 constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
@@ -128,6 +130,15 @@ struct History {
     size_t work_bytes = 0;
     rocfft_plan fwd = nullptr, inv = nullptr;
     rocfft_execution_info exec = nullptr;
+    // column path (n <= COL_NMAX, n = 2^a 3^b 5^c): fwd / inv are batched 1D
+    // row transforms, and k_columns does the column transforms and the
+    // multiplier; otherwise fwd / inv are 2D transforms and k_multiply runs
+    // between them
+    bool colpath = false;
+    int ncol = 0;                                 // columns l_x that can hold a nonzero multiplier
+    int npass = 0;
+    int8_t radix[COL_MAXPASS] = {};
+    void *tw = nullptr;                           // [n] e^{-2 pi i m / n}, plan precision
 };
 
 struct Local {
@@ -198,6 +209,7 @@ hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *m
                         const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
+hipError_t launch_columns(mhk_plan *P);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
 hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,

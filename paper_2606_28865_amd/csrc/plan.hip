@@ -154,7 +154,7 @@ static int64_t good_fft_size(int64_t nmin)
     int64_t m = (nmin + TILE - 1) / TILE;
     for (;; ++m) {
         int64_t r = m;
-        for (int f : {2, 3, 5, 7})
+        for (int f : {2, 3, 5})
             while (r % f == 0) r /= f;
         if (r == 1) return m * TILE;
     }
@@ -870,7 +870,6 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
 static double fft_cost(int64_t n)
 {
     double c = n <= 4096 ? 1.0 : 1.6;
-    if ((n / TILE) % 7 == 0) c *= 1.45;
     return c * (double)n * (double)n;
 }
 
@@ -1055,6 +1054,14 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     G.mult_c = pow(G.h, 4) / (G.period * G.period) * exp(-delta * alpha * alpha);
     TRY(upload(P, &G.fac, fac.data(), nh));
     if (G.trunc) TRY(build_trunc_table(P, qt, qw));
+    // columns l_x that can hold a nonzero multiplier
+    G.ncol = 0;
+    if (G.trunc) {
+        G.ncol = (int)std::min<int64_t>(nh, G.lmax + 1);
+    } else {
+        for (int64_t l = 0; l < nh; ++l)
+            if (fac[l] != 0.0) G.ncol = (int)l + 1;
+    }
 
     const int64_t nt2 = (int64_t)G.ntile * G.ntile;
     // per-tile lists of the sorted sources whose window [m0, m0 + w) (m0 =
@@ -1182,6 +1189,56 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         MHK_FFT(rocfft_setup());
         g_rocfft_ready = true;
     }
+    // column path: the column transforms in LDS need n <= COL_NMAX and
+    // radices 2, 3, 4, 5 (the grid sizes are 2^a 3^b 5^c)
+    {
+        int64_t r = G.n;
+        int np = 0;
+        bool ok = G.n <= COL_NMAX;
+        while (ok && r % 8 == 0 && np < COL_MAXPASS) { G.radix[np++] = 8; r /= 8; }
+        while (ok && r % 4 == 0 && np < COL_MAXPASS) { G.radix[np++] = 4; r /= 4; }
+        for (int f : {2, 3, 5})
+            while (ok && r % f == 0 && np < COL_MAXPASS) { G.radix[np++] = (int8_t)f; r /= f; }
+        G.colpath = ok && r == 1;
+        G.npass = G.colpath ? np : 0;
+    }
+    if (G.colpath) {
+        // batched 1D row transforms, in place on the padded rows
+        const size_t n1 = (size_t)G.n, nh1 = (size_t)(G.n / 2 + 1), one = 1;
+        const size_t rdist = n1 + 2, cdist = nh1;
+        rocfft_plan_description df = nullptr, di = nullptr;
+        MHK_FFT(rocfft_plan_description_create(&df));
+        MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real,
+                                                        rocfft_array_type_hermitian_interleaved, nullptr, nullptr, 1,
+                                                        &one, rdist, 1, &one, cdist));
+        MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward, fprec, 1, &n1,
+                                   4 * (size_t)P->p.batch * n1, df));
+        MHK_FFT(rocfft_plan_description_create(&di));
+        MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved,
+                                                        rocfft_array_type_real, nullptr, nullptr, 1, &one, cdist, 1,
+                                                        &one, rdist));
+        MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse, fprec, 1, &n1,
+                                   3 * (size_t)P->p.batch * n1, di));
+        rocfft_plan_description_destroy(df);
+        rocfft_plan_description_destroy(di);
+        // twiddles e^{-2 pi i m / n}
+        std::vector<double> tw(2 * n1);
+        for (size_t m = 0; m < n1; ++m) {
+            const long double a = -2.0L * M_PIl * (long double)m / (long double)n1;
+            tw[2 * m] = (double)cosl(a);
+            tw[2 * m + 1] = (double)sinl(a);
+        }
+        if (P->p.prec == MHK_FP64) {
+            double *d = nullptr;
+            TRY(upload(P, &d, tw.data(), (int64_t)tw.size()));
+            G.tw = d;
+        } else {
+            std::vector<float> tf(tw.begin(), tw.end());
+            float *d = nullptr;
+            TRY(upload(P, &d, tf.data(), (int64_t)tf.size()));
+            G.tw = d;
+        }
+    } else {
     size_t len[2] = {(size_t)G.n, (size_t)G.n};
     size_t rstr[2] = {1, (size_t)G.n + 2}, cstr[2] = {1, (size_t)(G.n / 2 + 1)};
     size_t rdist = (size_t)G.field, cdist = (size_t)(G.field / 2);
@@ -1198,6 +1255,7 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
                                fprec, 2, len, 3 * (size_t)P->p.batch, di));
     rocfft_plan_description_destroy(df);
     rocfft_plan_description_destroy(di);
+    }
     size_t w1 = 0, w2 = 0;
     MHK_FFT(rocfft_plan_get_work_buffer_size(G.fwd, &w1));
     MHK_FFT(rocfft_plan_get_work_buffer_size(G.inv, &w2));
@@ -1625,7 +1683,8 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
         void *buf[1] = {P->hist.grid};
         MHK_FFT(rocfft_execute(P->hist.fwd, buf, nullptr, P->hist.exec));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[2], st));
-        MHK_HIP(launch_multiply(P));
+        // column path: column transforms + multiplier; else the multiplier
+        MHK_HIP(P->hist.colpath ? launch_columns(P) : launch_multiply(P));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[3], st));
         MHK_FFT(rocfft_execute(P->hist.inv, buf, nullptr, P->hist.exec));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[4], st));
