@@ -100,6 +100,26 @@ def test_config0_alphas(cfg0, alpha):
     assert max(errs) < TOL
 
 
+def test_long_grid_2d_transforms(cfg0):
+    """A history grid longer than a column the column kernel holds in LDS
+    (n > 8192) takes rocFFT's 2D transforms with the separate multiplier
+    kernel: config 0 at alpha = 10 with delta = 2e-6 (k_max ~ 4000, n ~ 13000),
+    the history part alone against the oracle's (relative max-norm)."""
+    w = cfg0
+    print("case config0 alpha=10 delta=2e-6 (2D transforms)", flush=True)
+    plan = _plan(w, 10.0, delta=2e-6)
+    info = plan.info()
+    print(f"n {info['n_fine']}", flush=True)
+    assert info["n_fine"] > 8192
+    S, D, V = _run(plan, w, parts=O.PART_HISTORY)
+    So, Do, Vo = oracle_eval(w, 10.0, info["delta"], 3, parts=O.PART_HISTORY)
+    for g, o, name in ((S, So, "S"), (D, Do, "D"), (V, Vo, "V")):
+        err = rel_err(g.ravel(), o)
+        print(f"2D transforms {name}: err {err:.2e}", flush=True)
+        assert err < TOL, (name, err)
+    plan.close()
+
+
 def test_batch_matches_single(cfg0):
     """Three densities in one call equal three single calls (and the oracle)."""
     w = cfg0
