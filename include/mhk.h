@@ -23,9 +23,10 @@
  *    node order, with the batch index outermost: sigma[b][N_B].  Their type
  *    is double when params.prec == MHK_FP64 and float when MHK_FP32.
  *  - Eval calls are asynchronous on the stream given at plan creation; the
- *    outputs are valid once that stream has been synchronised.  A plan is
- *    not re-entrant; different plans may run concurrently on different
- *    streams.
+ *    outputs are valid once that stream has been synchronised (the plan's
+ *    internal second stream, which runs the level sums, is joined back into
+ *    it by an event within each eval).  A plan is not re-entrant; different
+ *    plans may run concurrently on different streams.
  *  - Every call returns an mhk_status; on error nothing is enqueued and
  *    mhk_last_error() (thread-local) describes the problem.
  *  - Boundary: n_panels panels of 16 Gauss-Legendre nodes each, panel
@@ -113,7 +114,7 @@ typedef struct {
     double level_radius[8];
     int64_t n_boundary, n_volume, n_targets, n_out;
     int64_t device_bytes; /* device memory owned by the plan                         */
-    /* milliseconds of the last eval per stage (0 unless timing was enabled)       */
+    /* milliseconds of the last timed eval per stage (see mhk_plan_set_timing)   */
     double ms_spread, ms_fft, ms_multiply, ms_interp, ms_levels, ms_local, ms_total;
     int history_truncated; /* 1: smoothly truncated history kernel, tabulated spectrum */
 } mhk_info;
@@ -170,7 +171,12 @@ mhk_status mhk_plan_capture(mhk_plan *plan, int parts, const void *sigma, const 
 mhk_status mhk_plan_launch_graph(mhk_plan *plan);
 
 /* Enable (1) or disable (0) per-stage timing with HIP events; when enabled,
- * each eval synchronises its stream at the end and fills the ms_* fields. */
+ * each eval records events on the plan's streams (without waiting), and
+ * mhk_plan_info waits for the last timed eval and fills the ms_* fields.
+ * The level sums run on a second stream of the plan beside the history
+ * part, so ms_levels overlaps ms_spread..ms_interp; ms_fft is the row
+ * transforms, ms_multiply the column transforms with the multiplier (or the
+ * 2D transforms' multiplier for grids longer than 8192). */
 mhk_status mhk_plan_set_timing(mhk_plan *plan, int enable);
 
 mhk_status mhk_plan_info(const mhk_plan *plan, mhk_info *info);

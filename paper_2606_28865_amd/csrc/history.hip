@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
 // multiplier pass become one read and one write of each column.  Columns
 // with l_x beyond the multiplier's support are only written with zeros.
 //
-// Transforms: self-sorting (Stockham) passes of radix 2, 3, 4, 5 or 8 on the
+// Transforms: self-sorting (Stockham) passes of radix 8, 9, 6, 4, 2, 3 or 5 on the
 // LDS copy; each pass reads every butterfly's inputs into registers, waits,
 // and writes the outputs in place.  Twiddles e^{-2 pi i m/n} come from a
 // table (conjugated for the inverse); both directions are unnormalised, like
@@ -270,6 +270,50 @@ template <int R, bool INV, typename T2> __device__ inline void dft(T2 *x)
         x[2] = csub(t0, t2);
         x[1] = cadd(t1, t3);
         x[3] = csub(t1, t3);
+    } else if constexpr (R == 6) {
+        // two DFTs of 3 on the even and odd points, combined with w6^k
+        T2 e[3] = {x[0], x[2], x[4]}, o[3] = {x[1], x[3], x[5]};
+        dft<3, INV>(e);
+        dft<3, INV>(o);
+        const T h = (T)0.86602540378443864676;
+        // w6 = e^{-+ i pi/3} = 1/2 -+ i sqrt(3)/2, w6^2 = -1/2 -+ i sqrt(3)/2
+        const T sg = INV ? (T)1 : (T)-1;
+        const T2 o1 = c2<T2>((T)0.5 * o[1].x - sg * h * o[1].y, (T)0.5 * o[1].y + sg * h * o[1].x);
+        const T2 o2 = c2<T2>((T)-0.5 * o[2].x - sg * h * o[2].y, (T)-0.5 * o[2].y + sg * h * o[2].x);
+        x[0] = cadd(e[0], o[0]);
+        x[3] = csub(e[0], o[0]);
+        x[1] = cadd(e[1], o1);
+        x[4] = csub(e[1], o1);
+        x[2] = cadd(e[2], o2);
+        x[5] = csub(e[2], o2);
+    } else if constexpr (R == 9) {
+        // three DFTs of 3 on the points t = 3u + r, twiddles w9^(r k), then
+        // DFTs of 3 across r
+        T2 a[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            a[r][0] = x[r];
+            a[r][1] = x[r + 3];
+            a[r][2] = x[r + 6];
+            dft<3, INV>(a[r]);
+        }
+        const T c1 = (T)0.76604444311897803520, s1 = (T)0.64278760968653932632;   // 2 pi / 9
+        const T c2v = (T)0.17364817766693034885, s2 = (T)0.98480775301220805936;  // 4 pi / 9
+        const T c4 = (T)-0.93969262078590838405, s4 = (T)0.34202014332566873304;  // 8 pi / 9
+        const T sg = INV ? (T)1 : (T)-1;
+        auto tw9 = [&](T2 z, T c, T sn) { return c2<T2>(c * z.x - sg * sn * z.y, c * z.y + sg * sn * z.x); };
+        a[1][1] = tw9(a[1][1], c1, s1);     // w9^1
+        a[1][2] = tw9(a[1][2], c2v, s2);    // w9^2
+        a[2][1] = tw9(a[2][1], c2v, s2);    // w9^2
+        a[2][2] = tw9(a[2][2], c4, s4);     // w9^4
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T2 b[3] = {a[0][k], a[1][k], a[2][k]};
+            dft<3, INV>(b);
+            x[k] = b[0];
+            x[k + 3] = b[1];
+            x[k + 6] = b[2];
+        }
     } else if constexpr (R == 8) {
         // two DFTs of 4 on the even and odd points, combined with w8^k
         T2 e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
@@ -360,6 +404,8 @@ __device__ inline void col_fft(T2 *buf, const T2 *tw, int N, const int8_t *radix
     for (int p = 0; p < npass; ++p) {
         const int r = radix[p];
         if (r == 8) col_pass<8, INV>(buf, tw, N, Ns);
+        else if (r == 9) col_pass<9, INV>(buf, tw, N, Ns);
+        else if (r == 6) col_pass<6, INV>(buf, tw, N, Ns);
         else if (r == 4) col_pass<4, INV>(buf, tw, N, Ns);
         else if (r == 2) col_pass<2, INV>(buf, tw, N, Ns);
         else if (r == 3) col_pass<3, INV>(buf, tw, N, Ns);

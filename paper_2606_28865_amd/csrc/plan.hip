@@ -1190,12 +1190,14 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         g_rocfft_ready = true;
     }
     // column path: the column transforms in LDS need n <= COL_NMAX and
-    // radices 2, 3, 4, 5 (the grid sizes are 2^a 3^b 5^c)
+    // radices 8, 9, 6, 4, 2, 3, 5 (the grid sizes are 2^a 3^b 5^c)
     {
         int64_t r = G.n;
         int np = 0;
         bool ok = G.n <= COL_NMAX;
         while (ok && r % 8 == 0 && np < COL_MAXPASS) { G.radix[np++] = 8; r /= 8; }
+        while (ok && r % 9 == 0 && np < COL_MAXPASS) { G.radix[np++] = 9; r /= 9; }
+        if (ok && r % 6 == 0 && np < COL_MAXPASS) { G.radix[np++] = 6; r /= 6; }
         while (ok && r % 4 == 0 && np < COL_MAXPASS) { G.radix[np++] = 4; r /= 4; }
         for (int f : {2, 3, 5})
             while (ok && r % f == 0 && np < COL_MAXPASS) { G.radix[np++] = (int8_t)f; r /= f; }
