@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
 
 // ---------------------------------------------------------------------------
 // Column transforms fused with the multiplier.  After the row transforms
-// (rocFFT, real-to-complex along x), every column l_x of the half spectrum is
+// (real-to-complex along x, below), every column l_x of the half spectrum is
 // an independent length-n sequence along y; the multiplier is applied between
 // the forward and the inverse column transforms, so one workgroup takes a
 // column from HBM into LDS, transforms it, multiplies, transforms back and
@@ -351,18 +351,19 @@ template <int R, bool INV, typename T2> __device__ inline void dft(T2 *x)
     }
 }
 
-// One radix-R pass of a length-N transform held in LDS; Ns = product of the
-// radices of the passes before it.
-template <int R, bool INV, typename T2>
-__device__ inline void col_pass(T2 *buf, const T2 *__restrict__ tw, int N, int Ns)
+// One radix-R pass of a length-N transform held in LDS by NT threads (N <=
+// NMAX); Ns = product of the radices of the passes before it.  The twiddle
+// table holds e^{-2 pi i m / (N ts)}, read at stride ts.
+template <int R, bool INV, int NT, int NMAX, typename T2>
+__device__ inline void fft_pass(T2 *buf, const T2 *__restrict__ tw, int ts, int N, int Ns)
 {
     typedef decltype(T2::x) T;
-    constexpr int MB = (COL_NMAX / R + CT - 1) / CT;
-    const int nb = N / R, step = N / (Ns * R);
+    constexpr int MB = (NMAX / R + NT - 1) / NT;
+    const int nb = N / R, step = N / (Ns * R) * ts;
     T2 v[MB][R];
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-        const int j = threadIdx.x + i * CT;
+        const int j = threadIdx.x + i * NT;
         if (j < nb) {
             // one twiddle load per butterfly, issued before the LDS reads;
             // w^t by repeated products
@@ -386,7 +387,7 @@ __device__ inline void col_pass(T2 *buf, const T2 *__restrict__ tw, int N, int N
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-        const int j = threadIdx.x + i * CT;
+        const int j = threadIdx.x + i * NT;
         if (j < nb) {
             dft<R, INV>(v[i]);
             const int k = j % Ns, o = (j - k) * R + k;
@@ -397,20 +398,77 @@ __device__ inline void col_pass(T2 *buf, const T2 *__restrict__ tw, int N, int N
     __syncthreads();
 }
 
-template <bool INV, typename T2>
-__device__ inline void col_fft(T2 *buf, const T2 *tw, int N, const int8_t *radix, int npass)
+template <bool INV, int NT, int NMAX, typename T2>
+__device__ inline void lds_fft(T2 *buf, const T2 *tw, int ts, int N, const int8_t *radix, int npass)
 {
     int Ns = 1;
     for (int p = 0; p < npass; ++p) {
         const int r = radix[p];
-        if (r == 8) col_pass<8, INV>(buf, tw, N, Ns);
-        else if (r == 9) col_pass<9, INV>(buf, tw, N, Ns);
-        else if (r == 6) col_pass<6, INV>(buf, tw, N, Ns);
-        else if (r == 4) col_pass<4, INV>(buf, tw, N, Ns);
-        else if (r == 2) col_pass<2, INV>(buf, tw, N, Ns);
-        else if (r == 3) col_pass<3, INV>(buf, tw, N, Ns);
-        else col_pass<5, INV>(buf, tw, N, Ns);
+        if (r == 8) fft_pass<8, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else if (r == 9) fft_pass<9, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else if (r == 6) fft_pass<6, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else if (r == 4) fft_pass<4, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else if (r == 2) fft_pass<2, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else if (r == 3) fft_pass<3, INV, NT, NMAX>(buf, tw, ts, N, Ns);
+        else fft_pass<5, INV, NT, NMAX>(buf, tw, ts, N, Ns);
         Ns *= r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row transforms (x direction), real to complex and back, one row per
+// workgroup, in place on the padded rows: the n reals of a row are n/2
+// complex points z_m = x_2m + i x_2m+1, transformed in LDS (length n/2,
+// twiddles of the length-n table at stride 2) and untangled:
+//   X_k = (Z_k + conj Z_{n/2-k})/2 - i e^{-2 pi i k/n} (Z_k - conj Z_{n/2-k})/2,
+// k = 0..n/2; the inverse forms Z_k = (X_k + conj X_{n/2-k}) + i e^{2 pi i k/n}
+// (X_k - conj X_{n/2-k}) and transforms back (unnormalised, as the column
+// transforms).
+// ---------------------------------------------------------------------------
+constexpr int RT = 256;            // threads per row workgroup
+
+template <typename T>
+struct RowArgs {
+    int64_t n;
+    int npass;
+    int8_t radix[COL_MAXPASS];     // of n/2
+    T *grid;                       // rows of n + 2 reals, consecutive
+    const typename Vec2<T>::type *tw;
+};
+
+template <bool INV, typename T>
+__global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
+{
+    typedef typename Vec2<T>::type T2;
+    extern __shared__ double lds_row[];
+    T2 *buf = reinterpret_cast<T2 *>(lds_row);
+    const int n = (int)A.n, h = n / 2;
+    T2 *c = reinterpret_cast<T2 *>(A.grid + (size_t)blockIdx.x * (size_t)(n + 2));   // h + 1 complex
+    const int tid = threadIdx.x;
+    if (!INV) {
+        for (int m = tid; m < h; m += RT) buf[m] = c[m];
+        __syncthreads();
+        lds_fft<false, RT, COL_NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
+        for (int k = tid; k <= h; k += RT) {
+            const T2 zk = buf[k == h ? 0 : k], zc = buf[k == 0 ? 0 : h - k];
+            const T2 w = A.tw[k];                                            // e^{-2 pi i k/n}
+            const T2 sp = c2<T2>(zk.x + zc.x, zk.y - zc.y);                  // Z_k + conj Z_{h-k}
+            const T2 dm = c2<T2>(zk.x - zc.x, zk.y + zc.y);                  // Z_k - conj Z_{h-k}
+            const T2 wd = cmul(w, dm);
+            c[k] = c2<T2>((T)0.5 * (sp.x + wd.y), (T)0.5 * (sp.y - wd.x));   // (sp - i w dm)/2
+        }
+    } else {
+        for (int k = tid; k < h; k += RT) {
+            const T2 a = c[k], bb = c[h - k];
+            const T2 sp = c2<T2>(a.x + bb.x, a.y - bb.y);                    // X_k + conj X_{h-k}
+            const T2 dm = c2<T2>(a.x - bb.x, a.y + bb.y);                    // X_k - conj X_{h-k}
+            const T2 w = A.tw[k];
+            const T2 wd = cmul(c2<T2>(w.x, -w.y), dm);                       // e^{+2 pi i k/n} dm
+            buf[k] = c2<T2>(sp.x - wd.y, sp.y + wd.x);                       // sp + i wd
+        }
+        __syncthreads();
+        lds_fft<true, RT, COL_NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
+        for (int m = tid; m < h; m += RT) c[m] = buf[m];
     }
 }
 
@@ -468,7 +526,7 @@ __global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_
         const T2 *in = base + (size_t)(grp == 2 ? 2 + part : grp) * fs;
         for (int y = threadIdx.x; y < n; y += CT) buf[y] = in[(size_t)y * nh];
         __syncthreads();
-        col_fft<false>(buf, A.tw, n, A.radix, A.npass);
+        lds_fft<false, CT, COL_NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         for (int ly = threadIdx.x; ly < n; ly += CT) {
             const double M = mult(ly);
             const T2 z = buf[ly];
@@ -482,7 +540,7 @@ __global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_
             }
         }
         __syncthreads();
-        col_fft<true>(buf, A.tw, n, A.radix, A.npass);
+        lds_fft<true, CT, COL_NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         // part 0 of D writes its column, part 1 adds to it (same thread, same
         // rows: no other thread touches these values)
         for (int y = threadIdx.x; y < n; y += CT) {
@@ -742,6 +800,30 @@ static hipError_t columns_t(mhk_plan *P)
     dim3 grid((unsigned)(((nh + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
     hipLaunchKernelGGL(k_columns<T>, grid, dim3(CT), lds, P->stream, A);
     return hipGetLastError();
+}
+
+template <bool INV, typename T>
+static hipError_t rows_t(mhk_plan *P)
+{
+    const History &G = P->hist;
+    RowArgs<T> A;
+    A.n = G.n;
+    A.npass = G.rnpass;
+    for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.rradix[i];
+    A.grid = (T *)G.grid;
+    A.tw = (const typename Vec2<T>::type *)G.tw;
+    const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)(G.n / 2);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_rows<INV, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * G.n;
+    hipLaunchKernelGGL((k_rows<INV, T>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows(mhk_plan *P, bool inverse)
+{
+    if (P->p.prec == MHK_FP64) return inverse ? rows_t<true, double>(P) : rows_t<false, double>(P);
+    return inverse ? rows_t<true, float>(P) : rows_t<false, float>(P);
 }
 
 hipError_t launch_columns(mhk_plan *P)

@@ -130,14 +130,16 @@ struct History {
     size_t work_bytes = 0;
     rocfft_plan fwd = nullptr, inv = nullptr;
     rocfft_execution_info exec = nullptr;
-    // column path (n <= COL_NMAX, n = 2^a 3^b 5^c): fwd / inv are batched 1D
-    // row transforms, and k_columns does the column transforms and the
-    // multiplier; otherwise fwd / inv are 2D transforms and k_multiply runs
-    // between them
+    // column path (n <= COL_NMAX, n = 2^a 3^b 5^c, even): k_rows does the
+    // row transforms and k_columns the column transforms with the
+    // multiplier; otherwise fwd / inv are rocFFT 2D transforms and k_multiply
+    // runs between them
     bool colpath = false;
     int ncol = 0;                                 // columns l_x that can hold a nonzero multiplier
     int npass = 0;
-    int8_t radix[COL_MAXPASS] = {};
+    int8_t radix[COL_MAXPASS] = {};               // passes of the column transforms (length n)
+    int rnpass = 0;
+    int8_t rradix[COL_MAXPASS] = {};              // passes of the row transforms (length n/2)
     void *tw = nullptr;                           // [n] e^{-2 pi i m / n}, plan precision
 };
 
@@ -210,6 +212,7 @@ hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *m
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_columns(mhk_plan *P);
+hipError_t launch_rows(mhk_plan *P, bool inverse);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
 hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,

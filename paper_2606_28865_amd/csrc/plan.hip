@@ -1191,38 +1191,20 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
     }
     // column path: the column transforms in LDS need n <= COL_NMAX and
     // radices 8, 9, 6, 4, 2, 3, 5 (the grid sizes are 2^a 3^b 5^c)
-    {
-        int64_t r = G.n;
-        int np = 0;
-        bool ok = G.n <= COL_NMAX;
-        while (ok && r % 8 == 0 && np < COL_MAXPASS) { G.radix[np++] = 8; r /= 8; }
-        while (ok && r % 9 == 0 && np < COL_MAXPASS) { G.radix[np++] = 9; r /= 9; }
-        if (ok && r % 6 == 0 && np < COL_MAXPASS) { G.radix[np++] = 6; r /= 6; }
-        while (ok && r % 4 == 0 && np < COL_MAXPASS) { G.radix[np++] = 4; r /= 4; }
+    auto factor = [](int64_t m, int8_t *radix, int &np) -> bool {
+        np = 0;
+        while (m % 8 == 0 && np < COL_MAXPASS) { radix[np++] = 8; m /= 8; }
+        while (m % 9 == 0 && np < COL_MAXPASS) { radix[np++] = 9; m /= 9; }
+        if (m % 6 == 0 && np < COL_MAXPASS) { radix[np++] = 6; m /= 6; }
+        while (m % 4 == 0 && np < COL_MAXPASS) { radix[np++] = 4; m /= 4; }
         for (int f : {2, 3, 5})
-            while (ok && r % f == 0 && np < COL_MAXPASS) { G.radix[np++] = (int8_t)f; r /= f; }
-        G.colpath = ok && r == 1;
-        G.npass = G.colpath ? np : 0;
-    }
+            while (m % f == 0 && np < COL_MAXPASS) { radix[np++] = (int8_t)f; m /= f; }
+        return m == 1;
+    };
+    G.colpath = G.n <= COL_NMAX && G.n % 2 == 0 && factor(G.n, G.radix, G.npass) &&
+                factor(G.n / 2, G.rradix, G.rnpass);
     if (G.colpath) {
-        // batched 1D row transforms, in place on the padded rows
-        const size_t n1 = (size_t)G.n, nh1 = (size_t)(G.n / 2 + 1), one = 1;
-        const size_t rdist = n1 + 2, cdist = nh1;
-        rocfft_plan_description df = nullptr, di = nullptr;
-        MHK_FFT(rocfft_plan_description_create(&df));
-        MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real,
-                                                        rocfft_array_type_hermitian_interleaved, nullptr, nullptr, 1,
-                                                        &one, rdist, 1, &one, cdist));
-        MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward, fprec, 1, &n1,
-                                   4 * (size_t)P->p.batch * n1, df));
-        MHK_FFT(rocfft_plan_description_create(&di));
-        MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved,
-                                                        rocfft_array_type_real, nullptr, nullptr, 1, &one, cdist, 1,
-                                                        &one, rdist));
-        MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse, fprec, 1, &n1,
-                                   3 * (size_t)P->p.batch * n1, di));
-        rocfft_plan_description_destroy(df);
-        rocfft_plan_description_destroy(di);
+        const size_t n1 = (size_t)G.n;
         // twiddles e^{-2 pi i m / n}
         std::vector<double> tw(2 * n1);
         for (size_t m = 0; m < n1; ++m) {
@@ -1241,35 +1223,36 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
             G.tw = d;
         }
     } else {
-    size_t len[2] = {(size_t)G.n, (size_t)G.n};
-    size_t rstr[2] = {1, (size_t)G.n + 2}, cstr[2] = {1, (size_t)(G.n / 2 + 1)};
-    size_t rdist = (size_t)G.field, cdist = (size_t)(G.field / 2);
-    rocfft_plan_description df = nullptr, di = nullptr;
-    MHK_FFT(rocfft_plan_description_create(&df));
-    MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
-                                                    nullptr, nullptr, 2, rstr, rdist, 2, cstr, cdist));
-    MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward,
-                               fprec, 2, len, 4 * (size_t)P->p.batch, df));
-    MHK_FFT(rocfft_plan_description_create(&di));
-    MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real,
-                                                    nullptr, nullptr, 2, cstr, cdist, 2, rstr, rdist));
-    MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse,
-                               fprec, 2, len, 3 * (size_t)P->p.batch, di));
-    rocfft_plan_description_destroy(df);
-    rocfft_plan_description_destroy(di);
+        // rocFFT 2D transforms around k_multiply
+        size_t len[2] = {(size_t)G.n, (size_t)G.n};
+        size_t rstr[2] = {1, (size_t)G.n + 2}, cstr[2] = {1, (size_t)(G.n / 2 + 1)};
+        size_t rdist = (size_t)G.field, cdist = (size_t)(G.field / 2);
+        rocfft_plan_description df = nullptr, di = nullptr;
+        MHK_FFT(rocfft_plan_description_create(&df));
+        MHK_FFT(rocfft_plan_description_set_data_layout(df, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
+                                                        nullptr, nullptr, 2, rstr, rdist, 2, cstr, cdist));
+        MHK_FFT(rocfft_plan_create(&G.fwd, rocfft_placement_inplace, rocfft_transform_type_real_forward,
+                                   fprec, 2, len, 4 * (size_t)P->p.batch, df));
+        MHK_FFT(rocfft_plan_description_create(&di));
+        MHK_FFT(rocfft_plan_description_set_data_layout(di, rocfft_array_type_hermitian_interleaved, rocfft_array_type_real,
+                                                        nullptr, nullptr, 2, cstr, cdist, 2, rstr, rdist));
+        MHK_FFT(rocfft_plan_create(&G.inv, rocfft_placement_inplace, rocfft_transform_type_real_inverse,
+                                   fprec, 2, len, 3 * (size_t)P->p.batch, di));
+        rocfft_plan_description_destroy(df);
+        rocfft_plan_description_destroy(di);
+        size_t w1 = 0, w2 = 0;
+        MHK_FFT(rocfft_plan_get_work_buffer_size(G.fwd, &w1));
+        MHK_FFT(rocfft_plan_get_work_buffer_size(G.inv, &w2));
+        G.work_bytes = std::max(w1, w2);
+        MHK_FFT(rocfft_execution_info_create(&G.exec));
+        if (G.work_bytes) {
+            char *wb = nullptr;
+            TRY(dalloc(P, &wb, (int64_t)G.work_bytes));
+            G.work = wb;
+            MHK_FFT(rocfft_execution_info_set_work_buffer(G.exec, G.work, G.work_bytes));
+        }
+        MHK_FFT(rocfft_execution_info_set_stream(G.exec, P->stream));
     }
-    size_t w1 = 0, w2 = 0;
-    MHK_FFT(rocfft_plan_get_work_buffer_size(G.fwd, &w1));
-    MHK_FFT(rocfft_plan_get_work_buffer_size(G.inv, &w2));
-    G.work_bytes = std::max(w1, w2);
-    MHK_FFT(rocfft_execution_info_create(&G.exec));
-    if (G.work_bytes) {
-        char *wb = nullptr;
-        TRY(dalloc(P, &wb, (int64_t)G.work_bytes));
-        G.work = wb;
-        MHK_FFT(rocfft_execution_info_set_work_buffer(G.exec, G.work, G.work_bytes));
-    }
-    MHK_FFT(rocfft_execution_info_set_stream(G.exec, P->stream));
     return MHK_OK;
 }
 
@@ -1683,12 +1666,20 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
         MHK_HIP(launch_spread(P, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_vol : nullptr));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[1], st));
         void *buf[1] = {P->hist.grid};
-        MHK_FFT(rocfft_execute(P->hist.fwd, buf, nullptr, P->hist.exec));
+        // column path: row transforms, column transforms with the
+        // multiplier, inverse row transforms; else rocFFT 2D transforms
+        // around the multiplier
+        if (P->hist.colpath)
+            MHK_HIP(launch_rows(P, false));
+        else
+            MHK_FFT(rocfft_execute(P->hist.fwd, buf, nullptr, P->hist.exec));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[2], st));
-        // column path: column transforms + multiplier; else the multiplier
         MHK_HIP(P->hist.colpath ? launch_columns(P) : launch_multiply(P));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[3], st));
-        MHK_FFT(rocfft_execute(P->hist.inv, buf, nullptr, P->hist.exec));
+        if (P->hist.colpath)
+            MHK_HIP(launch_rows(P, true));
+        else
+            MHK_FFT(rocfft_execute(P->hist.inv, buf, nullptr, P->hist.exec));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[4], st));
         MHK_HIP(launch_interp(P, ws, wd, wv));
     } else {
