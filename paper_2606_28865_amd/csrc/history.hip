@@ -436,7 +436,7 @@ struct RowArgs {
     const typename Vec2<T>::type *tw;
 };
 
-template <bool INV, typename T>
+template <bool INV, typename T, int NMAX>
 __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
 {
     typedef typename Vec2<T>::type T2;
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
     if (!INV) {
         for (int m = tid; m < h; m += RT) buf[m] = c[m];
         __syncthreads();
-        lds_fft<false, RT, COL_NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
+        lds_fft<false, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
         for (int k = tid; k <= h; k += RT) {
             const T2 zk = buf[k == h ? 0 : k], zc = buf[k == 0 ? 0 : h - k];
             const T2 w = A.tw[k];                                            // e^{-2 pi i k/n}
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
             buf[k] = c2<T2>(sp.x - wd.y, sp.y + wd.x);                       // sp + i wd
         }
         __syncthreads();
-        lds_fft<true, RT, COL_NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
+        lds_fft<true, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
         for (int m = tid; m < h; m += RT) c[m] = buf[m];
     }
 }
@@ -487,8 +487,8 @@ struct ColArgs {
 // One workgroup per (column, density, output): 0 S, 1 V, 2 D (from the D_x
 // and D_y spectra: -i (k_x Gx + k_y Gy) M, as two transforms whose results
 // are added).
-template <typename T>
-__global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_columns(ColArgs<T> A)
+template <typename T, int NMAX>
+__global__ void __launch_bounds__(CT) k_columns(ColArgs<T> A)
 {
     typedef typename Vec2<T>::type T2;
     extern __shared__ double lds_col[];
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_
         const T2 *in = base + (size_t)(grp == 2 ? 2 + part : grp) * fs;
         for (int y = threadIdx.x; y < n; y += CT) buf[y] = in[(size_t)y * nh];
         __syncthreads();
-        lds_fft<false, CT, COL_NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
+        lds_fft<false, CT, NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         for (int ly = threadIdx.x; ly < n; ly += CT) {
             const double M = mult(ly);
             const T2 z = buf[ly];
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(4))) k_
             }
         }
         __syncthreads();
-        lds_fft<true, CT, COL_NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
+        lds_fft<true, CT, NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         // part 0 of D writes its column, part 1 adds to it (same thread, same
         // rows: no other thread touches these values)
         for (int y = threadIdx.x; y < n; y += CT) {
@@ -795,10 +795,14 @@ static hipError_t columns_t(mhk_plan *P)
     A.lmax = G.lmax;
     const int64_t nh = G.n / 2 + 1;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)G.n;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_columns<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // register arrays sized for the longest column of the launch
+    const void *fn = G.n <= COL_NMAX / 2 ? (const void *)k_columns<T, COL_NMAX / 2> : (const void *)k_columns<T, COL_NMAX>;
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     dim3 grid((unsigned)(((nh + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
-    hipLaunchKernelGGL(k_columns<T>, grid, dim3(CT), lds, P->stream, A);
+    if (G.n <= COL_NMAX / 2)
+        hipLaunchKernelGGL((k_columns<T, COL_NMAX / 2>), grid, dim3(CT), lds, P->stream, A);
+    else
+        hipLaunchKernelGGL((k_columns<T, COL_NMAX>), grid, dim3(CT), lds, P->stream, A);
     return hipGetLastError();
 }
 
@@ -813,10 +817,11 @@ static hipError_t rows_t(mhk_plan *P)
     A.grid = (T *)G.grid;
     A.tw = (const typename Vec2<T>::type *)G.tw;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)(G.n / 2);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_rows<INV, T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * G.n;
-    hipLaunchKernelGGL((k_rows<INV, T>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
+    if (G.n <= COL_NMAX / 2)
+        hipLaunchKernelGGL((k_rows<INV, T, COL_NMAX / 2>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
+    else
+        hipLaunchKernelGGL((k_rows<INV, T, COL_NMAX>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
     return hipGetLastError();
 }
 
