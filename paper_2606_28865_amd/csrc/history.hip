@@ -355,7 +355,7 @@ template <int R, bool INV, typename T2> __device__ inline void dft(T2 *x)
 // NMAX); Ns = product of the radices of the passes before it.  The twiddle
 // table holds e^{-2 pi i m / (N ts)}, read at stride ts.
 template <int R, bool INV, int NT, int NMAX, typename T2>
-__device__ inline void fft_pass(T2 *buf, const T2 *__restrict__ tw, int ts, int N, int Ns)
+__device__ inline void fft_pass(T2 *buf, const double2 *__restrict__ tw, int ts, int N, int Ns)
 {
     typedef decltype(T2::x) T;
     constexpr int MB = (NMAX / R + NT - 1) / NT;
@@ -365,9 +365,10 @@ __device__ inline void fft_pass(T2 *buf, const T2 *__restrict__ tw, int ts, int 
     for (int i = 0; i < MB; ++i) {
         const int j = threadIdx.x + i * NT;
         if (j < nb) {
-            // one twiddle load per butterfly, issued before the LDS reads;
-            // w^t by repeated products
-            T2 w = c2<T2>((T)1, (T)0);
+            // one twiddle load per butterfly (issued before the LDS reads),
+            // w^t by repeated products in FP64 (R - 2 roundings of 1e-16),
+            // each rounded once to the transform's precision
+            double2 w = make_double2(1.0, 0.0);
             if (Ns > 1) {
                 w = tw[(j % Ns) * step];
                 if (INV) w.y = -w.y;
@@ -375,10 +376,10 @@ __device__ inline void fft_pass(T2 *buf, const T2 *__restrict__ tw, int ts, int 
 #pragma unroll
             for (int t = 0; t < R; ++t) v[i][t] = buf[j + t * nb];
             if (Ns > 1) {
-                T2 wt = w;
+                double2 wt = w;
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    v[i][t] = cmul(v[i][t], wt);
+                    v[i][t] = cmul(v[i][t], c2<T2>((T)wt.x, (T)wt.y));
                     if (t + 1 < R) wt = cmul(wt, w);
                 }
             }
@@ -399,7 +400,7 @@ __device__ inline void fft_pass(T2 *buf, const T2 *__restrict__ tw, int ts, int 
 }
 
 template <bool INV, int NT, int NMAX, typename T2>
-__device__ inline void lds_fft(T2 *buf, const T2 *tw, int ts, int N, const int8_t *radix, int npass)
+__device__ inline void lds_fft(T2 *buf, const double2 *tw, int ts, int N, const int8_t *radix, int npass)
 {
     int Ns = 1;
     for (int p = 0; p < npass; ++p) {
@@ -433,7 +434,7 @@ struct RowArgs {
     int npass;
     int8_t radix[COL_MAXPASS];     // of n/2
     T *grid;                       // rows of n + 2 reals, consecutive
-    const typename Vec2<T>::type *tw;
+    const double2 *tw;             // e^{-2 pi i m / n}, FP64 at both precisions
 };
 
 template <bool INV, typename T, int NMAX>
@@ -451,7 +452,8 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
         lds_fft<false, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
         for (int k = tid; k <= h; k += RT) {
             const T2 zk = buf[k == h ? 0 : k], zc = buf[k == 0 ? 0 : h - k];
-            const T2 w = A.tw[k];                                            // e^{-2 pi i k/n}
+            const double2 wd64 = A.tw[k];                                    // e^{-2 pi i k/n}
+            const T2 w = c2<T2>((T)wd64.x, (T)wd64.y);
             const T2 sp = c2<T2>(zk.x + zc.x, zk.y - zc.y);                  // Z_k + conj Z_{h-k}
             const T2 dm = c2<T2>(zk.x - zc.x, zk.y + zc.y);                  // Z_k - conj Z_{h-k}
             const T2 wd = cmul(w, dm);
@@ -462,8 +464,8 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
             const T2 a = c[k], bb = c[h - k];
             const T2 sp = c2<T2>(a.x + bb.x, a.y - bb.y);                    // X_k + conj X_{h-k}
             const T2 dm = c2<T2>(a.x - bb.x, a.y + bb.y);                    // X_k - conj X_{h-k}
-            const T2 w = A.tw[k];
-            const T2 wd = cmul(c2<T2>(w.x, -w.y), dm);                       // e^{+2 pi i k/n} dm
+            const double2 wd64 = A.tw[k];
+            const T2 wd = cmul(c2<T2>((T)wd64.x, (T)-wd64.y), dm);           // e^{+2 pi i k/n} dm
             buf[k] = c2<T2>(sp.x - wd.y, sp.y + wd.x);                       // sp + i wd
         }
         __syncthreads();
@@ -478,7 +480,7 @@ struct ColArgs {
     int B, ncol, npass;
     int8_t radix[COL_MAXPASS];
     T *grid;
-    const typename Vec2<T>::type *tw;
+    const double2 *tw;             // e^{-2 pi i m / n}, FP64 at both precisions
     const double *fac, *mtab;
     double c, alpha2, dk;
     int lmax;
@@ -786,7 +788,7 @@ static hipError_t columns_t(mhk_plan *P)
     A.npass = G.npass;
     for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.radix[i];
     A.grid = (T *)G.grid;
-    A.tw = (const typename Vec2<T>::type *)G.tw;
+    A.tw = (const double2 *)G.tw;
     A.fac = G.fac;
     A.mtab = G.trunc ? G.mtab : nullptr;
     A.c = G.mult_c;
@@ -815,7 +817,7 @@ static hipError_t rows_t(mhk_plan *P)
     A.npass = G.rnpass;
     for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.rradix[i];
     A.grid = (T *)G.grid;
-    A.tw = (const typename Vec2<T>::type *)G.tw;
+    A.tw = (const double2 *)G.tw;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)(G.n / 2);
     const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * G.n;
     if (G.n <= COL_NMAX / 2)

@@ -140,7 +140,7 @@ struct History {
     int8_t radix[COL_MAXPASS] = {};               // passes of the column transforms (length n)
     int rnpass = 0;
     int8_t rradix[COL_MAXPASS] = {};              // passes of the row transforms (length n/2)
-    void *tw = nullptr;                           // [n] e^{-2 pi i m / n}, plan precision
+    void *tw = nullptr;                           // [n] e^{-2 pi i m / n}, FP64
 };
 
 struct Local {

@@ -1212,16 +1212,9 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
             tw[2 * m] = (double)cosl(a);
             tw[2 * m + 1] = (double)sinl(a);
         }
-        if (P->p.prec == MHK_FP64) {
-            double *d = nullptr;
-            TRY(upload(P, &d, tw.data(), (int64_t)tw.size()));
-            G.tw = d;
-        } else {
-            std::vector<float> tf(tw.begin(), tw.end());
-            float *d = nullptr;
-            TRY(upload(P, &d, tf.data(), (int64_t)tf.size()));
-            G.tw = d;
-        }
+        double *d = nullptr;
+        TRY(upload(P, &d, tw.data(), (int64_t)tw.size()));
+        G.tw = d;
     } else {
         // rocFFT 2D transforms around k_multiply
         size_t len[2] = {(size_t)G.n, (size_t)G.n};
