@@ -44,6 +44,9 @@ def parse():
                          "captured HIP graph; serve: Poisson stream of Rothe-step requests; bie: Dirichlet "
                          "solve (Nystrom matrix, GMRES) on the 10-body geometry; heat: implicit-Euler "
                          "heat steps with the volume nodes as targets")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="evaluate the three alpha plans one after another on one stream (default: each plan "
+                         "on its own stream, the three evaluations of a step concurrent)")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--requests", type=int, default=120)
     return ap.parse_args()
@@ -93,20 +96,39 @@ def main():
     torch.cuda.set_device(dev)
     t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
     sigma, mu, fv, ft = t(w.sigma), t(w.mu), t(w.f_vol), t(w.f_trg)
+    # The three alpha problems of a step are independent: by default each plan
+    # has its own stream (default priority), the step forks them from the
+    # caller's stream and joins them back, so one plan's tail overlaps the
+    # next plan's start.
+    cur = torch.cuda.current_stream()
+    streams = [cur] * len(alphas) if a.one_stream else [torch.cuda.Stream() for _ in alphas]
     plans, plan_s = [], []
-    for al in alphas:
+    for al, s in zip(alphas, streams):
         t1 = time.time()
         prm = M.make_params(alpha=al, tol=a.tol, dx=w.dx)
-        p = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+        p = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=s)
         torch.cuda.synchronize()
         plan_s.append(time.time() - t1)
         plans.append(p)
         log(f"plan alpha={al}: {plan_s[-1]:.1f} s, grid {p.info()['n_fine']}, {p.info()['device_bytes'] / 1e9:.2f} GB")
     n_out = plans[0].n_out
-    outs = [p.eval(sigma, mu, fv, ft) for p in plans]
-    for _ in range(a.warmup):
-        for p, o in zip(plans, outs):
+    outs = []
+    for p, s in zip(plans, streams):
+        with torch.cuda.stream(s):
+            outs.append(p.eval(sigma, mu, fv, ft))
+    torch.cuda.synchronize()
+
+    def step():
+        for p, o, s in zip(plans, outs, streams):
+            if s is not cur:
+                s.wait_stream(cur)
             p.eval(sigma, mu, fv, ft, out=o)
+        for s in streams:
+            if s is not cur:
+                cur.wait_stream(s)
+
+    for _ in range(a.warmup):
+        step()
     torch.cuda.synchronize()
     log("warmup done")
     # stage events are recorded by the library on its streams during the timed
@@ -119,8 +141,7 @@ def main():
     ev0.record()
     wall0 = time.perf_counter()
     for _ in range(a.steps):
-        for p, o in zip(plans, outs):
-            p.eval(sigma, mu, fv, ft, out=o)
+        step()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -157,7 +178,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "multibody-10-starfish", "n_boundary": w.n_b, "n_volume": w.n_v,
                    "n_targets": w.n_t, "n_out": n_out, "alphas": alphas, "tol": a.tol,
-                   "batch": 1, "parallelism": "none"},
+                   "batch": 1, "parallelism": "none", "streams": 1 if a.one_stream else len(alphas)},
         "stage_ms": {k: [round(x, 4) for x in v] for k, v in stage.items()},
         "grid": [int(i["n_fine"]) for i in infos],
         "delta": [i["delta"] for i in infos],

@@ -218,7 +218,9 @@ __global__ void __launch_bounds__(256) k_multiply(int64_t n, int B, int64_t fiel
 // column from HBM into LDS, transforms it, multiplies, transforms back and
 // writes it: the 2D transforms' two column passes, their transposes and the
 // multiplier pass become one read and one write of each column.  Columns
-// with l_x beyond the multiplier's support are only written with zeros.
+// with l_x beyond the multiplier's support are neither written by the
+// forward row transforms nor touched here; the inverse row transforms take
+// them as zero.
 //
 // Transforms: self-sorting (Stockham) passes of radix 8, 9, 6, 4, 2, 3 or 5 on the
 // LDS copy; each pass reads every butterfly's inputs into registers, waits,
@@ -431,6 +433,7 @@ constexpr int RT = 256;            // threads per row workgroup
 template <typename T>
 struct RowArgs {
     int64_t n;
+    int ncol;                      // half-spectrum entries k < ncol can be nonzero after the multiplier
     int npass;
     int8_t radix[COL_MAXPASS];     // of n/2
     T *grid;                       // rows of n + 2 reals, consecutive
@@ -450,7 +453,8 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
         for (int m = tid; m < h; m += RT) buf[m] = c[m];
         __syncthreads();
         lds_fft<false, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
-        for (int k = tid; k <= h; k += RT) {
+        // only the columns that the multiplier keeps are read again
+        for (int k = tid; k < A.ncol; k += RT) {
             const T2 zk = buf[k == h ? 0 : k], zc = buf[k == 0 ? 0 : h - k];
             const double2 wd64 = A.tw[k];                                    // e^{-2 pi i k/n}
             const T2 w = c2<T2>((T)wd64.x, (T)wd64.y);
@@ -460,8 +464,10 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
             c[k] = c2<T2>((T)0.5 * (sp.x + wd.y), (T)0.5 * (sp.y - wd.x));   // (sp - i w dm)/2
         }
     } else {
+        // entries k >= ncol are zero (the column transforms leave them unwritten)
+        const T2 zero = c2<T2>((T)0, (T)0);
         for (int k = tid; k < h; k += RT) {
-            const T2 a = c[k], bb = c[h - k];
+            const T2 a = k < A.ncol ? c[k] : zero, bb = h - k < A.ncol ? c[h - k] : zero;
             const T2 sp = c2<T2>(a.x + bb.x, a.y - bb.y);                    // X_k + conj X_{h-k}
             const T2 dm = c2<T2>(a.x - bb.x, a.y + bb.y);                    // X_k - conj X_{h-k}
             const double2 wd64 = A.tw[k];
@@ -497,19 +503,16 @@ __global__ void __launch_bounds__(CT) k_columns(ColArgs<T> A)
     T2 *buf = reinterpret_cast<T2 *>(lds_col);
     const int n = (int)A.n, nh = n / 2 + 1;
     // consecutive columns on one XCD (workgroups are dealt to the 8 XCDs in
-    // turn), so that neighbouring columns share the XCD's L2 lines
-    const int per = (nh + 7) / 8;
+    // turn), so that neighbouring columns share the XCD's L2 lines; only the
+    // columns l_x < ncol that the multiplier keeps (the inverse row
+    // transforms take the others as zero)
+    const int per = (A.ncol + 7) / 8;
     const int lx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (lx >= nh) return;
+    if (lx >= A.ncol) return;
     const int b = blockIdx.y, grp = blockIdx.z;
     const size_t fs = (size_t)A.B * (A.field / 2);              // complex values per slot
     T2 *base = reinterpret_cast<T2 *>(A.grid) + (size_t)b * (A.field / 2) + lx;
     T2 *out = base + (size_t)grp * fs;
-    const T2 zero = c2<T2>((T)0, (T)0);
-    if (lx >= A.ncol) {
-        for (int y = threadIdx.x; y < n; y += CT) out[(size_t)y * nh] = zero;
-        return;
-    }
     const double ax = A.fac[lx];
     const double kx = A.dk * lx;
     auto mult = [&](int ly) -> double {
@@ -795,12 +798,12 @@ static hipError_t columns_t(mhk_plan *P)
     A.alpha2 = P->p.alpha * P->p.alpha;
     A.dk = 2.0 * M_PI / G.period;
     A.lmax = G.lmax;
-    const int64_t nh = G.n / 2 + 1;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)G.n;
     // register arrays sized for the longest column of the launch
     const void *fn = G.n <= COL_NMAX / 2 ? (const void *)k_columns<T, COL_NMAX / 2> : (const void *)k_columns<T, COL_NMAX>;
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    dim3 grid((unsigned)(((nh + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
+    if (G.ncol == 0) return hipSuccess;     // the multiplier is zero everywhere
+    dim3 grid((unsigned)(((G.ncol + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
     if (G.n <= COL_NMAX / 2)
         hipLaunchKernelGGL((k_columns<T, COL_NMAX / 2>), grid, dim3(CT), lds, P->stream, A);
     else
@@ -814,6 +817,7 @@ static hipError_t rows_t(mhk_plan *P)
     const History &G = P->hist;
     RowArgs<T> A;
     A.n = G.n;
+    A.ncol = G.ncol;
     A.npass = G.rnpass;
     for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.rradix[i];
     A.grid = (T *)G.grid;
