@@ -102,6 +102,10 @@ __device__ inline float bcast(float v, int k)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
+// x - floor(x) for x >= 0 (exact), one instruction
+__device__ inline double frac_part(double x) { return __builtin_amdgcn_fract(x); }
+__device__ inline float frac_part(float x) { return __builtin_amdgcn_fractf(x); }
+
 template <int BCH, typename T, int NC, int STRIDE>
 __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
@@ -142,28 +146,31 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
         qy[b] = A.q + ((size_t)2 * A.B + bb) * A.n_src;
     }
 
-    // one source against the lane's targets
-    auto pair = [&](double sxv, double syv, const T *qsv, const T *qxv, const T *qyv) {
+    // source k of the lanes' batch against the lane's targets; the source's
+    // strengths are handed over only where some lane is in range
+    auto pair = [&](int k, double sxv, double syv, const T *lqs, const T *lqx, const T *lqy) {
 #pragma unroll
         for (int i = 0; i < LV_TPL; ++i) {
             const T dx = (T)(x[i] - sxv), dy = (T)(y[i] - syv);
             const T f = (dx * dx + dy * dy) * fscale;
             if (f < f_max) {
                 const int sg = (int)f;
-                const T v = (T)2 * (f - (T)sg) - (T)1;
-                const T *c = s_tab + sg * STRIDE;
+                const T v = (T)2 * frac_part(f) - (T)1;
+                const T *c = s_tab + __umul24((unsigned)sg, (unsigned)STRIDE);
                 // p(v) and p'(v) by Horner's rule (K_j^S and, up to the
-                // factor d_scale, K_j^D)
-                T ks = c[NC - 1], kd = (T)0;
+                // factor d_scale, K_j^D); the derivative's first step is c_7
+                T kd = c[NC - 1];
+                T ks = fma(kd, v, c[NC - 2]);
 #pragma unroll
-                for (int k = NC - 2; k >= 0; --k) {
+                for (int m = NC - 3; m >= 0; --m) {
                     kd = fma(kd, v, ks);
-                    ks = fma(ks, v, c[k]);
+                    ks = fma(ks, v, c[m]);
                 }
 #pragma unroll
                 for (int b = 0; b < BCH; ++b) {
-                    S[i][b] = fma(qsv[b], ks, S[i][b]);
-                    D[i][b] = fma(fma(qxv[b], dx, qyv[b] * dy), kd, D[i][b]);
+                    const T qsv = bcast(lqs[b], k), qxv = bcast(lqx[b], k), qyv = bcast(lqy[b], k);
+                    S[i][b] = fma(qsv, ks, S[i][b]);
+                    D[i][b] = fma(fma(qxv, dx, qyv * dy), kd, D[i][b]);
                 }
             }
         }
@@ -195,16 +202,7 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                     lqy[b] = A.want_d ? qy[b][sl] : (T)0;
                 }
                 const int cnt = min(LV_WAVE, s1 - base);
-                for (int k = 0; k < cnt; ++k) {
-                    T cqs[BCH], cqx[BCH], cqy[BCH];
-#pragma unroll
-                    for (int b = 0; b < BCH; ++b) {
-                        cqs[b] = bcast(lqs[b], k);
-                        cqx[b] = bcast(lqx[b], k);
-                        cqy[b] = bcast(lqy[b], k);
-                    }
-                    pair(bcast(lx, k), bcast(ly, k), cqs, cqx, cqy);
-                }
+                for (int k = 0; k < cnt; ++k) pair(k, bcast(lx, k), bcast(ly, k), lqs, lqx, lqy);
             }
         }
     }
