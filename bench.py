@@ -240,7 +240,7 @@ LEVEL_FLOPS_PER_PAIR = 45.0
 # plans), FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by the counter's
 # reading for a 256 MiB device copy (profiles/multibody_fp64_hbm_counters.md).
 # None while the kernel has changed since the counters were taken.
-LEVEL_SUMS_HBM_BYTES = None
+LEVEL_SUMS_HBM_BYTES = 72.7e6
 
 
 def child_nodes(w, j):
