@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                     lqx[b] = A.want_d ? qx[b][sl] : (T)0;
                     lqy[b] = A.want_d ? qy[b][sl] : (T)0;
                 }
-                const int cnt = min(LV_WAVE, s1 - base);
+                const int cnt = __builtin_amdgcn_readfirstlane(min(LV_WAVE, s1 - base));   // wave-uniform: scalar loop test
                 for (int k = 0; k < cnt; ++k) pair(k, bcast(lx, k), bcast(ly, k), lqs, lqx, lqy);
             }
         }
