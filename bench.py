@@ -389,7 +389,8 @@ def run_precision(a):
 def run_batched(a):
     """64 densities per call on one 65536-node multi-body geometry (~1M volume
     nodes, 1M targets + boundary nodes), evaluated by replaying a captured HIP
-    graph; grid parameters from the autotuner; alpha in {3, 30}, FP32 and FP64."""
+    graph; grid parameters from the autotuner, timed at the same batch size;
+    alpha in {3, 30}, FP32 and FP64."""
     import torch
 
     import paper_2606_28865_amd as M
@@ -417,7 +418,7 @@ def run_batched(a):
     res = {}
     for alpha in (3.0, 30.0):
         for prec, dt, name, tol in ((M.MHK_FP32, torch.float32, "fp32", 1e-6), (M.MHK_FP64, torch.float64, "fp64", 1e-10)):
-            tun = autotune.tune(geometry, alpha, tol, prec, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx, batch=1,
+            tun = autotune.tune(geometry, alpha, tol, prec, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx, batch=B,
                                 cache=None, log=log)
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
