@@ -186,7 +186,10 @@ static void counting_sort(const std::vector<int64_t> &key, int64_t nkeys,
 // ---------------------------------------------------------------------------
 // Parameter rules
 // ---------------------------------------------------------------------------
-static double hist_eps(const mhk_params &p) { return p.prec == MHK_FP64 ? p.tol : 0.1 * p.tol; }
+// Truncation target of the history part (multiplier cut-off and window
+// width): the requested tolerance at both precisions; the FP32 rounding of
+// the spreading, transforms and interpolation stays well below it.
+static double hist_eps(const mhk_params &p) { return p.tol; }
 
 static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
 {
