@@ -62,6 +62,19 @@ def test_bands_and_levels():
     assert M.resolve_params(alpha=300.0, tol=1e-6, delta=1e-3)["kmax"] == 0.0
 
 
+def test_history_rule_shared_by_precisions():
+    """The history cut-off and window width follow the requested tolerance
+    at both precisions, so FP32 and FP64 plans of one problem share them."""
+    for alpha, tol in ((30.0, 1e-6), (3.0, 1e-6), (10.0, 1e-7)):
+        a = M.resolve_params(alpha=alpha, tol=tol, prec=M.MHK_FP64, delta=1e-4)
+        b = M.resolve_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, delta=1e-4)
+        assert a["kmax"] == b["kmax"] and a["wspread"] == b["wspread"]
+    # a tighter tolerance widens the window
+    w6 = M.resolve_params(alpha=10.0, tol=1e-6, prec=M.MHK_FP32, delta=1e-4)["wspread"]
+    w10 = M.resolve_params(alpha=10.0, tol=1e-10, prec=M.MHK_FP64, delta=1e-4)["wspread"]
+    assert w10 > w6
+
+
 @pytest.mark.parametrize("kw", [dict(alpha=-1.0, tol=1e-6, delta=1e-3), dict(alpha=1.0, tol=1e-1, delta=1e-3),
                                 dict(alpha=1.0, tol=1e-6), dict(alpha=1.0, tol=1e-6, delta=1e-3, J=9),
                                 dict(alpha=1.0, tol=1e-6, delta=1e-3, batch=0),
