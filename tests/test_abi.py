@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
 every function declared in include/mhk.h, applies the parameter rule of
-Section 6.4 and rejects invalid arguments."""
+Section 6.4 and rejects invalid arguments; without the library the
+binding raises."""
 import math
 import os
 import re
@@ -127,3 +128,21 @@ def test_nystrom_argument_validation():
     assert L.mhk_solve_dirichlet(None, None, None, None, None, 1e-10, 30, 100, None, None, C.byref(info)) == -1
     assert L.mhk_solve_neumann(None, None, None, None, None, 1e-10, 30, 100, None, None, C.byref(info)) == -1
     L.mhk_nystrom_destroy(None)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the binding raises on first use: there is
+    no other path to the results."""
+    import subprocess
+    import sys
+    code = ("import paper_2606_28865_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/libmhk.so'\n"
+            "try:\n"
+            "    L.resolve_params(alpha=10.0, tol=1e-6, delta=1e-3)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('no error')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
