@@ -75,8 +75,8 @@ def main():
         copy_probe()
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); the per-GPU "
-              "throughput at N=1 is the figure this workload reports.", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (got --gpus {a.gpus}); the reported "
+              "figure is one GPU's throughput, at N=1.", file=sys.stderr)
         sys.exit(2)
     if a.workload != "multibody":
         {"precision": run_precision, "batched": run_batched, "serve": run_serve, "bie": run_bie,
