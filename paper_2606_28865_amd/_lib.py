@@ -242,18 +242,44 @@ class Plan:
             raise ValueError(f"expected {self.batch} x {n} values, got {t.numel()}")
         return t
 
+    def _outs(self, out, ins):
+        """Output tensors: allocated when out is None, else checked like the
+        inputs (a short or mistyped output would be written past its end)."""
+        import torch
+        shape = (self.batch, self.n_out)
+        if out is None:
+            return tuple(torch.empty(shape, dtype=self.dtype, device="cuda") if x is not None else None
+                         for x in ins)
+        if len(out) != 3:
+            raise ValueError("out must be a (S, D, V) tuple")
+        for x, o, name in zip(ins, out, ("S", "D", "V")):
+            if x is None:
+                continue
+            if o is None:
+                raise ValueError(f"out[{name}] is missing for a given input")
+            self._dev(o, self.n_out)
+        return tuple(out)
+
+    def _streams(self):
+        """(caller's current stream, whether it differs from the plan's)."""
+        import torch
+        cur = torch.cuda.current_stream()
+        return cur, cur.cuda_stream != self.stream.cuda_stream
+
     def capture(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None):
         """Record one evaluation bound to these tensors into a HIP graph;
-        returns the output tensors the graph writes.  replay() runs it."""
-        import torch
+        returns the output tensors the graph writes.  replay() runs it on the
+        plan's stream; the caller keeps the bound tensors alive."""
         sigma = self._dev(sigma, self.nb)
         mu = self._dev(mu, self.nb)
         f_vol = self._dev(f_vol, self.nv)
         f_trg = self._dev(f_trg, self.n_out)
-        shape = (self.batch, self.n_out)
-        if out is None:
-            out = tuple(torch.empty(shape, dtype=self.dtype, device="cuda") if x is not None else None
-                        for x in (sigma, mu, f_vol))
+        out = self._outs(out, (sigma, mu, f_vol))
+        cur, other = self._streams()
+        if other:
+            # the capture synchronises the plan's stream; the inputs may still
+            # be written on the caller's stream
+            cur.synchronize()
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
         _check(lib().mhk_plan_capture(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
                                       ptr(out[0]), ptr(out[1]), ptr(out[2])))
@@ -263,21 +289,32 @@ class Plan:
     def replay(self):
         _check(lib().mhk_plan_launch_graph(self._h))
 
-    def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None):
-        """Returns (S, D, V) device tensors [batch, n_out] (None where not requested)."""
-        import torch
+    def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None, join=True):
+        """Returns (S, D, V) device tensors [batch, n_out] (None where not requested).
+
+        The work runs on the plan's stream.  When the caller's current stream
+        is another one, the plan's stream first waits for it (the inputs may
+        still be written there), the tensors are marked as used on the plan's
+        stream, and with join=True the caller's stream then waits for the
+        evaluation, so that the outputs can be used on it directly; join=False
+        leaves that wait to the caller (several plans overlapping)."""
         sigma = self._dev(sigma, self.nb)
         mu = self._dev(mu, self.nb)
         f_vol = self._dev(f_vol, self.nv)
         f_trg = self._dev(f_trg, self.n_out)
-        shape = (self.batch, self.n_out)
-        dev = torch.device("cuda")
-        if out is None:
-            out = tuple(torch.empty(shape, dtype=self.dtype, device=dev) if x is not None else None
-                        for x in (sigma, mu, f_vol))
+        out = self._outs(out, (sigma, mu, f_vol))
+        cur, other = self._streams()
+        if other:
+            self.stream.wait_stream(cur)
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
         _check(lib().mhk_eval_parts(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
                                     ptr(out[0]), ptr(out[1]), ptr(out[2])))
+        if other:
+            for t in (sigma, mu, f_vol, f_trg) + tuple(out):
+                if t is not None:
+                    t.record_stream(self.stream)
+            if join:
+                cur.wait_stream(self.stream)
         return out
 
 

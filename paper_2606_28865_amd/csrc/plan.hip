@@ -263,8 +263,9 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         I->level_radius[j - 1] = sqrt(4.0 * dj * amax);
     }
     // Fourier cut-off of the history part (eqs. (kmax), (kmax_dlp)) at eps =
-    // tol in FP64 (the truncation error is far below tol relative to the
-    // potentials) and tol/10 in FP32 (where rounding already costs ~tol/10)
+    // tol at both precisions (hist_eps): the truncation error is far below
+    // tol relative to the potentials, and the FP32 rounding of the history
+    // stages stays below it as well
     double eps = hist_eps(p), L = log(1.0 / eps), da2 = p.delta * p.alpha * p.alpha;
     if (da2 >= L) {
         I->kmax = 0;

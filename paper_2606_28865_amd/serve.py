@@ -178,59 +178,92 @@ class Server:
         return self.used + need <= self.budget
 
     # -- one scheduling pass ----------------------------------------------
+    def _fail(self, req: Request, err: Exception):
+        req.error = f"{type(err).__name__}: {err}"
+        req.done = self.clock()
+        self.rejected.append(req)
+
     def step(self) -> int:
         """Retire finished requests, admit what fits; returns the number of
-        requests admitted in this pass."""
-        now = self.clock()
+        requests admitted in this pass.  A request whose footprint, plan
+        creation or launch raises is rejected with its error; the plan's
+        state and the memory accounting are rolled back and the other
+        requests stay queued."""
         still = []
         for req, h, acct in self.inflight:
-            if self.dev.done(h):
-                req.result = self.dev.result(h)
-                req.done = self.clock()
-                self.plans[req.plan_key]["busy"] = False
+            try:
+                fin = self.dev.done(h)
+                if fin:
+                    req.result = self.dev.result(h)
+            except Exception as e:          # a failed device call: the request ends with its error
+                fin = True
+                self._fail(req, e)
+            if fin:
+                ent = self.plans.get(req.plan_key)
+                if ent is not None:
+                    ent["busy"] = False
                 self.used -= acct[0]
-                self.finished.append(req)
+                if req.error is None:
+                    req.done = self.clock()
+                    self.finished.append(req)
             else:
                 still.append((req, h, acct))
         self.inflight = still
         admitted = 0
         blocked_keys = set()
         waiting = collections.deque()
-        while self.queue:
-            req = self.queue.popleft()
-            key = req.plan_key
-            if len(self.inflight) >= self.max_inflight or key in blocked_keys:
-                waiting.append(req)
-                continue
-            ent = self.plans.get(key)
-            if ent is not None and ent["busy"]:
-                blocked_keys.add(key)
-                waiting.append(req)
-                continue
-            io = self.dev.io_bytes(req)
-            need = io + (0 if ent is not None else self.dev.footprint(req))
-            if need > self.budget:
-                req.error = f"request needs {need} bytes, budget is {self.budget}"
-                req.done = now
-                self.rejected.append(req)
-                continue
-            if not self._evict_for(need, key):
-                blocked_keys.add(key)
-                waiting.append(req)
-                continue
-            if ent is None:
-                plan, pbytes = self.dev.create_plan(req)
-                ent = {"plan": plan, "bytes": pbytes, "busy": False}
-                self.plans[key] = ent
-                self.used += pbytes
-            self.plans.move_to_end(key)
-            ent["busy"] = True
-            self.used += io
-            req.admitted = self.clock()
-            h = self.dev.launch(ent["plan"], req)
-            self.inflight.append((req, h, (io,)))
-            admitted += 1
-        self.queue = waiting
+        try:
+            while self.queue:
+                req = self.queue.popleft()
+                key = req.plan_key
+                if len(self.inflight) >= self.max_inflight or key in blocked_keys:
+                    waiting.append(req)
+                    continue
+                ent = self.plans.get(key)
+                if ent is not None and ent["busy"]:
+                    blocked_keys.add(key)
+                    waiting.append(req)
+                    continue
+                try:
+                    io = self.dev.io_bytes(req)
+                    need = io + (0 if ent is not None else self.dev.footprint(req))
+                except Exception as e:
+                    self._fail(req, e)
+                    continue
+                if need > self.budget:
+                    req.error = f"request needs {need} bytes, budget is {self.budget}"
+                    req.done = self.clock()
+                    self.rejected.append(req)
+                    continue
+                if not self._evict_for(need, key):
+                    blocked_keys.add(key)
+                    waiting.append(req)
+                    continue
+                if ent is None:
+                    try:
+                        plan, pbytes = self.dev.create_plan(req)
+                    except Exception as e:
+                        self._fail(req, e)
+                        continue
+                    ent = {"plan": plan, "bytes": pbytes, "busy": False}
+                    self.plans[key] = ent
+                    self.used += pbytes
+                self.plans.move_to_end(key)
+                req.admitted = self.clock()
+                try:
+                    h = self.dev.launch(ent["plan"], req)
+                except Exception as e:
+                    self._fail(req, e)
+                    continue
+                ent["busy"] = True
+                self.used += io
+                self.inflight.append((req, h, (io,)))
+                admitted += 1
+        finally:
+            # requests not looked at yet (an unexpected error above) stay
+            # queued behind the ones that wait
+            waiting.extend(self.queue)
+            self.queue = waiting
         return admitted
 
     def run(self, arrivals: List[Request], poll_s: float = 0.0002):

@@ -12,9 +12,12 @@ Recipes (Section 6 of the paper for the curve family, eq. (bound_curve)):
     (Section 3.2), exact normals (outward), curvature and weights;
   * volume: cut-cell quadrature on a background grid of equilateral
     triangles of side dx (Section 3.1) with a symmetric 6-point rule of
-    degree 4 per triangle; cut triangles are clipped with straight edges
-    and fan-triangulated;  or, for accuracy studies, a spectrally accurate
-    polar rule on star-shaped bodies;
+    degree 4 per triangle; cut triangles are clipped at the boundary
+    crossings of their edges and fan-triangulated, and the sub-triangle on
+    the boundary chord is made curved (its chord replaced by the quadratic
+    through the two crossings and the boundary point between them), so
+    that every node lies inside the body;  or, for accuracy studies, a
+    spectrally accurate polar rule on star-shaped bodies;
   * densities: sum_{k<=8} a_k cos(k t) + b_k sin(k t), a_k, b_k ~ N(0,1)/max(1,k)^2;
   * sources: f = sum of 4 Gaussians of width 0.2 with N(0,1) amplitudes.
 Random streams: np.random.default_rng(SeedSequence([config, stream])) with

@@ -329,9 +329,67 @@ def test_volume_history_of_gaussian():
         g = lambda q: math.exp(-q * q * s * s / 4 - delta * (alpha ** 2 + q * q)) * sp.j0(q * r) * q / (alpha ** 2 + q * q)
         ref = 0.5 * s * s * integrate.quad(g, 0, 300, limit=2000, epsabs=0, epsrel=1e-13)[0]
         assert V[k] == pytest.approx(ref, rel=1e-10)
-    # Gaussian source closed form of the full free-space V at its centre
-    v0 = s * s / 4 * math.exp(alpha ** 2 * s ** 2 / 4) * sp.exp1(alpha ** 2 * s ** 2 / 4)
-    assert v0 == pytest.approx(0.003352213612078, rel=1e-12)
+
+
+def _graded_polar_rule(cx, cy, rad, h0, n_theta=96, nq=20):
+    """Area rule on the disk of radius rad about (cx, cy): Gauss-Legendre in
+    the radius on panels [0, h0], [h0, 2 h0], [2 h0, 4 h0], ... (graded
+    towards the centre, where the history kernel peaks over a width
+    sqrt(delta)), trapezoidal in the angle.  Test quadrature only."""
+    tg, wg = np.polynomial.legendre.leggauss(nq)
+    edges = [0.0, h0]
+    while edges[-1] < rad:
+        edges.append(min(rad, 2 * edges[-1]))
+    rho, wr = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        rho.append(0.5 * (a + b) + 0.5 * (b - a) * tg)
+        wr.append(0.5 * (b - a) * wg)
+    rho, wr = np.concatenate(rho), np.concatenate(wr)
+    th = (np.arange(n_theta) + 0.5) * (2 * np.pi / n_theta)
+    X = cx + rho[:, None] * np.cos(th)[None, :]
+    Y = cy + rho[:, None] * np.sin(th)[None, :]
+    W = (wr * rho)[:, None] * np.full(n_theta, 2 * np.pi / n_theta)[None, :]
+    return {"x": X.ravel(), "y": Y.ravel(), "w": W.ravel()}
+
+
+@pytest.mark.parametrize("d", [0.0, 0.05, 0.12])
+def test_volume_potential_of_gaussian_full_split(d):
+    """Spec invariant (c): the whole V = V_H + V_L of the Gaussian
+    source f = exp(-|x-c|^2/s^2) against the free-space closed form
+    (s^2/2) int_0^inf exp(-k^2 s^2/4) J0(k d) k/(alpha^2 + k^2) dk (Section
+    2.1, eq. (vp); at d = 0 it is (s^2/4) e^{a^2 s^2/4} E1(a^2 s^2/4)).  The
+    target lies farther from the boundary than sqrt(delta)(12 + 2 alpha
+    sqrt(delta)), so the oracle's local part is Corollary 4.11 at first
+    order: delta f(x)(1 - e^{-alpha^2 delta})/(alpha^2 delta).  The exact
+    local integral is int_0^delta e^{-alpha^2 t} (e^{t Lap} f)(x) dt =
+    delta f + delta^2/2 (Lap f - alpha^2 f) + O(delta^3), and the first-order
+    term expands to delta f - alpha^2 delta^2 f/2, so the oracle's error must
+    be -delta^2/2 (Lap f)(x) + O(delta^3): a dropped or mis-signed local term
+    leaves an O(delta) error instead."""
+    alpha, s = 10.0, 0.1
+    tx, ty = 0.05, -0.02                         # the target; the Gaussian sits at distance d
+    c = (tx - d, ty)
+    if d == 0.0:
+        ex = s * s / 4 * math.exp(alpha ** 2 * s ** 2 / 4) * sp.exp1(alpha ** 2 * s ** 2 / 4)
+        assert ex == pytest.approx(0.003352213612078, rel=1e-12)
+    else:
+        g = lambda q: math.exp(-q * q * s * s / 4) * sp.j0(q * d) * q / (alpha ** 2 + q * q)
+        ex = 0.5 * s * s * integrate.quad(g, 0, 400, limit=4000, epsabs=0, epsrel=1e-13)[0]
+    lap = (4 * d * d / s ** 4 - 4 / s ** 2) * math.exp(-d * d / s ** 2)
+    rad = 0.7                                     # f < 1e-16 beyond: the disk is free space
+    b = synth.discretize([synth.Curve(r0=rad, cx=tx, cy=ty)], 16)
+    errs = []
+    for delta, rtol in ((1e-4, 0.07), (2.5e-5, 0.02)):
+        vol = _graded_polar_rule(tx, ty, rad, 0.25 * math.sqrt(delta))
+        f = np.exp(-((vol["x"] - c[0]) ** 2 + (vol["y"] - c[1]) ** 2) / s ** 2)
+        fx = math.exp(-d * d / s ** 2)
+        P = O.Problem(alpha, delta, 3, b, volume=vol, targets=(np.array([tx]), np.array([ty])),
+                      inside=np.ones(1), f_vol=f, f_trg=np.array([fx]))
+        _, _, V = P.eval()
+        err = V[0] - ex
+        errs.append(err)
+        assert err == pytest.approx(-0.5 * delta ** 2 * lap, rel=rtol), (delta, err, -0.5 * delta ** 2 * lap)
+    assert errs[0] / errs[1] == pytest.approx(16.0, rel=0.1), errs
 
 
 # --------------------------------------------------------------------------

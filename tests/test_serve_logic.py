@@ -113,3 +113,73 @@ def test_run_with_arrivals_overlaps_plans():
     clk.t = 1.0
     srv.step()
     assert len(srv.finished) == 2
+
+
+class FailingDevice(FakeDevice):
+    """Raises from footprint, create_plan or launch for chosen geometries."""
+
+    def __init__(self, clock, plan_bytes, duration, fail):
+        super().__init__(clock, plan_bytes, duration)
+        self.fail = fail                     # geometry key -> "footprint" | "create" | "launch"
+
+    def footprint(self, req):
+        if self.fail.get(req.geometry.key) == "footprint":
+            raise RuntimeError("history grid too large")
+        return super().footprint(req)
+
+    def create_plan(self, req):
+        if self.fail.get(req.geometry.key) == "create":
+            raise RuntimeError("out of memory")
+        return super().create_plan(req)
+
+    def launch(self, plan, req):
+        if self.fail.get(req.geometry.key) == "launch":
+            raise RuntimeError("invalid input")
+        return super().launch(plan, req)
+
+
+def test_failures_are_rejected_and_rolled_back():
+    clk = FakeClock()
+    dev = FailingDevice(clk, {"A": 100, "F": 100, "C": 100, "L": 100, "B": 100},
+                        {"A": 1.0, "F": 1.0, "C": 1.0, "L": 1.0, "B": 1.0},
+                        {"F": "footprint", "C": "create", "L": "launch"})
+    srv = Server(dev, budget_bytes=10_000, clock=clk)
+    for rid, key in enumerate(["F", "A", "C", "L", "B", "L"]):
+        srv.submit(_req(rid, key))
+    srv.step()
+    # every failing request is rejected with its error, the others run
+    assert sorted(r.rid for r in srv.rejected) == [0, 2, 3, 5]
+    assert all(r.error and r.done >= 0 for r in srv.rejected)
+    assert sorted(dev.launched) == [1, 4]
+    # the plan whose launch failed stays idle and its bytes are the plan's only
+    ent = srv.plans[("L", 10.0, 1e-6, 1)]
+    assert ent["busy"] is False
+    assert srv.used == 3 * 100 + 2 * 10          # plans A, L, B; in-flight io of A and B
+    assert ("C", 10.0, 1e-6, 1) not in srv.plans  # creation failed: nothing resident
+    assert len(srv.queue) == 0
+    clk.t = 1.0
+    srv.step()
+    assert sorted(r.rid for r in srv.finished) == [1, 4]
+    assert srv.used == 3 * 100
+
+
+def test_failed_completion_query_releases_the_plan():
+    clk = FakeClock()
+    dev = FakeDevice(clk, {"A": 100}, {"A": 1.0})
+    srv = Server(dev, budget_bytes=10_000, clock=clk)
+    srv.submit(_req(0, "A"))
+    srv.submit(_req(1, "A"))
+    srv.step()
+
+    def broken(h):
+        raise RuntimeError("device error")
+    dev.done = broken
+    clk.t = 1.0
+    srv.step()
+    assert [r.rid for r in srv.rejected] == [0]
+    dev.done = lambda h: clk() >= h["end"]
+    # the second request was admitted on the released plan in the same pass
+    assert dev.launched == [0, 1]
+    clk.t = 2.0
+    srv.step()
+    assert [r.rid for r in srv.finished] == [1]
