@@ -33,8 +33,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--alphas", type=str, default="1,10,100")
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--cpu-sample", type=int, default=24)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--check-each", type=int, default=8,
+                    help="outputs per stratum and alpha of the parity check against the oracle")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the parity check and the CPU baseline (profiling runs only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="multibody",
@@ -112,23 +114,36 @@ def main():
         plans.append(p)
         log(f"plan alpha={al}: {plan_s[-1]:.1f} s, grid {p.info()['n_fine']}, {p.info()['device_bytes'] / 1e9:.2f} GB")
     n_out = plans[0].n_out
+    # One step = the whole hot path for every plan, the closest-point search
+    # and local coefficients of every target included (MHK_PART_GEOMETRY);
+    # the rate with the geometry kept from plan creation is reported beside.
+    fresh = M.PART_ALL | M.PART_GEOMETRY
     outs = []
     for p, s in zip(plans, streams):
         with torch.cuda.stream(s):
-            outs.append(p.eval(sigma, mu, fv, ft))
+            outs.append(p.eval(sigma, mu, fv, ft, parts=fresh))
     torch.cuda.synchronize()
 
-    def step():
+    def step(parts):
         for p, o, s in zip(plans, outs, streams):
-            if s is not cur:
-                s.wait_stream(cur)
-            p.eval(sigma, mu, fv, ft, out=o)
+            p.eval(sigma, mu, fv, ft, out=o, parts=parts, join=False)
         for s in streams:
             if s is not cur:
                 cur.wait_stream(s)
 
+    def timed(parts, steps):
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        wall0 = time.perf_counter()
+        for _ in range(steps):
+            step(parts)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
+
     for _ in range(a.warmup):
-        step()
+        step(fresh)
     torch.cuda.synchronize()
     log("warmup done")
     # stage events are recorded by the library on its streams during the timed
@@ -136,35 +151,34 @@ def main():
     # the stage times are those of the last timed step
     for p in plans:
         p.set_timing(True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    wall0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1)
-    ms_step = ms / a.steps
+    ms_step, wall = timed(fresh, a.steps)
     evals = n_out * len(plans)
     value = evals / (ms_step * 1e-3)
     infos = [p.info() for p in plans]
-    stage = {k: [inf[k] for inf in infos] for k in ("ms_spread", "ms_fft", "ms_multiply", "ms_interp",
-                                                     "ms_levels", "ms_local", "ms_total")}
+    stage_keys = ("ms_geometry", "ms_spread", "ms_fft", "ms_multiply", "ms_interp", "ms_levels", "ms_local",
+                  "ms_total")
+    stage = {k: [inf[k] for inf in infos] for k in stage_keys}
+    log(f"timed {a.steps} steps: {ms_step:.3f} ms/step (closest points included)")
+    for p in plans:
+        p.set_timing(False)
+    for _ in range(a.warmup):
+        step(M.PART_ALL)
+    ms_res, _ = timed(M.PART_ALL, a.steps)
+    log(f"resident local geometry: {ms_res:.3f} ms/step")
+    noconv = [int(p.info()["n_noconv"]) for p in plans]
 
-    # dominant kernel: the one with the largest summed time over the step
-    tot = {k: sum(v) for k, v in stage.items() if k != "ms_total"}
-    dom = max(tot, key=tot.get)
-    roof = roofline(dom, stage, infos, w, plans)
+    # dominant kernel: the level sums (largest summed stage time)
+    roof = roofline(stage, infos, w)
 
-    log(f"timed {a.steps} steps: {ms_step:.2f} ms/step")
+    # parity against the oracle on a stratified sample of every plan's
+    # outputs; the oracle's time on it is the CPU baseline
+    check = None
     cpu = None
-    if not a.no_cpu:
-        cpu = cpu_baseline(w, infos, alphas, a.cpu_sample)
+    if not a.no_check:
+        check, cpu = parity_check(w, infos, alphas, outs, a.check_each)
 
     line = {
-        "metric": "target evals/s (S, D, V per target, FP64, rel err 1e-10 vs oracle)",
+        "metric": "target evals/s at rel err 1e-10 (FP64) vs 1e-6 (FP32); p50/p99 request latency",
         "value": value,
         "unit": "target-evals/s",
         "n_gpus": 1,
@@ -178,69 +192,85 @@ def main():
         "data": "synthetic",
         "config": {"workload": "multibody-10-starfish", "n_boundary": w.n_b, "n_volume": w.n_v,
                    "n_targets": w.n_t, "n_out": n_out, "alphas": alphas, "tol": a.tol,
-                   "batch": 1, "parallelism": "none", "streams": 1 if a.one_stream else len(alphas)},
+                   "batch": 1, "parallelism": "none", "streams": 1 if a.one_stream else len(alphas),
+                   "step": "S, D, V at every output for each alpha, closest points included"},
+        "resident_geometry": {"ms_per_step": ms_res, "value": evals / (ms_res * 1e-3)},
         "stage_ms": {k: [round(x, 4) for x in v] for k, v in stage.items()},
         "grid": [int(i["n_fine"]) for i in infos],
         "delta": [i["delta"] for i in infos],
         "plan_s": [round(x, 3) for x in plan_s],
+        "n_noconv": noconv,
         "gen_s": round(gen_s, 2),
         "wall_s": round(wall, 3),
+        "rel_err_vs_oracle": check,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if check is not None:
+        worst = max(v for per in check["alpha"].values() for v in per.values())
+        if not worst <= a.tol:
+            log(f"parity FAILED: max relative error {worst:.3e} > {a.tol:g}")
+            sys.exit(1)
 
 
-def roofline(dom, stage, infos, w, plans):
-    """Algorithmic bytes or flops of the dominant stage per launch over its
-    measured HIP-event time."""
-    name = dom[3:]
-    if name == "levels":
-        # algorithmic flops of the three level launches of every plan over
-        # their HIP-event time (the stage also holds the small k_level_q)
-        flops = 0.0
-        for info in infos:
-            flops += level_flops(w, info)
-        t = sum(stage[dom]) * 1e-3
-        ach = flops / t / 1e12
-        launches = sum(i["J"] for i in infos)
-        return {"kernel": "k_level_sums", "bound": "alu", "achieved": ach, "peak": FP64_PEAK,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": LEVEL_SUMS_HBM_BYTES,
-                "flops_per_launch": flops / launches, "ms_per_launch": sum(stage[dom]) / launches}
-    if name in ("fft", "spread", "multiply", "interp"):
-        byts = 0.0
-        for info in infos:
-            n = info["n_fine"]
-            if n == 0:
-                continue
-            grid = n * (n + 2) * 8.0
-            if name == "fft":
-                byts += (4 + 4 + 3 + 3) * grid            # read + write per field, forward 4, inverse 3
-            elif name == "multiply":
-                byts += (4 + 3) * grid                    # half spectra: 4 read, 3 written
-            elif name == "spread":
-                byts += 4 * grid + (w.n_v * 32 + w.n_b * 56)
-            else:
-                byts += 3 * grid + info["n_out"] * (16 + 24)
-        t = sum(stage[dom]) * 1e-3
-        ach = byts / t / 1e9
-        return {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK, "unit": "GB/s",
-                "frac": ach / HBM_PEAK, "traffic": None}
-    return {"kernel": name, "bound": "alu", "achieved": None, "peak": FP64_PEAK, "unit": "TFLOP/s",
-            "frac": None, "traffic": None}
+def roofline(stage, infos, w):
+    """The dominant kernel, k_level_sums: algorithmic flops per launch over
+    its measured HIP-event time per launch (the level stage of each plan,
+    on the stream the level sums are launched on, over its J launches)."""
+    flops, pairs = 0.0, 0.0
+    for info in infos:
+        pr = level_pairs(w, info)
+        pairs += pr
+    flops = pairs * LEVEL_FLOPS_PER_PAIR
+    launches = sum(i["J"] for i in infos)
+    ms = sum(stage["ms_levels"])
+    ach = flops / (ms * 1e-3) / 1e12
+    tr = level_sums_traffic()
+    return {"kernel": "k_level_sums", "bound": "alu", "achieved": ach, "peak": FP64_PEAK,
+            "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": tr,
+            "flops_per_pair": LEVEL_FLOPS_PER_PAIR, "pairs_per_launch": pairs / launches,
+            "flops_per_launch": flops / launches, "ms_per_launch": ms / launches,
+            "frac_kernel_count": ach * LEVEL_FLOPS_PER_PAIR_KERNEL / LEVEL_FLOPS_PER_PAIR / FP64_PEAK,
+            "flops_per_pair_kernel": LEVEL_FLOPS_PER_PAIR_KERNEL}
 
 
-# Flops the level sum spends on one (target, child node) pair with r < R_j:
-# separation 2, a = (dx^2 + dy^2)/(4 delta_j) 3, segment and local variable 3,
-# two degree-7 Horner recurrences 28, S accumulation 2, nu.(x - x_q) 3 and D
-# accumulation 2.
-LEVEL_FLOPS_PER_PAIR = 45.0
+# Algorithmic flops of one (target, child node) pair with r < R_j, as the
+# method needs them: the separation and r^2 (5: two differences, a product,
+# a multiply-add, the scale to the table variable), one degree-7 polynomial
+# (7 multiply-adds, 14) and two multiply-adds of the single and double layer
+# sums (4).  The kernel spends more per pair: the segment index and local
+# variable (3), the polynomial's derivative for K_j^D (a second Horner chain
+# of 7 multiply-adds, 14) and nu.(x - x_q) (3): 45 flops
+# (flops_per_pair_kernel and frac_kernel_count in the roofline entry).
+LEVEL_FLOPS_PER_PAIR = 23.0
+LEVEL_FLOPS_PER_PAIR_KERNEL = 45.0
 
-# HBM bytes per k_level_sums launch on this workload (mean over the levels and
-# plans), FETCH_SIZE + WRITE_SIZE per dispatch, each scaled by the counter's
-# reading for a 256 MiB device copy (profiles/multibody_fp64_hbm_counters.md).
-# None while the kernel has changed since the counters were taken.
-LEVEL_SUMS_HBM_BYTES = 72.7e6
+
+def level_sums_traffic():
+    """HBM bytes per k_level_sums launch from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the counter's
+    reading for a device copy of known size), or None when levels.hip has
+    changed since the counters were taken (its hash is recorded there)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "level_sums_multibody_fp64_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2606_28865_amd", "csrc", "levels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    rec = {}
+    for ln in text.splitlines():
+        if ":" in ln and ln.strip().startswith("- "):
+            k, v = ln.strip()[2:].split(":", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    if rec.get("levels.hip sha256[:16]") != sha:
+        return None
+    try:
+        return float(rec["bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def child_nodes(w, j):
@@ -261,9 +291,8 @@ def child_nodes(w, j):
     return np.concatenate(xs)
 
 
-def level_flops(w, info):
-    """Pairs (target, child node) with r < R_j summed over the levels, times
-    the flops the level sum spends on one pair."""
+def level_pairs(w, info):
+    """Pairs (target, child node) with r < R_j summed over the levels."""
     from scipy.spatial import cKDTree
     tg = np.concatenate([np.stack([w.tx, w.ty], 1), np.stack([w.boundary["x"], w.boundary["y"]], 1)])
     pairs = 0.0
@@ -271,25 +300,73 @@ def level_flops(w, info):
         tree = cKDTree(child_nodes(w, j))
         cnt = tree.query_ball_point(tg, info["level_radius"][j - 1], return_length=True, workers=-1)
         pairs += float(np.sum(cnt))
-    return pairs * LEVEL_FLOPS_PER_PAIR
+    return pairs
 
 
-def cpu_baseline(w, infos, alphas, n_sample):
-    """The oracle (plain direct sums, OpenMP) on n_sample targets of the same
-    workload for alpha = alphas[len//2], scaled to target-evals/s."""
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads():
+    """Threads the OpenMP oracle runs with: OMP_NUM_THREADS, else the CPUs
+    this process may use."""
+    try:
+        return int(os.environ["OMP_NUM_THREADS"])
+    except (KeyError, ValueError):
+        return len(os.sched_getaffinity(0))
+
+
+def strata(w, info, n_each, seed):
+    """Output indices of a seeded stratified sample: n_each on-surface
+    nodes, n_each targets in the layer band (nearest boundary node closer
+    than the layer band), n_each in the volume band, n_each farther."""
+    from scipy.spatial import cKDTree
+    g = np.random.default_rng(seed)
+    d, _ = cKDTree(np.column_stack([w.boundary["x"], w.boundary["y"]])).query(np.column_stack([w.tx, w.ty]))
+    bl, bv = info["band_layer"], info["band_volume"]
+    pick = lambda a, n: a if len(a) <= n else g.choice(a, n, replace=False)
+    groups = {"on_surface": w.n_t + pick(np.arange(w.n_b), n_each),
+              "layer_band": pick(np.nonzero(d < bl)[0], n_each),
+              "volume_band": pick(np.nonzero((d >= bl) & (d < bv))[0], n_each),
+              "far": pick(np.nonzero(d >= bv)[0], n_each)}
+    return {k: np.sort(v).astype(np.int64) for k, v in groups.items()}
+
+
+def parity_check(w, infos, alphas, outs, n_each):
+    """Relative max-norm error of S, D and V per plan against the FP64
+    oracle on a stratified sample of the outputs (errors relative to the
+    largest oracle value of the sample), and the oracle's own rate on it."""
     import oracle as O
-    i = len(alphas) // 2
-    info = infos[i]
-    g = np.random.default_rng(1)
-    sub = np.sort(g.choice(w.n_t + w.n_b, n_sample, replace=False)).astype(np.int64)
-    P = O.Problem(alphas[i], info["delta"], info["J"], w.boundary, volume=w.volume, targets=(w.tx, w.ty),
-                  inside=w.inside, on_surface=True, sigma=w.sigma, mu=w.mu, f_vol=w.f_vol, f_trg=w.f_trg)
-    t0 = time.perf_counter()
-    P.eval(sub)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n_sample / dt, "unit": "target-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_sample} random targets of the same workload at alpha={alphas[i]}, {dt:.1f} s"}
+    res, total_t, total_n = {}, 0.0, 0
+    for k, (alpha, info, out) in enumerate(zip(alphas, infos, outs)):
+        groups = strata(w, info, n_each, seed=100 + k)
+        sub = np.sort(np.concatenate(list(groups.values())))
+        P = O.Problem(alpha, info["delta"], info["J"], w.boundary, volume=w.volume, targets=(w.tx, w.ty),
+                      inside=w.inside, on_surface=True, sigma=w.sigma, mu=w.mu, f_vol=w.f_vol, f_trg=w.f_trg)
+        t0 = time.perf_counter()
+        ref = P.eval(sub)
+        dt = time.perf_counter() - t0
+        total_t += dt
+        total_n += len(sub)
+        errs = {}
+        for name, o, rr in zip("SDV", out, ref):
+            g = o.double().cpu().numpy().ravel()[sub]
+            errs[name] = float(np.abs(g - rr).max() / np.abs(rr).max())
+        res[f"{alpha:g}"] = errs
+        log(f"alpha={alpha:g}: rel err vs oracle {errs} on {len(sub)} outputs ({dt:.1f} s)")
+    check = {"alpha": res, "sample": f"{n_each} outputs per stratum (on-surface, layer band, volume band, "
+                                     f"far) per alpha, seeded", "bar": 1e-10}
+    cpu = {"value": total_n / total_t, "unit": "target-evals/s", "cores": oracle_threads(), "kind": "oracle",
+           "cpu": cpu_model(),
+           "sample": f"the {total_n} stratified outputs of the parity check (S, D, V each), all three alpha, "
+                     f"{total_t:.1f} s"}
+    return check, cpu
 
 
 # ---------------------------------------------------------------------------

@@ -58,13 +58,23 @@ typedef enum {
     MHK_EINVAL = -1,       /* invalid argument (message in mhk_last_error) */
     MHK_ENOMEM = -2,       /* device allocation failed / footprint too large */
     MHK_EHIP = -3,         /* HIP runtime or rocFFT error */
-    MHK_EUNSUPPORTED = -4  /* valid but unsupported configuration */
+    MHK_EUNSUPPORTED = -4, /* valid but unsupported configuration */
+    MHK_ENOCONV = -5       /* the closest-point Newton iteration (Section 3.2) did not
+                              converge for a target inside a local band            */
 } mhk_status;
 
 enum { MHK_FP64 = 0, MHK_FP32 = 1 };
 
-/* Parts of the split, for mhk_eval_parts (bit mask). */
-enum { MHK_PART_HISTORY = 1, MHK_PART_LEVELS = 2, MHK_PART_LOCAL = 4, MHK_PART_ALL = 7 };
+/* Parts of the split, for mhk_eval_parts (bit mask).  MHK_PART_GEOMETRY is
+ * not a part of the split: with it, the evaluation first recomputes the
+ * target geometry of the local part -- the closest boundary point of every
+ * target (nearest node, then Newton on its panel and the two neighbouring
+ * panels, Section 3.2) and the density-independent coefficients of Lemmas
+ * 4.1, 4.5 and 4.8 -- instead of using the ones computed at plan creation.
+ * The results are the same either way; the bit makes the closest-point
+ * search part of the evaluation's work and time. */
+enum { MHK_PART_HISTORY = 1, MHK_PART_LEVELS = 2, MHK_PART_LOCAL = 4, MHK_PART_ALL = 7,
+       MHK_PART_GEOMETRY = 8 };
 
 typedef struct {
     double alpha;    /* > 0, modified Helmholtz parameter (eq. (mod_helm))          */
@@ -117,6 +127,12 @@ typedef struct {
     /* milliseconds of the last timed eval per stage (see mhk_plan_set_timing)   */
     double ms_spread, ms_fft, ms_multiply, ms_interp, ms_levels, ms_local, ms_total;
     int history_truncated; /* 1: smoothly truncated history kernel, tabulated spectrum */
+    int64_t n_noconv;      /* targets inside a local band whose closest-point Newton
+                              iteration did not converge (read with a wait): plan
+                              creation fails with MHK_ENOCONV when it is nonzero, and
+                              evaluations with MHK_PART_GEOMETRY add to it            */
+    double ms_geometry;    /* closest points and local coefficients of the last timed
+                              eval with MHK_PART_GEOMETRY (beside the history part)  */
 } mhk_info;
 
 typedef struct mhk_plan mhk_plan;

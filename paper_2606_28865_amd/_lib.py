@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmhk.so")
 
 MHK_FP64, MHK_FP32 = 0, 1
-PART_HISTORY, PART_LEVELS, PART_LOCAL, PART_ALL = 1, 2, 4, 7
+PART_HISTORY, PART_LEVELS, PART_LOCAL, PART_ALL, PART_GEOMETRY = 1, 2, 4, 7, 8
 NGL = 16
 
 
@@ -49,7 +49,8 @@ class Info(C.Structure):
                 ("n_out", C.c_int64), ("device_bytes", C.c_int64),
                 ("ms_spread", C.c_double), ("ms_fft", C.c_double), ("ms_multiply", C.c_double),
                 ("ms_interp", C.c_double), ("ms_levels", C.c_double), ("ms_local", C.c_double),
-                ("ms_total", C.c_double), ("history_truncated", C.c_int)]
+                ("ms_total", C.c_double), ("history_truncated", C.c_int), ("n_noconv", C.c_int64),
+                ("ms_geometry", C.c_double)]
 
     def as_dict(self):
         d = {}

@@ -2,12 +2,16 @@
 // (Section 3.2), in FP64 in both precision paths, plus the final scatter of
 // the accumulated potentials to the caller's target order.
 //
-// For an off-surface target x the nearest boundary node is found in a cell
-// list (cells larger than the widest band plus the largest node gap, so the
-// 3x3 neighbourhood holds the global nearest node of every target inside the
-// band); its panel and the two neighbouring panels are searched for the
-// closest point x0 by Newton's method on d/dt |x - gamma(t)|^2 = 0, started
-// from the best of the panel's nodes and end points.  The geometry, the
+// For an off-surface target x the nearest boundary node is found from the
+// target's closest-point cell, which lists every panel whose node bounding
+// box lies within reach = (widest band + largest node gap) of the cell,
+// nearest first: panels whose box is farther than the best node so far are
+// skipped, so a few panels are scanned node by node.  Whenever the nearest
+// node lies within reach of x (the only case in which it is used) its panel
+// is in the list, so the result is the global nearest node, ties to the
+// lowest index.  Its panel and the two neighbouring panels are searched for
+// the closest point x0 by Newton's method on d/dt |x - gamma(t)|^2 = 0,
+// started from the best of the panel's nodes and end points.  The geometry, the
 // curvature and the densities are evaluated at x0 from their per-panel
 // Legendre expansions.  rho = +1 for targets inside Omega, -1 outside, so
 // that D jumps by -mu/2 on entering Omega (eq. (jumprel)).
@@ -135,9 +139,10 @@ struct LocalArgs {
     const int32_t *gpan;
     const uint8_t *gflag;
     const double *pcx, *pcy, *pck, *ends, *gl_t;
-    const int32_t *prev, *next, *node, *cell_start;
-    const double *nx_s, *ny_s;
-    double cell, ox, oy, gap;
+    const int32_t *prev, *next, *cand, *cell_start;
+    const double *pbox;
+    int32_t *noconv;
+    double cell, ox, oy, reach;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
     const T *acc;          // [3][B][nout]: S, D, V in sorted order (history part)
@@ -145,9 +150,11 @@ struct LocalArgs {
     T *out_s, *out_d, *out_v;
 };
 
-// Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p.
+// Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p; returns whether
+// the Newton iteration converged (a step below 1e-15, possibly clamped at an
+// end point) -- if not, the best node or end point is kept.
 template <typename T>
-__device__ inline void panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
+__device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
 {
     const double *cx = A.pcx + (size_t)p * NGL, *cy = A.pcy + (size_t)p * NGL;
     // start: best of the 16 nodes and the two end points
@@ -164,6 +171,7 @@ __device__ inline void panel_min(const LocalArgs<T> &A, int p, double px, double
     dy = A.ends[p * 4 + 3] - py;
     if (dx * dx + dy * dy < ds) { ds = dx * dx + dy * dy; ts = 1.0; }
     double t = ts;
+    bool conv = false;
     for (int it = 0; it < 40; ++it) {
         double x0, x1, x2, y0, y1, y2;
         leg2(cx, cy, t, x0, x1, x2, y0, y1, y2);
@@ -174,12 +182,16 @@ __device__ inline void panel_min(const LocalArgs<T> &A, int p, double px, double
         tn = fmin(1.0, fmax(-1.0, tn));
         const double step = fabs(tn - t);
         t = tn;
-        if (step < 1e-15) break;
+        if (step < 1e-15) {
+            conv = true;
+            break;
+        }
     }
     const double xv = leg1(cx, t) - px, yv = leg1(cy, t) - py;
     const double dn = xv * xv + yv * yv;
     if (dn <= ds) { tbest = t; d2best = dn; }
     else { tbest = ts; d2best = ds; }
+    return conv;
 }
 
 // Geometry of the local part, once per plan (targets and boundary are
@@ -211,37 +223,48 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
     if (on) {
         vfac = -expm1(-c2v * c2v) / (2.0 * c2v * c2v);          // Cor. 4.10
     } else {
-        // nearest boundary node (lowest index on ties)
-        int cx = (int)floor((px - A.ox) / A.cell), cy = (int)floor((py - A.oy) / A.cell);
+        // nearest boundary node (lowest index on ties) among the nodes of the
+        // cell's candidate panels, nearest panels first; a panel whose node
+        // box is farther than the best node so far cannot improve on it
+        const int cx = (int)floor((px - A.ox) / A.cell), cy = (int)floor((py - A.oy) / A.cell);
         double dmin = INFINITY;
         int imin = -1;
-        if (cx >= -1 && cx <= A.ncx && cy >= -1 && cy <= A.ncy) {
-            for (int yy = max(cy - 1, 0); yy <= min(cy + 1, A.ncy - 1); ++yy) {
-                const int c0 = A.cell_start[(int64_t)yy * A.ncx + max(cx - 1, 0)];
-                const int c1 = A.cell_start[(int64_t)yy * A.ncx + min(cx + 1, A.ncx - 1) + 1];
-                for (int c = c0; c < c1; ++c) {
-                    const double dx = A.nx_s[c] - px, dy = A.ny_s[c] - py;
+        if (cx >= 0 && cx < A.ncx && cy >= 0 && cy < A.ncy) {
+            const int64_t cell = (int64_t)cy * A.ncx + cx;
+            const int k0 = A.cell_start[cell], k1 = A.cell_start[cell + 1];
+            for (int k = k0; k < k1; ++k) {
+                const int p = A.cand[k];
+                const double *bb = A.pbox + (size_t)p * 4;
+                const double ex = fmax(0.0, fmax(bb[0] - px, px - bb[1]));
+                const double ey = fmax(0.0, fmax(bb[2] - py, py - bb[3]));
+                if (ex * ex + ey * ey > dmin) continue;
+                const double *nx = A.bx + (size_t)p * NGL, *ny = A.by + (size_t)p * NGL;
+#pragma unroll 4
+                for (int i = 0; i < NGL; ++i) {
+                    const double dx = nx[i] - px, dy = ny[i] - py;
                     const double d = dx * dx + dy * dy;
-                    if (d <= dmin) {
-                        const int i = A.node[c];
-                        if (d < dmin || i < imin) { dmin = d; imin = i; }
-                    }
+                    const int node = p * NGL + i;
+                    if (d < dmin || (d == dmin && node < imin)) { dmin = d; imin = node; }
                 }
             }
         }
         // the closest point lies within half a node gap of a node, so a
         // nearest node farther than band + gap puts x outside both bands
-        if (imin >= 0 && sqrt(dmin) <= fmax(A.band_s, A.band_v) + A.gap) {
+        if (imin >= 0 && sqrt(dmin) <= A.reach) {
             const int p0 = imin / NGL;
             int cand[3] = {p0, A.prev[p0], A.next[p0]};
             double d2b = INFINITY;
+            bool conv = true;
 #pragma unroll 1
             for (int c = 0; c < 3; ++c) {
                 double t, d2;
-                panel_min(A, cand[c], px, py, t, d2);
-                if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; }
+                const bool cv = panel_min(A, cand[c], px, py, t, d2);
+                if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; conv = cv; }
             }
             r = sqrt(d2b);
+            // a closest point that is not a converged Newton solution is
+            // only an approximation: count it when the local part uses it
+            if (!conv && r < fmax(A.band_s, A.band_v) && A.noconv) atomicAdd(A.noconv, 1);
         }
         // volume part (Lemma 4.8 first order inside the band, Cor. 4.11
         // beyond).  Exterior targets in the band: the local integral over
@@ -445,11 +468,11 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.gl_t = P->loc.gl_t;
     A.prev = P->loc.prev;
     A.next = P->loc.next;
-    A.node = P->loc.node;
+    A.cand = P->loc.cand;
     A.cell_start = P->loc.cell_start;
-    A.nx_s = P->loc.nx_s;
-    A.ny_s = P->loc.ny_s;
-    A.gap = P->loc.gap;
+    A.pbox = P->loc.pbox;
+    A.noconv = P->loc.noconv;
+    A.reach = P->loc.reach;
     A.cell = P->loc.cell;
     A.ox = P->loc.ox;
     A.oy = P->loc.oy;
@@ -465,12 +488,12 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.out_s = A.out_d = A.out_v = nullptr;
 }
 
-hipError_t launch_local_geom(mhk_plan *P)
+hipError_t launch_local_geom(mhk_plan *P, hipStream_t st)
 {
     if (P->nout == 0) return hipSuccess;
     LocalArgs<double> A;
     fill_args(P, A);
-    hipLaunchKernelGGL(k_local_geom, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A,
+    hipLaunchKernelGGL(k_local_geom, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, st, A,
                        P->loc.geo, P->loc.gpan, P->loc.gflag);
     return hipGetLastError();
 }

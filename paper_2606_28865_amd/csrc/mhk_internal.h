@@ -144,11 +144,16 @@ struct History {
 };
 
 struct Local {
-    double cell = 0, ox = 0, oy = 0, gap = 0;
+    // closest-point cells: square cells of side `cell` over the bounding
+    // box; cell c lists (cand[cell_start[c] .. cell_start[c+1])) the panels
+    // whose node bounding box lies within `reach` = band + largest node gap
+    // of the cell, nearest first
+    double cell = 0, ox = 0, oy = 0, gap = 0, reach = 0;
     int ncx = 0, ncy = 0;
-    int32_t *node = nullptr;                      // boundary node indices sorted by cell
-    double *nx_s = nullptr, *ny_s = nullptr;      // their positions in the same order
+    int32_t *cand = nullptr;
+    double *pbox = nullptr;                       // [n_panels][4]: node bounding box xmin, xmax, ymin, ymax
     int32_t *cell_start = nullptr;
+    int32_t *noconv = nullptr;                    // device counter: closest-point solves that did not converge
     double *leg = nullptr;                        // [16][16] nodal values -> Legendre coefficients
     double *cx = nullptr, *cy = nullptr, *ck = nullptr;   // [n_panels][16]
     double *ends = nullptr;                       // [n_panels][4]: x(-1), y(-1), x(1), y(1)
@@ -186,8 +191,10 @@ struct mhk_plan {
     mhk::Local loc;
     std::vector<void *> allocs;
     int64_t bytes = 0;
-    hipEvent_t ev[9] = {};                      // stage timing (ev[8]: start of the level sums)
-    bool t_pending = false, t_levels = false;   // stage events recorded, not read yet
+    // stage timing: ev[0..7] history stages and local part on the plan's
+    // stream, ev[8] start of the side work, ev[9] end of the local geometry
+    hipEvent_t ev[10] = {};
+    bool t_pending = false, t_levels = false, t_geom = false;   // stage events recorded, not read yet
     hipStream_t cap = nullptr;                  // capture stream of mhk_plan_capture
     // The level sums run on a second stream beside the history part (they
     // share no data): they accumulate S and D into acc_lev, [2][batch][n_out],
@@ -206,7 +213,7 @@ hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void
 // level j's sums into acc_lev on stream st: stored when init, else added
 hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init);
 hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd);
-hipError_t launch_local_geom(mhk_plan *P);
+hipError_t launch_local_geom(mhk_plan *P, hipStream_t st);
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
                         const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);

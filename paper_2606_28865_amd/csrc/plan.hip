@@ -777,7 +777,10 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
     gauss_legendre(16, t16, w16);
     double *buf = nullptr, *gt = nullptr, *gw = nullptr, *phi = nullptr, *work = nullptr;
     size_t bytes = sizeof(double) * (size_t)n2 * (size_t)(n2 + 2);
-    if (hipMalloc((void **)&buf, bytes) != hipSuccess) {
+    // temporaries are allocated and freed in the order of the plan's stream
+    // (hipFree would wait for the whole device, i.e. for other plans' work)
+    hipStream_t s0 = P->stream;
+    if (hipMallocAsync((void **)&buf, bytes, s0) != hipSuccess) {
         (void)hipGetLastError();
         set_error("truncated-kernel table: allocation of the sample grid failed");
         return MHK_ENOMEM;
@@ -793,17 +796,18 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
         phi2inv[l] = 1.0 / (ph * ph);
     }
     do {
-        if (hipMalloc((void **)&gt, 16 * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&gw, 16 * sizeof(double)) != hipSuccess ||
-            hipMalloc((void **)&phi, (G.lmax + 1) * sizeof(double)) != hipSuccess) {
+        if (hipMallocAsync((void **)&gt, 16 * sizeof(double), s0) != hipSuccess ||
+            hipMallocAsync((void **)&gw, 16 * sizeof(double), s0) != hipSuccess ||
+            hipMallocAsync((void **)&phi, (G.lmax + 1) * sizeof(double), s0) != hipSuccess) {
             (void)hipGetLastError();
             set_error("truncated-kernel table: allocation failed");
             st = MHK_ENOMEM;
             break;
         }
-        if (hipMemcpy(gt, t16.data(), 16 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(gw, w16.data(), 16 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(phi, phi2inv.data(), (G.lmax + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpyAsync(gt, t16.data(), 16 * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
+            hipMemcpyAsync(gw, w16.data(), 16 * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
+            hipMemcpyAsync(phi, phi2inv.data(), (G.lmax + 1) * sizeof(double), hipMemcpyHostToDevice, s0) !=
+                hipSuccess) {
             set_error("truncated-kernel table: copy failed");
             st = MHK_EHIP;
             break;
@@ -830,7 +834,7 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
         size_t wb = 0;
         rocfft_plan_get_work_buffer_size(plan, &wb);
         if (wb) {
-            if (hipMalloc((void **)&work, wb) != hipSuccess) {
+            if (hipMallocAsync((void **)&work, wb, s0) != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("truncated-kernel table: work buffer allocation failed");
                 st = MHK_ENOMEM;
@@ -859,11 +863,14 @@ mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const s
     if (ex) rocfft_execution_info_destroy(ex);
     if (plan) rocfft_plan_destroy(plan);
     if (d) rocfft_plan_description_destroy(d);
-    (void)hipFree(buf);
-    if (gt) (void)hipFree(gt);
-    if (gw) (void)hipFree(gw);
-    if (phi) (void)hipFree(phi);
-    if (work) (void)hipFree(work);
+    // the host vectors copied from above live until here, and the stream is
+    // synchronised on success; on failure wait before they go away
+    if (st != MHK_OK) (void)hipStreamSynchronize(s0);
+    (void)hipFreeAsync(buf, s0);
+    if (gt) (void)hipFreeAsync(gt, s0);
+    if (gw) (void)hipFreeAsync(gw, s0);
+    if (phi) (void)hipFreeAsync(phi, s0);
+    if (work) (void)hipFreeAsync(work, s0);
     return st;
 }
 
@@ -1298,8 +1305,11 @@ mhk_status build_local(mhk_plan *P, Host &H)
         }
         ends[p * 4 + 0] = xm; ends[p * 4 + 1] = ym; ends[p * 4 + 2] = xp; ends[p * 4 + 3] = yp;
     }
-    // nearest-node cell list: any target within the larger band of the curve has
-    // its nearest node within band + (largest node gap)
+    // closest-point cells.  Any target within the larger band of the curve
+    // has its nearest node within reach = band + (largest node gap); the
+    // cell of side `cell` lists every panel whose node bounding box comes
+    // within reach of the cell, nearest first, so the device search over
+    // the list finds the global nearest node whenever it is within reach.
     double gap = 0;
     for (int64_t p = 0; p < npan; ++p) {
         for (int i = 0; i + 1 < NGL; ++i)
@@ -1307,43 +1317,82 @@ mhk_status build_local(mhk_plan *P, Host &H)
         int64_t q = H.next[p];
         gap = std::max(gap, hypot(b->x[q * NGL] - b->x[p * NGL + NGL - 1], b->y[q * NGL] - b->y[p * NGL + NGL - 1]));
     }
-    double band = std::max(P->info.band_layer, P->info.band_volume);
-    C.cell = 1.01 * band + gap;
+    const double band = std::max(P->info.band_layer, P->info.band_volume);
+    C.gap = gap;
+    C.reach = band + gap;
     C.ox = H.xmin - 1e-9;
     C.oy = H.ymin - 1e-9;
+    // cells of half the reach (a target's list then spans 2.5 reaches), at
+    // most 2^22 of them
+    const double ext = std::max(H.xmax - C.ox, H.ymax - C.oy);
+    C.cell = std::max(0.5 * C.reach, ext / 2048.0);
     int64_t ncx = (int64_t)floor((H.xmax - C.ox) / C.cell) + 1;
     int64_t ncy = (int64_t)floor((H.ymax - C.oy) / C.cell) + 1;
-    if (ncx * ncy > (int64_t)1 << 26) {
-        set_error("local cell grid too large");
-        return MHK_EUNSUPPORTED;
-    }
     C.ncx = (int)ncx;
     C.ncy = (int)ncy;
-    std::vector<int64_t> key(nb);
-    for (int64_t i = 0; i < nb; ++i) {
-        int64_t ix = std::min<int64_t>(ncx - 1, (int64_t)floor((b->x[i] - C.ox) / C.cell));
-        int64_t iy = std::min<int64_t>(ncy - 1, (int64_t)floor((b->y[i] - C.oy) / C.cell));
-        key[i] = iy * ncx + ix;
+    std::vector<double> pbox(npan * 4);
+    for (int64_t p = 0; p < npan; ++p) {
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        for (int i = 0; i < NGL; ++i) {
+            x0 = std::min(x0, b->x[p * NGL + i]); x1 = std::max(x1, b->x[p * NGL + i]);
+            y0 = std::min(y0, b->y[p * NGL + i]); y1 = std::max(y1, b->y[p * NGL + i]);
+        }
+        pbox[p * 4 + 0] = x0; pbox[p * 4 + 1] = x1; pbox[p * 4 + 2] = y0; pbox[p * 4 + 3] = y1;
     }
-    std::vector<int32_t> order, start;
-    counting_sort(key, ncx * ncy, order, start);
+    {
+        // every (cell, panel) pair with box-to-box distance <= reach; the
+        // cells a panel can reach lie in its box grown by reach
+        std::vector<int32_t> start(ncx * ncy + 1, 0), cand;
+        std::vector<std::array<int64_t, 2>> pairs;   // cell, panel
+        auto cl = [&](double v, double o, int64_t nc) {
+            return std::min<int64_t>(nc - 1, std::max<int64_t>(0, (int64_t)floor((v - o) / C.cell)));
+        };
+        for (int64_t p = 0; p < npan; ++p) {
+            const double *bb = &pbox[p * 4];
+            for (int64_t iy = cl(bb[2] - C.reach, C.oy, ncy); iy <= cl(bb[3] + C.reach, C.oy, ncy); ++iy)
+                for (int64_t ix = cl(bb[0] - C.reach, C.ox, ncx); ix <= cl(bb[1] + C.reach, C.ox, ncx); ++ix) {
+                    const double cx0 = C.ox + ix * C.cell, cy0 = C.oy + iy * C.cell;
+                    const double ex = std::max(0.0, std::max(bb[0] - (cx0 + C.cell), cx0 - bb[1]));
+                    const double ey = std::max(0.0, std::max(bb[2] - (cy0 + C.cell), cy0 - bb[3]));
+                    if (ex * ex + ey * ey <= C.reach * C.reach) pairs.push_back({iy * ncx + ix, p});
+                }
+        }
+        if (pairs.size() > ((size_t)1 << 31)) {
+            set_error("closest-point cell lists too large");
+            return MHK_EUNSUPPORTED;
+        }
+        // per cell, panels in increasing distance of their box from the cell centre
+        auto dist_c = [&](int64_t c, int64_t p) {
+            const double xc = C.ox + ((c % ncx) + 0.5) * C.cell, yc = C.oy + ((c / ncx) + 0.5) * C.cell;
+            const double *bb = &pbox[p * 4];
+            const double ex = std::max(0.0, std::max(bb[0] - xc, xc - bb[1]));
+            const double ey = std::max(0.0, std::max(bb[2] - yc, yc - bb[3]));
+            return ex * ex + ey * ey;
+        };
+        std::sort(pairs.begin(), pairs.end(), [&](const std::array<int64_t, 2> &a, const std::array<int64_t, 2> &c) {
+            if (a[0] != c[0]) return a[0] < c[0];
+            const double da = dist_c(a[0], a[1]), dc = dist_c(c[0], c[1]);
+            return da != dc ? da < dc : a[1] < c[1];
+        });
+        cand.resize(std::max<size_t>(1, pairs.size()));
+        for (size_t k = 0; k < pairs.size(); ++k) {
+            start[pairs[k][0] + 1]++;
+            cand[k] = (int32_t)pairs[k][1];
+        }
+        for (int64_t c = 0; c < ncx * ncy; ++c) start[c + 1] += start[c];
+        TRY(upload(P, &C.cand, cand.data(), (int64_t)cand.size()));
+        TRY(upload(P, &C.cell_start, start.data(), (int64_t)start.size()));
+    }
+    TRY(upload(P, &C.pbox, pbox.data(), npan * 4));
+    {
+        int32_t zero = 0;
+        TRY(upload(P, &C.noconv, &zero, 1));
+    }
     std::vector<int32_t> prev(npan), next(npan);
     for (int64_t p = 0; p < npan; ++p) {
         prev[p] = (int32_t)H.prev[p];
         next[p] = (int32_t)H.next[p];
     }
-    TRY(upload(P, &C.node, order.data(), nb));
-    {
-        std::vector<double> sx(nb), sy(nb);
-        for (int64_t k = 0; k < nb; ++k) {
-            sx[k] = b->x[order[k]];
-            sy[k] = b->y[order[k]];
-        }
-        TRY(upload(P, &C.nx_s, sx.data(), nb));
-        TRY(upload(P, &C.ny_s, sy.data(), nb));
-    }
-    C.gap = gap;
-    TRY(upload(P, &C.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &C.leg, leg.data(), NGL * NGL));
     TRY(upload(P, &C.cx, cx.data(), nb));
     TRY(upload(P, &C.cy, cy.data(), nb));
@@ -1442,7 +1491,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j, tgx, tgy));
     TRY(build_history(P, H, tgx, tgy));
     TRY(build_local(P, H));
-    MHK_HIP(launch_local_geom(P));
+    MHK_HIP(launch_local_geom(P, P->stream));
     {
         char *a = nullptr;
         TRY(dalloc(P, &a, 3 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
@@ -1460,7 +1509,17 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     P->info.n_targets = P->nt;
     P->info.n_out = P->nout;
     P->info.device_bytes = P->bytes;
-    MHK_HIP(hipDeviceSynchronize());
+    // only the plan's own stream is waited for: work of other plans on other
+    // streams keeps running while a plan is created
+    MHK_HIP(hipStreamSynchronize(P->stream));
+    int32_t noconv = 0;
+    MHK_HIP(hipMemcpy(&noconv, P->loc.noconv, sizeof(noconv), hipMemcpyDeviceToHost));
+    P->info.n_noconv = noconv;
+    if (noconv > 0) {
+        set_error("closest-point Newton iteration did not converge for " + std::to_string(noconv) +
+                  " targets inside a local band");
+        return MHK_ENOCONV;
+    }
     return MHK_OK;
 }
 
@@ -1559,8 +1618,15 @@ mhk_status mhk_plan_info(const mhk_plan *P, mhk_info *info)
         set_error("plan or info is NULL");
         return MHK_EINVAL;
     }
-    TRY(collect_timing(const_cast<mhk_plan *>(P)));
-    *info = P->info;
+    mhk_plan *Q = const_cast<mhk_plan *>(P);
+    TRY(collect_timing(Q));
+    // closest-point solves that did not converge, counted on the device by
+    // the evaluations queued so far
+    MHK_HIP(hipStreamSynchronize(Q->stream));
+    int32_t noconv = 0;
+    MHK_HIP(hipMemcpy(&noconv, Q->loc.noconv, sizeof(noconv), hipMemcpyDeviceToHost));
+    Q->info.n_noconv = noconv;
+    *info = Q->info;
     return MHK_OK;
 }
 
@@ -1583,7 +1649,7 @@ mhk_status validate_eval(const mhk_plan *P, int parts, const void *sigma, const 
         set_error("plan is NULL");
         return MHK_EINVAL;
     }
-    if (parts < 0 || parts > MHK_PART_ALL) {
+    if (parts < 0 || parts > (MHK_PART_ALL | MHK_PART_GEOMETRY)) {
         set_error("invalid parts mask");
         return MHK_EINVAL;
     }
@@ -1610,11 +1676,12 @@ mhk_status collect_timing(mhk_plan *P)
 {
     if (!P->t_pending) return MHK_OK;
     P->t_pending = false;
-    const bool levels = P->t_levels;
+    const bool levels = P->t_levels, geom = P->t_geom;
     MHK_HIP(hipEventSynchronize(P->ev[7]));
-    float ms[8] = {0};
+    float ms[8] = {0}, mg = 0;
     for (int e = 1; e <= 5; ++e) MHK_HIP(hipEventElapsedTime(&ms[e], P->ev[e - 1], P->ev[e]));
-    if (levels) MHK_HIP(hipEventElapsedTime(&ms[6], P->ev[8], P->ev[6]));
+    if (geom) MHK_HIP(hipEventElapsedTime(&mg, P->ev[8], P->ev[9]));
+    if (levels) MHK_HIP(hipEventElapsedTime(&ms[6], geom ? P->ev[9] : P->ev[8], P->ev[6]));
     // the local part starts when both the history part and the levels are done
     float t5 = 0, t6 = 0, t7 = 0;
     MHK_HIP(hipEventElapsedTime(&t5, P->ev[0], P->ev[5]));
@@ -1627,6 +1694,7 @@ mhk_status collect_timing(mhk_plan *P)
     P->info.ms_interp = ms[5];
     P->info.ms_levels = ms[6];
     P->info.ms_local = ms[7];
+    P->info.ms_geometry = mg;
     P->info.ms_total = t7;
     return MHK_OK;
 }
@@ -1646,10 +1714,23 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     // two overlap (the level sums are bound by LDS and FP64 issue, the FFTs by
     // memory).  They write acc_lev; the local part adds it.
     const bool levels = (parts & MHK_PART_LEVELS) && (ws || wd) && P->J > 0;
+    // the local geometry (closest points, MHK_PART_GEOMETRY) depends on
+    // nothing but the plan: it goes first on the side stream, beside the
+    // history part, or on the plan's stream when there are no level sums
+    const bool geom = (parts & MHK_PART_GEOMETRY) && (parts & MHK_PART_LOCAL);
+    if (geom && !levels) {
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[8], st));
+        MHK_HIP(launch_local_geom(P, st));
+        if (P->timing) MHK_HIP(hipEventRecord(P->ev[9], st));
+    }
     if (levels) {
         MHK_HIP(hipEventRecord(P->fork_ev, st));
         MHK_HIP(hipStreamWaitEvent(P->side, P->fork_ev, 0));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[8], P->side));
+        if (geom) {
+            MHK_HIP(launch_local_geom(P, P->side));
+            if (P->timing) MHK_HIP(hipEventRecord(P->ev[9], P->side));
+        }
         for (int j = 1; j <= P->J; ++j) {
             MHK_HIP(launch_level_densities(P, P->side, j, ws ? sigma : nullptr, wd ? mu : nullptr));
             MHK_HIP(launch_level_sums(P, P->side, j, ws, wd, j == 1));
@@ -1697,6 +1778,7 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
         MHK_HIP(hipEventRecord(P->ev[7], st));
         P->t_pending = true;
         P->t_levels = levels;
+        P->t_geom = geom;
     }
     return MHK_OK;
 }
