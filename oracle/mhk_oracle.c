@@ -351,9 +351,14 @@ int or_refine_level(const or_problem *P, int j, double *x, double *y, double *nx
 /* ------------------------------------------------------------------------ */
 /* Closest boundary point (Section 3.2): nearest node by brute force (lowest
  * index on ties) selects a panel; the squared distance to that panel's
- * polynomial and to its two neighbours' is minimised over t in [-1,1]
- * (dense sampling, then Newton on d/dt |x - gamma(t)|^2 = 0), and the best
- * of the three is kept.                                                      */
+ * polynomial and to its two neighbours' is minimised over t in [-1,1] and
+ * the best of the three is kept.  On each panel the minimisation is
+ * Newton's method on d/dt |x - gamma(t)|^2 = 0, started from the nearest of
+ * the panel's two end points and 16 nodes, safeguarded as the reading of the
+ * paper's "Newton" that always ends at a local minimum: a step that does not
+ * decrease the distance is halved, and where the squared distance is not
+ * convex a fixed step of 1/4 downhill replaces the Newton step; it stops
+ * when a step is below 1e-15.                                                */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t panel; double t, x0, y0, r;
@@ -361,38 +366,51 @@ typedef struct {
     double txx, tyy;    /* gamma''(t)  */
 } or_cp;
 
-static void or_panel_min(const double *cx, const double *cy, double px, double py,
-                         double *tbest, double *d2best)
+static double or_d2(const double *cx, const double *cy, double t, double px, double py)
 {
-    double bt = -1.0, bd = INFINITY;
-    for (int i = 0; i <= 64; ++i) {
-        double t = -cos(OR_PI * i / 64.0), x, y;
-        or_eval_poly(cx, t, &x, NULL, NULL);
-        or_eval_poly(cy, t, &y, NULL, NULL);
-        double d = (x - px) * (x - px) + (y - py) * (y - py);
-        if (d < bd) { bd = d; bt = t; }
+    double x, y;
+    or_eval_poly(cx, t, &x, NULL, NULL);
+    or_eval_poly(cy, t, &y, NULL, NULL);
+    return (x - px) * (x - px) + (y - py) * (y - py);
+}
+
+/* returns 1 when the iteration converged */
+static int or_panel_min(const double *cx, const double *cy, const double *nx, const double *ny,
+                        double px, double py, double *tbest, double *d2best)
+{
+    /* start: the nearest of the end point -1, the nodes, the end point +1 */
+    double bt = -1.0, bd = or_d2(cx, cy, -1.0, px, py);
+    for (int i = 0; i < OR_NGL; ++i) {
+        double d = (nx[i] - px) * (nx[i] - px) + (ny[i] - py) * (ny[i] - py);
+        if (d < bd) { bd = d; bt = g_bx[i]; }
     }
-    double t = bt;
+    {
+        double d = or_d2(cx, cy, 1.0, px, py);
+        if (d < bd) { bd = d; bt = 1.0; }
+    }
+    double t = bt, phi = or_d2(cx, cy, t, px, py);
+    int conv = 0;
     for (int it = 0; it < 60; ++it) {
         double x, y, x1, y1, x2, y2;
         or_eval_poly(cx, t, &x, &x1, &x2);
         or_eval_poly(cy, t, &y, &y1, &y2);
         double g = (x - px) * x1 + (y - py) * y1;
-        double gp = x1 * x1 + y1 * y1 + (x - px) * x2 + (y - py) * y2;
-        if (!(gp > 0.0)) break;
-        double dt = g / gp, tn = t - dt;
-        if (tn > 1.0) tn = 1.0;
-        if (tn < -1.0) tn = -1.0;
-        double step = fabs(tn - t);
-        t = tn;
-        if (step < 1e-15) break;
+        double h = x1 * x1 + y1 * y1 + (x - px) * x2 + (y - py) * y2;
+        double step = h > 0.0 ? -g / h : (g > 0.0 ? -0.25 : 0.25);
+        double tn = fmin(1.0, fmax(-1.0, t + step)), dn = phi;
+        for (int k = 0; k <= 52; ++k) {
+            dn = or_d2(cx, cy, tn, px, py);
+            if (dn <= phi) break;
+            step *= 0.5;
+            tn = fmin(1.0, fmax(-1.0, t + step));
+        }
+        double moved = fabs(tn - t);
+        if (dn <= phi) { t = tn; phi = dn; }
+        if (moved < 1e-15) { conv = 1; break; }
     }
-    double x, y;
-    or_eval_poly(cx, t, &x, NULL, NULL);
-    or_eval_poly(cy, t, &y, NULL, NULL);
-    double d = (x - px) * (x - px) + (y - py) * (y - py);
-    if (d <= bd) { *tbest = t; *d2best = d; }
-    else { *tbest = bt; *d2best = bd; }
+    *tbest = t;
+    *d2best = phi;
+    return conv;
 }
 
 static void or_closest(const or_problem *P, double px, double py, or_cp *cp)
@@ -412,7 +430,7 @@ static void or_closest(const or_problem *P, double px, double py, or_cp *cp)
         double cx[OR_NGL], cy[OR_NGL], t, d2;
         or_coeffs(P->bx + p * OR_NGL, 1, cx);
         or_coeffs(P->by + p * OR_NGL, 1, cy);
-        or_panel_min(cx, cy, px, py, &t, &d2);
+        or_panel_min(cx, cy, P->bx + p * OR_NGL, P->by + p * OR_NGL, px, py, &t, &d2);
         if (d2 < dbest) {
             dbest = d2;
             cp->panel = p; cp->t = t;

@@ -150,14 +150,18 @@ struct LocalArgs {
     T *out_s, *out_d, *out_v;
 };
 
-// Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p; returns whether
-// the Newton iteration converged (a step below 1e-15, possibly clamped at an
-// end point) -- if not, the best node or end point is kept.
+// Minimise |x - gamma_p(t)|^2 over t in [-1, 1] on panel p by Newton's
+// method on d/dt, safeguarded: started from the nearest of the panel's nodes
+// and end points; a step that does not decrease the distance is halved
+// (bisection towards the current point), and where the distance is not
+// convex (beyond a centre of curvature) a fixed step of 1/4 downhill is
+// tried instead of the Newton step.  Returns whether the iteration
+// converged (a step below 1e-15, possibly held at an end point).
 template <typename T>
 __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
 {
     const double *cx = A.pcx + (size_t)p * NGL, *cy = A.pcy + (size_t)p * NGL;
-    // start: best of the 16 nodes and the two end points
+    // start: best of the two end points and the 16 nodes
     double ts = -1.0;
     double dx = A.ends[p * 4 + 0] - px, dy = A.ends[p * 4 + 1] - py;
     double ds = dx * dx + dy * dy;
@@ -170,27 +174,41 @@ __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double
     dx = A.ends[p * 4 + 2] - px;
     dy = A.ends[p * 4 + 3] - py;
     if (dx * dx + dy * dy < ds) { ds = dx * dx + dy * dy; ts = 1.0; }
-    double t = ts;
+    double t = ts, phi;
+    {
+        const double xv = leg1(cx, t) - px, yv = leg1(cy, t) - py;
+        phi = xv * xv + yv * yv;
+    }
     bool conv = false;
-    for (int it = 0; it < 40; ++it) {
+#pragma unroll 1
+    for (int it = 0; it < 60; ++it) {
         double x0, x1, x2, y0, y1, y2;
         leg2(cx, cy, t, x0, x1, x2, y0, y1, y2);
-        const double g = (x0 - px) * x1 + (y0 - py) * y1;
-        const double gp = x1 * x1 + y1 * y1 + (x0 - px) * x2 + (y0 - py) * y2;
-        if (!(gp > 0.0)) break;
-        double tn = t - g / gp;
-        tn = fmin(1.0, fmax(-1.0, tn));
-        const double step = fabs(tn - t);
-        t = tn;
-        if (step < 1e-15) {
+        const double ex = x0 - px, ey = y0 - py;
+        const double g = ex * x1 + ey * y1;
+        const double h = x1 * x1 + y1 * y1 + ex * x2 + ey * y2;
+        double step = h > 0.0 ? -g / h : (g > 0.0 ? -0.25 : 0.25);
+        double tn = fmin(1.0, fmax(-1.0, t + step)), dn = phi;
+#pragma unroll 1
+        for (int k = 0; k <= 52; ++k) {
+            const double xv = leg1(cx, tn) - px, yv = leg1(cy, tn) - py;
+            dn = xv * xv + yv * yv;
+            if (dn <= phi) break;
+            step *= 0.5;
+            tn = fmin(1.0, fmax(-1.0, t + step));
+        }
+        const double moved = fabs(tn - t);
+        if (dn <= phi) {
+            t = tn;
+            phi = dn;
+        }
+        if (moved < 1e-15) {
             conv = true;
             break;
         }
     }
-    const double xv = leg1(cx, t) - px, yv = leg1(cy, t) - py;
-    const double dn = xv * xv + yv * yv;
-    if (dn <= ds) { tbest = t; d2best = dn; }
-    else { tbest = ts; d2best = ds; }
+    tbest = t;
+    d2best = phi;
     return conv;
 }
 
