@@ -357,8 +357,9 @@ int or_refine_level(const or_problem *P, int j, double *x, double *y, double *nx
  * the panel's two end points and 16 nodes, safeguarded as the reading of the
  * paper's "Newton" that always ends at a local minimum: a step that does not
  * decrease the distance is halved, and where the squared distance is not
- * convex a fixed step of 1/4 downhill replaces the Newton step; it stops
- * when a step is below 1e-15.                                                */
+ * convex a fixed step of 1/4 downhill replaces the Newton step; Newton steps
+ * below 1e-6 where it is convex are taken as they are (the distance is flat
+ * below its rounding there); it stops when a step is below 1e-15.            */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t panel; double t, x0, y0, r;
@@ -397,7 +398,16 @@ static int or_panel_min(const double *cx, const double *cy, const double *nx, co
         double g = (x - px) * x1 + (y - py) * y1;
         double h = x1 * x1 + y1 * y1 + (x - px) * x2 + (y - py) * y2;
         double step = h > 0.0 ? -g / h : (g > 0.0 ? -0.25 : 0.25);
-        double tn = fmin(1.0, fmax(-1.0, t + step)), dn = phi;
+        double tn = fmin(1.0, fmax(-1.0, t + step));
+        if (h > 0.0 && fabs(step) < 1e-6) {
+            /* near a minimum the distance is flat below its rounding: plain
+               Newton steps, driven by the derivative */
+            double moved = fabs(tn - t);
+            t = tn;
+            if (moved < 1e-15) { conv = 1; break; }
+            continue;
+        }
+        double dn = phi;
         for (int k = 0; k <= 52; ++k) {
             dn = or_d2(cx, cy, tn, px, py);
             if (dn <= phi) break;
@@ -408,6 +418,7 @@ static int or_panel_min(const double *cx, const double *cy, const double *nx, co
         if (dn <= phi) { t = tn; phi = dn; }
         if (moved < 1e-15) { conv = 1; break; }
     }
+    phi = or_d2(cx, cy, t, px, py);
     *tbest = t;
     *d2best = phi;
     return conv;

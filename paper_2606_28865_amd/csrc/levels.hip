@@ -11,15 +11,19 @@
 // a >= a_max are below the requested accuracy and skipped.
 //
 // Work decomposition: a wavefront owns 64 consecutive targets of the Morton
-// order.  At plan time the cells (side R_j/4) that can hold a source within
-// R_j of one of its targets are turned into a short list of ranges of the
-// cell-sorted sources.  The wavefront reads its ranges and then, range by
-// range, 64 sources at a time with vector loads (lane l holds source l) and
-// hands each source to all lanes with readlane; each lane keeps its target's
-// sums in registers: no atomics, no barriers in the loop, deterministic
-// summation order.  The kernel table sits in LDS (shared by the wavefronts of
-// a workgroup) with a padded segment stride so that the per-lane gathers of
-// different segments spread over the LDS banks.
+// order, one per lane, and a flat list (built at plan time) of the sources
+// within R_j of its targets' bounding box.  It reads the list 64 sources at
+// a time with vector loads (lane l holds source l) -- the next batch is
+// loaded while the current one is summed -- and hands each source to all
+// lanes with readlane; each lane keeps its target's sums in registers: no
+// atomics, no barriers in the loop, deterministic summation order.  Sources
+// are taken two at a time with no branch per lane: a lane out of range of a
+// source reads the table's last segment, which is zero, and a pair of
+// sources out of range of every lane is skipped as a whole.  The two
+// polynomial evaluations are independent, so their table reads and
+// multiply-adds interleave.  The kernel table sits in LDS (shared by the
+// wavefronts of a workgroup) with a padded segment stride so that the
+// per-lane gathers of different segments spread over the LDS banks.
 //
 // Precision: T = double (FP64 path) or float (FP32 path).  In the FP32 path
 // the separation x - x_q is formed in FP64 from FP64 positions and rounded
@@ -81,7 +85,7 @@ struct LevelArgs {
     const double *tx, *ty;
     double inv4d, a_max, seg_inv, d_scale;
     int nseg, B;
-    const int32_t *blk_ofs, *blk_rng, *wave_order;
+    const int32_t *wave_ofs, *wave_src, *wave_order;
     const double *sx, *sy;
     const T *q, *tab;
     T *acc_s, *acc_d;     // [B][nout] each (sorted order)
@@ -106,117 +110,152 @@ __device__ inline float bcast(float v, int k)
 __device__ inline double frac_part(double x) { return __builtin_amdgcn_fract(x); }
 __device__ inline float frac_part(float x) { return __builtin_amdgcn_fractf(x); }
 
+// One batch of up to 64 sources held one per lane: positions and strengths.
+template <typename T, int BCH>
+struct SrcBatch {
+    double x, y;
+    T qs[BCH], qx[BCH], qy[BCH];
+};
+
+// Source k of a batch against the lane's target: separation, table segment
+// (the zero segment out of range), local variable.
+template <typename T>
+struct PairGeo {
+    T dx, dy, v;
+    const T *c;
+};
+
+template <typename T, int STRIDE>
+__device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv, T fscale, T f_max,
+                                      const T *s_tab, int zseg, bool &in)
+{
+    PairGeo<T> g;
+    g.dx = (T)(x - sxv);
+    g.dy = (T)(y - syv);
+    const T f = (g.dx * g.dx + g.dy * g.dy) * fscale;
+    in = f < f_max;
+    const int sg = in ? (int)f : zseg;
+    g.v = in ? (T)2 * frac_part(f) - (T)1 : (T)0;
+    g.c = s_tab + __umul24((unsigned)sg, (unsigned)STRIDE);
+    return g;
+}
+
 template <int BCH, typename T, int NC, int STRIDE>
 __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
     extern __shared__ double lds[];
-    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg][STRIDE]
+    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg + 1][STRIDE], the last segment zero
     const int tid = threadIdx.x;
-    for (int i = tid; i < A.nseg * STRIDE; i += LV_BLOCK) s_tab[i] = A.tab[i];
+    for (int i = tid; i < (A.nseg + 1) * STRIDE; i += LV_BLOCK) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
     __syncthreads();
 
-    // one wavefront = LV_TPW consecutive targets with their own source ranges
-    // (the wave number is wave-uniform); lane l holds targets l, l + 64, ...
+    const int lane = tid % LV_WAVE;
+    // one wavefront = LV_WAVE consecutive targets with their own source list
+    // (the wave number is wave-uniform)
     const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (LV_BLOCK / LV_WAVE) + tid / LV_WAVE]);
-    double x[LV_TPL], y[LV_TPL];
-    int64_t t[LV_TPL];
-#pragma unroll
-    for (int i = 0; i < LV_TPL; ++i) {
-        t[i] = (int64_t)wave * LV_TPW + i * LV_WAVE + (tid % LV_WAVE);
-        x[i] = y[i] = 0.0;
-        if (t[i] < A.nout) {
-            x[i] = A.tx[t[i]];
-            y[i] = A.ty[t[i]];
-        }
+    const int64_t t = (int64_t)wave * LV_WAVE + lane;
+    double x = 0.0, y = 0.0;
+    if (t < A.nout) {
+        x = A.tx[t];
+        y = A.ty[t];
     }
     const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
     // segment coordinate f = a seg_inv = r^2 inv4d seg_inv in one product
     const T fscale = (T)(A.inv4d * A.seg_inv), f_max = (T)(A.a_max * A.seg_inv);
-    T S[LV_TPL][BCH], D[LV_TPL][BCH];
+    const int zseg = A.nseg;
+    T S[BCH], D[BCH];
 #pragma unroll
-    for (int i = 0; i < LV_TPL; ++i)
-#pragma unroll
-        for (int b = 0; b < BCH; ++b) S[i][b] = D[i][b] = (T)0;
-    const T *qs[BCH], *qx[BCH], *qy[BCH];
-#pragma unroll
-    for (int b = 0; b < BCH; ++b) {
-        const int bb = b0 + min(b, nbh - 1);
-        qs[b] = A.q + ((size_t)0 * A.B + bb) * A.n_src;
-        qx[b] = A.q + ((size_t)1 * A.B + bb) * A.n_src;
-        qy[b] = A.q + ((size_t)2 * A.B + bb) * A.n_src;
-    }
-
-    // source k of the lanes' batch against the lane's targets; the source's
-    // strengths are handed over only where some lane is in range
-    auto pair = [&](int k, double sxv, double syv, const T *lqs, const T *lqx, const T *lqy) {
-#pragma unroll
-        for (int i = 0; i < LV_TPL; ++i) {
-            const T dx = (T)(x[i] - sxv), dy = (T)(y[i] - syv);
-            const T f = (dx * dx + dy * dy) * fscale;
-            if (f < f_max) {
-                const int sg = (int)f;
-                const T v = (T)2 * frac_part(f) - (T)1;
-                const T *c = s_tab + __umul24((unsigned)sg, (unsigned)STRIDE);
-                // p(v) and p'(v) by Horner's rule (K_j^S and, up to the
-                // factor d_scale, K_j^D); the derivative's first step is c_7
-                T kd = c[NC - 1];
-                T ks = fma(kd, v, c[NC - 2]);
-#pragma unroll
-                for (int m = NC - 3; m >= 0; --m) {
-                    kd = fma(kd, v, ks);
-                    ks = fma(ks, v, c[m]);
-                }
-#pragma unroll
-                for (int b = 0; b < BCH; ++b) {
-                    const T qsv = bcast(lqs[b], k), qxv = bcast(lqx[b], k), qyv = bcast(lqy[b], k);
-                    S[i][b] = fma(qsv, ks, S[i][b]);
-                    D[i][b] = fma(fma(qxv, dx, qyv * dy), kd, D[i][b]);
-                }
-            }
-        }
-    };
-    // The wave's ranges and, per range, its sources 64 at a time are read
-    // with vector loads, lane l holding item l, and handed to the whole wave
-    // one by one with readlane: no scalar loads are in flight in the loop,
-    // so the waits for the kernel-table reads from LDS (which share their
-    // counter with scalar loads) never wait for source data.
-    const int lane = tid % LV_WAVE;
-    const int r0 = A.blk_ofs[wave], r1 = A.blk_ofs[wave + 1];
-    for (int rb = r0; rb < r1; rb += LV_WAVE) {
-        int my_s0 = 0, my_s1 = 0;
-        if (rb + lane < r1) {
-            my_s0 = A.blk_rng[2 * (rb + lane)];
-            my_s1 = A.blk_rng[2 * (rb + lane) + 1];
-        }
-        const int rcnt = min(LV_WAVE, r1 - rb);
-        for (int ri = 0; ri < rcnt; ++ri) {
-            const int s0 = __builtin_amdgcn_readlane(my_s0, ri), s1 = __builtin_amdgcn_readlane(my_s1, ri);
-            for (int base = s0; base < s1; base += LV_WAVE) {
-                const int sl = min(base + lane, s1 - 1);
-                const double lx = A.sx[sl], ly = A.sy[sl];
-                T lqs[BCH], lqx[BCH], lqy[BCH];
-#pragma unroll
-                for (int b = 0; b < BCH; ++b) {
-                    lqs[b] = A.want_s ? qs[b][sl] : (T)0;
-                    lqx[b] = A.want_d ? qx[b][sl] : (T)0;
-                    lqy[b] = A.want_d ? qy[b][sl] : (T)0;
-                }
-                const int cnt = __builtin_amdgcn_readfirstlane(min(LV_WAVE, s1 - base));   // wave-uniform: scalar loop test
-                for (int k = 0; k < cnt; ++k) pair(k, bcast(lx, k), bcast(ly, k), lqs, lqx, lqy);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < LV_TPL; ++i) {
-        if (t[i] < A.nout) {
+    for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
+    // strengths of density b0 + b: q[c][b0 + b][s] for c = S, D_x, D_y
+    const size_t fstride = (size_t)A.B * A.n_src;
+    const T *q0 = A.q + (size_t)b0 * A.n_src;
+    // lane l of a batch holds source l of the list; lanes past its end hold a
+    // far-away source of zero strength
+    auto load = [&](int pos, int end, SrcBatch<T, BCH> &sb) {
+        if (pos < end) {
+            const int s = A.wave_src[pos];
+            sb.x = A.sx[s];
+            sb.y = A.sy[s];
 #pragma unroll
             for (int b = 0; b < BCH; ++b) {
-                if (b < nbh) {
-                    const size_t o = (size_t)(b0 + b) * A.nout + t[i];
-                    const T s = S[i][b], d = D[i][b] * (T)A.d_scale;
-                    if (A.want_s) A.acc_s[o] = A.init ? s : A.acc_s[o] + s;
-                    if (A.want_d) A.acc_d[o] = A.init ? d : A.acc_d[o] + d;
+                const T *qb = q0 + (size_t)min(b, nbh - 1) * A.n_src + s;
+                sb.qs[b] = A.want_s ? qb[0] : (T)0;
+                sb.qx[b] = A.want_d ? qb[fstride] : (T)0;
+                sb.qy[b] = A.want_d ? qb[2 * fstride] : (T)0;
+            }
+        } else {
+            sb.x = sb.y = 1e30;
+#pragma unroll
+            for (int b = 0; b < BCH; ++b) sb.qs[b] = sb.qx[b] = sb.qy[b] = (T)0;
+        }
+    };
+    auto accumulate = [&](const SrcBatch<T, BCH> &sb, int k, const PairGeo<T> &g, T ks, T kd) {
+#pragma unroll
+        for (int b = 0; b < BCH; ++b) {
+            const T qsv = bcast(sb.qs[b], k), qxv = bcast(sb.qx[b], k), qyv = bcast(sb.qy[b], k);
+            S[b] = fma(qsv, ks, S[b]);
+            D[b] = fma(fma(qxv, g.dx, qyv * g.dy), kd, D[b]);
+        }
+    };
+    const int c0 = A.wave_ofs[wave], c1 = A.wave_ofs[wave + 1];
+    SrcBatch<T, BCH> cur, nxt;
+    load(c0 + lane, c1, cur);
+    for (int base = c0; base < c1; base += LV_WAVE) {
+        load(base + LV_WAVE + lane, c1, nxt);            // next batch in flight while this one is summed
+        const int cnt = __builtin_amdgcn_readfirstlane(min(LV_WAVE, c1 - base));
+        if (BCH == 1) {
+            for (int k = 0; k < cnt; k += 2) {
+                // sources k and k + 1 (past the batch's end: a lane holding
+                // the far-away source of zero strength)
+                bool in0, in1;
+                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
+                                                          s_tab, zseg, in0);
+                const PairGeo<T> g1 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k + 1), bcast(cur.y, k + 1), fscale,
+                                                          f_max, s_tab, zseg, in1);
+                if (__ballot(in0 || in1) == 0) continue;
+                // p(v) and p'(v) by Horner's rule for both sources (K_j^S
+                // and, up to the factor d_scale, K_j^D); the derivative's
+                // first step is c_7
+                T kd0 = g0.c[NC - 1], kd1 = g1.c[NC - 1];
+                T ks0 = fma(kd0, g0.v, g0.c[NC - 2]), ks1 = fma(kd1, g1.v, g1.c[NC - 2]);
+#pragma unroll
+                for (int m = NC - 3; m >= 0; --m) {
+                    kd0 = fma(kd0, g0.v, ks0);
+                    kd1 = fma(kd1, g1.v, ks1);
+                    ks0 = fma(ks0, g0.v, g0.c[m]);
+                    ks1 = fma(ks1, g1.v, g1.c[m]);
                 }
+                accumulate(cur, k, g0, ks0, kd0);
+                accumulate(cur, k + 1, g1, ks1, kd1);
+            }
+        } else {
+            // several densities: the strengths of one source already fill
+            // the registers, so one source at a time
+            for (int k = 0; k < cnt; ++k) {
+                bool in0;
+                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
+                                                          s_tab, zseg, in0);
+                if (__ballot(in0) == 0) continue;
+                T kd0 = g0.c[NC - 1];
+                T ks0 = fma(kd0, g0.v, g0.c[NC - 2]);
+#pragma unroll
+                for (int m = NC - 3; m >= 0; --m) {
+                    kd0 = fma(kd0, g0.v, ks0);
+                    ks0 = fma(ks0, g0.v, g0.c[m]);
+                }
+                accumulate(cur, k, g0, ks0, kd0);
+            }
+        }
+        cur = nxt;
+    }
+    if (t < A.nout) {
+#pragma unroll
+        for (int b = 0; b < BCH; ++b) {
+            if (b < nbh) {
+                const size_t o = (size_t)(b0 + b) * A.nout + t;
+                const T s = S[b], d = D[b] * (T)A.d_scale;
+                if (A.want_s) A.acc_s[o] = A.init ? s : A.acc_s[o] + s;
+                if (A.want_d) A.acc_d[o] = A.init ? d : A.acc_d[o] + d;
             }
         }
     }
@@ -254,8 +293,8 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     A.d_scale = level_d_scale(L);
     A.nseg = L.nseg;
     A.B = B;
-    A.blk_ofs = L.blk_ofs;
-    A.blk_rng = L.blk_rng;
+    A.wave_ofs = L.wave_ofs;
+    A.wave_src = L.wave_src;
     A.wave_order = L.wave_order;
     A.sx = L.sx;
     A.sy = L.sy;
@@ -267,8 +306,8 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     A.want_d = want_d;
     A.init = init;
     const int bch = B == 1 ? 1 : LV_BCH;
-    dim3 grid((unsigned)((P->nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)), (unsigned)((B + bch - 1) / bch));
-    const size_t lds = sizeof(T) * (size_t)L.nseg * STRIDE;
+    dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK), (unsigned)((B + bch - 1) / bch));
+    const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (bch == 1) {
         if (lds > 64 * 1024)

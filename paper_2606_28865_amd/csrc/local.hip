@@ -155,7 +155,9 @@ struct LocalArgs {
 // and end points; a step that does not decrease the distance is halved
 // (bisection towards the current point), and where the distance is not
 // convex (beyond a centre of curvature) a fixed step of 1/4 downhill is
-// tried instead of the Newton step.  Returns whether the iteration
+// tried instead of the Newton step; Newton steps below 1e-6 where the
+// distance is convex are taken as they are (there the distance is flat below
+// its rounding, and the derivative decides).  Returns whether the iteration
 // converged (a step below 1e-15, possibly held at an end point).
 template <typename T>
 __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
@@ -188,7 +190,19 @@ __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double
         const double g = ex * x1 + ey * y1;
         const double h = x1 * x1 + y1 * y1 + ex * x2 + ey * y2;
         double step = h > 0.0 ? -g / h : (g > 0.0 ? -0.25 : 0.25);
-        double tn = fmin(1.0, fmax(-1.0, t + step)), dn = phi;
+        double tn = fmin(1.0, fmax(-1.0, t + step));
+        if (h > 0.0 && fabs(step) < 1e-6) {
+            // close to a minimum the distance is flat below its rounding:
+            // plain Newton steps, driven by the derivative
+            const double moved = fabs(tn - t);
+            t = tn;
+            if (moved < 1e-15) {
+                conv = true;
+                break;
+            }
+            continue;
+        }
+        double dn = phi;
 #pragma unroll 1
         for (int k = 0; k <= 52; ++k) {
             const double xv = leg1(cx, tn) - px, yv = leg1(cy, tn) - py;
@@ -206,6 +220,10 @@ __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double
             conv = true;
             break;
         }
+    }
+    {
+        const double xv = leg1(cx, t) - px, yv = leg1(cy, t) - py;
+        phi = xv * xv + yv * yv;
     }
     tbest = t;
     d2best = phi;

@@ -41,8 +41,6 @@ constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
 constexpr int LV_WAVE = 64;      // lanes per level-sum wavefront
-constexpr int LV_TPL = 1;        // targets per lane of the level sums
-constexpr int LV_TPW = LV_WAVE * LV_TPL;   // targets per wavefront (one source range list each)
 constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
 
 void set_error(const std::string &msg);
@@ -68,12 +66,13 @@ struct Level {
     double *sw = nullptr;                         // w
     int32_t *code = nullptr;                      // (panel * nchild + child) * 16 + node
     int32_t *cell_start = nullptr;                // [ncx*ncy + 1]
-    // per block of LV_BLOCK sorted targets: ranges of sorted sources covering
-    // the union of the targets' cell neighbourhoods
-    int32_t *blk_ofs = nullptr;                   // [n_blocks + 1]
+    // per wavefront of LV_WAVE sorted targets: the sorted sources within R_j
+    // of the wavefront's target bounding box, as one flat list of indices
+    // (wave_src[wave_ofs[w] .. wave_ofs[w + 1]))
+    int32_t *wave_ofs = nullptr;                  // [n_waves + 1]
     int32_t *wave_order = nullptr;                // wavefronts in decreasing order of candidate work
-    int32_t *blk_rng = nullptr;                   // [n_ranges][2]
-    int64_t n_ranges = 0;
+    int32_t *wave_src = nullptr;                  // [n_cand]
+    int64_t n_cand = 0;
     double *interp = nullptr;                     // [nchild][16][16] parent -> child values
     double *tab = nullptr;                        // [nseg][TAB_STRIDE]: K_j^S per segment (K_j^D from its derivative)
     float *tabf = nullptr;                        // FP32 path: [nseg][TABF_STRIDE]

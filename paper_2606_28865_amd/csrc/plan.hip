@@ -565,16 +565,18 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     TRY(upload(P, &L.code, code.data(), L.n_src));
     TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
     TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
-    // per wavefront of LV_TPW targets: for every cell row, the cells that
-    // can hold a source within R_j of one of the wave's targets (row gap g to
-    // the target, half-width sqrt(R_j^2 - g^2) in x), merged into row
-    // intervals and mapped to ranges of sorted sources (waves past the last
-    // target get no ranges)
+    // per wavefront of LV_WAVE targets: the sources within R_j of the
+    // wavefront's target bounding box.  Candidates come from the cells (side
+    // R_j / LV_CDIV) that can hold a source within R_j of one of its targets
+    // (per cell row, the row gap g to the target and half-width
+    // sqrt(R_j^2 - g^2) in x), read in sorted order and kept if within R_j of
+    // the box; no target of the wavefront is in range of a source that is
+    // not listed.  Wavefronts past the last target get empty lists.
     {
         const int64_t nout = (int64_t)tgx.size();
-        const int64_t nblk = ((nout + LV_BLOCK * LV_TPL - 1) / (LV_BLOCK * LV_TPL)) * (LV_BLOCK / LV_WAVE);
-        const double R = L.radius;
-        std::vector<int32_t> bofs(nblk + 1, 0), rng;
+        const int64_t nwave = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
+        const double R = L.radius, R2 = R * R * (1.0 + 1e-9);
+        std::vector<int32_t> wofs(nwave + 1, 0), src;
         std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
         auto col = [&](double x) {
             return std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((x - L.ox) / L.cell)));
@@ -582,10 +584,14 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
         auto row = [&](double y) {
             return std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((y - L.oy) / L.cell)));
         };
-        for (int64_t b = 0; b < nblk; ++b) {
+        for (int64_t b = 0; b < nwave; ++b) {
             iv.clear();
-            for (int64_t t = b * LV_TPW; t < std::min(nout, (b + 1) * LV_TPW); ++t) {
+            const int64_t t0 = b * LV_WAVE, t1 = std::min(nout, (b + 1) * LV_WAVE);
+            double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
+            for (int64_t t = t0; t < t1; ++t) {
                 const double tx = tgx[t], ty = tgy[t];
+                bx0 = std::min(bx0, tx); bx1 = std::max(bx1, tx);
+                by0 = std::min(by0, ty); by1 = std::max(by1, ty);
                 for (int64_t r = row(ty - R); r <= row(ty + R); ++r) {
                     const double ylo = L.oy + r * L.cell, yhi = ylo + L.cell;
                     const double g = std::max(0.0, std::max(ylo - ty, ty - yhi));
@@ -595,7 +601,6 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
                 }
             }
             std::sort(iv.begin(), iv.end());
-            int64_t last_end = -1;
             for (size_t i = 0; i < iv.size();) {
                 int64_t r = iv[i][0], x0 = iv[i][1], x1 = iv[i][2];
                 size_t k = i + 1;
@@ -603,36 +608,29 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
                     x1 = std::max(x1, iv[k][2]);
                     ++k;
                 }
-                int32_t s0 = start[r * ncx + x0], s1 = start[r * ncx + x1 + 1];
-                if (s1 > s0) {
-                    if ((int64_t)s0 == last_end && !rng.empty()) {
-                        rng.back() = s1;           // contiguous with the previous range
-                    } else {
-                        rng.push_back(s0);
-                        rng.push_back(s1);
-                    }
-                    last_end = s1;
+                for (int32_t s = start[r * ncx + x0]; s < start[r * ncx + x1 + 1]; ++s) {
+                    const double ex = std::max(0.0, std::max(bx0 - sx[s], sx[s] - bx1));
+                    const double ey = std::max(0.0, std::max(by0 - sy[s], sy[s] - by1));
+                    if (ex * ex + ey * ey <= R2) src.push_back(s);
                 }
                 i = k;
             }
-            bofs[b + 1] = (int32_t)(rng.size() / 2);
+            if (src.size() > (size_t)INT32_MAX) {
+                set_error("level candidate lists too large");
+                return MHK_EUNSUPPORTED;
+            }
+            wofs[b + 1] = (int32_t)src.size();
         }
-        L.n_ranges = (int64_t)rng.size() / 2;
-        // schedule the wavefronts heaviest first (candidate sources x targets),
-        // so that the long ones start early and each workgroup holds four
-        // wavefronts of similar work
-        std::vector<int64_t> work(nblk, 0);
-        for (int64_t b = 0; b < nblk; ++b) {
-            int64_t nt_w = std::max<int64_t>(0, std::min(nout, (b + 1) * LV_TPW) - b * LV_TPW);
-            for (int32_t r = bofs[b]; r < bofs[b + 1]; ++r) work[b] += (int64_t)(rng[2 * r + 1] - rng[2 * r]);
-            work[b] *= (nt_w > 0 ? 1 : 0);
-        }
-        std::vector<int32_t> worder(nblk);
+        L.n_cand = (int64_t)src.size();
+        // schedule the wavefronts heaviest first, so that the long ones start
+        // early and each workgroup holds wavefronts of similar work
+        std::vector<int32_t> worder(nwave);
         std::iota(worder.begin(), worder.end(), 0);
-        std::stable_sort(worder.begin(), worder.end(), [&](int32_t a, int32_t c) { return work[a] > work[c]; });
-        TRY(upload(P, &L.wave_order, worder.data(), nblk));
-        TRY(upload(P, &L.blk_ofs, bofs.data(), nblk + 1));
-        TRY(upload(P, &L.blk_rng, rng.data(), std::max<int64_t>(2, (int64_t)rng.size())));
+        std::stable_sort(worder.begin(), worder.end(),
+                         [&](int32_t a, int32_t c) { return wofs[a + 1] - wofs[a] > wofs[c + 1] - wofs[c]; });
+        TRY(upload(P, &L.wave_order, worder.data(), nwave));
+        TRY(upload(P, &L.wave_ofs, wofs.data(), nwave + 1));
+        TRY(upload(P, &L.wave_src, src.data(), std::max<int64_t>(1, (int64_t)src.size())));
     }
     {
         char *q = nullptr;
