@@ -268,6 +268,22 @@ __global__ void __launch_bounds__(BT) k_rhs(int64_t n, int64_t off, double a, co
 
 static inline unsigned nb_of(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
 
+// GMRES workspace: device vectors and the host mirror of the small ones.
+struct GmresWs {
+    int nblk = 0;               // blocks of the two-stage dot products
+    double *V = nullptr;        // [m + 1][n] Krylov basis
+    double *wv = nullptr;       // [n]
+    double *rv = nullptr;       // [n] residual / right-hand side
+    double *part = nullptr;     // [(m + 1) nblk] partial sums
+    double *hd = nullptr;       // [2 (m + 1) + 1] h (two passes) and |w|^2
+    double *yd = nullptr;       // [m] least-squares solution
+    double *hh = nullptr;       // host, [2 (m + 1) + 1 + m]: mirror of hd, then y
+    // host arrays of the least-squares problem: H [(m + 1) m], cs, sn, yv [m], g [m + 1]
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *yv = nullptr;
+};
+
+static inline int gmres_nblk(int64_t n) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + BT - 1) / BT)); }
+
 static mhk_status nys_alloc(double **p, int64_t count)
 {
     *p = nullptr;
@@ -296,7 +312,7 @@ static mhk_status nys_workspace(mhk_nystrom *N, int m)
 {
     if (m <= N->m_cap) return MHK_OK;
     nys_free_ws(N);
-    N->nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (N->n + BT - 1) / BT));
+    N->nblk = gmres_nblk(N->n);
     BIE_TRY(nys_alloc(&N->V, (int64_t)(m + 1) * N->n));
     BIE_TRY(nys_alloc(&N->wv, N->n));
     BIE_TRY(nys_alloc(&N->rv, N->n));
@@ -311,6 +327,27 @@ static mhk_status nys_workspace(mhk_nystrom *N, int m)
     }
     N->m_cap = m;
     N->ws_bytes = (int64_t)sizeof(double) * ((int64_t)(m + 3) * N->n + (int64_t)(m + 1) * N->nblk + 3 * (m + 1));
+    return MHK_OK;
+}
+
+// The object's own workspace as a GmresWs, with host arrays for restart m.
+struct OwnWs {
+    GmresWs W;
+    std::vector<double> H, cs, sn, g, yv;
+};
+
+static mhk_status own_workspace(mhk_nystrom *N, int m, OwnWs &o)
+{
+    BIE_TRY(nys_workspace(N, m));
+    o.H.assign((size_t)(m + 1) * m, 0.0);
+    o.cs.assign(m, 0.0);
+    o.sn.assign(m, 0.0);
+    o.g.assign(m + 1, 0.0);
+    o.yv.assign(m, 0.0);
+    GmresWs &W = o.W;
+    W.nblk = N->nblk;
+    W.V = N->V; W.wv = N->wv; W.rv = N->rv; W.part = N->part; W.hd = N->hd; W.yd = N->yd; W.hh = N->hh;
+    W.H = o.H.data(); W.cs = o.cs.data(); W.sn = o.sn.data(); W.g = o.g.data(); W.yv = o.yv.data();
     return MHK_OK;
 }
 
@@ -333,12 +370,12 @@ static hipError_t gemv(const mhk_nystrom *N, double shift, const double *x, doub
 }
 
 // out[0..count) = dot products of V_0..V_{count-1} with w (device result)
-static hipError_t dots(const mhk_nystrom *N, const double *V, int count, const double *w, double *out,
-                       hipStream_t st)
+static hipError_t dots(const mhk_nystrom *N, const GmresWs &W, const double *V, int count, const double *w,
+                       double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_dots, dim3((unsigned)N->nblk, (unsigned)count), dim3(BT), 0, st, N->n, V, w, N->nblk,
-                       N->part);
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)count), dim3(BT), 0, st, N->part, N->nblk, out);
+    hipLaunchKernelGGL(k_dots, dim3((unsigned)W.nblk, (unsigned)count), dim3(BT), 0, st, N->n, V, w, W.nblk,
+                       W.part);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)count), dim3(BT), 0, st, W.part, W.nblk, out);
     return hipGetLastError();
 }
 
@@ -354,15 +391,14 @@ static mhk_status fetch(mhk_nystrom *N, const double *d, int count, double *h, h
 // Gram-Schmidt with one re-orthogonalisation on the device, Givens rotations
 // of the small Hessenberg matrix on the host.  Converged when the true
 // residual |b - A x| <= tol |b| at the end of a cycle.
-static mhk_status gmres(mhk_nystrom *N, double shift, const double *b, double *x, double tol, int m, int maxit,
-                        hipStream_t st, mhk_solve_info *info)
+static mhk_status gmres(mhk_nystrom *N, const GmresWs &W, double shift, const double *b, double *x, double tol,
+                        int m, int maxit, hipStream_t st, mhk_solve_info *info)
 {
     const int64_t n = N->n;
-    BIE_TRY(nys_workspace(N, m));
-    double *hh = N->hh, *h1 = N->hd, *h2 = N->hd + (m + 1), *nrm = N->hd + 2 * (m + 1);
+    double *hh = W.hh, *h1 = W.hd, *h2 = W.hd + (m + 1), *nrm = W.hd + 2 * (m + 1);
     hipLaunchKernelGGL(k_fill, dim3(nb_of(n)), dim3(BT), 0, st, n, 0.0, x);
     BIE_HIP(hipGetLastError());
-    BIE_HIP(dots(N, b, 1, b, nrm, st));
+    BIE_HIP(dots(N, W, b, 1, b, nrm, st));
     double bn2;
     BIE_TRY(fetch(N, nrm, 1, &bn2, st));
     const double bnorm = sqrt(bn2);
@@ -374,21 +410,21 @@ static mhk_status gmres(mhk_nystrom *N, double shift, const double *b, double *x
         set_error("right-hand side is not finite");
         return MHK_EINVAL;
     }
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
+    double *H = W.H, *cs = W.cs, *sn = W.sn, *g = W.g, *yv = W.yv;
     int total = 0;
     bool first = true;
     for (;;) {
         // r = b - A x
         if (first) {
-            BIE_HIP(hipMemcpyAsync(N->rv, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            BIE_HIP(hipMemcpyAsync(W.rv, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         } else {
-            BIE_HIP(gemv(N, shift, x, N->wv, st));
-            hipLaunchKernelGGL(k_axpby, dim3(nb_of(n)), dim3(BT), 0, st, n, 1.0, b, -1.0, (const double *)N->wv,
-                               N->rv);
+            BIE_HIP(gemv(N, shift, x, W.wv, st));
+            hipLaunchKernelGGL(k_axpby, dim3(nb_of(n)), dim3(BT), 0, st, n, 1.0, b, -1.0, (const double *)W.wv,
+                               W.rv);
             BIE_HIP(hipGetLastError());
         }
         first = false;
-        BIE_HIP(dots(N, N->rv, 1, N->rv, nrm, st));
+        BIE_HIP(dots(N, W, W.rv, 1, W.rv, nrm, st));
         double r2;
         BIE_TRY(fetch(N, nrm, 1, &r2, st));
         const double beta = sqrt(r2);
@@ -405,26 +441,26 @@ static mhk_status gmres(mhk_nystrom *N, double shift, const double *b, double *x
             info->converged = 0;
             break;
         }
-        hipLaunchKernelGGL(k_normalize, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)N->rv,
-                           (const double *)nrm, N->V);
+        hipLaunchKernelGGL(k_normalize, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)W.rv,
+                           (const double *)nrm, W.V);
         BIE_HIP(hipGetLastError());
-        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(g, g + m + 1, 0.0);
         g[0] = beta;
         int jend = 0;
         for (int j = 0; j < m; ++j) {
-            const double *vj = N->V + (int64_t)j * n;
-            BIE_HIP(gemv(N, shift, vj, N->wv, st));
-            BIE_HIP(dots(N, N->V, j + 1, N->wv, h1, st));
-            hipLaunchKernelGGL(k_orth, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)N->V, j + 1,
-                               (const double *)h1, N->wv);
-            BIE_HIP(dots(N, N->V, j + 1, N->wv, h2, st));
-            hipLaunchKernelGGL(k_orth, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)N->V, j + 1,
-                               (const double *)h2, N->wv);
-            BIE_HIP(dots(N, N->wv, 1, N->wv, nrm, st));
-            hipLaunchKernelGGL(k_normalize, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)N->wv,
-                               (const double *)nrm, N->V + (int64_t)(j + 1) * n);
+            const double *vj = W.V + (int64_t)j * n;
+            BIE_HIP(gemv(N, shift, vj, W.wv, st));
+            BIE_HIP(dots(N, W, W.V, j + 1, W.wv, h1, st));
+            hipLaunchKernelGGL(k_orth, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)W.V, j + 1,
+                               (const double *)h1, W.wv);
+            BIE_HIP(dots(N, W, W.V, j + 1, W.wv, h2, st));
+            hipLaunchKernelGGL(k_orth, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)W.V, j + 1,
+                               (const double *)h2, W.wv);
+            BIE_HIP(dots(N, W, W.wv, 1, W.wv, nrm, st));
+            hipLaunchKernelGGL(k_normalize, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)W.wv,
+                               (const double *)nrm, W.V + (int64_t)(j + 1) * n);
             BIE_HIP(hipGetLastError());
-            BIE_TRY(fetch(N, N->hd, 2 * (m + 1) + 1, hh, st));
+            BIE_TRY(fetch(N, W.hd, 2 * (m + 1) + 1, hh, st));
             double *col = &H[(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 1) + i];
             const double hn = sqrt(std::max(0.0, hh[2 * (m + 1)]));
@@ -454,9 +490,9 @@ static mhk_status gmres(mhk_nystrom *N, double shift, const double *b, double *x
         }
         double *yh = hh + 2 * (m + 1) + 1;
         for (int i = 0; i < jend; ++i) yh[i] = yv[i];
-        BIE_HIP(hipMemcpyAsync(N->yd, yh, sizeof(double) * jend, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_combine, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)N->V, jend,
-                           (const double *)N->yd, x);
+        BIE_HIP(hipMemcpyAsync(W.yd, yh, sizeof(double) * jend, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_combine, dim3(nb_of(n)), dim3(BT), 0, st, n, (const double *)W.V, jend,
+                           (const double *)W.yd, x);
         BIE_HIP(hipGetLastError());
         // the pinned buffer is reused by the next fetch: wait for the copy
         BIE_HIP(hipStreamSynchronize(st));
@@ -601,11 +637,13 @@ mhk_status mhk_nystrom_solve(mhk_nystrom *N, double shift, const double *rhs, do
         return MHK_EINVAL;
     }
     memset(info, 0, sizeof(*info));
+    OwnWs o;
+    BIE_TRY(own_workspace(N, restart, o));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BIE_HIP(hipEventCreate(&e0));
     BIE_HIP(hipEventCreate(&e1));
     BIE_HIP(hipEventRecord(e0, N->stream));
-    mhk_status st = gmres(N, shift, rhs, x, tol, restart, maxit, N->stream, info);
+    mhk_status st = gmres(N, o.W, shift, rhs, x, tol, restart, maxit, N->stream, info);
     if (st == MHK_OK) {
         BIE_HIP(hipEventRecord(e1, N->stream));
         BIE_HIP(hipEventSynchronize(e1));
@@ -632,7 +670,8 @@ static mhk_status solve_common(mhk_plan *P, mhk_nystrom *N, int neumann, const d
     hipStream_t st = P->stream;
     const int64_t nt = P->nt, nb = P->nb, nout = P->nout;
     BIE_TRY(nys_scratch(N, nout));
-    BIE_TRY(nys_workspace(N, restart));
+    OwnWs o;
+    BIE_TRY(own_workspace(N, restart, o));
     double *w1 = N->work, *w2 = N->work + N->work_n;
     hipEvent_t ev[4] = {};
     for (auto &e : ev) BIE_HIP(hipEventCreate(&e));
@@ -651,7 +690,7 @@ static mhk_status solve_common(mhk_plan *P, mhk_nystrom *N, int neumann, const d
             if (rc != MHK_OK) break;
             if (!f_vol) hipLaunchKernelGGL(k_fill, dim3(nb_of(nout)), dim3(BT), 0, st, nout, 0.0, u);
             hipLaunchKernelGGL(k_rhs, dim3(nb_of(nb)), dim3(BT), 0, st, nb, nt, 1.0, (const double *)u, 1.0,
-                               (const double *)w1, N->rv);
+                               (const double *)w1, o.W.rv);
         } else {
             if (f_vol) {
                 rc = mhk_eval_parts(P, MHK_PART_ALL, nullptr, nullptr, f_vol, f_trg, nullptr, nullptr, u);
@@ -660,14 +699,14 @@ static mhk_status solve_common(mhk_plan *P, mhk_nystrom *N, int neumann, const d
                 hipLaunchKernelGGL(k_fill, dim3(nb_of(nout)), dim3(BT), 0, st, nout, 0.0, u);
             }
             hipLaunchKernelGGL(k_rhs, dim3(nb_of(nb)), dim3(BT), 0, st, nb, (int64_t)0, 1.0, g, -1.0,
-                               (const double *)(u + nt), N->rv);
+                               (const double *)(u + nt), o.W.rv);
         }
         SOLVE_HIP(hipGetLastError());
         SOLVE_HIP(hipEventRecord(ev[1], st));
-        // GMRES on (-/+ 1/2 I + K); the right-hand side lives in N->rv, which
-        // GMRES overwrites, so it is first copied to w2
-        SOLVE_HIP(hipMemcpyAsync(w2, N->rv, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
-        rc = gmres(N, neumann ? 0.5 : -0.5, w2, dens, tol, restart, maxit, st, info);
+        // GMRES on (-/+ 1/2 I + K); the right-hand side lives in the
+        // residual vector, which GMRES overwrites, so it is first copied to w2
+        SOLVE_HIP(hipMemcpyAsync(w2, o.W.rv, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
+        rc = gmres(N, o.W, neumann ? 0.5 : -0.5, w2, dens, tol, restart, maxit, st, info);
         if (rc != MHK_OK) break;
         SOLVE_HIP(hipEventRecord(ev[2], st));
         // representation at every output
