@@ -359,7 +359,8 @@ int or_refine_level(const or_problem *P, int j, double *x, double *y, double *nx
  * decrease the distance is halved, and where the squared distance is not
  * convex a fixed step of 1/4 downhill replaces the Newton step; Newton steps
  * below 1e-6 where it is convex are taken as they are (the distance is flat
- * below its rounding there); it stops when a step is below 1e-15.            */
+ * below its rounding there) and end the iteration once one is below 1e-12,
+ * after one more Newton step; a damped step below 1e-15 also ends it.        */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t panel; double t, x0, y0, r;
@@ -402,9 +403,20 @@ static int or_panel_min(const double *cx, const double *cy, const double *nx, co
         if (h > 0.0 && fabs(step) < 1e-6) {
             /* near a minimum the distance is flat below its rounding: plain
                Newton steps, driven by the derivative */
+            /* quadratic convergence: after a step below 1e-12 the error is at
+               the rounding level */
             double moved = fabs(tn - t);
             t = tn;
-            if (moved < 1e-15) { conv = 1; break; }
+            if (moved < 1e-12) {
+                /* one more Newton step brings t to the rounding level also
+                   where the convergence is slow */
+                or_eval_poly(cx, t, &x, &x1, &x2);
+                or_eval_poly(cy, t, &y, &y1, &y2);
+                double h2 = x1 * x1 + y1 * y1 + (x - px) * x2 + (y - py) * y2;
+                if (h2 > 0.0) t = fmin(1.0, fmax(-1.0, t - ((x - px) * x1 + (y - py) * y1) / h2));
+                conv = 1;
+                break;
+            }
             continue;
         }
         double dn = phi;

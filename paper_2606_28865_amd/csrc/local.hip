@@ -157,8 +157,10 @@ struct LocalArgs {
 // convex (beyond a centre of curvature) a fixed step of 1/4 downhill is
 // tried instead of the Newton step; Newton steps below 1e-6 where the
 // distance is convex are taken as they are (there the distance is flat below
-// its rounding, and the derivative decides).  Returns whether the iteration
-// converged (a step below 1e-15, possibly held at an end point).
+// its rounding, and the derivative decides) and end the iteration once one is
+// below 1e-12, after one more Newton step.  Returns whether the iteration
+// converged (that, or a damped step below 1e-15, possibly held at an end
+// point).
 template <typename T>
 __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
 {
@@ -194,9 +196,18 @@ __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double
         if (h > 0.0 && fabs(step) < 1e-6) {
             // close to a minimum the distance is flat below its rounding:
             // plain Newton steps, driven by the derivative
+            // quadratic convergence: after a step below 1e-12 the error is
+            // at the rounding level (a stricter test can fail on rounding
+            // noise of the step itself)
             const double moved = fabs(tn - t);
             t = tn;
-            if (moved < 1e-15) {
+            if (moved < 1e-12) {
+                // one more Newton step brings t to the rounding level also
+                // where the convergence is slow (small curvature of |x - gamma|^2)
+                leg2(cx, cy, t, x0, x1, x2, y0, y1, y2);
+                const double e2x = x0 - px, e2y = y0 - py;
+                const double h2 = x1 * x1 + y1 * y1 + e2x * x2 + e2y * y2;
+                if (h2 > 0.0) t = fmin(1.0, fmax(-1.0, t - (e2x * x1 + e2y * y1) / h2));
                 conv = true;
                 break;
             }
