@@ -32,6 +32,7 @@ template <typename T>
 struct SpreadArgs {
     int64_t n, field, nb, nv;
     int ntile, B;
+    int tbx0, tby0, ntbx;  // the launch covers tiles tbx0.. (ntbx per row) x tby0..: the box of the sources' windows
     double beta;
     const double *bgx, *bgy, *bw, *bwx, *bwy;
     const int32_t *bidx, *blofs, *blist;
@@ -112,7 +113,8 @@ __global__ void __launch_bounds__(SB) k_spread(SpreadArgs<T> A)
 {
     constexpr int PAD = W - 1, PT = TILE + 2 * PAD;
     __shared__ double acc[PT * PT];
-    const int tile = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const int tile = (A.tby0 + (int)blockIdx.x / A.ntbx) * A.ntile + A.tbx0 + (int)blockIdx.x % A.ntbx;
+    const int b = blockIdx.y, tid = threadIdx.x;
     const int x0 = (tile % A.ntile) * TILE, y0 = (tile / A.ntile) * TILE;
     const size_t fs = (size_t)A.B * A.field;
     T *gS = A.grid + (size_t)b * A.field, *gV = gS + fs, *gX = gV + fs, *gY = gX + fs;
@@ -433,6 +435,9 @@ constexpr int RT = 256;            // threads per row workgroup
 template <typename T>
 struct RowArgs {
     int64_t n;
+    int r0, nrow;                  // rows r0 .. r0 + nrow - 1 of every field of the launch
+    int m0, m1;                    // forward: complex points [m0, m1) of a row are read, the others are zero;
+                                   // inverse: complex points [m0, m1) are written back
     int ncol;                      // half-spectrum entries k < ncol can be nonzero after the multiplier
     int npass;
     int8_t radix[COL_MAXPASS];     // of n/2
@@ -447,10 +452,13 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
     extern __shared__ double lds_row[];
     T2 *buf = reinterpret_cast<T2 *>(lds_row);
     const int n = (int)A.n, h = n / 2;
-    T2 *c = reinterpret_cast<T2 *>(A.grid + (size_t)blockIdx.x * (size_t)(n + 2));   // h + 1 complex
+    const size_t slot = blockIdx.x / A.nrow, row = A.r0 + blockIdx.x % A.nrow;
+    T2 *c = reinterpret_cast<T2 *>(A.grid + (slot * (size_t)n + row) * (size_t)(n + 2));   // h + 1 complex
     const int tid = threadIdx.x;
     if (!INV) {
-        for (int m = tid; m < h; m += RT) buf[m] = c[m];
+        // the row is zero outside the sources' windows
+        const T2 zero = c2<T2>((T)0, (T)0);
+        for (int m = tid; m < h; m += RT) buf[m] = m >= A.m0 && m < A.m1 ? c[m] : zero;
         __syncthreads();
         lds_fft<false, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
         // only the columns that the multiplier keeps are read again
@@ -476,7 +484,8 @@ __global__ void __launch_bounds__(RT) k_rows(RowArgs<T> A)
         }
         __syncthreads();
         lds_fft<true, RT, NMAX / 2>(buf, A.tw, 2, h, A.radix, A.npass);
-        for (int m = tid; m < h; m += RT) c[m] = buf[m];
+        // only the points the interpolation windows use
+        for (int m = A.m0 + tid; m < A.m1; m += RT) c[m] = buf[m];
     }
 }
 
@@ -484,6 +493,8 @@ template <typename T>
 struct ColArgs {
     int64_t n, field;
     int B, ncol, npass;
+    int iy0, iy1;          // rows [iy0, iy1) of the input columns can be nonzero (the sources' windows)
+    int oy0, oy1;          // rows [oy0, oy1) of the output columns are written (the targets' windows)
     int8_t radix[COL_MAXPASS];
     T *grid;
     const double2 *tw;             // e^{-2 pi i m / n}, FP64 at both precisions
@@ -529,7 +540,8 @@ __global__ void __launch_bounds__(CT) k_columns(ColArgs<T> A)
     const int nparts = grp == 2 ? 2 : 1;
     for (int part = 0; part < nparts; ++part) {
         const T2 *in = base + (size_t)(grp == 2 ? 2 + part : grp) * fs;
-        for (int y = threadIdx.x; y < n; y += CT) buf[y] = in[(size_t)y * nh];
+        const T2 zero = c2<T2>((T)0, (T)0);
+        for (int y = threadIdx.x; y < n; y += CT) buf[y] = y >= A.iy0 && y < A.iy1 ? in[(size_t)y * nh] : zero;
         __syncthreads();
         lds_fft<false, CT, NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         for (int ly = threadIdx.x; ly < n; ly += CT) {
@@ -548,7 +560,7 @@ __global__ void __launch_bounds__(CT) k_columns(ColArgs<T> A)
         lds_fft<true, CT, NMAX>(buf, A.tw, 1, n, A.radix, A.npass);
         // part 0 of D writes its column, part 1 adds to it (same thread, same
         // rows: no other thread touches these values)
-        for (int y = threadIdx.x; y < n; y += CT) {
+        for (int y = A.oy0 + threadIdx.x; y < A.oy1; y += CT) {
             T2 v = buf[y];
             if (part == 1) v = cadd(out[(size_t)y * nh], v);
             out[(size_t)y * nh] = v;
@@ -708,7 +720,11 @@ hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const do
 template <int W, typename T>
 static hipError_t spread_w(mhk_plan *P, const SpreadArgs<T> &A)
 {
-    dim3 grid((unsigned)(A.ntile * A.ntile), (unsigned)A.B);
+    const History &G = P->hist;
+    // column path: only the tiles of the sources' windows (the transforms
+    // read nothing else); rocFFT's 2D transforms read the whole grid
+    const int nty = G.colpath ? (G.sy1 - 1) / TILE - A.tby0 + 1 : A.ntile;
+    dim3 grid((unsigned)(A.ntbx * nty), (unsigned)A.B);
     hipLaunchKernelGGL((k_spread<W, T>), grid, dim3(SB), 0, P->stream, A);
     return hipGetLastError();
 }
@@ -751,6 +767,9 @@ static hipError_t spread_t(mhk_plan *P, const void *sigma, const void *mu, const
     A.nv = P->nv;
     A.ntile = G.ntile;
     A.B = P->p.batch;
+    A.tbx0 = G.colpath ? G.sx0 / TILE : 0;
+    A.tby0 = G.colpath ? G.sy0 / TILE : 0;
+    A.ntbx = G.colpath ? (G.sx1 - 1) / TILE - A.tbx0 + 1 : G.ntile;
     A.beta = G.beta;
     A.bgx = G.bgx; A.bgy = G.bgy; A.bw = G.bw; A.bwx = G.bwx; A.bwy = G.bwy;
     A.bidx = G.bidx; A.blofs = G.blofs; A.blist = G.blist;
@@ -798,6 +817,10 @@ static hipError_t columns_t(mhk_plan *P)
     A.alpha2 = P->p.alpha * P->p.alpha;
     A.dk = 2.0 * M_PI / G.period;
     A.lmax = G.lmax;
+    A.iy0 = G.sy0;
+    A.iy1 = G.sy1;
+    A.oy0 = G.ty0;
+    A.oy1 = G.ty1;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)G.n;
     // register arrays sized for the longest column of the launch
     const void *fn = G.n <= COL_NMAX / 2 ? (const void *)k_columns<T, COL_NMAX / 2> : (const void *)k_columns<T, COL_NMAX>;
@@ -822,8 +845,15 @@ static hipError_t rows_t(mhk_plan *P)
     for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.rradix[i];
     A.grid = (T *)G.grid;
     A.tw = (const double2 *)G.tw;
+    // forward: the rows and columns of the sources' windows; inverse: those
+    // of the targets' windows
+    A.r0 = INV ? G.ty0 : G.sy0;
+    A.nrow = INV ? G.ty1 - G.ty0 : G.sy1 - G.sy0;
+    A.m0 = (INV ? G.tx0 : G.sx0) / 2;
+    A.m1 = ((INV ? G.tx1 : G.sx1) + 1) / 2;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)(G.n / 2);
-    const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * G.n;
+    const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * A.nrow;
+    if (rows <= 0) return hipSuccess;
     if (G.n <= COL_NMAX / 2)
         hipLaunchKernelGGL((k_rows<INV, T, COL_NMAX / 2>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
     else

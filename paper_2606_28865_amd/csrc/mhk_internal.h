@@ -135,6 +135,12 @@ struct History {
     // runs between them
     bool colpath = false;
     int ncol = 0;                                 // columns l_x that can hold a nonzero multiplier
+    // column path: grid index ranges [lo, hi) holding the sources' windows
+    // (spread, forward row transforms, column inputs) and the targets'
+    // windows (column outputs, inverse row transforms, interpolation); the
+    // grid outside them is neither written nor read
+    int sx0 = 0, sx1 = 0, sy0 = 0, sy1 = 0;
+    int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
     int npass = 0;
     int8_t radix[COL_MAXPASS] = {};               // passes of the column transforms (length n)
     int rnpass = 0;

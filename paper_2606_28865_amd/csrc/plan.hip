@@ -1121,6 +1121,17 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         iy = std::min<int64_t>(G.ntile - 1, std::max<int64_t>(0, iy));
         return iy * G.ntile + ix;
     };
+    // grid rows and columns that hold the sources' windows [m0, m0 + w),
+    // m0 = ceil(g - w/2) as the spreading kernel forms it: [sup[0], sup[1])
+    // in x, [sup[2], sup[3]) in y
+    int64_t sup[4] = {G.n, 0, G.n, 0};
+    auto support = [&](const std::vector<double> &gx, const std::vector<double> &gy) {
+        for (size_t s = 0; s < gx.size(); ++s) {
+            const int64_t mx = (int64_t)ceil(gx[s] - 0.5 * G.w), my = (int64_t)ceil(gy[s] - 0.5 * G.w);
+            sup[0] = std::min(sup[0], mx); sup[1] = std::max(sup[1], mx + G.w);
+            sup[2] = std::min(sup[2], my); sup[3] = std::max(sup[3], my + G.w);
+        }
+    };
     // boundary sources
     {
         const mhk_boundary *b = H.b;
@@ -1139,6 +1150,7 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
             wy[s] = b->w[i] * b->ny[i];
         }
         G.nbs = nb;
+        support(gx, gy);
         TRY(upload(P, &G.bgx, gx.data(), nb));
         TRY(upload(P, &G.bgy, gy.data(), nb));
         TRY(upload(P, &G.bw, w.data(), nb));
@@ -1162,12 +1174,17 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
             w[s] = H.v->w[i];
         }
         G.nvs = nv;
+        support(gx, gy);
         TRY(upload(P, &G.vgx, gx.data(), nv));
         TRY(upload(P, &G.vgy, gy.data(), nv));
         TRY(upload(P, &G.vw, w.data(), nv));
         TRY(upload(P, &G.vidx, order.data(), nv));
         TRY(tile_lists(gx, gy, &G.vlofs, &G.vlist));
     }
+    G.sx0 = (int)std::max<int64_t>(0, sup[0]);
+    G.sx1 = (int)std::min<int64_t>(G.n, sup[1]);
+    G.sy0 = (int)std::max<int64_t>(0, sup[2]);
+    G.sy1 = (int)std::min<int64_t>(G.n, sup[3]);
     // targets by tile (they are sorted with tiles contiguous)
     {
         std::vector<int32_t> xy, rng;
@@ -1184,6 +1201,18 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
         }
         rng.push_back((int32_t)tgx.size());
         G.n_ttiles = (int)xy.size();
+        // grid rows and columns that the interpolation windows use
+        int64_t x0 = G.n, x1 = 0, y0 = G.n, y1 = 0;
+        for (int64_t s = 0; s < (int64_t)tgx.size(); ++s) {
+            const double gx = (tgx[s] - G.ox) / G.h, gy = (tgy[s] - G.oy) / G.h;
+            const int64_t mx = (int64_t)ceil(gx - 0.5 * G.w), my = (int64_t)ceil(gy - 0.5 * G.w);
+            x0 = std::min(x0, mx); x1 = std::max(x1, mx + G.w);
+            y0 = std::min(y0, my); y1 = std::max(y1, my + G.w);
+        }
+        G.tx0 = (int)std::max<int64_t>(0, x0);
+        G.tx1 = (int)std::min<int64_t>(G.n, x1);
+        G.ty0 = (int)std::max<int64_t>(0, y0);
+        G.ty1 = (int)std::min<int64_t>(G.n, y1);
         TRY(upload(P, &G.ttile_xy, xy.data(), (int64_t)xy.size()));
         TRY(upload(P, &G.ttile_rng, rng.data(), (int64_t)rng.size()));
     }
