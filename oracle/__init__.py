@@ -37,6 +37,7 @@ class _Problem(C.Structure):
         ("n_trg", C.c_int64), ("tx", C.c_void_p), ("ty", C.c_void_p), ("inside", C.c_void_p),
         ("on_surface", C.c_int),
         ("sigma", C.c_void_p), ("mu", C.c_void_p), ("f_vol", C.c_void_p), ("f_trg", C.c_void_p),
+        ("local_order", C.c_int), ("f_jet", C.c_void_p),
     ]
 
 
@@ -125,7 +126,11 @@ class Problem:
 
     def __init__(self, alpha, delta, J, boundary, volume=None, targets=None,
                  inside=None, on_surface=False, sigma=None, mu=None, f_vol=None,
-                 f_trg=None, parts=PART_ALL):
+                 f_trg=None, parts=PART_ALL, local_order=1, f_jet=None):
+        """local_order 1 keeps the local expansions to first order (Section
+        4.1); 2 adds their printed second-order terms, with f_jet the
+        gradient and Hessian of f at the targets, [5][n_out] = f_x, f_y,
+        f_xx, f_xy, f_yy (needed for V)."""
         self._keep = []
         p = _Problem()
         p.alpha, p.delta, p.J, p.parts = float(alpha), float(delta), int(J), int(parts)
@@ -150,6 +155,11 @@ class Problem:
         p.on_surface = int(bool(on_surface))
         p.sigma = self._ptr(_f64(sigma)); p.mu = self._ptr(_f64(mu))
         p.f_vol = self._ptr(_f64(f_vol)); p.f_trg = self._ptr(_f64(f_trg))
+        p.local_order = int(local_order)
+        if f_jet is not None:
+            f_jet = np.ascontiguousarray(f_jet, dtype=np.float64)
+            assert f_jet.shape == (5, int(p.n_trg) + (nb if on_surface else 0)), f_jet.shape
+        p.f_jet = self._ptr(f_jet)
         self.c = p
         self.n_b = nb
         self.n_out = int(p.n_trg) + (nb if on_surface else 0)

@@ -257,6 +257,79 @@ static void or_eval_poly(const double *c, double t, double *v, double *d1, doubl
     if (d2) *d2 = e;
 }
 
+/* P_k and their first four t-derivatives, by the recurrences
+ * P_{k+1}^{(m)} = P_{k-1}^{(m)} + (2k+1) P_k^{(m-1)}.                        */
+static void or_legendre_d4(double t, double D[5][OR_NGL])
+{
+    double dP[OR_NGL], ddP[OR_NGL];
+    or_legendre_all(t, D[0], dP, ddP);
+    for (int k = 0; k < OR_NGL; ++k) { D[1][k] = dP[k]; D[2][k] = ddP[k]; }
+    for (int m = 3; m <= 4; ++m) {
+        D[m][0] = 0.0; D[m][1] = 0.0;
+        for (int k = 1; k < OR_NGL - 1; ++k) D[m][k + 1] = D[m][k - 1] + (2 * k + 1) * D[m - 1][k];
+    }
+}
+
+/* Taylor coefficients F_0..F_4 in tau = t - t* of the panel polynomial c. */
+static void or_taylor(const double *c, double D[5][OR_NGL], double F[5])
+{
+    static const double fact[5] = {1, 1, 2, 6, 24};
+    for (int m = 0; m <= 4; ++m) {
+        double a = 0.0;
+        for (int k = 0; k < OR_NGL; ++k) a += c[k] * D[m][k];
+        F[m] = a / fact[m];
+    }
+}
+
+/* Local data at a boundary point in the tangent-line parameterisation of
+ * Section 4.1: xi along the unit tangent T0 (increasing t), the boundary the
+ * graph eta = gamma(xi) along the inward normal N0, gamma(xi) = kappa0 xi^2/2
+ * + g3 xi^3/6 + g4 xi^4/24 + ...  Derivatives in xi of a function on the
+ * boundary follow from its Taylor series in tau = t - t* and the reversion of
+ * xi(tau) = c1 tau + c2 tau^2 + c3 tau^3 + c4 tau^4, i.e.
+ * tau = b1 xi + b2 xi^2 + b3 xi^3 + b4 xi^4.                                  */
+typedef struct {
+    double T0x, T0y, N0x, N0y;      /* unit tangent and inward normal            */
+    double b[5];                    /* reversion coefficients b1..b4 (b[0] = 0)   */
+    double kh, g3, g4;              /* second, third, fourth xi-derivative of the graph */
+} or_tl;
+
+/* d^m/dxi^m, m = 0..4, of a function with Taylor coefficients F in tau */
+static void or_xi_derivs(const or_tl *L, const double F[5], double d[5])
+{
+    const double b1 = L->b[1], b2 = L->b[2], b3 = L->b[3], b4 = L->b[4];
+    const double g1 = F[1] * b1;
+    const double g2 = F[1] * b2 + F[2] * b1 * b1;
+    const double g3 = F[1] * b3 + F[2] * 2.0 * b1 * b2 + F[3] * b1 * b1 * b1;
+    const double g4 = F[1] * b4 + F[2] * (b2 * b2 + 2.0 * b1 * b3) + F[3] * 3.0 * b1 * b1 * b2 + F[4] * b1 * b1 * b1 * b1;
+    d[0] = F[0]; d[1] = g1; d[2] = 2.0 * g2; d[3] = 6.0 * g3; d[4] = 24.0 * g4;
+}
+
+static void or_tangent_line(const double *cx, const double *cy, double D[5][OR_NGL], or_tl *L)
+{
+    double X[5], Y[5];
+    or_taylor(cx, D, X);
+    or_taylor(cy, D, Y);
+    const double sp = sqrt(X[1] * X[1] + Y[1] * Y[1]);
+    L->T0x = X[1] / sp; L->T0y = Y[1] / sp;
+    L->N0x = -L->T0y; L->N0y = L->T0x;          /* inward for a counter-clockwise curve */
+    double c[5], e[5];
+    for (int m = 0; m <= 4; ++m) {
+        c[m] = X[m] * L->T0x + Y[m] * L->T0y;
+        e[m] = X[m] * L->N0x + Y[m] * L->N0y;
+    }
+    c[0] = 0.0; e[0] = 0.0; e[1] = 0.0;
+    const double c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4];
+    L->b[0] = 0.0;
+    L->b[1] = 1.0 / c1;
+    L->b[2] = -c2 / (c1 * c1 * c1);
+    L->b[3] = (2.0 * c2 * c2 - c1 * c3) / pow(c1, 5);
+    L->b[4] = (5.0 * c1 * c2 * c3 - c1 * c1 * c4 - 5.0 * c2 * c2 * c2) / pow(c1, 7);
+    double h[5];
+    or_xi_derivs(L, e, h);
+    L->kh = h[2]; L->g3 = h[3]; L->g4 = h[4];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Problem description                                                        */
 /* ------------------------------------------------------------------------ */
@@ -278,6 +351,12 @@ typedef struct {
     int on_surface;             /* 1: boundary nodes appended as targets     */
     /* densities */
     const double *sigma, *mu, *f_vol, *f_trg;   /* f_trg: n_trg (+n_B)        */
+    /* local expansions kept to first order (1, Section 4.1) or to the
+     * printed second-order terms (2): then f_jet holds the gradient and the
+     * Hessian of f at the targets, [5][n_trg (+n_B)] = f_x, f_y, f_xx, f_xy,
+     * f_yy (Lemma 4.8 and its corollaries need f_eta, f_eta eta, f_xi xi) */
+    int local_order;
+    const double *f_jet;
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -475,14 +554,33 @@ int or_closest_point(const or_problem *P, double px, double py, double *out)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Local parts, first order in delta* (Lemmas 4.1, 4.5, 4.8; Corollaries
- * 4.4, 4.7, 4.10, 4.11).                                                     */
+/* Local parts (Lemmas 4.1, 4.5, 4.8; Corollaries 4.4, 4.7, 4.10, 4.11) to
+ * first order in delta* (order 1, as Section 4.1 keeps them) or with the
+ * printed second-order terms (order 2).                                       */
 /* ------------------------------------------------------------------------ */
 typedef struct { double S, D; } or_sd;
 
+/* Boundary data at the closest point for the second-order terms: the graph
+ * derivatives g3, g4 of the tangent-line parameterisation and the
+ * xi-derivatives s[0..4], m[0..4] of sigma and mu. */
+typedef struct { double g3, g4, s[5], m[5]; } or_bjet;
+
+/* (2 erf(c2) - 4 c2 e^{-c2^2}/sqrt(pi)) / c2^3, the c1 = 0 value of Q0 */
+static __float128 or_q0_on(__float128 c2)
+{
+    return (2 * erfq(c2) - 4 * c2 * expq(-c2 * c2) / sqrtq(M_PIq)) / (c2 * c2 * c2);
+}
+
+/* (1 - (1 + c2^2) e^{-c2^2}) / c2^4 */
+static __float128 or_v2(__float128 c2)
+{
+    __float128 a = c2 * c2;
+    return (-expm1q(-a) - a * expq(-a)) / (a * a);
+}
+
 /* Off-surface, layer potentials: x0 data given. */
-static or_sd or_local_layer(double r, double rho, double ds, double alpha,
-                            double kappa0, double sigma0, double mu0, double mu0pp)
+static or_sd or_local_layer(double r, double rho, double ds, double alpha, double kappa0, double sigma0,
+                            double mu0, double mu0pp, int order, const or_bjet *J)
 {
     or_sd o = { 0.0, 0.0 };
     double sq = sqrt(ds);
@@ -494,19 +592,54 @@ static or_sd or_local_layer(double r, double rho, double ds, double alpha,
     o.S = sq * sigma0 * P0 / 4.0 + ds * rho * kappa0 * sigma0 * P1 / 8.0;
     o.D = -rho * mu0 * U0 / 4.0 - sq * kappa0 * mu0 * (P0 + U1) / 8.0
           - ds * (rho * mu0pp * P1 / 8.0 + 3.0 * rho * kappa0 * kappa0 * mu0 * (P1 + U2) / 32.0);
+    if (order >= 2) {
+        const double P2 = c[5], P3 = c[6], Q0 = c[7], Q1 = c[8], U3 = c[12], U4 = c[13];
+        const double k = kappa0, g3 = J->g3, g4 = J->g4;
+        const double s1 = J->s[1], s2 = J->s[2], m1 = J->m[1], m2 = J->m[2], m4 = J->m[4];
+        const double d32 = ds * sq, d2 = ds * ds;
+        /* eq. (slp_local1), delta*^{3/2} and delta*^2 terms */
+        o.S += d32 * (k * k * sigma0 / 32.0 * (Q0 + 3.0 * P2) + s2 / 8.0 * Q0)
+               + d2 * rho * (k * k * k * sigma0 / 64.0 * (-3.0 * Q1 + 5.0 * P3)
+                             + (3.0 * k * s2 / 16.0 + s1 * g3 / 8.0 + sigma0 * g4 / 32.0) * Q1);
+        /* eq. (dlp_local1), delta*^{3/2} and delta*^2 terms.  Reading: the
+         * gamma'''' term of the delta*^{3/2} bracket is -mu0 g4 (3 Q0 + P2)/32;
+         * the printed lemma groups it with the kappa^3 term under
+         * (3 Q0 - U3).  The series expansion of the local integral (tangent-
+         * line coordinates, Gaussian moments in xi) gives the form used
+         * here, both agree at c1 = 0 (Corollary 4.7), and only this form
+         * converges at order 5/2 against brute-force quadrature. */
+        o.D += d32 * (5.0 * k * k * k * mu0 / 64.0 * (3.0 * Q0 - U3) - mu0 * g4 / 32.0 * (3.0 * Q0 + P2)
+                      + 3.0 * k * m2 / 16.0 * (-Q0 - P2) + m1 * g3 / 8.0 * (-2.0 * Q0 - P2))
+               + d2 * (35.0 * rho * k * k * k * k * mu0 / 512.0 * (9.0 * Q1 + 2.0 * P3 - U4)
+                       - rho * m4 / 32.0 * Q1 - 15.0 * rho * k * k * m2 / 64.0 * (Q1 + P3))
+               - d2 * (5.0 * rho * k * m1 * g3 / 16.0 * (2.0 * Q1 + P3)
+                       + (5.0 * rho * k * mu0 * g4 / 64.0 + 5.0 * rho * mu0 * g3 * g3 / 96.0) * (3.0 * Q1 + P3));
+    }
     return o;
 }
 
-/* On-surface layer potentials (Corollaries 4.4 and 4.7, first order). */
-static or_sd or_local_layer_on(double ds, double alpha, double kappa0, double sigma0, double mu0)
+/* On-surface layer potentials (Corollaries 4.4 and 4.7). */
+static or_sd or_local_layer_on(double ds, double alpha, double kappa0, double sigma0, double mu0, int order,
+                               const or_bjet *J)
 {
     or_sd o;
     __float128 sq = sqrtq((__float128)ds), c2 = alpha * sq;
     __float128 e = erfq(c2) / c2;
     o.S = (double)(sq * sigma0 * e / 2);
     o.D = (double)(-sq * kappa0 * mu0 * e / 4);
+    if (order >= 2) {
+        const __float128 q = or_q0_on(c2) * sq * sq * sq, k = kappa0;
+        o.S += (double)(q * (k * k * sigma0 / 32 + (__float128)J->s[2] / 8));
+        o.D += (double)(q * (15 * k * k * k * mu0 / 64 - 3 * (__float128)mu0 * J->g4 / 32
+                             - 3 * k * (__float128)J->m[2] / 16 - (__float128)J->m[1] * J->g3 / 4));
+    }
     return o;
 }
+
+/* f and its derivatives at the target in the frame of the closest point:
+ * f_eta along the inward normal N0 and the second derivatives along N0 and
+ * along the tangent T0 (Lemma 4.8); lap = f_xx + f_yy. */
+typedef struct { double fe, fee, fxx, lap; } or_fjet;
 
 /* Volume local part with delta (Lemma 4.8 / Cor. 4.10 / Cor. 4.11).
  * where: 0 interior off-surface, 1 on-surface, 2 exterior off-surface.
@@ -516,20 +649,65 @@ static or_sd or_local_layer_on(double ds, double alpha, double kappa0, double si
  * applies to it; to first order, with f taken at the closest boundary
  * point (f0; the difference to f(x) is of the neglected order),
  * V_L = delta f0 [(1 - e^{-c2^2})/c2^2 - W0(c1, c2)/4].  f0 is NaN when f on
- * the boundary is unknown. */
-static double or_local_vol(double r, int where, double delta, double alpha, double f)
+ * the boundary is unknown.  Order 2 adds the printed delta^{3/2} and
+ * delta^2 terms at interior and on-surface targets; exterior targets keep
+ * the first-order complement form. */
+static double or_local_vol(double r, int where, double delta, double alpha, double f, double kappa0,
+                           int order, const or_fjet *F)
 {
     __float128 sq = sqrtq((__float128)delta), c2 = alpha * sq;
     double band = (double)(sq * (12 + 2 * c2));
-    if (where == 1)
-        return (double)(delta * f * (-expm1q(-c2 * c2)) / (2 * c2 * c2));
-    if (r >= band)
-        return where == 2 ? 0.0 : (double)(delta * f * (-expm1q(-c2 * c2)) / (c2 * c2));
+    const int two = order >= 2 && where != 2;
+    if (where == 1) {
+        double v = (double)(delta * f * (-expm1q(-c2 * c2)) / (2 * c2 * c2));
+        if (two)   /* eq. (vp_local2) */
+            v += (double)(sq * sq * sq * or_q0_on(c2) * (2 * (__float128)F->fe - (__float128)f * kappa0) / 8
+                          + (__float128)delta * delta * (F->fee + F->fxx) / 2 * or_v2(c2));
+        return v;
+    }
+    if (r >= band) {
+        if (where == 2) return 0.0;
+        double v = (double)(delta * f * (-expm1q(-c2 * c2)) / (c2 * c2));
+        if (two)   /* eq. (vp_local3) */
+            v += (double)((__float128)delta * delta * F->lap * or_v2(c2));
+        return v;
+    }
     double c[17];
     or_local_coeffs(r / (double)sq, (double)c2, c);
     if (where == 2)
         return delta * f * ((double)(-expm1q(-c2 * c2) / (c2 * c2)) - c[15] / 4.0);
-    return delta * f * c[15] / 4.0;
+    double v = delta * f * c[15] / 4.0;
+    if (two) {   /* eq. (vp_local1) */
+        const double Q0 = c[7], Q1 = c[8], W1 = c[16], k = kappa0;
+        v += delta * sqrt(delta) * (2.0 * F->fe - f * k) / 8.0 * Q0
+             + delta * delta * ((F->fe * k / 8.0 - 3.0 * f * k * k / 32.0 - F->fee / 8.0) * Q1
+                                + (F->fee + F->fxx) / 8.0 * W1);
+    }
+    return v;
+}
+
+/* Second-order data at the boundary point t of panel pn: the graph
+ * derivatives and the xi-derivatives of sigma and mu (or_bjet), and f's
+ * derivatives at the target in the frame (T0, N0) of that point (or_fjet). */
+static void or_boundary_jets(const or_problem *P, const double *cs, const double *cm, int64_t pn, double t,
+                             double gx, double gy, double hxx, double hxy, double hyy, or_bjet *BJ, or_fjet *FJ)
+{
+    double cx[OR_NGL], cy[OR_NGL], D[5][OR_NGL], F[5];
+    or_coeffs(P->bx + pn * OR_NGL, 1, cx);
+    or_coeffs(P->by + pn * OR_NGL, 1, cy);
+    or_legendre_d4(t, D);
+    or_tl L;
+    or_tangent_line(cx, cy, D, &L);
+    BJ->g3 = L.g3;
+    BJ->g4 = L.g4;
+    or_taylor(cs + pn * OR_NGL, D, F);
+    or_xi_derivs(&L, F, BJ->s);
+    or_taylor(cm + pn * OR_NGL, D, F);
+    or_xi_derivs(&L, F, BJ->m);
+    FJ->fe = gx * L.N0x + gy * L.N0y;
+    FJ->fee = hxx * L.N0x * L.N0x + 2.0 * hxy * L.N0x * L.N0y + hyy * L.N0y * L.N0y;
+    FJ->fxx = hxx * L.T0x * L.T0x + 2.0 * hxy * L.T0x * L.T0y + hyy * L.T0y * L.T0y;
+    FJ->lap = hxx + hyy;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -615,32 +793,48 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
         }
         /* local asymptotic parts */
         if (P->parts & 4) {
+            const int order = P->local_order >= 2 ? 2 : 1;
             double fx = P->f_trg ? P->f_trg[it] : 0.0;
+            /* gradient and Hessian of f at the target (order 2) */
+            double gx = 0, gy = 0, hxx = 0, hxy = 0, hyy = 0;
+            if (order >= 2 && P->f_jet) {
+                gx = P->f_jet[0 * ntot + it]; gy = P->f_jet[1 * ntot + it];
+                hxx = P->f_jet[2 * ntot + it]; hxy = P->f_jet[3 * ntot + it]; hyy = P->f_jet[4 * ntot + it];
+            }
+            or_bjet BJ;
+            or_fjet FJ;
+            memset(&BJ, 0, sizeof BJ);
+            memset(&FJ, 0, sizeof FJ);
             if (on) {
                 double sg = P->sigma ? P->sigma[ib] : 0.0, mm = P->mu ? P->mu[ib] : 0.0;
-                or_sd l = or_local_layer_on(dstar, alpha, P->bkappa[ib], sg, mm);
+                if (order >= 2)
+                    or_boundary_jets(P, cs, cm, ib / OR_NGL, g_bx[ib % OR_NGL], gx, gy, hxx, hxy, hyy, &BJ, &FJ);
+                or_sd l = or_local_layer_on(dstar, alpha, P->bkappa[ib], sg, mm, order, &BJ);
                 s += l.S; d += l.D;
-                if (P->f_trg) v += or_local_vol(0.0, 1, delta, alpha, fx);
+                if (P->f_trg) v += or_local_vol(0.0, 1, delta, alpha, fx, P->bkappa[ib], order, &FJ);
             } else {
                 double sqs = sqrt(dstar);
                 double bandS = sqs * (12.0 + 2.0 * alpha * sqs);
                 or_cp cp;
                 or_closest(P, px, py, &cp);
                 double rho = inside ? 1.0 : -1.0;
+                double P_[OR_NGL], dP[OR_NGL], ddP[OR_NGL];
+                or_legendre_all(cp.t, P_, dP, ddP);
+                const double *a_k = ck + cp.panel * OR_NGL;
+                double kk = 0;
+                for (int q = 0; q < OR_NGL; ++q) kk += a_k[q] * P_[q];
+                if (order >= 2) or_boundary_jets(P, cs, cm, cp.panel, cp.t, gx, gy, hxx, hxy, hyy, &BJ, &FJ);
                 if (cp.r < bandS) {
-                    double P_[OR_NGL], dP[OR_NGL], ddP[OR_NGL];
-                    or_legendre_all(cp.t, P_, dP, ddP);
-                    const double *a_s = cs + cp.panel * OR_NGL, *a_m = cm + cp.panel * OR_NGL,
-                                 *a_k = ck + cp.panel * OR_NGL;
-                    double sg = 0, mm = 0, mt = 0, mtt = 0, kk = 0;
+                    const double *a_s = cs + cp.panel * OR_NGL, *a_m = cm + cp.panel * OR_NGL;
+                    double sg = 0, mm = 0, mt = 0, mtt = 0;
                     for (int q = 0; q < OR_NGL; ++q) {
                         sg += a_s[q] * P_[q]; mm += a_m[q] * P_[q];
-                        mt += a_m[q] * dP[q]; mtt += a_m[q] * ddP[q]; kk += a_k[q] * P_[q];
+                        mt += a_m[q] * dP[q]; mtt += a_m[q] * ddP[q];
                     }
                     double sp2 = cp.tx * cp.tx + cp.ty * cp.ty;
                     double tdot = cp.tx * cp.txx + cp.ty * cp.tyy;
                     double mss = (mtt - mt * tdot / sp2) / sp2;    /* arclength 2nd derivative */
-                    or_sd l = or_local_layer(cp.r, rho, dstar, alpha, kk, sg, mm, mss);
+                    or_sd l = or_local_layer(cp.r, rho, dstar, alpha, kk, sg, mm, mss, order, &BJ);
                     s += l.S; d += l.D;
                 }
                 if (P->f_trg) {
@@ -648,14 +842,12 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
                         /* f at the closest boundary point (exterior targets) */
                         double f0 = NAN;
                         if (fb) {
-                            double P_[OR_NGL], dP[OR_NGL], ddP[OR_NGL];
-                            or_legendre_all(cp.t, P_, dP, ddP);
                             f0 = 0.0;
                             for (int q = 0; q < OR_NGL; ++q) f0 += cf[cp.panel * OR_NGL + q] * P_[q];
                         }
                         fx = f0;
                     }
-                    v += or_local_vol(cp.r, inside ? 0 : 2, delta, alpha, fx);
+                    v += or_local_vol(cp.r, inside ? 0 : 2, delta, alpha, fx, kk, order, &FJ);
                 }
             }
         }

@@ -378,7 +378,7 @@ def test_volume_potential_of_gaussian_full_split(d):
     lap = (4 * d * d / s ** 4 - 4 / s ** 2) * math.exp(-d * d / s ** 2)
     rad = 0.7                                     # f < 1e-16 beyond: the disk is free space
     b = synth.discretize([synth.Curve(r0=rad, cx=tx, cy=ty)], 16)
-    errs = []
+    errs, errs2 = [], []
     for delta, rtol in ((1e-4, 0.07), (2.5e-5, 0.02)):
         vol = _graded_polar_rule(tx, ty, rad, 0.25 * math.sqrt(delta))
         f = np.exp(-((vol["x"] - c[0]) ** 2 + (vol["y"] - c[1]) ** 2) / s ** 2)
@@ -389,7 +389,19 @@ def test_volume_potential_of_gaussian_full_split(d):
         err = V[0] - ex
         errs.append(err)
         assert err == pytest.approx(-0.5 * delta ** 2 * lap, rel=rtol), (delta, err, -0.5 * delta ** 2 * lap)
+        # second order (Corollary 4.11 with f_xx + f_yy): the O(delta^2) error
+        # is removed and what is left is O(delta^3)
+        gx, gy = -2 * (tx - c[0]) / s ** 2 * fx, -2 * (ty - c[1]) / s ** 2 * fx
+        hxx = (4 * (tx - c[0]) ** 2 / s ** 4 - 2 / s ** 2) * fx
+        hyy = (4 * (ty - c[1]) ** 2 / s ** 4 - 2 / s ** 2) * fx
+        hxy = 4 * (tx - c[0]) * (ty - c[1]) / s ** 4 * fx
+        assert hxx + hyy == pytest.approx(lap, rel=1e-12)
+        fj = np.array([[gx], [gy], [hxx], [hxy], [hyy]])
+        P2 = O.Problem(alpha, delta, 3, b, volume=vol, targets=(np.array([tx]), np.array([ty])),
+                       inside=np.ones(1), f_vol=f, f_trg=np.array([fx]), f_jet=fj, local_order=2)
+        errs2.append(P2.eval()[2][0] - ex)
     assert errs[0] / errs[1] == pytest.approx(16.0, rel=0.1), errs
+    assert abs(errs2[1]) < 0.02 * abs(errs[1]) and abs(errs2[0] / errs2[1]) > 40, (errs, errs2)
 
 
 # --------------------------------------------------------------------------
@@ -471,3 +483,144 @@ def test_closest_point_brute_force():
         dmin = np.abs(gx - p).min()
         assert cp["r"] <= dmin + 1e-10
         assert cp["r"] >= dmin - 1e-7
+
+
+# --------------------------------------------------------------------------
+# Second-order local expansions (local_order = 2): the printed delta*^{3/2}
+# and delta*^2 terms of Lemmas 4.1, 4.5, 4.8 and Corollaries 4.4, 4.7, 4.10,
+# 4.11.  With them the local error falls from O(delta*^{3/2}) to
+# O(delta*^{5/2}) (O(delta^3) far from the boundary): a factor of 16 in
+# delta* divides it by ~1000 instead of ~64.
+# --------------------------------------------------------------------------
+def _layer_brute(cv, x, t0, ds, alpha, dens):
+    """S_{L,A} and D_{L,A} at x by adaptive quadrature over the curve
+    parameter near t0 of the time-integrated kernel (the density dens(t) in
+    the curve parameter)."""
+    sq = math.sqrt(ds)
+
+    def geo(tp):
+        g, g1, _ = cv.eval(np.array([tp]))
+        return g[0], g1[0]
+
+    def fs(tp):
+        g, g1 = geo(tp)
+        return _gr_scipy(abs(complex(*x) - g), alpha, ds) * dens(tp) * abs(g1)
+
+    def fd(tp):
+        g, g1 = geo(tp)
+        r = abs(complex(*x) - g)
+        a = r * r / (4 * ds)
+        grd = integrate.quad(lambda u: math.exp(-a * math.exp(u) - alpha ** 2 * ds * math.exp(-u) + u),
+                             0, max(1.0, math.log(800 / max(a, 1e-300))), epsabs=0, epsrel=1e-12,
+                             limit=200)[0] / (8 * math.pi * ds)
+        nu = (g1.imag - 1j * g1.real) / abs(g1)
+        dd = complex(*x) - g
+        return grd * (dd.real * nu.real + dd.imag * nu.imag) * dens(tp) * abs(g1)
+    w = 14 * sq / 0.45
+    brk = [t0 - w, t0 - w / 4, t0, t0 + w / 4, t0 + w]
+    s = sum(integrate.quad(fs, brk[i], brk[i + 1], epsabs=1e-16, epsrel=1e-12, limit=300)[0] for i in range(4))
+    d = sum(integrate.quad(fd, brk[i], brk[i + 1], epsabs=1e-16, epsrel=1e-12, limit=300)[0] for i in range(4))
+    return s, d
+
+
+@pytest.mark.parametrize("curve", ["circle", "star3"])
+def test_local_layer_order2_vs_brute_force(curve):
+    """S_{L,A}, D_{L,A} with the second-order terms (Lemmas 4.1, 4.5;
+    Corollaries 4.4, 4.7) against brute-force quadrature, with the oscillating
+    density cos 3t + 0.3, off the curve on both sides and at a boundary node.
+    The 3-armed curve has non-constant curvature (gamma''' != 0).  Reading:
+    the gamma'''' term of Lemma 4.5's delta*^{3/2} bracket multiplies
+    (3 Q0 + P2); with the printed grouping under (3 Q0 - U3) the D error
+    stays O(delta*^{3/2})."""
+    alpha = 10.0
+    cv = synth.Curve(r0=0.5) if curve == "circle" else synth.Curve(r0=0.5, a=0.06, l1=3)
+    bnd = synth.discretize([cv], 48 if curve == "circle" else 64)
+    sig = np.cos(3 * bnd["t"]) + 0.3
+    dens = lambda t: math.cos(3 * t) + 0.3
+    node = 37                                     # an on-surface target
+    errs = []
+    for ds in (4e-4, 2.5e-5):
+        sq = math.sqrt(ds)
+        specs = [(0.3, -1.5 * sq), (1.1, 2.0 * sq), (2.0, -0.4 * sq)]
+        tx, ty, ins = [], [], []
+        for t0, off in specs:
+            g, g1, _ = cv.eval(np.array([t0]))
+            z = g[0] + off * (g1[0].imag - 1j * g1[0].real) / abs(g1[0])
+            tx.append(z.real); ty.append(z.imag); ins.append(1 if off < 0 else 0)
+        P = O.Problem(alpha, ds, 0, bnd, targets=(np.array(tx), np.array(ty)), inside=np.array(ins),
+                      on_surface=True, sigma=sig, mu=sig, parts=O.PART_LOCAL, local_order=2)
+        S, D, _ = P.eval(np.array([0, 1, 2, 3 + node]))
+        e = []
+        for k, (t0, _) in enumerate(specs):
+            s, d = _layer_brute(cv, (tx[k], ty[k]), t0, ds, alpha, dens)
+            e.append((abs(S[k] - s), abs(D[k] - d)))
+        # on-surface: D is the principal value (the average of the two sides)
+        s, d = _layer_brute(cv, (bnd["x"][node], bnd["y"][node]), bnd["t"][node], ds, alpha, dens)
+        e.append((abs(S[3] - s), abs(D[3] - d)))
+        errs.append(e)
+    errs = np.array(errs)                          # [ds][target][S, D]
+    ratio = errs[0] / errs[1]
+    assert np.all(ratio > 400), (errs, ratio)      # O(delta*^{5/2}): 1024; first order gives ~64
+    assert errs[1, :, 0].max() < 5e-10 and errs[1, :, 1].max() < 2e-8, errs
+
+
+_QC = dict(c0=1.0, cx=0.7, cy=-0.4, cxx=0.5, cxy=-0.3, cyy=0.8)
+
+
+def _quad_f(x, y):
+    c = _QC
+    return c["c0"] + c["cx"] * x + c["cy"] * y + c["cxx"] * x * x + c["cxy"] * x * y + c["cyy"] * y * y
+
+
+def _quad_jet(x, y):
+    c = _QC
+    return np.array([c["cx"] + 2 * c["cxx"] * x + c["cxy"] * y, c["cy"] + c["cxy"] * x + 2 * c["cyy"] * y,
+                     np.full_like(x, 2 * c["cxx"]), np.full_like(x, c["cxy"]), np.full_like(x, 2 * c["cyy"])])
+
+
+def _disk_local_volume(R, alpha, r0, th0, d):
+    """int_0^d e^{-alpha^2 t} int_disk G_t(x - y) f(y) dy dt for the quadratic
+    f of _QC at x = r0 (cos th0, sin th0): f in angular modes a_m(rho')
+    e^{i m theta}, whose angular integrals against the heat kernel are
+    modified Bessel functions I_m."""
+    c = _QC
+
+    def modes(rp):
+        a1 = rp * (c["cx"] - 1j * c["cy"]) / 2
+        a2 = rp * rp * (c["cxx"] - c["cyy"]) / 4 - 1j * rp * rp * c["cxy"] / 4
+        return {0: c["c0"] + rp * rp * (c["cxx"] + c["cyy"]) / 2, 1: a1, -1: np.conj(a1), 2: a2, -2: np.conj(a2)}
+
+    def inner(t):
+        def g(rp):
+            s = sum((a * np.exp(1j * m * th0)).real * sp.ive(abs(m), r0 * rp / (2 * t)) for m, a in modes(rp).items())
+            return rp * s * math.exp(-(r0 - rp) ** 2 / (4 * t)) / (2 * t)
+        lo, hi = max(0.0, r0 - 40 * math.sqrt(t)), min(R, r0 + 40 * math.sqrt(t))
+        return integrate.quad(g, lo, hi, points=[r0] if lo < r0 < hi else None, epsabs=0, epsrel=1e-12,
+                              limit=300)[0]
+    return integrate.quad(lambda t: math.exp(-alpha ** 2 * t) * inner(t), 0, d, epsabs=0, epsrel=1e-11,
+                          limit=300)[0]
+
+
+def test_local_volume_order2_disk():
+    """V_L with the second-order terms (Lemma 4.8, Corollary 4.10) for a
+    quadratic f (its second-order Taylor expansion is exact) near the
+    boundary of a disk and at a boundary node, against the local integral by
+    Fourier-Bessel quadrature: error O(delta^{5/2})."""
+    R, alpha = 0.5, 10.0
+    bnd = synth.discretize([synth.Curve(r0=R)], 32)
+    node = 5
+    errs = []
+    for d in (1e-3, 6.25e-5):
+        sq = math.sqrt(d)
+        tg = [(R - 1.2 * sq, 0.4), (R - 0.3 * sq, 1.9), (R - 3.0 * sq, 3.0)]
+        tx = np.array([a * math.cos(b) for a, b in tg]); ty = np.array([a * math.sin(b) for a, b in tg])
+        X = np.concatenate([tx, bnd["x"]]); Y = np.concatenate([ty, bnd["y"]])
+        P = O.Problem(alpha, d, 0, bnd, targets=(tx, ty), inside=np.ones(3), on_surface=True, f_trg=_quad_f(X, Y),
+                      f_jet=_quad_jet(X, Y), parts=O.PART_LOCAL, local_order=2)
+        _, _, V = P.eval(np.array([0, 1, 2, 3 + node]))
+        ref = [_disk_local_volume(R, alpha, a, b, d) for a, b in tg]
+        ref.append(_disk_local_volume(R, alpha, R, math.atan2(bnd["y"][node], bnd["x"][node]), d))
+        errs.append(np.abs(V - np.array(ref)))
+    errs = np.array(errs)
+    assert np.all(errs[0] / errs[1] > 400), errs   # O(delta^{5/2}): 1024
+    assert errs[1].max() < 1e-10, errs
