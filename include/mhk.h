@@ -249,6 +249,28 @@ mhk_status mhk_nystrom_apply(mhk_nystrom *nys, double shift, const double *x, do
 mhk_status mhk_nystrom_solve(mhk_nystrom *nys, double shift, const double *rhs, double *x, double tol,
                              int restart, int maxit, mhk_solve_info *info);
 
+/* As mhk_nystrom_solve, for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the GMRES workspace -- the Krylov basis, residual and product vectors,
+ * partial sums of the dot products and the small Hessenberg data -- comes
+ * from one fixed device array of 32 MiB in the library, not from
+ * allocations, and the host side of the least-squares problem from the
+ * stack.  The call allocates nothing: no hipMalloc, hipHostMalloc or
+ * hipFree.  Limits: restart <= 64, and (restart + 3) N_B + (restart + 1)
+ * min(256, N_B/256) + 3 restart doubles (each part rounded up to 256 bytes)
+ * within the 32 MiB (N_B = 16384 allows restart 60); larger requests fail
+ * with MHK_EINVAL before anything is enqueued.  Every GPU holds its own copy
+ * of the array for the life of the process (its address is looked up on the
+ * first call made with that device current), and every call on that GPU
+ * shares it: calls that overlap on one GPU (other host threads, other
+ * objects' streams) race and must be serialised by the caller.  The array
+ * keeps the last call's contents; nothing in it is read before it is
+ * written.  Otherwise as mhk_nystrom_solve (same results, the object's
+ * stream, synchronised at the end); ms_gmres and ms_total are host-clock
+ * times. */
+mhk_status mhk_nystrom_solve_noalloc(mhk_nystrom *nys, double shift, const double *rhs, double *x, double tol,
+                                     int restart, int maxit, mhk_solve_info *info);
+
 /* Dirichlet problem with data g [N_B] and optional source (f_vol [N_V] at
  * the volume nodes and f_trg [n_out] at the outputs, both or neither):
  * mu [N_B] receives the layer density, u [n_out] the solution at every

@@ -75,7 +75,8 @@ class SolveInfo(C.Structure):
 EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
            "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_capture", "mhk_plan_launch_graph",
            "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error",
-           "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_solve_dirichlet",
+           "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_nystrom_solve_noalloc",
+           "mhk_solve_dirichlet",
            "mhk_solve_neumann", "mhk_heat_step", "mhk_nystrom_info", "mhk_nystrom_destroy"]
 _VOID = ("mhk_plan_destroy", "mhk_last_error", "mhk_nystrom_destroy")
 
@@ -108,6 +109,7 @@ def lib():
         L.mhk_nystrom_create.argtypes = [d, P(Boundary), vp, P(vp)]
         L.mhk_nystrom_apply.argtypes = [vp, d, vp, vp]
         L.mhk_nystrom_solve.argtypes = [vp, d, vp, vp, d, i, i, P(SolveInfo)]
+        L.mhk_nystrom_solve_noalloc.argtypes = [vp, d, vp, vp, d, i, i, P(SolveInfo)]
         L.mhk_solve_dirichlet.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
         L.mhk_solve_neumann.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
         L.mhk_heat_step.argtypes = [vp, vp, vp, vp, vp, d, i, i, vp, vp, P(SolveInfo)]
@@ -368,14 +370,19 @@ class Nystrom:
         _check(lib().mhk_nystrom_apply(self._h, float(shift), _f64_dev(x, self.n, "x"), _f64_dev(out, self.n, "y")))
         return out
 
-    def solve(self, rhs, shift, tol=1e-12, restart=60, maxit=500, out=None):
+    def solve(self, rhs, shift, tol=1e-12, restart=60, maxit=500, out=None, noalloc=False):
+        """GMRES solve of (shift I + K) x = rhs.  noalloc=True calls
+        mhk_nystrom_solve_noalloc (workspace from the library's fixed scratch
+        array; out must then be given, and restart <= 64)."""
         import torch
         if out is None:
+            if noalloc:
+                raise ValueError("noalloc=True needs the output vector")
             out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         info = SolveInfo()
-        _check(lib().mhk_nystrom_solve(self._h, float(shift), _f64_dev(rhs, self.n, "rhs"),
-                                       _f64_dev(out, self.n, "x"), float(tol), int(restart), int(maxit),
-                                       C.byref(info)))
+        fn = lib().mhk_nystrom_solve_noalloc if noalloc else lib().mhk_nystrom_solve
+        _check(fn(self._h, float(shift), _f64_dev(rhs, self.n, "rhs"), _f64_dev(out, self.n, "x"), float(tol),
+                  int(restart), int(maxit), C.byref(info)))
         return out, info.as_dict()
 
 

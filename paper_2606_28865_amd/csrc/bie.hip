@@ -7,8 +7,10 @@
 // column zero), 2 GiB at N_B = 16384 and 34 GiB at 65536, resident in HBM for
 // the life of the object.  The product y = (shift I + K) x streams K once per
 // call (HBM bound: 8 N_B^2 bytes); every other GMRES step is O(N_B m).
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mhk_internal.h"
@@ -269,6 +271,8 @@ __global__ void __launch_bounds__(BT) k_rhs(int64_t n, int64_t off, double a, co
 static inline unsigned nb_of(int64_t n) { return (unsigned)((n + BT - 1) / BT); }
 
 // GMRES workspace: device vectors and the host mirror of the small ones.
+// The object's own workspace (nys_workspace) or the fixed scratch array of
+// mhk_nystrom_solve_noalloc.
 struct GmresWs {
     int nblk = 0;               // blocks of the two-stage dot products
     double *V = nullptr;        // [m + 1][n] Krylov basis
@@ -501,6 +505,42 @@ static mhk_status gmres(mhk_nystrom *N, const GmresWs &W, double shift, const do
     return MHK_OK;
 }
 
+// Scratch of mhk_nystrom_solve_noalloc: one fixed device array of
+// NOALLOC_DOUBLES doubles (32 MiB), held by every GPU the library runs on
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it stands for no device address): the address of each
+// device's copy is looked up once, with that device current, and kept.
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)4 << 20;
+constexpr int NOALLOC_MAX_RESTART = 64;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static mhk_status scratch_base(double **out)
+{
+    int dev = 0;
+    BIE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("device index out of the range of the scratch table");
+        return MHK_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(e));
+            return MHK_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MHK_OK;
+}
+
+static inline int64_t round256(int64_t count) { return (count + 31) / 32 * 32; }   // doubles -> 256 B
+
 static mhk_status check_solve(mhk_plan *P, mhk_nystrom *N, const void *g, const void *f_vol, const void *f_trg,
                               double tol, int restart, int maxit, const void *dens, const void *u)
 {
@@ -654,6 +694,61 @@ mhk_status mhk_nystrom_solve(mhk_nystrom *N, double shift, const double *rhs, do
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return st;
+}
+
+mhk_status mhk_nystrom_solve_noalloc(mhk_nystrom *N, double shift, const double *rhs, double *x, double tol,
+                                     int restart, int maxit, mhk_solve_info *info)
+{
+    if (!N || !rhs || !x || !info || rhs == x) {
+        set_error("null Nystrom matrix, vector or info, or rhs aliases x");
+        return MHK_EINVAL;
+    }
+    if (!(tol > 0.0 && tol < 1.0) || restart < 1 || restart > NOALLOC_MAX_RESTART || maxit < 1) {
+        set_error("need 0 < tol < 1, 1 <= restart <= " + std::to_string(NOALLOC_MAX_RESTART) + ", maxit >= 1");
+        return MHK_EINVAL;
+    }
+    const int m = restart;
+    const int64_t n = N->n;
+    const int nblk = gmres_nblk(n);
+    const int64_t nV = round256((int64_t)(m + 1) * n), nvec = round256(n), npart = round256((int64_t)(m + 1) * nblk),
+                  nhd = round256(2 * (m + 1) + 1), nyd = round256(m);
+    const int64_t need = nV + 2 * nvec + npart + nhd + nyd;
+    if (need > NOALLOC_DOUBLES) {
+        set_error("GMRES needs " + std::to_string(need * 8) + " bytes of scratch at N_B = " + std::to_string(n) +
+                  " and restart " + std::to_string(m) + "; the fixed scratch holds " +
+                  std::to_string(NOALLOC_DOUBLES * 8));
+        return MHK_EINVAL;
+    }
+    double *base = nullptr;
+    BIE_TRY(scratch_base(&base));
+    GmresWs W;
+    W.nblk = nblk;
+    W.V = base;
+    W.wv = W.V + nV;
+    W.rv = W.wv + nvec;
+    W.part = W.rv + nvec;
+    W.hd = W.part + npart;
+    W.yd = W.hd + nhd;
+    // host side of the least-squares problem on the stack (restart <= 64)
+    double hh[2 * (NOALLOC_MAX_RESTART + 1) + 1 + NOALLOC_MAX_RESTART];
+    double H[(NOALLOC_MAX_RESTART + 1) * NOALLOC_MAX_RESTART];
+    double cs[NOALLOC_MAX_RESTART], sn[NOALLOC_MAX_RESTART], g[NOALLOC_MAX_RESTART + 1], yv[NOALLOC_MAX_RESTART];
+    W.hh = hh;
+    W.H = H;
+    W.cs = cs;
+    W.sn = sn;
+    W.g = g;
+    W.yv = yv;
+    memset(info, 0, sizeof(*info));
+    const auto t0 = std::chrono::steady_clock::now();
+    const mhk_status st = gmres(N, W, shift, rhs, x, tol, m, maxit, N->stream, info);
+    if (st == MHK_OK) {
+        // GMRES ends with the stream synchronised
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->ms_gmres = ms;
+        info->ms_total = ms;
+    }
     return st;
 }
 
