@@ -140,7 +140,7 @@ struct LocalArgs {
     const uint8_t *gflag;
     const double *pcx, *pcy, *pck, *ends, *gl_t;
     const int32_t *prev, *next, *cand, *cell_start;
-    const double *pbox;
+    const double *pbox, *cbox;
     int32_t *noconv;
     double cell, ox, oy, reach;
     int ncx, ncy;
@@ -304,6 +304,14 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
             bool conv = true;
 #pragma unroll 1
             for (int c = 0; c < 3; ++c) {
+                // a neighbouring panel whose curve box is farther than the
+                // best distance so far cannot improve on it (ties are kept)
+                if (c > 0) {
+                    const double *bb = A.cbox + (size_t)cand[c] * 4;
+                    const double ex = fmax(0.0, fmax(bb[0] - px, px - bb[1]));
+                    const double ey = fmax(0.0, fmax(bb[2] - py, py - bb[3]));
+                    if (ex * ex + ey * ey > d2b) continue;
+                }
                 double t, d2;
                 const bool cv = panel_min(A, cand[c], px, py, t, d2);
                 if (d2 < d2b) { d2b = d2; pbest = cand[c]; tbest = t; conv = cv; }
@@ -518,6 +526,7 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.cand = P->loc.cand;
     A.cell_start = P->loc.cell_start;
     A.pbox = P->loc.pbox;
+    A.cbox = P->loc.cbox;
     A.noconv = P->loc.noconv;
     A.reach = P->loc.reach;
     A.cell = P->loc.cell;

@@ -157,6 +157,7 @@ struct Local {
     int ncx = 0, ncy = 0;
     int32_t *cand = nullptr;
     double *pbox = nullptr;                       // [n_panels][4]: node bounding box xmin, xmax, ymin, ymax
+    double *cbox = nullptr;                       // [n_panels][4]: box of the panel's whole curve (with a margin)
     int32_t *cell_start = nullptr;
     int32_t *noconv = nullptr;                    // device counter: closest-point solves that did not converge
     double *leg = nullptr;                        // [16][16] nodal values -> Legendre coefficients

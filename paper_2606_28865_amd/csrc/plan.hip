@@ -1412,6 +1412,35 @@ mhk_status build_local(mhk_plan *P, Host &H)
     }
     TRY(upload(P, &C.pbox, pbox.data(), npan * 4));
     {
+        // box of each panel's whole curve gamma(t), t in [-1, 1]: 129
+        // Chebyshev points of its Legendre series, grown by 1% of its size
+        // (the curve between the points bulges far less); a neighbouring
+        // panel whose box is farther than the best distance found cannot hold
+        // the closest point
+        std::vector<double> cbox(npan * 4);
+        const int ns = 129;
+        for (int64_t p = 0; p < npan; ++p) {
+            double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+            for (int i = 0; i < ns; ++i) {
+                const double t = -cos(M_PI * i / (ns - 1));
+                double p0 = 1, p1 = t, xv = cx[p * NGL] + cx[p * NGL + 1] * t, yv = cy[p * NGL] + cy[p * NGL + 1] * t;
+                for (int k = 1; k + 1 < NGL; ++k) {
+                    const double p2 = ((2 * k + 1) * t * p1 - k * p0) / (k + 1);
+                    p0 = p1;
+                    p1 = p2;
+                    xv += cx[p * NGL + k + 1] * p2;
+                    yv += cy[p * NGL + k + 1] * p2;
+                }
+                x0 = std::min(x0, xv); x1 = std::max(x1, xv);
+                y0 = std::min(y0, yv); y1 = std::max(y1, yv);
+            }
+            const double m = 0.01 * std::max(x1 - x0, y1 - y0) + 1e-12;
+            cbox[p * 4 + 0] = x0 - m; cbox[p * 4 + 1] = x1 + m;
+            cbox[p * 4 + 2] = y0 - m; cbox[p * 4 + 3] = y1 + m;
+        }
+        TRY(upload(P, &C.cbox, cbox.data(), npan * 4));
+    }
+    {
         int32_t zero = 0;
         TRY(upload(P, &C.noconv, &zero, 1));
     }
