@@ -91,6 +91,12 @@ typedef struct {
     int batch;       /* number of densities / sources per eval call, >= 1           */
     double upsamp;   /* fine-grid oversampling of the NUFFT; <= 0: 2.0              */
     int wspread;     /* spreading window width in grid points; <= 0: from tol       */
+    int local_order; /* local expansions of Section 4.1: 0 or 1 keep the first-order
+                        terms (error O(delta*^{3/2})), 2 adds the printed
+                        delta*^{3/2} and delta*^2 terms of Lemmas 4.1, 4.5, 4.8
+                        and Corollaries 4.4, 4.7, 4.10, 4.11 (error
+                        O(delta*^{5/2})); with 2, f_trg carries f's gradient and
+                        Hessian (see mhk_eval)                                       */
 } mhk_params;
 
 typedef struct {
@@ -159,8 +165,11 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *boun
  * levels + local).  Any of sigma, mu, f_vol may be NULL: the matching output
  * is then not written.  sigma, mu: [batch][N_B]; f_vol: [batch][N_V] values
  * of f at the volume nodes; f_trg: [batch][n_out] values of f at the targets
- * (needed by the local part of V, Lemma 4.8; required when f_vol is given);
- * out_S, out_D, out_V: [batch][n_out]. */
+ * (needed by the local part of V, Lemma 4.8; required when f_vol is given),
+ * or, for a plan with local_order = 2, [batch][6][n_out]: f, f_x, f_y, f_xx,
+ * f_xy, f_yy at the targets (the second-order terms of Lemma 4.8 need f's
+ * normal and second derivatives; exterior targets keep the first-order
+ * complement form); out_S, out_D, out_V: [batch][n_out]. */
 mhk_status mhk_eval(mhk_plan *plan, const void *sigma, const void *mu, const void *f_vol,
                     const void *f_trg, void *out_S, void *out_D, void *out_V);
 

@@ -22,7 +22,7 @@ NGL = 16
 class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("prec", C.c_int), ("J", C.c_int),
                 ("delta", C.c_double), ("dx", C.c_double), ("batch", C.c_int),
-                ("upsamp", C.c_double), ("wspread", C.c_int)]
+                ("upsamp", C.c_double), ("wspread", C.c_int), ("local_order", C.c_int)]
 
 
 class Boundary(C.Structure):
@@ -134,9 +134,9 @@ def _check(rc):
         raise MhkError(rc, lib().mhk_last_error().decode())
 
 
-def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0):
+def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0, local_order=1):
     return Params(float(alpha), float(tol), int(prec), int(J), float(delta), float(dx), int(batch),
-                  float(upsamp), int(wspread))
+                  float(upsamp), int(wspread), int(local_order))
 
 
 def resolve_params(**kw):
@@ -215,6 +215,8 @@ class Plan:
         self.n_out = self.nt + (self.nb if on_surface else 0)
         self.batch = int(params.batch)
         self.dtype = torch.float64 if params.prec == MHK_FP64 else torch.float32
+        # f at the targets: the value, or (local_order 2) the value, gradient and Hessian
+        self.f_rows = 6 if int(params.local_order) == 2 else 1
 
     def close(self):
         if getattr(self, "_h", None):
@@ -276,7 +278,7 @@ class Plan:
         sigma = self._dev(sigma, self.nb)
         mu = self._dev(mu, self.nb)
         f_vol = self._dev(f_vol, self.nv)
-        f_trg = self._dev(f_trg, self.n_out)
+        f_trg = self._dev(f_trg, self.f_rows * self.n_out)
         out = self._outs(out, (sigma, mu, f_vol))
         cur, other = self._streams()
         if other:
@@ -304,7 +306,7 @@ class Plan:
         sigma = self._dev(sigma, self.nb)
         mu = self._dev(mu, self.nb)
         f_vol = self._dev(f_vol, self.nv)
-        f_trg = self._dev(f_trg, self.n_out)
+        f_trg = self._dev(f_trg, self.f_rows * self.n_out)
         out = self._outs(out, (sigma, mu, f_vol))
         cur, other = self._streams()
         if other:

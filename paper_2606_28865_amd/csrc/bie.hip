@@ -548,8 +548,8 @@ static mhk_status check_solve(mhk_plan *P, mhk_nystrom *N, const void *g, const 
         set_error("null plan, Nystrom matrix, data or output pointer");
         return MHK_EINVAL;
     }
-    if (P->p.prec != MHK_FP64 || P->p.batch != 1) {
-        set_error("the boundary integral solves need an FP64 plan with batch 1");
+    if (P->p.prec != MHK_FP64 || P->p.batch != 1 || P->p.local_order >= 2) {
+        set_error("the boundary integral solves need an FP64 plan with batch 1 and first-order local expansions");
         return MHK_EUNSUPPORTED;
     }
     if (P->nout != P->nt + P->nb) {

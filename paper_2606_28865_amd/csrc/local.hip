@@ -26,7 +26,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const double *__restrict__ leg,
                                                       const T *__restrict__ sigma,
                                                       const T *__restrict__ mu,
-                                                      const T *__restrict__ f_trg, int64_t nout, int64_t nt,
+                                                      const T *__restrict__ f_trg, int64_t nout, int frows, int64_t nt,
                                                       double *__restrict__ cs, double *__restrict__ cm,
                                                       double *__restrict__ cf)
 {
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_panel_coeffs(int64_t npan, int B, const
     }
     if (f_trg) {
         const int64_t b = pb / npan, p = pb % npan;
-        const T *f = f_trg + b * nout + nt + p * NGL;
+        const T *f = f_trg + b * frows * nout + nt + p * NGL;
         double v = 0;
 #pragma unroll
         for (int i = 0; i < NGL; ++i) v = fma(row[i], (double)f[i], v);
@@ -123,6 +123,125 @@ __device__ inline double leg1(const double *__restrict__ c, double t)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// Second-order local expansions (local_order = 2)
+// ---------------------------------------------------------------------------
+// Taylor coefficients F[m] = c^(m)(t)/m!, m = 0..4, of a Legendre series at
+// t, with P_{k+1}^(m) = P_{k-1}^(m) + (2k+1) P_k^(m-1) for the derivatives.
+__device__ inline void leg_taylor4(const double *__restrict__ c, double t, double F[5])
+{
+    double pm[5] = {1.0, 0.0, 0.0, 0.0, 0.0}, p[5] = {t, 1.0, 0.0, 0.0, 0.0};
+    double v[5] = {c[0] + c[1] * t, c[1], 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 1; k < NGL - 1; ++k) {
+        double pn[5];
+        pn[0] = ((2.0 * k + 1.0) / (k + 1.0)) * t * p[0] - ((double)k / (k + 1.0)) * pm[0];
+#pragma unroll
+        for (int m = 1; m < 5; ++m) pn[m] = pm[m] + (2 * k + 1) * p[m - 1];
+        const double a = c[k + 1];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            pm[m] = p[m];
+            p[m] = pn[m];
+            v[m] = fma(a, pn[m], v[m]);
+        }
+    }
+    F[0] = v[0];
+    F[1] = v[1];
+    F[2] = v[2] * 0.5;
+    F[3] = v[3] * (1.0 / 6.0);
+    F[4] = v[4] * (1.0 / 24.0);
+}
+
+// Derivatives d^m/dxi^m (m = 1, 2, 4; d[0] the value) of a function with
+// Taylor coefficients F in tau = t - t*, where tau = b1 xi + b2 xi^2 + b3 xi^3
+// + b4 xi^4 is the reversion of the tangent-line coordinate xi(tau).
+__device__ inline void xi_derivs(const double F[5], double b1, double b2, double b3, double b4, double d[5])
+{
+    const double g1 = F[1] * b1;
+    const double g2 = F[1] * b2 + F[2] * b1 * b1;
+    const double g3 = F[1] * b3 + F[2] * 2.0 * b1 * b2 + F[3] * b1 * b1 * b1;
+    const double g4 = F[1] * b4 + F[2] * (b2 * b2 + 2.0 * b1 * b3) + F[3] * 3.0 * b1 * b1 * b2 + F[4] * b1 * b1 * b1 * b1;
+    d[0] = F[0];
+    d[1] = g1;
+    d[2] = 2.0 * g2;
+    d[3] = 6.0 * g3;
+    d[4] = 24.0 * g4;
+}
+
+// Tangent-line parameterisation of the boundary at t on a panel with
+// Legendre coefficients cx, cy (Section 4.1): unit tangent T0 (increasing t),
+// inward normal N0 = (-T0y, T0x) (counter-clockwise curves), the reversion
+// coefficients b1..b4 of xi(tau) = (gamma(t* + tau) - gamma(t*)).T0, and the
+// third and fourth xi-derivatives g3, g4 of the boundary's height
+// (gamma(t* + tau) - gamma(t*)).N0 over the tangent line.
+__device__ inline void tangent_line(const double *__restrict__ cx, const double *__restrict__ cy, double t,
+                                    double &tx, double &ty, double b[4], double &g3, double &g4)
+{
+    double X[5], Y[5];
+    leg_taylor4(cx, t, X);
+    leg_taylor4(cy, t, Y);
+    const double sp = sqrt(X[1] * X[1] + Y[1] * Y[1]);
+    tx = X[1] / sp;
+    ty = Y[1] / sp;
+    const double nx = -ty, ny = tx;
+    double c[5], e[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        c[m] = X[m] * tx + Y[m] * ty;
+        e[m] = X[m] * nx + Y[m] * ny;
+    }
+    e[0] = 0.0;
+    e[1] = 0.0;
+    const double c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4];
+    const double i1 = 1.0 / c1, i2 = i1 * i1, i3 = i2 * i1;
+    b[0] = i1;
+    b[1] = -c2 * i3;
+    b[2] = (2.0 * c2 * c2 - c1 * c3) * i3 * i2;
+    b[3] = (5.0 * c1 * c2 * c3 - c1 * c1 * c4 - 5.0 * c2 * c2 * c2) * i3 * i3 * i1;
+    double h[5];
+    xi_derivs(e, b[0], b[1], b[2], b[3], h);
+    g3 = h[3];
+    g4 = h[4];
+}
+
+// (2 erf(c) - 4 c e^{-c^2}/sqrt(pi))/c^3, the value of Q0 at c1 = 0
+// (Corollaries 4.4, 4.7, 4.10); its Taylor series below c = 1/2, where the
+// difference cancels.
+__device__ inline double q0_on(double c)
+{
+    if (c < 0.5) {
+        // (4/sqrt(pi)) sum_{n>=1} (-1)^{n+1} 2n c^{2n-2} / (n! (2n+1))
+        const double x = c * c;
+        double s = 0.0, term = 1.0;   // term = x^{n-1}/n!
+        for (int n = 1; n <= 14; ++n) {
+            term = n == 1 ? 1.0 : term * x / n;
+            const double v = 2.0 * n / (2.0 * n + 1.0) * term;
+            s += (n % 2 == 1) ? v : -v;
+        }
+        return s * 2.2567583341910251478;   // 4/sqrt(pi)
+    }
+    return (2.0 * erf(c) - 2.2567583341910251478 * c * exp(-c * c)) / (c * c * c);
+}
+
+// (1 - (1 + c^2) e^{-c^2})/c^4 (Corollaries 4.10, 4.11); its Taylor series
+// below c = 1/2.
+__device__ inline double v2_far(double c)
+{
+    const double x = c * c;
+    if (c < 0.5) {
+        // sum_{n>=2} (-1)^n (n - 1) x^{n-2} / n!
+        double s = 0.0, term = 0.5;   // term = x^{n-2}/n!
+        for (int n = 2; n <= 16; ++n) {
+            if (n > 2) term *= x / n;
+            const double v = (n - 1) * term;
+            s += (n % 2 == 0) ? v : -v;
+        }
+        return s;
+    }
+    return (-expm1(-x) - x * exp(-x)) / (x * x);
+}
+
 template <typename T>
 struct LocalArgs {
     int64_t nout, nt, nb, npan;
@@ -145,6 +264,8 @@ struct LocalArgs {
     double cell, ox, oy, reach;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
+    int order;             // local expansions: 1 first order, 2 with the second-order terms
+    int frows;             // rows of f_trg per density: 1 (f) or 6 (f and its gradient and Hessian)
     const T *acc;          // [3][B][nout]: S, D, V in sorted order (history part)
     const T *lev;          // [2][B][nout]: S, D of the level sums, or null
     T *out_s, *out_d, *out_v;
@@ -249,6 +370,15 @@ __device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double
 // inside the layer band with a closest point; bit 1: exterior target inside
 // the volume band) and geo[k * nout + s] for k = GEO_T, GEO_P0, ... GEO_VFAC.
 enum { GEO_T, GEO_P0, GEO_P1, GEO_U0, GEO_U1, GEO_U2, GEO_KAP, GEO_MF1, GEO_MF2, GEO_VFAC, GEO_N };
+// second-order plans store more per target: the coefficients of the
+// delta*^{3/2} and delta*^2 layer terms (Q0, Q1, P2, P3, U3, U4; zero but Q0
+// on the boundary), the reversion coefficients b1..b4 and the curve's g3, g4
+// at the closest point, its unit tangent, and the factors A, B, C of the V
+// terms delta^{3/2}(2 f_eta - f kappa0)/8 A + delta^2 [(f_eta kappa0/8 -
+// 3 f kappa0^2/32 - f_etaeta/8) B + (f_etaeta + f_xixi)/8 C]
+enum { GEO_Q0 = GEO_N, GEO_Q1, GEO_P2, GEO_P3, GEO_U3, GEO_U4, GEO_B1, GEO_B2, GEO_B3, GEO_B4, GEO_G3, GEO_G4,
+       GEO_TX, GEO_TY, GEO_VA, GEO_VB, GEO_VC, GEO_N2 };
+static_assert(GEO_N == LOCAL_GEO_N1 && GEO_N2 == LOCAL_GEO_N2, "local geometry layout");
 
 __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double *__restrict__ geo,
                                                     int32_t *__restrict__ pan, uint8_t *__restrict__ flag)
@@ -363,6 +493,78 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
         }
     }
     const int64_t n = A.nout;
+    if (A.order >= 2) {
+        double q0 = 0, q1 = 0, p2 = 0, p3 = 0, u3 = 0, u4 = 0, bb[4] = {0, 0, 0, 0}, g3 = 0, g4 = 0;
+        double ttx = 1.0, tty = 0.0, va = 0.0, vb = 0.0, vc = 0.0;
+        // the boundary point whose tangent line is used: the node itself on
+        // the boundary, the closest point elsewhere
+        int pp = -1;
+        double tt = 0.0;
+        if (on) {
+            const int64_t i = idx - A.nt;
+            pp = (int)(i / NGL);
+            tt = A.gl_t[i % NGL];
+        } else if (pbest >= 0) {
+            pp = pbest;
+            tt = tbest;
+        }
+        if (pp >= 0) {
+            tangent_line(A.pcx + (size_t)pp * NGL, A.pcy + (size_t)pp * NGL, tt, ttx, tty, bb, g3, g4);
+            if (!on) kap = leg1(A.pck + (size_t)pp * NGL, tt);
+        }
+        if (on) {
+            q0 = q0_on(c2);                                   // Cor. 4.4, 4.7 (c1 = 0)
+            va = q0_on(c2v);                                  // Cor. 4.10
+            vc = 4.0 * v2_far(c2v);
+        } else {
+            if (near_s) {
+                // Lemma 4.1, 4.5 coefficients at c1 = r / sqrt(delta*)
+                const double c1 = r / sq, a = 0.5 * c1;
+                const double em = erfcx(a - c2), ep = erfcx(a + c2);
+                const double pre = exp(-a * a - c2 * c2);
+                const double phim = pre * (em - ep), phip = pre * (em + ep);
+                const double z = 1.1283791670955125739 * 2.0 * c2 * pre;   // 4 c2 e^{-c1^2/4 - c2^2}/sqrt(pi)
+                q0 = (phim - z) / (c2 * c2 * c2) + c1 * phip / (c2 * c2);
+                q1 = c1 * q0;
+                p2 = c1 * c1 * phim / c2;
+                p3 = c1 * p2;
+                u3 = c1 * c1 * c1 * phip;
+                u4 = c1 * u3;
+            }
+            if (inside && r < A.band_v) {
+                // Lemma 4.8 coefficients at c1 = r / sqrt(delta)
+                const double c1 = r / sv, a = 0.5 * c1;
+                const double em = erfcx(a - c2v), ep = erfcx(a + c2v), e0 = erfcx(a);
+                const double pre = exp(-a * a - c2v * c2v);
+                const double phim = pre * (em - ep), phip = pre * (em + ep);
+                const double z = 1.1283791670955125739 * 2.0 * c2v * pre;
+                const double w0 = (-4.0 * expm1(-c2v * c2v) + pre * ((e0 - em) + (e0 - ep))) / (c2v * c2v);
+                const double lam = pre * e0;                  // e^{-c2^2} erfc(c1/2)
+                va = (phim - z) / (c2v * c2v * c2v) + c1 * phip / (c2v * c2v);
+                vb = c1 * va;
+                vc = (2.0 * w0 - c1 * phim / c2v + 4.0 * (lam - 2.0 * exp(-c2v * c2v))) / (c2v * c2v);
+            } else if (inside) {
+                vc = 8.0 * v2_far(c2v);                       // Cor. 4.11
+            }
+        }
+        geo[GEO_Q0 * n + s] = q0;
+        geo[GEO_Q1 * n + s] = q1;
+        geo[GEO_P2 * n + s] = p2;
+        geo[GEO_P3 * n + s] = p3;
+        geo[GEO_U3 * n + s] = u3;
+        geo[GEO_U4 * n + s] = u4;
+        geo[GEO_B1 * n + s] = bb[0];
+        geo[GEO_B2 * n + s] = bb[1];
+        geo[GEO_B3 * n + s] = bb[2];
+        geo[GEO_B4 * n + s] = bb[3];
+        geo[GEO_G3 * n + s] = g3;
+        geo[GEO_G4 * n + s] = g4;
+        geo[GEO_TX * n + s] = ttx;
+        geo[GEO_TY * n + s] = tty;
+        geo[GEO_VA * n + s] = va;
+        geo[GEO_VB * n + s] = vb;
+        geo[GEO_VC * n + s] = vc;
+    }
     geo[GEO_T * n + s] = tbest;
     geo[GEO_P0 * n + s] = P0;
     geo[GEO_P1 * n + s] = P1;
@@ -411,6 +613,34 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
         }
     }
 
+    // second order: coefficients, tangent-line data and the boundary point
+    // (the node itself on the boundary, the closest point elsewhere)
+    const bool o2 = do_local && A.order >= 2;
+    double q0 = 0, q1 = 0, p2 = 0, p3 = 0, u3 = 0, u4 = 0, bb[4] = {0, 0, 0, 0}, g3 = 0, g4 = 0;
+    double ttx = 1.0, tty = 0.0, va = 0, vb = 0, vc = 0, kap2 = 0.0, tt2 = 0.0;
+    int pp2 = -1;
+    if (o2) {
+        q0 = A.geo[GEO_Q0 * n + s]; q1 = A.geo[GEO_Q1 * n + s];
+        p2 = A.geo[GEO_P2 * n + s]; p3 = A.geo[GEO_P3 * n + s];
+        u3 = A.geo[GEO_U3 * n + s]; u4 = A.geo[GEO_U4 * n + s];
+        bb[0] = A.geo[GEO_B1 * n + s]; bb[1] = A.geo[GEO_B2 * n + s];
+        bb[2] = A.geo[GEO_B3 * n + s]; bb[3] = A.geo[GEO_B4 * n + s];
+        g3 = A.geo[GEO_G3 * n + s]; g4 = A.geo[GEO_G4 * n + s];
+        ttx = A.geo[GEO_TX * n + s]; tty = A.geo[GEO_TY * n + s];
+        va = A.geo[GEO_VA * n + s]; vb = A.geo[GEO_VB * n + s]; vc = A.geo[GEO_VC * n + s];
+        if (on) {
+            const int64_t i = idx - A.nt;
+            pp2 = (int)(i / NGL);
+            tt2 = A.gl_t[i % NGL];
+            kap2 = A.bk[i];
+        } else {
+            pp2 = pbest;
+            tt2 = A.geo[GEO_T * n + s];
+            kap2 = A.geo[GEO_KAP * n + s];
+        }
+    }
+    const double d32 = A.dstar * sq, d2 = A.dstar * A.dstar;
+
 #pragma unroll 1
     for (int b = 0; b < A.B; ++b) {
         const size_t ob = (size_t)b * A.nout + idx;
@@ -425,6 +655,17 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                 } else if (near_s) {
                     const double sg = leg1(A.cs + ((size_t)b * A.npan + pbest) * NGL, tbest);
                     v += sq * sg * P0 * 0.25 + A.dstar * rho * kap * sg * P1 * 0.125;     // Lemma 4.1
+                }
+                if (o2 && (on || near_s) && pp2 >= 0) {
+                    // delta*^{3/2} and delta*^2 terms of Lemma 4.1 (Cor. 4.4 on the boundary)
+                    double F[5], d[5];
+                    leg_taylor4(A.cs + ((size_t)b * A.npan + pp2) * NGL, tt2, F);
+                    xi_derivs(F, bb[0], bb[1], bb[2], bb[3], d);
+                    const double s0 = on ? (double)A.sigma[(size_t)b * A.nb + (idx - A.nt)] : d[0];
+                    const double k = kap2;
+                    v += d32 * (k * k * s0 / 32.0 * (q0 + 3.0 * p2) + d[2] / 8.0 * q0) +
+                         d2 * rho * (k * k * k * s0 / 64.0 * (-3.0 * q1 + 5.0 * p3) +
+                                     (3.0 * k * d[2] / 16.0 + d[1] * g3 / 8.0 + s0 * g4 / 32.0) * q1);
                 }
             }
             A.out_s[ob] = (T)v;
@@ -443,18 +684,53 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
                     v += -rho * m0 * U0 * 0.25 - sq * kap * m0 * (P0 + U1) * 0.125                // Lemma 4.5
                          - A.dstar * (rho * mss * P1 * 0.125 + 3.0 * rho * kap * kap * m0 * (P1 + U2) / 32.0);
                 }
+                if (o2 && (on || near_s) && pp2 >= 0) {
+                    // delta*^{3/2} and delta*^2 terms of Lemma 4.5 (Cor. 4.7 on
+                    // the boundary); the gamma'''' term of the delta*^{3/2}
+                    // bracket multiplies (3 Q0 + P2) (the series of the local
+                    // integral; the kappa^3 term keeps (3 Q0 - U3))
+                    double F[5], d[5];
+                    leg_taylor4(A.cm + ((size_t)b * A.npan + pp2) * NGL, tt2, F);
+                    xi_derivs(F, bb[0], bb[1], bb[2], bb[3], d);
+                    const double m0 = on ? (double)A.mu[(size_t)b * A.nb + (idx - A.nt)] : d[0];
+                    const double k = kap2;
+                    v += d32 * (5.0 * k * k * k * m0 / 64.0 * (3.0 * q0 - u3) - m0 * g4 / 32.0 * (3.0 * q0 + p2) +
+                                3.0 * k * d[2] / 16.0 * (-q0 - p2) + d[1] * g3 / 8.0 * (-2.0 * q0 - p2)) +
+                         d2 * (35.0 * rho * k * k * k * k * m0 / 512.0 * (9.0 * q1 + 2.0 * p3 - u4) -
+                               rho * d[4] / 32.0 * q1 - 15.0 * rho * k * k * d[2] / 64.0 * (q1 + p3)) -
+                         d2 * (5.0 * rho * k * d[1] * g3 / 16.0 * (2.0 * q1 + p3) +
+                               (5.0 * rho * k * m0 * g4 / 64.0 + 5.0 * rho * m0 * g3 * g3 / 96.0) * (3.0 * q1 + p3));
+                }
             }
             A.out_d[ob] = (T)v;
         }
         if (wv) {
             double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
             if (do_local) {
+                // f (and with second order its gradient and Hessian) at the target
+                const T *fr = A.f_trg + (size_t)b * A.frows * A.nout + idx;
                 double f;
                 if (ext)
                     f = A.cf ? leg1(A.cf + ((size_t)b * A.npan + pbest) * NGL, tbest) : NAN;
                 else
-                    f = (double)A.f_trg[ob];
+                    f = (double)fr[0];
                 v += A.delta * f * vfac;
+                if (o2 && !ext) {
+                    // delta^{3/2} and delta^2 terms of Lemma 4.8 (Cor. 4.10 on the
+                    // boundary, Cor. 4.11 far from it): f's derivatives along
+                    // the inward normal N0 = (-t_y, t_x) and the tangent t
+                    const size_t nn = (size_t)A.nout;
+                    const double fx = (double)fr[nn], fy = (double)fr[2 * nn];
+                    const double fxx = (double)fr[3 * nn], fxy = (double)fr[4 * nn], fyy = (double)fr[5 * nn];
+                    const double nx = -tty, ny = ttx;
+                    const double fe = fx * nx + fy * ny;
+                    const double fee = fxx * nx * nx + 2.0 * fxy * nx * ny + fyy * ny * ny;
+                    const double fxi = fxx * ttx * ttx + 2.0 * fxy * ttx * tty + fyy * tty * tty;
+                    const double k = kap2;
+                    v += A.delta * sqrt(A.delta) * (2.0 * fe - f * k) / 8.0 * va +
+                         A.delta * A.delta * ((fe * k / 8.0 - 3.0 * f * k * k / 32.0 - fee / 8.0) * vb +
+                                              (fee + fxi) / 8.0 * vc);
+                }
             }
             A.out_v[ob] = (T)v;
         }
@@ -480,7 +756,8 @@ static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, c
 {
     const int64_t tot = P->npan * NGL * P->p.batch;
     hipLaunchKernelGGL(k_panel_coeffs<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
-                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, (const T *)f_bnd, P->nout, P->nt,
+                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, (const T *)f_bnd, P->nout,
+                       P->p.local_order >= 2 ? 6 : 1, P->nt,
                        P->loc.csig, P->loc.cmu, P->loc.cf);
     return hipGetLastError();
 }
@@ -539,6 +816,8 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.dstar = P->dstar;
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
+    A.order = P->p.local_order >= 2 ? 2 : 1;
+    A.frows = A.order >= 2 ? 6 : 1;
     A.acc = (const T *)P->acc;
     A.lev = nullptr;
     A.out_s = A.out_d = A.out_v = nullptr;

@@ -42,6 +42,8 @@ constexpr int MAXW = 16;         // maximum spreading window width
 constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
 constexpr int LV_WAVE = 64;      // lanes per level-sum wavefront
 constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
+constexpr int LOCAL_GEO_N1 = 10; // doubles of local geometry per target, first-order plans
+constexpr int LOCAL_GEO_N2 = 27; // the same with the second-order terms (local_order = 2)
 
 void set_error(const std::string &msg);
 

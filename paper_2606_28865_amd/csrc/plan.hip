@@ -233,6 +233,11 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         double kmax = 0.9 * M_PI / p.dx;
         p.delta = log(1.0 / p.tol) / (kmax * kmax + p.alpha * p.alpha);
     }
+    if (p.local_order == 0) p.local_order = 1;
+    if (p.local_order != 1 && p.local_order != 2) {
+        set_error("local_order must be 0, 1 or 2");
+        return MHK_EINVAL;
+    }
     if (p.upsamp <= 0) p.upsamp = 2.0;
     if (p.upsamp < 1.25 || p.upsamp > 3.0) {
         set_error("upsamp must be in [1.25, 3]");
@@ -1461,7 +1466,7 @@ mhk_status build_local(mhk_plan *P, Host &H)
     TRY(dalloc(P, &C.cmu, (int64_t)P->p.batch * nb));
     TRY(dalloc(P, &C.cf, (int64_t)P->p.batch * nb));
     // per-plan geometry of the local part (closest points and coefficients)
-    TRY(dalloc(P, &C.geo, 10 * std::max<int64_t>(P->nout, 1)));
+    TRY(dalloc(P, &C.geo, (P->p.local_order >= 2 ? LOCAL_GEO_N2 : LOCAL_GEO_N1) * std::max<int64_t>(P->nout, 1)));
     TRY(dalloc(P, &C.gpan, std::max<int64_t>(P->nout, 1)));
     TRY(dalloc(P, &C.gflag, std::max<int64_t>(P->nout, 1)));
     return MHK_OK;
@@ -1637,7 +1642,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
         s += ns * (8 * 5 + 4) + 3 * B * ns * 8;
     }
     s += nb * (8 * 3 + 4) + 3 * B * nb * 8;   // local
-    s += nout * (10 * 8 + 4 + 1);             // local geometry per target
+    s += nout * ((p.local_order >= 2 ? LOCAL_GEO_N2 : LOCAL_GEO_N1) * 8 + 4 + 1);   // local geometry per target
     if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {

@@ -459,6 +459,22 @@ class GaussSource:
             out += a * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / s)
         return out
 
+    def jet(self, x, y):
+        """[6, n]: f, f_x, f_y, f_xx, f_xy, f_yy at the points (analytic)."""
+        s = 2 * self.width ** 2
+        x, y = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float))
+        out = np.zeros((6,) + x.shape)
+        for cx, cy, a in zip(self.cx, self.cy, self.amp):
+            dx, dy = x - cx, y - cy
+            g = a * np.exp(-(dx * dx + dy * dy) / s)
+            out[0] += g
+            out[1] += -2 * dx / s * g
+            out[2] += -2 * dy / s * g
+            out[3] += (4 * dx * dx / s ** 2 - 2 / s) * g
+            out[4] += 4 * dx * dy / s ** 2 * g
+            out[5] += (4 * dy * dy / s ** 2 - 2 / s) * g
+        return out
+
 
 def gauss_source(g: np.random.Generator, centers_x, centers_y, width=0.2):
     return GaussSource(np.asarray(centers_x, float), np.asarray(centers_y, float),

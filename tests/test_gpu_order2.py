@@ -1,0 +1,101 @@
+"""Parity of second-order plans (local_order = 2: the delta*^{3/2} and
+delta*^2 terms of Lemmas 4.1, 4.5, 4.8 and Corollaries 4.4, 4.7, 4.10,
+4.11) with the oracle at the same order, the FP64 path at 1e-10 relative
+per potential; f's gradient and Hessian at the targets come from the
+analytic Gaussian sources, [6][n_out] rows f, f_x, f_y, f_xx, f_xy, f_yy."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from helpers import rel_err, small_multibody, stratified_subset
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _jets(w, batch_src=None):
+    X = np.concatenate([w.tx, w.boundary["x"]])
+    Y = np.concatenate([w.ty, w.boundary["y"]])
+    src = w.meta["fsrc"] if batch_src is None else batch_src
+    return src.jet(X, Y), src(w.volume["x"], w.volume["y"])
+
+
+def _oracle(w, alpha, delta, sigma, mu, f_vol, jet, subset=None):
+    P = O.Problem(alpha, delta, 3, w.boundary, volume=w.volume, targets=(w.tx, w.ty), inside=w.inside,
+                  on_surface=True, sigma=sigma, mu=mu, f_vol=f_vol, f_trg=jet[0], f_jet=jet[1:],
+                  local_order=2)
+    return P.eval(subset)
+
+
+@pytest.mark.parametrize("alpha", [10.0, 3.0])
+def test_order2_config0_all_targets(alpha):
+    """Config 0 (starfish, 64x64 grid with exterior targets, boundary nodes)."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    print(f"case order2 config0 alpha={alpha}", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx, local_order=2), w.boundary, w.volume,
+                  (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    jet, fv = _jets(w)
+    S, D, V = plan.eval(_dev(w.sigma), _dev(w.mu), _dev(fv), _dev(jet))
+    torch.cuda.synchronize()
+    So, Do, Vo = _oracle(w, alpha, info["delta"], w.sigma, w.mu, fv, jet)
+    errs = [rel_err(S.cpu().numpy(), So), rel_err(D.cpu().numpy(), Do), rel_err(V.cpu().numpy(), Vo)]
+    print(f"order2 config0 alpha={alpha}: errors {errs}", flush=True)
+    assert max(errs) < TOL, errs
+    # the second-order terms are there: the first-order plan differs
+    plan1 = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx), w.boundary, w.volume, (w.tx, w.ty, w.inside),
+                   on_surface=True)
+    S1, D1, V1 = plan1.eval(_dev(w.sigma), _dev(w.mu), _dev(fv), _dev(jet[0]))
+    torch.cuda.synchronize()
+    assert float((S1 - S).abs().max()) > 1e-6 * float(S.abs().max())
+
+
+def test_order2_batch_of_two():
+    """Two densities and sources per call (batch indexing of the jets)."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    print("case order2 config0 batch 2", flush=True)
+    g = np.random.default_rng(9)
+    src2 = synth.gauss_source(g, np.array([0.3, -0.2, 0.1, -0.4]), np.array([0.1, 0.3, -0.5, -0.1]))
+    jet1, fv1 = _jets(w)
+    jet2, fv2 = _jets(w, src2)
+    sig = np.stack([w.sigma, np.roll(w.sigma, 37)])
+    mu = np.stack([w.mu, 0.5 * w.mu])
+    plan = M.Plan(M.make_params(alpha=10.0, tol=TOL, dx=w.dx, batch=2, local_order=2), w.boundary, w.volume,
+                  (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    out = plan.eval(_dev(sig), _dev(mu), _dev(np.stack([fv1, fv2])), _dev(np.stack([jet1, jet2])))
+    torch.cuda.synchronize()
+    for b, (jet, fv) in enumerate(((jet1, fv1), (jet2, fv2))):
+        ref = _oracle(w, 10.0, info["delta"], sig[b], mu[b], fv, jet)
+        errs = [rel_err(o[b].cpu().numpy(), r) for o, r in zip(out, ref)]
+        print(f"order2 batch item {b}: errors {errs}", flush=True)
+        assert max(errs) < TOL, (b, errs)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 30.0])
+def test_order2_multibody_sampled(alpha):
+    """3-body workload with the fine split delta = 2e-5, stratified sample."""
+    import paper_2606_28865_amd as M
+    w = small_multibody()
+    print(f"case order2 multibody alpha={alpha}", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=TOL, delta=2e-5, local_order=2), w.boundary, w.volume,
+                  (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    jet, fv = _jets(w)
+    S, D, V = plan.eval(_dev(w.sigma), _dev(w.mu), _dev(fv), _dev(jet))
+    torch.cuda.synchronize()
+    sub = stratified_subset(w, info["band_volume"])
+    So, Do, Vo = _oracle(w, alpha, info["delta"], w.sigma, w.mu, fv, jet, subset=sub)
+    errs = [rel_err(S.cpu().numpy().ravel()[sub], So), rel_err(D.cpu().numpy().ravel()[sub], Do),
+            rel_err(V.cpu().numpy().ravel()[sub], Vo)]
+    print(f"order2 multibody alpha={alpha}: errors {errs}", flush=True)
+    assert max(errs) < TOL, errs
