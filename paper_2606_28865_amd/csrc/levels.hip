@@ -29,7 +29,10 @@
 // the separation x - x_q is formed in FP64 from FP64 positions and rounded
 // once, so that its relative error is that of one rounding even when the
 // separation is far smaller than the coordinates; the table (degree 7), the
-// kernel evaluation and the accumulation are FP32.
+// kernel evaluation and the accumulation are FP32.  The FP64 path keeps its
+// table's three highest coefficients, each below 4e-8 of K_j(0), as floats
+// and starts Horner's rule over them in FP32 (52 bytes of table per pair
+// instead of 64); the rest is FP64.
 #include "mhk_internal.h"
 
 namespace mhk {
@@ -140,7 +143,79 @@ __device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv
     return g;
 }
 
-template <int BCH, typename T, int NC, int STRIDE>
+// p(v) and p'(v) of a table segment by Horner's rule for two sources at
+// once (K_j^S and, up to the factor d_scale, K_j^D); the derivative's first
+// step is c_7.  FP32 table: eight floats.
+__device__ inline void horner2(const PairGeo<float> &g0, const PairGeo<float> &g1, float &ks0, float &kd0,
+                               float &ks1, float &kd1)
+{
+    kd0 = g0.c[TAB_NC - 1];
+    kd1 = g1.c[TAB_NC - 1];
+    ks0 = fmaf(kd0, g0.v, g0.c[TAB_NC - 2]);
+    ks1 = fmaf(kd1, g1.v, g1.c[TAB_NC - 2]);
+#pragma unroll
+    for (int m = TAB_NC - 3; m >= 0; --m) {
+        kd0 = fmaf(kd0, g0.v, ks0);
+        kd1 = fmaf(kd1, g1.v, ks1);
+        ks0 = fmaf(ks0, g0.v, g0.c[m]);
+        ks1 = fmaf(ks1, g1.v, g1.c[m]);
+    }
+}
+
+// FP64 table: c_0..c_4 as doubles, then c_5..c_7 as floats; the high part
+// goes through Horner's rule in FP32 and the result continues in FP64 (the
+// same order as the plan's accuracy check of the table).
+__device__ inline void horner_hi(const double *c, double v, float &ks, float &kd)
+{
+    const float *h = reinterpret_cast<const float *>(c + TAB_NC64);
+    const float vf = (float)v;
+    kd = h[2];
+    ks = fmaf(kd, vf, h[1]);
+    kd = fmaf(kd, vf, ks);
+    ks = fmaf(ks, vf, h[0]);
+}
+__device__ inline void horner2(const PairGeo<double> &g0, const PairGeo<double> &g1, double &ks0, double &kd0,
+                               double &ks1, double &kd1)
+{
+    float hs0, hd0, hs1, hd1;
+    horner_hi(g0.c, g0.v, hs0, hd0);
+    horner_hi(g1.c, g1.v, hs1, hd1);
+    ks0 = hs0;
+    kd0 = hd0;
+    ks1 = hs1;
+    kd1 = hd1;
+#pragma unroll
+    for (int m = TAB_NC64 - 1; m >= 0; --m) {
+        kd0 = fma(kd0, g0.v, ks0);
+        kd1 = fma(kd1, g1.v, ks1);
+        ks0 = fma(ks0, g0.v, g0.c[m]);
+        ks1 = fma(ks1, g1.v, g1.c[m]);
+    }
+}
+__device__ inline void horner1(const PairGeo<float> &g, float &ks, float &kd)
+{
+    kd = g.c[TAB_NC - 1];
+    ks = fmaf(kd, g.v, g.c[TAB_NC - 2]);
+#pragma unroll
+    for (int m = TAB_NC - 3; m >= 0; --m) {
+        kd = fmaf(kd, g.v, ks);
+        ks = fmaf(ks, g.v, g.c[m]);
+    }
+}
+__device__ inline void horner1(const PairGeo<double> &g, double &ks, double &kd)
+{
+    float hs, hd;
+    horner_hi(g.c, g.v, hs, hd);
+    ks = hs;
+    kd = hd;
+#pragma unroll
+    for (int m = TAB_NC64 - 1; m >= 0; --m) {
+        kd = fma(kd, g.v, ks);
+        ks = fma(ks, g.v, g.c[m]);
+    }
+}
+
+template <int BCH, typename T, int STRIDE>
 __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
 {
     extern __shared__ double lds[];
@@ -213,18 +288,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                 const PairGeo<T> g1 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k + 1), bcast(cur.y, k + 1), fscale,
                                                           f_max, s_tab, zseg, in1);
                 if (__ballot(in0 || in1) == 0) continue;
-                // p(v) and p'(v) by Horner's rule for both sources (K_j^S
-                // and, up to the factor d_scale, K_j^D); the derivative's
-                // first step is c_7
-                T kd0 = g0.c[NC - 1], kd1 = g1.c[NC - 1];
-                T ks0 = fma(kd0, g0.v, g0.c[NC - 2]), ks1 = fma(kd1, g1.v, g1.c[NC - 2]);
-#pragma unroll
-                for (int m = NC - 3; m >= 0; --m) {
-                    kd0 = fma(kd0, g0.v, ks0);
-                    kd1 = fma(kd1, g1.v, ks1);
-                    ks0 = fma(ks0, g0.v, g0.c[m]);
-                    ks1 = fma(ks1, g1.v, g1.c[m]);
-                }
+                T ks0, kd0, ks1, kd1;
+                horner2(g0, g1, ks0, kd0, ks1, kd1);
                 accumulate(cur, k, g0, ks0, kd0);
                 accumulate(cur, k + 1, g1, ks1, kd1);
             }
@@ -236,13 +301,8 @@ __global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
                 const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
                                                           s_tab, zseg, in0);
                 if (__ballot(in0) == 0) continue;
-                T kd0 = g0.c[NC - 1];
-                T ks0 = fma(kd0, g0.v, g0.c[NC - 2]);
-#pragma unroll
-                for (int m = NC - 3; m >= 0; --m) {
-                    kd0 = fma(kd0, g0.v, ks0);
-                    ks0 = fma(ks0, g0.v, g0.c[m]);
-                }
+                T ks0, kd0;
+                horner1(g0, ks0, kd0);
                 accumulate(cur, k, g0, ks0, kd0);
             }
         }
@@ -277,7 +337,7 @@ hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void
     return P->p.prec == MHK_FP64 ? level_q<double>(P, st, j, sigma, mu) : level_q<float>(P, st, j, sigma, mu);
 }
 
-template <typename T, int NC, int STRIDE>
+template <typename T, int STRIDE>
 static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
     Level &L = P->lev[j - 1];
@@ -311,22 +371,22 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (bch == 1) {
         if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void *)k_level_sums<1, T, NC, STRIDE>,
+            (void)hipFuncSetAttribute((const void *)k_level_sums<1, T, STRIDE>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<1, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
+        hipLaunchKernelGGL((k_level_sums<1, T, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
     } else {
         if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void *)k_level_sums<LV_BCH, T, NC, STRIDE>,
+            (void)hipFuncSetAttribute((const void *)k_level_sums<LV_BCH, T, STRIDE>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, NC, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
+        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
-    if (P->p.prec == MHK_FP64) return level_sums<double, TAB_NC, TAB_STRIDE>(P, st, j, want_s, want_d, init);
-    return level_sums<float, TABF_NC, TABF_STRIDE>(P, st, j, want_s, want_d, init);
+    if (P->p.prec == MHK_FP64) return level_sums<double, TAB_STRIDE>(P, st, j, want_s, want_d, init);
+    return level_sums<float, TABF_STRIDE>(P, st, j, want_s, want_d, init);
 }
 
 }  // namespace mhk

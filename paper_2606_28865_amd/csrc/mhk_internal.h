@@ -32,7 +32,9 @@ constexpr int NGL = 16;          // Gauss-Legendre nodes per panel (Section 3.2)
 constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolation
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
 constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
-constexpr int TAB_STRIDE = 9;    // doubles per segment in LDS (18 dwords: spreads segments over the banks)
+constexpr int TAB_NC64 = 5;      // FP64 path: c_0..c_4 stored as doubles, c_5..c_7 as floats
+constexpr int TAB_STRIDE = 7;    // doubles per segment in LDS: c_0..c_4, three floats and a pad
+                                 // (14 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: floats per segment
 constexpr int COL_NMAX = 8192;   // longest history-grid column transformed in LDS

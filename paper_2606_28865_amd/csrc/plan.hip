@@ -651,7 +651,12 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     // dK_j^S/da, which the level sums take from the derivative of the same
     // polynomial (one LDS table read per coefficient serves both kernels).
     // FP64 path: degree 7 on segments of 1/16 (S ~1e-15, D ~3e-13 of the
-    // kernels at a = 0); FP32 path: degree 7 on segments of 1/4, stored as
+    // kernels at a = 0), c_0..c_4 stored as doubles and c_5..c_7 as floats:
+    // relative to K_j(0) the high coefficients are below 4e-8, so their
+    // rounding and an FP32 Horner pass over them cost ~1e-15 of K_j(0)
+    // (c_4, ~2e-6, would cost ~1e-13 of K_j(0) and up to ~6e-13 of K_j^D(0)
+    // through the derivative), and each pair reads 52 bytes of table
+    // instead of 64.  FP32 path: degree 7 on segments of 1/4, stored as
     // floats.
     LevelQuad Q;
     const double b_j = P->p.alpha * P->p.alpha * L.delta_j;
@@ -700,7 +705,15 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
                 tprev = tcur;
                 tcur = tnext;
             }
-            for (int k = 0; k < nc; ++k) tab[(size_t)sgi * stride + k] = (double)mono[k];
+            double *row = &tab[(size_t)sgi * stride];
+            if (fp64) {
+                for (int k = 0; k < TAB_NC64; ++k) row[k] = (double)mono[k];
+                float hi[2 * (TAB_STRIDE - TAB_NC64)] = {};
+                for (int k = TAB_NC64; k < nc; ++k) hi[k - TAB_NC64] = (float)mono[k];
+                memcpy(row + TAB_NC64, hi, sizeof hi);
+            } else {
+                for (int k = 0; k < nc; ++k) row[k] = (double)mono[k];
+            }
         }
         // accuracy check of the table and of its derivative against direct
         // quadrature, in the arithmetic of the device evaluation
@@ -717,10 +730,29 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
             int sgi = (int)(a * L.seg_inv);
             double v = 2.0 * (a * L.seg_inv - sgi) - 1.0;
             const double *c = &tab[(size_t)sgi * stride];
-            double pS = c[nc - 1], dS = 0;
-            for (int k = nc - 2; k >= 0; --k) {
-                dS = dS * v + pS;
-                pS = pS * v + c[k];
+            double pS, dS;
+            if (fp64) {
+                // the device's order: Horner over c_7..c_5 in FP32, then c_4..c_0 in FP64
+                float hi[TAB_NC - TAB_NC64];
+                memcpy(hi, c + TAB_NC64, sizeof hi);
+                const float vf = (float)v;
+                float kd = hi[2], ks = fmaf(kd, vf, hi[1]);
+                kd = fmaf(kd, vf, ks);
+                ks = fmaf(ks, vf, hi[0]);
+                pS = ks;
+                dS = kd;
+                for (int k = TAB_NC64 - 1; k >= 0; --k) {
+                    dS = fma(dS, v, pS);
+                    pS = fma(pS, v, c[k]);
+                }
+            } else {
+                // the FP32 path evaluates in float; its bound (1e-8) leaves room for that
+                pS = c[nc - 1];
+                dS = 0;
+                for (int k = nc - 2; k >= 0; --k) {
+                    dS = dS * v + pS;
+                    pS = pS * v + c[k];
+                }
             }
             emax = std::max(emax, fabs(pS - i0 * cS) / k0S);
             emax = std::max(emax, fabs(dS * dscale - i1 * cD) / k0D);
