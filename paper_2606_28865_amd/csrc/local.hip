@@ -264,7 +264,6 @@ struct LocalArgs {
     double cell, ox, oy, reach;
     int ncx, ncy;
     double alpha, delta, dstar, band_s, band_v;
-    int order;             // local expansions: 1 first order, 2 with the second-order terms
     int frows;             // rows of f_trg per density: 1 (f) or 6 (f and its gradient and Hessian)
     const T *acc;          // [3][B][nout]: S, D, V in sorted order (history part)
     const T *lev;          // [2][B][nout]: S, D of the level sums, or null
@@ -380,6 +379,9 @@ enum { GEO_Q0 = GEO_N, GEO_Q1, GEO_P2, GEO_P3, GEO_U3, GEO_U4, GEO_B1, GEO_B2, G
        GEO_TX, GEO_TY, GEO_VA, GEO_VB, GEO_VC, GEO_N2 };
 static_assert(GEO_N == LOCAL_GEO_N1 && GEO_N2 == LOCAL_GEO_N2, "local geometry layout");
 
+// ORDER is the order of the local expansions (1 or 2); first-order plans
+// get a kernel without the second-order registers.
+template <int ORDER>
 __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double *__restrict__ geo,
                                                     int32_t *__restrict__ pan, uint8_t *__restrict__ flag)
 {
@@ -493,7 +495,7 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
         }
     }
     const int64_t n = A.nout;
-    if (A.order >= 2) {
+    if (ORDER >= 2) {
         double q0 = 0, q1 = 0, p2 = 0, p3 = 0, u3 = 0, u4 = 0, bb[4] = {0, 0, 0, 0}, g3 = 0, g4 = 0;
         double ttx = 1.0, tty = 0.0, va = 0.0, vb = 0.0, vc = 0.0;
         // the boundary point whose tangent line is used: the node itself on
@@ -581,7 +583,7 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
 
 // Local part of an evaluation from the per-plan geometry, added to the
 // accumulated history and level sums, and the scatter to the caller's order.
-template <typename T>
+template <typename T, int ORDER>
 __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -615,7 +617,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
 
     // second order: coefficients, tangent-line data and the boundary point
     // (the node itself on the boundary, the closest point elsewhere)
-    const bool o2 = do_local && A.order >= 2;
+    const bool o2 = do_local && ORDER >= 2;
     double q0 = 0, q1 = 0, p2 = 0, p3 = 0, u3 = 0, u4 = 0, bb[4] = {0, 0, 0, 0}, g3 = 0, g4 = 0;
     double ttx = 1.0, tty = 0.0, va = 0, vb = 0, vc = 0, kap2 = 0.0, tt2 = 0.0;
     int pp2 = -1;
@@ -816,8 +818,7 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.dstar = P->dstar;
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
-    A.order = P->p.local_order >= 2 ? 2 : 1;
-    A.frows = A.order >= 2 ? 6 : 1;
+    A.frows = P->p.local_order >= 2 ? 6 : 1;
     A.acc = (const T *)P->acc;
     A.lev = nullptr;
     A.out_s = A.out_d = A.out_v = nullptr;
@@ -828,8 +829,11 @@ hipError_t launch_local_geom(mhk_plan *P, hipStream_t st)
     if (P->nout == 0) return hipSuccess;
     LocalArgs<double> A;
     fill_args(P, A);
-    hipLaunchKernelGGL(k_local_geom, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, st, A,
-                       P->loc.geo, P->loc.gpan, P->loc.gflag);
+    const dim3 grid((unsigned)((P->nout + 255) / 256));
+    if (P->p.local_order >= 2)
+        hipLaunchKernelGGL(k_local_geom<2>, grid, dim3(256), 0, st, A, P->loc.geo, P->loc.gpan, P->loc.gflag);
+    else
+        hipLaunchKernelGGL(k_local_geom<1>, grid, dim3(256), 0, st, A, P->loc.geo, P->loc.gpan, P->loc.gflag);
     return hipGetLastError();
 }
 
@@ -848,7 +852,11 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
     A.out_s = (T *)out_s;
     A.out_d = (T *)out_d;
     A.out_v = (T *)out_v;
-    hipLaunchKernelGGL(k_local<T>, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, P->stream, A);
+    const dim3 grid((unsigned)((P->nout + 255) / 256));
+    if (P->p.local_order >= 2)
+        hipLaunchKernelGGL((k_local<T, 2>), grid, dim3(256), 0, P->stream, A);
+    else
+        hipLaunchKernelGGL((k_local<T, 1>), grid, dim3(256), 0, P->stream, A);
     return hipGetLastError();
 }
 
