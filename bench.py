@@ -253,7 +253,7 @@ def level_sums_traffic():
     reading for a device copy of known size), or None when levels.hip has
     changed since the counters were taken (its hash is recorded there)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "level_sums_multibody_fp64_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", "multibody_fp64_hbm_counters.md")
     src = os.path.join(ROOT, "paper_2606_28865_amd", "csrc", "levels.hip")
     try:
         text = open(path).read()
@@ -262,8 +262,8 @@ def level_sums_traffic():
         return None
     rec = {}
     for ln in text.splitlines():
-        if ":" in ln and ln.strip().startswith("- "):
-            k, v = ln.strip()[2:].split(":", 1)
+        if ": " in ln and ln.strip().startswith("- "):
+            k, v = ln.strip()[2:].split(": ", 1)
             rec[k.strip()] = v.strip().strip("`")
     if rec.get("levels.hip sha256[:16]") != sha:
         return None
