@@ -199,6 +199,8 @@ def main():
         "grid": [int(i["n_fine"]) for i in infos],
         "delta": [i["delta"] for i in infos],
         "plan_s": [round(x, 3) for x in plan_s],
+        "plan_ms_phases": {"phases": ["inputs", "target_sort", "levels", "history", "local", "total"],
+                           "ms": [[round(x, 1) for x in i["ms_plan"]] for i in infos]},
         "n_noconv": noconv,
         "gen_s": round(gen_s, 2),
         "wall_s": round(wall, 3),

@@ -139,6 +139,11 @@ typedef struct {
                               evaluations with MHK_PART_GEOMETRY add to it            */
     double ms_geometry;    /* closest points and local coefficients of the last timed
                               eval with MHK_PART_GEOMETRY (beside the history part)  */
+    double ms_plan[6];     /* host-clock milliseconds of plan creation: [0] input checks
+                              and bounding box, [1] target sort, [2] dyadic levels
+                              (child nodes, cells, candidate lists, tables), [3] history
+                              part (source binning, window, multiplier, FFT set-up),
+                              [4] local part (panel data, closest points), [5] total  */
 } mhk_info;
 
 typedef struct mhk_plan mhk_plan;

@@ -50,13 +50,13 @@ class Info(C.Structure):
                 ("ms_spread", C.c_double), ("ms_fft", C.c_double), ("ms_multiply", C.c_double),
                 ("ms_interp", C.c_double), ("ms_levels", C.c_double), ("ms_local", C.c_double),
                 ("ms_total", C.c_double), ("history_truncated", C.c_int), ("n_noconv", C.c_int64),
-                ("ms_geometry", C.c_double)]
+                ("ms_geometry", C.c_double), ("ms_plan", C.c_double * 6)]
 
     def as_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            d[name] = list(v) if name == "level_radius" else v
+            d[name] = list(v) if name in ("level_radius", "ms_plan") else v
         return d
 
 

@@ -238,4 +238,46 @@ hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double
 hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const double *phi2inv, double c,
                               double *mtab, hipStream_t s);
 
+// Device-side binning of plan creation (bin.hip); every call is
+// asynchronous on st and allocates its temporaries in the order of st.
+// Stable sort of (key, value) pairs by the low `bits` bits of the keys.
+hipError_t dev_sort_pairs(uint32_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t st);
+// out[0..n]: exclusive prefix sums of in[0..n), out[n] the total (also in
+// *total as int64, for the caller's overflow check).
+hipError_t dev_scan(const int32_t *in, int32_t *out, int64_t n, int64_t *total, hipStream_t st);
+// start[c], c in [0, nkeys]: first index of key c in a sorted key array.
+hipError_t dev_cell_starts(const uint32_t *keys, int64_t n, int64_t nkeys, int32_t *start, hipStream_t st);
+// Targets sorted by the Morton key of cells of side hh from (ox, oy).
+hipError_t dev_sort_targets(const double *x, const double *y, const int8_t *in, int64_t n, double ox, double oy,
+                            double hh, double *sx, double *sy, int8_t *sin, int32_t *sidx, hipStream_t st);
+// Child nodes of a dyadic level, sorted by cells, with the cell starts.
+hipError_t dev_child_nodes(int64_t n_src, int nch, const double *Tm, const double *bx, const double *by,
+                           const double *bnx, const double *bny, const double *bw, const double *glw, double ox,
+                           double oy, double cell, int64_t ncx, int64_t ncy, double *sx, double *sy, double *sw,
+                           double *swx, double *swy, int32_t *code, int32_t *cell_start, hipStream_t st);
+// Per-wavefront candidate lists of a level: counts, then (after the scan of
+// the counts into ofs) the lists and the wavefronts in decreasing work.
+hipError_t dev_wave_counts(const double *tx, const double *ty, int64_t nout, int64_t nwave, double R, double R2,
+                           double ox, double oy, double cell, int64_t ncx, int64_t ncy, const int32_t *start,
+                           const double *sx, const double *sy, int32_t *cnt, hipStream_t st);
+hipError_t dev_wave_fill(const double *tx, const double *ty, int64_t nout, int64_t nwave, double R, double R2,
+                         double ox, double oy, double cell, int64_t ncx, int64_t ncy, const int32_t *start,
+                         const double *sx, const double *sy, const int32_t *ofs, int32_t *out, int32_t *order,
+                         hipStream_t st);
+// History sources by spreading tile (sorted arrays, window bounds into
+// sup, list offsets into lofs) and their per-tile lists.
+hipError_t dev_sources_by_tile(const double *x, const double *y, const double *w, const double *nx, const double *ny,
+                               int64_t n, double ox, double oy, double h, int64_t ntile, int W, double *gx, double *gy,
+                               double *gw, double *gwx, double *gwy, int32_t *idx, int *sup, int32_t *lofs,
+                               int32_t **tstart_out, int64_t *total, hipStream_t st);
+hipError_t dev_tile_fill(const double *gx, const double *gy, const int32_t *tstart, int64_t ntile, int W,
+                         const int32_t *lofs, int32_t *list, hipStream_t st);
+// Runs of equal tiles along the sorted targets, and their window bounds.
+hipError_t dev_target_tiles_count(const double *tx, const double *ty, int64_t n, double ox, double oy, double h,
+                                  int64_t ntile, int W, int *win, int32_t **flag_out, int32_t **pos_out,
+                                  int64_t *runs_dev, hipStream_t st);
+hipError_t dev_target_tiles_fill(const double *tx, const double *ty, int64_t n, double ox, double oy, double h,
+                                 int64_t ntile, const int32_t *flag, const int32_t *pos, int32_t *xy, int32_t *rng,
+                                 hipStream_t st);
+
 }  // namespace mhk

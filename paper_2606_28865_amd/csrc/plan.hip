@@ -6,6 +6,7 @@
 // device work on the plan's stream.
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -171,17 +172,6 @@ static inline uint32_t spread_bits(uint32_t v)
 }
 static inline uint32_t morton(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
-// Stable counting sort of keys in [0, nkeys): returns order and key starts.
-static void counting_sort(const std::vector<int64_t> &key, int64_t nkeys,
-                          std::vector<int32_t> &order, std::vector<int32_t> &start)
-{
-    start.assign(nkeys + 1, 0);
-    for (int64_t k : key) start[k + 1]++;
-    for (int64_t i = 0; i < nkeys; ++i) start[i + 1] += start[i];
-    std::vector<int32_t> pos(start.begin(), start.end() - 1);
-    order.assign(key.size(), 0);
-    for (size_t i = 0; i < key.size(); ++i) order[pos[key[i]]++] = (int32_t)i;
-}
 
 // ---------------------------------------------------------------------------
 // Parameter rules
@@ -334,6 +324,49 @@ static mhk_status upload(mhk_plan *P, T **ptr, const T *host, int64_t count)
         mhk_status st_ = (x);           \
         if (st_ != MHK_OK) return st_;  \
     } while (0)
+
+// Temporaries of plan creation, allocated and freed in the order of the
+// plan's stream (hipFree would wait for the whole device, i.e. for other
+// plans' work).  Host data uploaded through upload() must stay alive until
+// the stream has been synchronised.
+struct StreamTmp {
+    hipStream_t st;
+    std::vector<void *> ptrs;
+    explicit StreamTmp(hipStream_t s) : st(s) {}
+    StreamTmp(const StreamTmp &) = delete;
+    StreamTmp &operator=(const StreamTmp &) = delete;
+    ~StreamTmp()
+    {
+        for (void *q : ptrs) (void)hipFreeAsync(q, st);
+    }
+    template <typename T>
+    mhk_status alloc(T **ptr, int64_t n)
+    {
+        *ptr = nullptr;
+        if (hipMallocAsync((void **)ptr, sizeof(T) * (size_t)std::max<int64_t>(1, n), st) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("temporary device allocation of plan creation failed");
+            return MHK_ENOMEM;
+        }
+        ptrs.push_back(*ptr);
+        return MHK_OK;
+    }
+    template <typename T>
+    mhk_status upload(T **ptr, const T *host, int64_t n)
+    {
+        TRY(alloc(ptr, n));
+        if (n > 0) MHK_HIP(hipMemcpyAsync(*ptr, host, sizeof(T) * (size_t)n, hipMemcpyHostToDevice, st));
+        return MHK_OK;
+    }
+    // device -> host copy of a few values, waiting for the stream
+    template <typename T>
+    mhk_status fetch(T *host, const T *dev, int64_t n)
+    {
+        MHK_HIP(hipMemcpyAsync(host, dev, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, st));
+        MHK_HIP(hipStreamSynchronize(st));
+        return MHK_OK;
+    }
+};
 
 static void free_plan(mhk_plan *P)
 {
@@ -490,11 +523,12 @@ void host_common(Host &H)
 // the 16-point Gauss-Legendre nodes of each child interval, with geometry
 // interpolated by the parent's degree-15 polynomial, normals renormalised,
 // and weights w_GL,child * speed * 2^-j.
-mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &tgx, const std::vector<double> &tgy)
+mhk_status build_level(mhk_plan *P, Host &H, int j)
 {
     Level &L = P->lev[j - 1];
     const mhk_boundary *b = H.b;
     const int64_t npan = b->n_panels;
+    const hipStream_t st = P->stream;
     L.nchild = 1 << j;
     L.n_src = npan * L.nchild * NGL;
     L.delta_j = P->delta / pow(4.0, j - 1);
@@ -509,32 +543,7 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
             double s = -1.0 + (2.0 * c + 1.0 + H.gl_t[k]) / nch;
             lagrange_row(H.gl_t, H.bary, s, &T[((size_t)c * NGL + k) * NGL]);
         }
-    std::vector<double> cx(L.n_src), cy(L.n_src), cwx(L.n_src), cwy(L.n_src), cw(L.n_src);
-    for (int64_t p = 0; p < npan; ++p) {
-        const int64_t o = p * NGL;
-        double sp[NGL];
-        for (int i = 0; i < NGL; ++i) sp[i] = b->w[o + i] / H.gl_w[i];
-        for (int c = 0; c < nch; ++c)
-            for (int k = 0; k < NGL; ++k) {
-                const double *row = &T[((size_t)c * NGL + k) * NGL];
-                double x = 0, y = 0, nx = 0, ny = 0, s = 0;
-                for (int i = 0; i < NGL; ++i) {
-                    x += row[i] * b->x[o + i];
-                    y += row[i] * b->y[o + i];
-                    nx += row[i] * b->nx[o + i];
-                    ny += row[i] * b->ny[o + i];
-                    s += row[i] * sp[i];
-                }
-                double nn = sqrt(nx * nx + ny * ny);
-                int64_t q = (p * nch + c) * NGL + k;
-                double wq = H.gl_w[k] * s / nch;
-                cx[q] = x;
-                cy[q] = y;
-                cw[q] = wq;
-                cwx[q] = wq * nx / nn;
-                cwy[q] = wq * ny / nn;
-            }
-    }
+    TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
     // cells of side R_j / LV_CDIV over the bounding box of sources and targets
     L.cell = L.radius / LV_CDIV;
     L.ox = H.xmin - 1e-9;
@@ -547,95 +556,46 @@ mhk_status build_level(mhk_plan *P, Host &H, int j, const std::vector<double> &t
     }
     L.ncx = (int)ncx;
     L.ncy = (int)ncy;
-    std::vector<int64_t> key(L.n_src);
-    for (int64_t q = 0; q < L.n_src; ++q) {
-        int64_t ix = std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((cx[q] - L.ox) / L.cell)));
-        int64_t iy = std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((cy[q] - L.oy) / L.cell)));
-        key[q] = iy * ncx + ix;
-    }
-    std::vector<int32_t> order, start;
-    counting_sort(key, ncx * ncy, order, start);
-    std::vector<double> sx(L.n_src), sy(L.n_src), swx(L.n_src), swy(L.n_src), sw(L.n_src);
-    std::vector<int32_t> code(L.n_src);
-    for (int64_t s = 0; s < L.n_src; ++s) {
-        int32_t q = order[s];
-        sx[s] = cx[q]; sy[s] = cy[q]; sw[s] = cw[q]; swx[s] = cwx[q]; swy[s] = cwy[q];
-        code[s] = q;
-    }
-    TRY(upload(P, &L.sx, sx.data(), L.n_src));
-    TRY(upload(P, &L.sy, sy.data(), L.n_src));
-    TRY(upload(P, &L.sw, sw.data(), L.n_src));
-    TRY(upload(P, &L.swx, swx.data(), L.n_src));
-    TRY(upload(P, &L.swy, swy.data(), L.n_src));
-    TRY(upload(P, &L.code, code.data(), L.n_src));
-    TRY(upload(P, &L.cell_start, start.data(), (int64_t)start.size()));
-    TRY(upload(P, &L.interp, T.data(), (int64_t)T.size()));
+    // child nodes (geometry interpolated from the parent panels), sorted by
+    // cell on the device
+    TRY(dalloc(P, &L.sx, L.n_src));
+    TRY(dalloc(P, &L.sy, L.n_src));
+    TRY(dalloc(P, &L.sw, L.n_src));
+    TRY(dalloc(P, &L.swx, L.n_src));
+    TRY(dalloc(P, &L.swy, L.n_src));
+    TRY(dalloc(P, &L.code, L.n_src));
+    TRY(dalloc(P, &L.cell_start, ncx * ncy + 1));
+    StreamTmp tmp(st);
+    double *glw = nullptr;
+    TRY(tmp.upload(&glw, H.gl_w.data(), NGL));
+    MHK_HIP(dev_child_nodes(L.n_src, nch, L.interp, P->bx, P->by, P->bnx, P->bny, P->bw, glw, L.ox, L.oy, L.cell,
+                            ncx, ncy, L.sx, L.sy, L.sw, L.swx, L.swy, L.code, L.cell_start, st));
     // per wavefront of LV_WAVE targets: the sources within R_j of the
-    // wavefront's target bounding box.  Candidates come from the cells (side
-    // R_j / LV_CDIV) that can hold a source within R_j of one of its targets
-    // (per cell row, the row gap g to the target and half-width
-    // sqrt(R_j^2 - g^2) in x), read in sorted order and kept if within R_j of
-    // the box; no target of the wavefront is in range of a source that is
-    // not listed.  Wavefronts past the last target get empty lists.
+    // wavefront's target bounding box (flat lists, counted, scanned, then
+    // filled on the device); wavefronts past the last target get empty lists
     {
-        const int64_t nout = (int64_t)tgx.size();
+        const int64_t nout = P->nout;
         const int64_t nwave = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
         const double R = L.radius, R2 = R * R * (1.0 + 1e-9);
-        std::vector<int32_t> wofs(nwave + 1, 0), src;
-        std::vector<std::array<int64_t, 3>> iv;   // row, x0, x1
-        auto col = [&](double x) {
-            return std::min<int64_t>(ncx - 1, std::max<int64_t>(0, (int64_t)floor((x - L.ox) / L.cell)));
-        };
-        auto row = [&](double y) {
-            return std::min<int64_t>(ncy - 1, std::max<int64_t>(0, (int64_t)floor((y - L.oy) / L.cell)));
-        };
-        for (int64_t b = 0; b < nwave; ++b) {
-            iv.clear();
-            const int64_t t0 = b * LV_WAVE, t1 = std::min(nout, (b + 1) * LV_WAVE);
-            double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
-            for (int64_t t = t0; t < t1; ++t) {
-                const double tx = tgx[t], ty = tgy[t];
-                bx0 = std::min(bx0, tx); bx1 = std::max(bx1, tx);
-                by0 = std::min(by0, ty); by1 = std::max(by1, ty);
-                for (int64_t r = row(ty - R); r <= row(ty + R); ++r) {
-                    const double ylo = L.oy + r * L.cell, yhi = ylo + L.cell;
-                    const double g = std::max(0.0, std::max(ylo - ty, ty - yhi));
-                    if (g > R) continue;
-                    const double hw = sqrt(R * R - g * g);
-                    iv.push_back({r, col(tx - hw), col(tx + hw)});
-                }
-            }
-            std::sort(iv.begin(), iv.end());
-            for (size_t i = 0; i < iv.size();) {
-                int64_t r = iv[i][0], x0 = iv[i][1], x1 = iv[i][2];
-                size_t k = i + 1;
-                while (k < iv.size() && iv[k][0] == r && iv[k][1] <= x1 + 1) {
-                    x1 = std::max(x1, iv[k][2]);
-                    ++k;
-                }
-                for (int32_t s = start[r * ncx + x0]; s < start[r * ncx + x1 + 1]; ++s) {
-                    const double ex = std::max(0.0, std::max(bx0 - sx[s], sx[s] - bx1));
-                    const double ey = std::max(0.0, std::max(by0 - sy[s], sy[s] - by1));
-                    if (ex * ex + ey * ey <= R2) src.push_back(s);
-                }
-                i = k;
-            }
-            if (src.size() > (size_t)INT32_MAX) {
-                set_error("level candidate lists too large");
-                return MHK_EUNSUPPORTED;
-            }
-            wofs[b + 1] = (int32_t)src.size();
+        int32_t *cnt = nullptr;
+        int64_t *tot = nullptr;
+        TRY(tmp.alloc(&cnt, nwave));
+        TRY(tmp.alloc(&tot, 1));
+        TRY(dalloc(P, &L.wave_ofs, nwave + 1));
+        TRY(dalloc(P, &L.wave_order, nwave));
+        MHK_HIP(dev_wave_counts(P->tx, P->ty, nout, nwave, R, R2, L.ox, L.oy, L.cell, ncx, ncy, L.cell_start, L.sx,
+                                L.sy, cnt, st));
+        MHK_HIP(dev_scan(cnt, L.wave_ofs, nwave, tot, st));
+        int64_t total = 0;
+        TRY(tmp.fetch(&total, tot, 1));
+        if (total > (int64_t)INT32_MAX) {
+            set_error("level candidate lists too large");
+            return MHK_EUNSUPPORTED;
         }
-        L.n_cand = (int64_t)src.size();
-        // schedule the wavefronts heaviest first, so that the long ones start
-        // early and each workgroup holds wavefronts of similar work
-        std::vector<int32_t> worder(nwave);
-        std::iota(worder.begin(), worder.end(), 0);
-        std::stable_sort(worder.begin(), worder.end(),
-                         [&](int32_t a, int32_t c) { return wofs[a + 1] - wofs[a] > wofs[c + 1] - wofs[c]; });
-        TRY(upload(P, &L.wave_order, worder.data(), nwave));
-        TRY(upload(P, &L.wave_ofs, wofs.data(), nwave + 1));
-        TRY(upload(P, &L.wave_src, src.data(), std::max<int64_t>(1, (int64_t)src.size())));
+        L.n_cand = total;
+        TRY(dalloc(P, &L.wave_src, std::max<int64_t>(1, total)));
+        MHK_HIP(dev_wave_fill(P->tx, P->ty, nout, nwave, R, R2, L.ox, L.oy, L.cell, ncx, ncy, L.cell_start, L.sx,
+                              L.sy, L.wave_ofs, L.wave_src, L.wave_order, st));
     }
     {
         char *q = nullptr;
@@ -1011,7 +971,7 @@ mhk_status history_geometry(mhk_plan *P, const Host &H)
     return MHK_OK;
 }
 
-mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, const std::vector<double> &tgy)
+mhk_status build_history(mhk_plan *P, Host &H)
 {
     History &G = P->hist;
     const double alpha = P->p.alpha, delta = P->delta;
@@ -1109,149 +1069,81 @@ mhk_status build_history(mhk_plan *P, Host &H, const std::vector<double> &tgx, c
             if (fac[l] != 0.0) G.ncol = (int)l + 1;
     }
 
-    const int64_t nt2 = (int64_t)G.ntile * G.ntile;
-    // per-tile lists of the sorted sources whose window [m0, m0 + w) (m0 =
-    // ceil(g - w/2), as the spreading kernel forms it) meets the tile in
-    // both axes; w <= 16 < TILE, so a window meets at most 2 tiles per axis
-    auto tile_lists = [&](const std::vector<double> &gx, const std::vector<double> &gy, int32_t **lofs,
-                          int32_t **list) -> mhk_status {
-        const int64_t ns = (int64_t)gx.size();
-        const int W = G.w;
-        auto span = [&](double g, int64_t &t0, int64_t &t1) {
-            const int64_t m0 = (int64_t)ceil(g - 0.5 * W);
-            t0 = std::max<int64_t>(0, (int64_t)floor((double)m0 / TILE));
-            t1 = std::min<int64_t>(G.ntile - 1, (int64_t)floor((double)(m0 + W - 1) / TILE));
-        };
-        std::vector<int32_t> ofs(nt2 + 1, 0);
-        for (int pass = 0; pass < 2; ++pass) {
-            std::vector<int32_t> fill;
-            std::vector<int32_t> ent;
-            if (pass == 1) {
-                for (int64_t t = 0; t < nt2; ++t) ofs[t + 1] += ofs[t];
-                fill.assign(ofs.begin(), ofs.end() - 1);
-                ent.assign((size_t)std::max<int32_t>(1, ofs[nt2]), 0);
-            }
-            for (int64_t s = 0; s < ns; ++s) {
-                int64_t x0, x1, y0, y1;
-                span(gx[s], x0, x1);
-                span(gy[s], y0, y1);
-                for (int64_t ty = y0; ty <= y1; ++ty)
-                    for (int64_t tx = x0; tx <= x1; ++tx) {
-                        const int64_t t = ty * G.ntile + tx;
-                        if (pass == 0)
-                            ofs[t + 1]++;
-                        else
-                            ent[fill[t]++] = (int32_t)s;
-                    }
-            }
-            if (pass == 1) {
-                TRY(upload(P, list, ent.data(), (int64_t)ent.size()));
-                TRY(upload(P, lofs, ofs.data(), nt2 + 1));
-            }
-        }
-        return MHK_OK;
-    };
-    auto tile_of = [&](double x, double y) -> int64_t {
-        int64_t ix = (int64_t)floor((x - G.ox) / G.h) / TILE;
-        int64_t iy = (int64_t)floor((y - G.oy) / G.h) / TILE;
-        ix = std::min<int64_t>(G.ntile - 1, std::max<int64_t>(0, ix));
-        iy = std::min<int64_t>(G.ntile - 1, std::max<int64_t>(0, iy));
-        return iy * G.ntile + ix;
-    };
-    // grid rows and columns that hold the sources' windows [m0, m0 + w),
-    // m0 = ceil(g - w/2) as the spreading kernel forms it: [sup[0], sup[1])
-    // in x, [sup[2], sup[3]) in y
-    int64_t sup[4] = {G.n, 0, G.n, 0};
-    auto support = [&](const std::vector<double> &gx, const std::vector<double> &gy) {
-        for (size_t s = 0; s < gx.size(); ++s) {
-            const int64_t mx = (int64_t)ceil(gx[s] - 0.5 * G.w), my = (int64_t)ceil(gy[s] - 0.5 * G.w);
-            sup[0] = std::min(sup[0], mx); sup[1] = std::max(sup[1], mx + G.w);
-            sup[2] = std::min(sup[2], my); sup[3] = std::max(sup[3], my + G.w);
-        }
-    };
-    // boundary sources
+    // Sources sorted by 32 x 32 tile of the grid, per-tile lists of the
+    // sorted sources whose window [m0, m0 + w) (m0 = ceil(g - w/2), as the
+    // spreading kernel forms it) meets the tile in both axes, and the grid
+    // rows and columns the windows use; targets (already sorted with tiles
+    // contiguous) as runs of tiles, and the rows and columns of their
+    // interpolation windows.  All on the device; the few totals and bounds
+    // the launches need come back in one wait.
     {
-        const mhk_boundary *b = H.b;
-        int64_t nb = b->n_panels * NGL;
-        std::vector<int64_t> key(nb);
-        for (int64_t i = 0; i < nb; ++i) key[i] = tile_of(b->x[i], b->y[i]);
-        std::vector<int32_t> order, start;
-        counting_sort(key, nt2, order, start);
-        std::vector<double> gx(nb), gy(nb), w(nb), wx(nb), wy(nb);
-        for (int64_t s = 0; s < nb; ++s) {
-            int32_t i = order[s];
-            gx[s] = (b->x[i] - G.ox) / G.h;
-            gy[s] = (b->y[i] - G.oy) / G.h;
-            w[s] = b->w[i];
-            wx[s] = b->w[i] * b->nx[i];
-            wy[s] = b->w[i] * b->ny[i];
-        }
+        const hipStream_t st = P->stream;
+        StreamTmp tmp(st);
+        const int64_t nb = H.b->n_panels * NGL, nv = H.v ? H.v->n : 0, nout = P->nout;
+        const int64_t nt2 = (int64_t)G.ntile * G.ntile;
+        const int n = (int)G.n;
+        // window bounds [x0, x1) x [y0, y1): sources in bnd[0..3], targets in bnd[4..7]
+        const int bnd0[8] = {n, 0, n, 0, n, 0, n, 0};
+        int *bnd = nullptr;
+        int64_t *tots = nullptr;   // boundary list, volume list, target tile runs
+        TRY(tmp.upload(&bnd, bnd0, 8));
+        TRY(tmp.alloc(&tots, 3));
         G.nbs = nb;
-        support(gx, gy);
-        TRY(upload(P, &G.bgx, gx.data(), nb));
-        TRY(upload(P, &G.bgy, gy.data(), nb));
-        TRY(upload(P, &G.bw, w.data(), nb));
-        TRY(upload(P, &G.bwx, wx.data(), nb));
-        TRY(upload(P, &G.bwy, wy.data(), nb));
-        TRY(upload(P, &G.bidx, order.data(), nb));
-        TRY(tile_lists(gx, gy, &G.blofs, &G.blist));
-    }
-    // volume sources
-    {
-        int64_t nv = H.v ? H.v->n : 0;
-        std::vector<int64_t> key(nv);
-        for (int64_t i = 0; i < nv; ++i) key[i] = tile_of(H.v->x[i], H.v->y[i]);
-        std::vector<int32_t> order, start;
-        counting_sort(key, nt2, order, start);
-        std::vector<double> gx(nv), gy(nv), w(nv);
-        for (int64_t s = 0; s < nv; ++s) {
-            int32_t i = order[s];
-            gx[s] = (H.v->x[i] - G.ox) / G.h;
-            gy[s] = (H.v->y[i] - G.oy) / G.h;
-            w[s] = H.v->w[i];
-        }
+        TRY(dalloc(P, &G.bgx, nb));
+        TRY(dalloc(P, &G.bgy, nb));
+        TRY(dalloc(P, &G.bw, nb));
+        TRY(dalloc(P, &G.bwx, nb));
+        TRY(dalloc(P, &G.bwy, nb));
+        TRY(dalloc(P, &G.bidx, nb));
+        TRY(dalloc(P, &G.blofs, nt2 + 1));
+        int32_t *bstart = nullptr, *vstart = nullptr, *tflag = nullptr, *tpos = nullptr;
+        MHK_HIP(dev_sources_by_tile(P->bx, P->by, P->bw, P->bnx, P->bny, nb, G.ox, G.oy, G.h, G.ntile, G.w, G.bgx,
+                                    G.bgy, G.bw, G.bwx, G.bwy, G.bidx, bnd, G.blofs, &bstart, tots + 0, st));
+        tmp.ptrs.push_back(bstart);
         G.nvs = nv;
-        support(gx, gy);
-        TRY(upload(P, &G.vgx, gx.data(), nv));
-        TRY(upload(P, &G.vgy, gy.data(), nv));
-        TRY(upload(P, &G.vw, w.data(), nv));
-        TRY(upload(P, &G.vidx, order.data(), nv));
-        TRY(tile_lists(gx, gy, &G.vlofs, &G.vlist));
-    }
-    G.sx0 = (int)std::max<int64_t>(0, sup[0]);
-    G.sx1 = (int)std::min<int64_t>(G.n, sup[1]);
-    G.sy0 = (int)std::max<int64_t>(0, sup[2]);
-    G.sy1 = (int)std::min<int64_t>(G.n, sup[3]);
-    // targets by tile (they are sorted with tiles contiguous)
-    {
-        std::vector<int32_t> xy, rng;
-        int64_t last = -1;
-        for (int64_t s = 0; s < (int64_t)tgx.size(); ++s) {
-            int64_t ix = (int64_t)floor((tgx[s] - G.ox) / G.h) / TILE;
-            int64_t iy = (int64_t)floor((tgy[s] - G.oy) / G.h) / TILE;
-            int64_t t = iy * G.ntile + ix;
-            if (t != last) {
-                xy.push_back((int32_t)t);
-                rng.push_back((int32_t)s);
-                last = t;
-            }
+        double *vx = nullptr, *vy = nullptr, *vw = nullptr;
+        TRY(tmp.upload(&vx, nv ? H.v->x : nullptr, nv));
+        TRY(tmp.upload(&vy, nv ? H.v->y : nullptr, nv));
+        TRY(tmp.upload(&vw, nv ? H.v->w : nullptr, nv));
+        TRY(dalloc(P, &G.vgx, nv));
+        TRY(dalloc(P, &G.vgy, nv));
+        TRY(dalloc(P, &G.vw, nv));
+        TRY(dalloc(P, &G.vidx, nv));
+        TRY(dalloc(P, &G.vlofs, nt2 + 1));
+        MHK_HIP(dev_sources_by_tile(vx, vy, vw, nullptr, nullptr, nv, G.ox, G.oy, G.h, G.ntile, G.w, G.vgx, G.vgy,
+                                    G.vw, nullptr, nullptr, G.vidx, bnd, G.vlofs, &vstart, tots + 1, st));
+        tmp.ptrs.push_back(vstart);
+        MHK_HIP(dev_target_tiles_count(P->tx, P->ty, nout, G.ox, G.oy, G.h, G.ntile, G.w, bnd + 4, &tflag, &tpos,
+                                       tots + 2, st));
+        tmp.ptrs.push_back(tflag);
+        tmp.ptrs.push_back(tpos);
+        int64_t tot[3];
+        int bh[8];
+        MHK_HIP(hipMemcpyAsync(tot, tots, sizeof tot, hipMemcpyDeviceToHost, st));
+        TRY(tmp.fetch(bh, bnd, 8));
+        if (tot[0] > (int64_t)INT32_MAX || tot[1] > (int64_t)INT32_MAX) {
+            set_error("spreading tile lists too large");
+            return MHK_EUNSUPPORTED;
         }
-        rng.push_back((int32_t)tgx.size());
-        G.n_ttiles = (int)xy.size();
-        // grid rows and columns that the interpolation windows use
-        int64_t x0 = G.n, x1 = 0, y0 = G.n, y1 = 0;
-        for (int64_t s = 0; s < (int64_t)tgx.size(); ++s) {
-            const double gx = (tgx[s] - G.ox) / G.h, gy = (tgy[s] - G.oy) / G.h;
-            const int64_t mx = (int64_t)ceil(gx - 0.5 * G.w), my = (int64_t)ceil(gy - 0.5 * G.w);
-            x0 = std::min(x0, mx); x1 = std::max(x1, mx + G.w);
-            y0 = std::min(y0, my); y1 = std::max(y1, my + G.w);
-        }
-        G.tx0 = (int)std::max<int64_t>(0, x0);
-        G.tx1 = (int)std::min<int64_t>(G.n, x1);
-        G.ty0 = (int)std::max<int64_t>(0, y0);
-        G.ty1 = (int)std::min<int64_t>(G.n, y1);
-        TRY(upload(P, &G.ttile_xy, xy.data(), (int64_t)xy.size()));
-        TRY(upload(P, &G.ttile_rng, rng.data(), (int64_t)rng.size()));
+        TRY(dalloc(P, &G.blist, std::max<int64_t>(1, tot[0])));
+        TRY(dalloc(P, &G.vlist, std::max<int64_t>(1, tot[1])));
+        MHK_HIP(dev_tile_fill(G.bgx, G.bgy, bstart, G.ntile, G.w, G.blofs, G.blist, st));
+        MHK_HIP(dev_tile_fill(G.vgx, G.vgy, vstart, G.ntile, G.w, G.vlofs, G.vlist, st));
+        G.n_ttiles = (int)tot[2];
+        TRY(dalloc(P, &G.ttile_xy, std::max<int64_t>(1, tot[2])));
+        TRY(dalloc(P, &G.ttile_rng, tot[2] + 1));
+        MHK_HIP(dev_target_tiles_fill(P->tx, P->ty, nout, G.ox, G.oy, G.h, G.ntile, tflag, tpos, G.ttile_xy,
+                                      G.ttile_rng, st));
+        G.sx0 = std::max(0, bh[0]);
+        G.sx1 = std::min(n, bh[1]);
+        G.sy0 = std::max(0, bh[2]);
+        G.sy1 = std::min(n, bh[3]);
+        G.tx0 = std::max(0, bh[4]);
+        G.tx1 = std::min(n, bh[5]);
+        G.ty0 = std::max(0, bh[6]);
+        G.ty1 = std::min(n, bh[7]);
+        // the temporaries are freed in stream order; the host arrays they
+        // were filled from stay alive until plan creation returns
     }
     // grids and FFT plans
     {
@@ -1507,6 +1399,15 @@ mhk_status build_local(mhk_plan *P, Host &H)
 mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_volume *v,
                   const mhk_targets *t, void *stream, mhk_plan *P)
 {
+    using clk = std::chrono::steady_clock;
+    const auto t_start = clk::now();
+    auto t_mark = t_start;
+    // host-clock time of a phase of plan creation, into info.ms_plan[k]
+    auto lap = [&](int k) {
+        const auto now = clk::now();
+        P->info.ms_plan[k] += std::chrono::duration<double, std::milli>(now - t_mark).count();
+        t_mark = now;
+    };
     TRY(check_inputs(params, b, v, t));
     TRY(resolve(params, &P->info, &P->p));
     P->es = P->p.prec == MHK_FP64 ? sizeof(double) : sizeof(float);
@@ -1529,6 +1430,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     H.v = (v && v->n > 0) ? v : nullptr;
     H.t = t;
     host_common(H);
+    lap(0);
 
     // boundary arrays in caller order
     TRY(upload(P, &P->bx, b->x, P->nb));
@@ -1543,7 +1445,6 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     TRY(history_geometry(P, H));
     // targets sorted in Morton order of cells of one grid step (or of a virtual
     // grid of step R_J/8 when there is no history grid)
-    std::vector<double> tgx, tgy;
     {
         double hh, ox, oy;
         if (G.active) {
@@ -1556,33 +1457,25 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
             ox = H.xmin - hh;
             oy = H.ymin - hh;
         }
-        int64_t nout = P->nout;
-        std::vector<uint64_t> key(nout);
-        for (int64_t i = 0; i < nout; ++i) {
-            uint32_t ix = (uint32_t)std::max(0.0, floor((H.tx[i] - ox) / hh));
-            uint32_t iy = (uint32_t)std::max(0.0, floor((H.ty[i] - oy) / hh));
-            key[i] = ((uint64_t)morton(std::min<uint32_t>(ix, 65535), std::min<uint32_t>(iy, 65535)) << 32) | (uint64_t)i;
-        }
-        std::sort(key.begin(), key.end());
-        std::vector<double> sx(nout), sy(nout);
-        std::vector<int8_t> sin(nout);
-        std::vector<int32_t> sidx(nout);
-        for (int64_t s = 0; s < nout; ++s) {
-            int64_t i = (int64_t)(key[s] & 0xffffffffu);
-            sx[s] = H.tx[i];
-            sy[s] = H.ty[i];
-            sin[s] = H.tin[i];
-            sidx[s] = (int32_t)i;
-        }
-        TRY(upload(P, &P->tx, sx.data(), nout));
-        TRY(upload(P, &P->ty, sy.data(), nout));
-        TRY(upload(P, &P->tin, sin.data(), nout));
-        TRY(upload(P, &P->tidx, sidx.data(), nout));
-        tgx.swap(sx);
-        tgy.swap(sy);
+        const int64_t nout = P->nout;
+        StreamTmp tmp(P->stream);
+        double *rx = nullptr, *ry = nullptr;
+        int8_t *rin = nullptr;
+        TRY(tmp.upload(&rx, H.tx.data(), nout));
+        TRY(tmp.upload(&ry, H.ty.data(), nout));
+        TRY(tmp.upload(&rin, H.tin.data(), nout));
+        TRY(dalloc(P, &P->tx, nout));
+        TRY(dalloc(P, &P->ty, nout));
+        TRY(dalloc(P, &P->tin, nout));
+        TRY(dalloc(P, &P->tidx, nout));
+        MHK_HIP(dev_sort_targets(rx, ry, rin, nout, ox, oy, hh, P->tx, P->ty, P->tin, P->tidx, P->stream));
     }
-    for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j, tgx, tgy));
-    TRY(build_history(P, H, tgx, tgy));
+    lap(1);
+    for (int j = 1; j <= P->J; ++j) TRY(build_level(P, H, j));
+    lap(2);
+    TRY(build_history(P, H));
+    MHK_HIP(hipStreamSynchronize(P->stream));
+    lap(3);
     TRY(build_local(P, H));
     MHK_HIP(launch_local_geom(P, P->stream));
     {
@@ -1605,6 +1498,8 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     // only the plan's own stream is waited for: work of other plans on other
     // streams keeps running while a plan is created
     MHK_HIP(hipStreamSynchronize(P->stream));
+    lap(4);
+    P->info.ms_plan[5] = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
     int32_t noconv = 0;
     MHK_HIP(hipMemcpy(&noconv, P->loc.noconv, sizeof(noconv), hipMemcpyDeviceToHost));
     P->info.n_noconv = noconv;
