@@ -662,58 +662,112 @@ __device__ double history_kernel(double r, double alpha, double delta, const dou
     return s * 0.5 * hp / (4.0 * M_PI);
 }
 
-// Samples h^2 G^H(r) chi(r) of the smoothly truncated history kernel on a
-// centred periodic grid of 2n x 2n points of step h (rows padded to 2n+2),
-// chi(r) = erfc((r - rmid) slope)/2, zero beyond rcut.
-__global__ void __launch_bounds__(256) k_trunc_samples(double *buf, int64_t n2, double h, double alpha,
-                                                       double delta, double rcut, double rmid, double slope,
+// Samples of the smoothly truncated history kernel on the quarter grid
+// x = mx h, y = my h, 0 <= mx, my < M (the kernel is even in x and y and
+// zero for |x| or |y| >= M h): h^2 G^H(r) chi(x) chi(y), chi(s) =
+// erfc((s - rmid) slope)/2, row-major [my][mx].
+__global__ void __launch_bounds__(256) k_trunc_samples(double *buf, int64_t M, double h, double alpha,
+                                                       double delta, double rmid, double slope,
                                                        const double *__restrict__ gt,
                                                        const double *__restrict__ gw)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n2 * n2) return;
-    const int64_t iy = id / n2, ix = id % n2;
-    const double x = (ix < n2 / 2 ? ix : ix - n2) * h, y = (iy < n2 / 2 ? iy : iy - n2) * h;
-    const double ax = fabs(x), ay = fabs(y);
-    double v = 0.0;
-    if (ax < rcut && ay < rcut)
-        v = h * h * history_kernel(sqrt(x * x + y * y), alpha, delta, gt, gw) * 0.25 * erfc((ax - rmid) * slope) *
-            erfc((ay - rmid) * slope);
-    buf[iy * (n2 + 2) + ix] = v;
+    if (id >= M * M) return;
+    const int64_t my = id / M, mx = id % M;
+    const double x = mx * h, y = my * h;
+    buf[id] = h * h * history_kernel(sqrt(x * x + y * y), alpha, delta, gt, gw) * 0.25 * erfc((x - rmid) * slope) *
+              erfc((y - rmid) * slope);
 }
 
-// Multiplier table on the kept modes from the spectrum of the samples: the
-// transform of the even kernel is real; mode l of the period-P grid is mode
-// 2l of the period-2P sample grid.
-__global__ void __launch_bounds__(256) k_trunc_table(const double *__restrict__ spec, int64_t n2, int lmax,
+// One separable step of the cosine transform of the even samples:
+//   out[a][b] = sum_{k < K} c_k cos(2 pi a k / n) in[b][k],  c_0 = 1, c_k = 2,
+// for a < NA, b < NB (the +-k pairs of the even sequence folded into c_k).
+// Tiles of 64 x 64 outputs per 256-thread workgroup, 4 x 4 per thread, the
+// cosine factors (from a table of cos(2 pi m / n) at m = a k mod n) and the
+// input staged through LDS 32 values of k at a time.
+constexpr int CS_T = 64, CS_K = 32;
+__global__ void __launch_bounds__(256) k_cos_step(const double *__restrict__ in, int64_t K, int64_t NA, int64_t NB,
+                                                  int n, const double *__restrict__ costab, double *__restrict__ out)
+{
+    __shared__ double ca[CS_K][CS_T + 1];
+    __shared__ double ib[CS_K][CS_T + 1];
+    const int tid = threadIdx.x;
+    const int64_t a0 = (int64_t)blockIdx.x * CS_T, b0 = (int64_t)blockIdx.y * CS_T;
+    const int ta = tid / 16, tb = tid % 16;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < K; k0 += CS_K) {
+        for (int e = tid; e < CS_K * CS_T; e += 256) {
+            const int kk = e / CS_T, aa = e % CS_T;
+            const int64_t k = k0 + kk, a = a0 + aa;
+            double v = 0.0;
+            if (k < K && a < NA) v = (k == 0 ? 1.0 : 2.0) * costab[(int)((a * k) % n)];
+            ca[kk][aa] = v;
+        }
+        for (int e = tid; e < CS_K * CS_T; e += 256) {
+            const int bb = e / CS_K, kk = e % CS_K;
+            const int64_t k = k0 + kk, b = b0 + bb;
+            ib[kk][bb] = (k < K && b < NB) ? in[b * K + k] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < CS_K; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                av[i] = ca[kk][ta + 16 * i];
+                bv[i] = ib[kk][tb + 16 * i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t a = a0 + ta + 16 * i, b = b0 + tb + 16 * j;
+            if (a < NA && b < NB) out[a * NB + b] = acc[i][j];
+        }
+}
+
+// Multiplier table on the kept modes |l_x|, |l_y| <= lmax from the cosine
+// transform tr[l_y][l_x] (l >= 0; the kernel's transform is real and even).
+__global__ void __launch_bounds__(256) k_trunc_table(const double *__restrict__ tr, int lmax,
                                                      const double *__restrict__ phi2inv, double c,
                                                      double *__restrict__ mtab)
 {
     const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w = lmax + 1;
     if (id >= (2 * (int64_t)lmax + 1) * w) return;
-    const int64_t lx = id % w, fy = id / w - lmax;
-    const int64_t ky2 = ((2 * fy) % n2 + n2) % n2, kx2 = 2 * lx;
-    const double re = spec[2 * (ky2 * (n2 / 2 + 1) + kx2)];
-    mtab[id] = c * re * phi2inv[lx] * phi2inv[fy < 0 ? -fy : fy];
+    const int64_t lx = id % w, fy = id / w - lmax, ly = fy < 0 ? -fy : fy;
+    mtab[id] = c * tr[ly * w + lx] * phi2inv[lx] * phi2inv[ly];
 }
 
-hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,
-                                       double rmid, double slope, const double *gl_t, const double *gl_w,
-                                       hipStream_t s)
+hipError_t launch_trunc_kernel_samples(double *buf, int64_t M, double h, double alpha, double delta, double rmid,
+                                       double slope, const double *gl_t, const double *gl_w, hipStream_t s)
 {
-    const int64_t tot = n2 * n2;
-    hipLaunchKernelGGL(k_trunc_samples, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, buf, n2, h, alpha,
-                       delta, rcut, rmid, slope, gl_t, gl_w);
+    const int64_t tot = M * M;
+    hipLaunchKernelGGL(k_trunc_samples, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, buf, M, h, alpha,
+                       delta, rmid, slope, gl_t, gl_w);
     return hipGetLastError();
 }
 
-hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const double *phi2inv, double c,
-                              double *mtab, hipStream_t s)
+hipError_t launch_cos_step(const double *in, int64_t K, int64_t NA, int64_t NB, int n, const double *costab,
+                           double *out, hipStream_t s)
+{
+    dim3 grid((unsigned)((NA + CS_T - 1) / CS_T), (unsigned)((NB + CS_T - 1) / CS_T));
+    hipLaunchKernelGGL(k_cos_step, grid, dim3(256), 0, s, in, K, NA, NB, n, costab, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_trunc_table(const double *tr, int lmax, const double *phi2inv, double c, double *mtab,
+                              hipStream_t s)
 {
     const int64_t tot = (2 * (int64_t)lmax + 1) * (lmax + 1);
-    hipLaunchKernelGGL(k_trunc_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, spec, n2, lmax, phi2inv,
-                       c, mtab);
+    hipLaunchKernelGGL(k_trunc_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tr, lmax, phi2inv, c,
+                       mtab);
     return hipGetLastError();
 }
 

@@ -232,11 +232,12 @@ hipError_t launch_columns(mhk_plan *P);
 hipError_t launch_rows(mhk_plan *P, bool inverse);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
-hipError_t launch_trunc_kernel_samples(double *buf, int64_t n2, double h, double alpha, double delta, double rcut,
-                                       double rmid, double slope, const double *gl_t, const double *gl_w,
-                                       hipStream_t s);
-hipError_t launch_trunc_table(const double *spec, int64_t n2, int lmax, const double *phi2inv, double c,
-                              double *mtab, hipStream_t s);
+hipError_t launch_trunc_kernel_samples(double *buf, int64_t M, double h, double alpha, double delta, double rmid,
+                                       double slope, const double *gl_t, const double *gl_w, hipStream_t s);
+hipError_t launch_cos_step(const double *in, int64_t K, int64_t NA, int64_t NB, int n, const double *costab,
+                           double *out, hipStream_t s);
+hipError_t launch_trunc_table(const double *tr, int lmax, const double *phi2inv, double c, double *mtab,
+                              hipStream_t s);
 
 // Device-side binning of plan creation (bin.hip); every call is
 // asynchronous on st and allocates its temporaries in the order of st.

@@ -753,120 +753,59 @@ double window_ft(double k, double half_width, double beta, const std::vector<dou
 
 // Multiplier table of the smoothly truncated history kernel g_T(x, y) =
 // G^H(r) chi(|x|) chi(|y|), chi = 1 up to the separation bound D and 0
-// beyond D + trans:
-// samples on a 2n x 2n grid of the same step (period 2P, which holds the
-// support of g_T without overlap), one real-to-complex FFT, and the even
-// modes, which are the modes of the period-P grid.
+// beyond D + trans.  Its Fourier coefficients on the period-P grid are the
+// transform of its samples of step h over the period 2P that holds its
+// support without overlap, at the even modes 2l, i.e. the sums
+//   T(l_x, l_y) = sum_{x, y} h^2 g_T(x, y) cos(2 pi l_x m_x / n) cos(2 pi l_y m_y / n)
+// over the samples x = m_x h, y = m_y h (g_T is even, so the transform is
+// real and the +-m terms pair up).  Only |l| <= lmax is kept and the
+// samples vanish beyond M = ceil((D + trans)/h), so the two separable
+// cosine sums over the M x M quarter grid cost O(lmax M^2) multiply-adds
+// on the device (no FFT plan to build).
 mhk_status build_trunc_table(mhk_plan *P, const std::vector<double> &qt, const std::vector<double> &qw)
 {
     History &G = P->hist;
     const double rmid = G.trunc_d + 0.5 * G.trunc_w, slope = 11.8 / G.trunc_w;
     const double rcut = G.trunc_d + G.trunc_w;
-    const int64_t n2 = 2 * G.n;
     G.lmax = (int)floor(G.kcut * G.period / (2 * M_PI));
-    if (2 * G.lmax > n2 / 2) {
+    if (2 * G.lmax > G.n) {
         set_error("truncated-kernel table: too many modes for the grid");
         return MHK_EUNSUPPORTED;
     }
+    const int64_t M = std::min<int64_t>(G.n, (int64_t)ceil(rcut / G.h));
+    const int64_t L1 = G.lmax + 1;
     std::vector<double> t16, w16;
     gauss_legendre(16, t16, w16);
-    double *buf = nullptr, *gt = nullptr, *gw = nullptr, *phi = nullptr, *work = nullptr;
-    size_t bytes = sizeof(double) * (size_t)n2 * (size_t)(n2 + 2);
-    // temporaries are allocated and freed in the order of the plan's stream
-    // (hipFree would wait for the whole device, i.e. for other plans' work)
-    hipStream_t s0 = P->stream;
-    if (hipMallocAsync((void **)&buf, bytes, s0) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error("truncated-kernel table: allocation of the sample grid failed");
-        return MHK_ENOMEM;
-    }
-    mhk_status st = MHK_OK;
-    rocfft_plan plan = nullptr;
-    rocfft_execution_info ex = nullptr;
-    rocfft_plan_description d = nullptr;
-    std::vector<double> phi2inv(G.lmax + 1);
+    std::vector<double> phi2inv(L1);
     for (int l = 0; l <= G.lmax; ++l) {
         double k = 2 * M_PI * l / G.period;
         double ph = window_ft(k, 0.5 * G.w * G.h, G.beta, qt, qw);
         phi2inv[l] = 1.0 / (ph * ph);
     }
-    do {
-        if (hipMallocAsync((void **)&gt, 16 * sizeof(double), s0) != hipSuccess ||
-            hipMallocAsync((void **)&gw, 16 * sizeof(double), s0) != hipSuccess ||
-            hipMallocAsync((void **)&phi, (G.lmax + 1) * sizeof(double), s0) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("truncated-kernel table: allocation failed");
-            st = MHK_ENOMEM;
-            break;
-        }
-        if (hipMemcpyAsync(gt, t16.data(), 16 * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
-            hipMemcpyAsync(gw, w16.data(), 16 * sizeof(double), hipMemcpyHostToDevice, s0) != hipSuccess ||
-            hipMemcpyAsync(phi, phi2inv.data(), (G.lmax + 1) * sizeof(double), hipMemcpyHostToDevice, s0) !=
-                hipSuccess) {
-            set_error("truncated-kernel table: copy failed");
-            st = MHK_EHIP;
-            break;
-        }
-        if (launch_trunc_kernel_samples(buf, n2, G.h, P->p.alpha, P->delta, rcut, rmid, slope, gt, gw, P->stream) !=
-            hipSuccess) {
-            set_error("truncated-kernel sample launch failed");
-            st = MHK_EHIP;
-            break;
-        }
-        size_t len[2] = {(size_t)n2, (size_t)n2};
-        size_t rstr[2] = {1, (size_t)n2 + 2}, cstr[2] = {1, (size_t)(n2 / 2 + 1)};
-        if (rocfft_plan_description_create(&d) != rocfft_status_success ||
-            rocfft_plan_description_set_data_layout(d, rocfft_array_type_real, rocfft_array_type_hermitian_interleaved,
-                                                    nullptr, nullptr, 2, rstr, (size_t)n2 * (n2 + 2), 2, cstr,
-                                                    (size_t)n2 * (n2 / 2 + 1)) != rocfft_status_success ||
-            rocfft_plan_create(&plan, rocfft_placement_inplace, rocfft_transform_type_real_forward,
-                               rocfft_precision_double, 2, len, 1, d) != rocfft_status_success ||
-            rocfft_execution_info_create(&ex) != rocfft_status_success) {
-            set_error("truncated-kernel table: rocFFT plan failed");
-            st = MHK_EHIP;
-            break;
-        }
-        size_t wb = 0;
-        rocfft_plan_get_work_buffer_size(plan, &wb);
-        if (wb) {
-            if (hipMallocAsync((void **)&work, wb, s0) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("truncated-kernel table: work buffer allocation failed");
-                st = MHK_ENOMEM;
-                break;
-            }
-            rocfft_execution_info_set_work_buffer(ex, work, wb);
-        }
-        rocfft_execution_info_set_stream(ex, P->stream);
-        void *io[1] = {buf};
-        if (rocfft_execute(plan, io, nullptr, ex) != rocfft_status_success) {
-            set_error("truncated-kernel table: FFT failed");
-            st = MHK_EHIP;
-            break;
-        }
-        const int64_t nt = (2 * (int64_t)G.lmax + 1) * (G.lmax + 1);
-        st = dalloc(P, &G.mtab, nt);
-        if (st != MHK_OK) break;
-        const double c = pow(G.h, 4) / (G.period * G.period);   // samples carry h^2: spectrum ~ transform
-        if (launch_trunc_table(buf, n2, G.lmax, phi, c, G.mtab, P->stream) != hipSuccess ||
-            hipStreamSynchronize(P->stream) != hipSuccess) {
-            set_error("truncated-kernel table kernel failed");
-            st = MHK_EHIP;
-            break;
-        }
-    } while (0);
-    if (ex) rocfft_execution_info_destroy(ex);
-    if (plan) rocfft_plan_destroy(plan);
-    if (d) rocfft_plan_description_destroy(d);
-    // the host vectors copied from above live until here, and the stream is
-    // synchronised on success; on failure wait before they go away
-    if (st != MHK_OK) (void)hipStreamSynchronize(s0);
-    (void)hipFreeAsync(buf, s0);
-    if (gt) (void)hipFreeAsync(gt, s0);
-    if (gw) (void)hipFreeAsync(gw, s0);
-    if (phi) (void)hipFreeAsync(phi, s0);
-    if (work) (void)hipFreeAsync(work, s0);
-    return st;
+    std::vector<double> costab(G.n);
+    for (int64_t m = 0; m < G.n; ++m) costab[m] = (double)cosl(2.0L * M_PIl * (long double)m / (long double)G.n);
+    const hipStream_t st = P->stream;
+    StreamTmp tmp(st);
+    double *samp = nullptr, *half = nullptr, *tr = nullptr, *gt = nullptr, *gw = nullptr, *phi = nullptr,
+           *ctab = nullptr;
+    TRY(tmp.alloc(&samp, M * M));
+    TRY(tmp.alloc(&half, L1 * M));
+    TRY(tmp.alloc(&tr, L1 * L1));
+    TRY(tmp.upload(&gt, t16.data(), 16));
+    TRY(tmp.upload(&gw, w16.data(), 16));
+    TRY(tmp.upload(&phi, phi2inv.data(), L1));
+    TRY(tmp.upload(&ctab, costab.data(), G.n));
+    TRY(dalloc(P, &G.mtab, (2 * (int64_t)G.lmax + 1) * L1));
+    MHK_HIP(launch_trunc_kernel_samples(samp, M, G.h, P->p.alpha, P->delta, rmid, slope, gt, gw, st));
+    // half[l_x][m_y] = sum_{m_x} c cos(l_x m_x) samp[m_y][m_x]
+    MHK_HIP(launch_cos_step(samp, M, L1, M, (int)G.n, ctab, half, st));
+    // tr[l_y][l_x] = sum_{m_y} c cos(l_y m_y) half[l_x][m_y]
+    MHK_HIP(launch_cos_step(half, M, L1, L1, (int)G.n, ctab, tr, st));
+    const double c = pow(G.h, 4) / (G.period * G.period);   // samples carry h^2: spectrum ~ transform
+    MHK_HIP(launch_trunc_table(tr, G.lmax, phi, c, G.mtab, st));
+    // the host vectors uploaded above must outlive the copies
+    MHK_HIP(hipStreamSynchronize(st));
+    return MHK_OK;
 }
 
 // Relative cost of rocFFT 2D transforms of size n x n (per point), measured
