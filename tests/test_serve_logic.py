@@ -21,29 +21,33 @@ class FakeDevice:
         self.plan_bytes = plan_bytes        # geometry key -> bytes
         self.duration = duration            # geometry key -> seconds per eval
         self.created, self.destroyed, self.launched = [], [], []
+        self.groups, self.inputs, self.batches = [], [], []
 
-    def footprint(self, req):
+    def footprint(self, req, batch=1):
         return self.plan_bytes[req.geometry.key]
 
-    def io_bytes(self, req):
+    def io_bytes(self, req, batch=1):
         return 10
 
-    def create_plan(self, req):
+    def create_plan(self, req, batch=1):
         self.created.append(req.plan_key)
+        self.batches.append(batch)
         return {"key": req.plan_key}, self.plan_bytes[req.geometry.key]
 
     def destroy_plan(self, plan):
         self.destroyed.append(plan["key"])
 
-    def launch(self, plan, req):
-        self.launched.append(req.rid)
-        return {"end": self.clock() + self.duration[req.geometry.key], "rid": req.rid}
+    def launch(self, plan, group):
+        self.launched.extend(r.rid for r in group)
+        self.groups.append([r.rid for r in group])
+        self.inputs.append([r.u_n for r in group])
+        return {"end": self.clock() + self.duration[group[0].geometry.key], "rids": [r.rid for r in group]}
 
     def done(self, h):
         return self.clock() >= h["end"]
 
     def result(self, h):
-        return ("result", h["rid"])
+        return [("result", rid) for rid in h["rids"]]
 
 
 def _geo(key):
@@ -76,11 +80,11 @@ def test_admission_eviction_and_order():
     clk.t = 1.0                      # A finishes: second A reuses the resident plan
     srv.step()
     assert dev.launched[2] == 1
-    assert dev.created.count(("A", 10.0, 1e-6, 1)) == 1
+    assert dev.created.count(("A", 10.0, 1e-6, 1, "eval")) == 1
     clk.t = 2.0
     srv.step()                       # second A done; C admitted after evicting idle plans
     assert 3 in dev.launched
-    assert ("B", 10.0, 1e-6, 1) in dev.destroyed
+    assert ("B", 10.0, 1e-6, 1, "eval") in dev.destroyed
     clk.t = 3.5
     srv.step()
     assert sorted(r.rid for r in srv.finished) == [0, 1, 2, 3]
@@ -122,20 +126,20 @@ class FailingDevice(FakeDevice):
         super().__init__(clock, plan_bytes, duration)
         self.fail = fail                     # geometry key -> "footprint" | "create" | "launch"
 
-    def footprint(self, req):
+    def footprint(self, req, batch=1):
         if self.fail.get(req.geometry.key) == "footprint":
             raise RuntimeError("history grid too large")
-        return super().footprint(req)
+        return super().footprint(req, batch)
 
-    def create_plan(self, req):
+    def create_plan(self, req, batch=1):
         if self.fail.get(req.geometry.key) == "create":
             raise RuntimeError("out of memory")
-        return super().create_plan(req)
+        return super().create_plan(req, batch)
 
-    def launch(self, plan, req):
-        if self.fail.get(req.geometry.key) == "launch":
+    def launch(self, plan, group):
+        if self.fail.get(group[0].geometry.key) == "launch":
             raise RuntimeError("invalid input")
-        return super().launch(plan, req)
+        return super().launch(plan, group)
 
 
 def test_failures_are_rejected_and_rolled_back():
@@ -152,10 +156,10 @@ def test_failures_are_rejected_and_rolled_back():
     assert all(r.error and r.done >= 0 for r in srv.rejected)
     assert sorted(dev.launched) == [1, 4]
     # the plan whose launch failed stays idle and its bytes are the plan's only
-    ent = srv.plans[("L", 10.0, 1e-6, 1)]
+    ent = srv.plans[("L", 10.0, 1e-6, 1, "eval")]
     assert ent["busy"] is False
     assert srv.used == 3 * 100 + 2 * 10          # plans A, L, B; in-flight io of A and B
-    assert ("C", 10.0, 1e-6, 1) not in srv.plans  # creation failed: nothing resident
+    assert ("C", 10.0, 1e-6, 1, "eval") not in srv.plans  # creation failed: nothing resident
     assert len(srv.queue) == 0
     clk.t = 1.0
     srv.step()
@@ -183,3 +187,52 @@ def test_failed_completion_query_releases_the_plan():
     clk.t = 2.0
     srv.step()
     assert [r.rid for r in srv.finished] == [1]
+
+
+def test_coalescing_into_the_plan_batch():
+    """Queued requests of one plan are launched together, up to the plan's
+    batch; a request of another plan is not drawn into the group."""
+    clk = FakeClock()
+    dev = FakeDevice(clk, {"A": 100, "B": 100}, {"A": 1.0, "B": 1.0})
+    srv = Server(dev, budget_bytes=10_000, clock=clk, max_batch=4)
+    for rid, key in enumerate(["A", "A", "B", "A", "A", "A", "A"]):
+        srv.submit(_req(rid, key))
+    assert srv.step() == 5
+    assert dev.groups == [[0, 1, 3, 4], [2]]
+    assert dev.batches == [4, 4]
+    assert [r.rid for r in srv.queue] == [5, 6]
+    clk.t = 1.0
+    srv.step()
+    assert dev.groups[-1] == [5, 6]
+    clk.t = 2.0
+    srv.step()
+    assert sorted(r.rid for r in srv.finished) == list(range(7))
+    assert all(r.result == ("result", r.rid) for r in srv.finished)
+    assert {r.rid: r.batched_with for r in srv.finished} == {0: 4, 1: 4, 3: 4, 4: 4, 2: 1, 5: 2, 6: 2}
+
+
+def test_heat_chain_steps_depend_on_each_other():
+    """A heat chain's step n + 1 is submitted only when step n has finished,
+    with step n's result as its input; two chains overlap."""
+    from paper_2606_28865_amd.serve import HeatChain
+    clk = FakeClock()
+    dev = FakeDevice(clk, {"H1": 100, "H2": 100}, {"H1": 1.0, "H2": 2.0})
+    srv = Server(dev, budget_bytes=10_000, clock=clk, max_batch=4)
+    chains = [HeatChain(i, _geo(k), 10.0, 1e-10, f"u0-{k}", lambda n: n, 3, rid0=100 * (i + 1))
+              for i, k in enumerate(["H1", "H2"])]
+    for c in chains:
+        srv.submit(c.first())
+    srv.step()
+    assert dev.groups == [[101], [201]]          # heat steps are never coalesced
+    assert dev.inputs == [["u0-H1"], ["u0-H2"]]
+    assert dev.batches == [1, 1]
+    for t in (1.0, 2.0, 3.0, 4.0, 5.0, 6.0):
+        clk.t = t
+        srv.step()
+    # t = 2: 201 and 102 finish in launch order, so 202 is queued before 103
+    assert [g[0] for g in dev.groups] == [101, 201, 102, 202, 103, 203]
+    # each step's input is the previous step's result
+    assert dev.inputs[2] == ["result"] and dev.inputs[4] == ["result"]
+    assert all(c.finished for c in chains)
+    assert [s.step for s in chains[0].steps] == [1, 2, 3]
+    assert sorted(r.rid for r in srv.finished) == [101, 102, 103, 201, 202, 203]
