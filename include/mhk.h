@@ -97,6 +97,10 @@ typedef struct {
                         and Corollaries 4.4, 4.7, 4.10, 4.11 (error
                         O(delta*^{5/2})); with 2, f_trg carries f's gradient and
                         Hessian (see mhk_eval)                                       */
+    int lv_block;    /* tile shape of the dyadic-level sums: targets per workgroup,
+                        256 or 512 (0: 256); the same sums in another order       */
+    int lv_bch;      /* densities per pass of the level sums for batch > 1: 1, 2, 4
+                        or 8 (0: 4); each kernel-table evaluation serves them all */
 } mhk_params;
 
 typedef struct {

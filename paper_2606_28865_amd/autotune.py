@@ -1,4 +1,6 @@
-"""Autotuner for the history grid: oversampling factor and window width.
+"""Autotuner for the history grid (oversampling factor, window width) and
+the tile shapes of the dyadic-level sums (targets per workgroup, densities
+per pass).
 
 For one geometry, alpha, tolerance and precision, each candidate (upsamp,
 wspread) is built as a plan with the same split delta, timed on the device
@@ -10,8 +12,11 @@ the evaluation, not for the rounding of its inputs, which the local layer
 terms amplify through the density's second derivative): a candidate is
 admissible when its relative max-norm difference to the reference is below
 the tolerance for S, D and V.  The fastest admissible candidate wins.
-Results are cached in a JSON file keyed by the problem's sizes and
-parameters.
+Then, on that grid, the level-sum tile shapes (lv_block 256 or 512 targets
+per workgroup; lv_bch 2, 4 or 8 densities per pass when batch > 1) are timed
+the same way; they change only the order of the sums, so their results are
+checked against the same reference and the fastest is kept.  Results are
+cached in a JSON file keyed by the problem's sizes and parameters.
 
 Everything runs through the library (no CPU fallback); the reference is the
 library's own FP64 path, whose agreement with the oracle is what the parity
@@ -31,9 +36,10 @@ DEFAULT_CANDIDATES = [(2.0, 0), (1.75, 0), (1.5, 0), (2.0, -1), (1.5, 1), (1.25,
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mhk_autotune.json")
 
 
-def _key(geometry, alpha, tol, prec, batch):
+def _key(geometry, alpha, tol, prec, batch, tiles=True):
     b, v, t = geometry["boundary"], geometry.get("volume"), geometry["targets"]
-    return f"nb{len(b['x'])}-nv{0 if v is None else len(v['x'])}-nt{len(t[0])}-a{alpha:g}-t{tol:g}-p{prec}-b{batch}"
+    return (f"nb{len(b['x'])}-nv{0 if v is None else len(v['x'])}-nt{len(t[0])}-a{alpha:g}-t{tol:g}-p{prec}"
+            f"-b{batch}" + ("-tiles" if tiles else ""))
 
 
 def _rel(a, b):
@@ -44,13 +50,19 @@ def _rel(a, b):
     return float(np.abs(a[m] - b[m]).max() / (s if s > 0 else 1.0))
 
 
+def tile_candidates(batch):
+    """(lv_block, lv_bch) pairs tried on the chosen grid."""
+    bchs = (1,) if batch == 1 else tuple(b for b in (2, 4, 8) if b <= max(2, batch))
+    return [(nb, bc) for nb in (256, 512) for bc in bchs]
+
+
 def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, candidates=None, reps=3,
-         cache=CACHE, log=None):
+         cache=CACHE, log=None, tiles=True):
     """geometry: dict(boundary=..., volume=..., targets=(x, y, inside), on_surface=bool);
     densities: (sigma, mu, f_vol, f_trg) host arrays of one density.
     Returns dict(upsamp, wspread, ms, err, table)."""
     import torch
-    key = _key(geometry, alpha, tol, prec, batch)
+    key = _key(geometry, alpha, tol, prec, batch, tiles)
     if cache and os.path.exists(cache):
         try:
             db = json.load(open(cache))
@@ -77,15 +89,12 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
     ref_plan.close()
     ins = [dev(x, dt) for x in densities]
     w0 = L.resolve_params(alpha=alpha, tol=tol, prec=prec, delta=delta)["wspread"]
-    table = []
-    for ups, dw in cands:
-        ws = max(4, min(16, w0 + dw))
+    def trial(ups, ws, lv_block=0, lv_bch=0):
         try:
             p = L.Plan(L.make_params(alpha=alpha, tol=tol, prec=prec, delta=delta, batch=batch, upsamp=ups,
-                                     wspread=ws), *geo, on_surface=on)
+                                     wspread=ws, lv_block=lv_block, lv_bch=lv_bch), *geo, on_surface=on)
         except L.MhkError as e:
-            table.append({"upsamp": ups, "wspread": ws, "error": str(e)})
-            continue
+            return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "error": str(e)}
         out = p.eval(*ins)
         torch.cuda.synchronize()
         err = max(_rel(o[0], r[0]) for o, r in zip(out, ref))
@@ -97,18 +106,28 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         info = p.info()
-        table.append({"upsamp": ups, "wspread": ws, "ms": ms, "err": err, "n_fine": info["n_fine"],
-                      "sigma_eff": None})
-        if log:
-            log(f"autotune alpha={alpha} ups={ups} w={ws}: {ms:.3f} ms, err {err:.2e}, n {info['n_fine']}")
         p.close()
         del out
+        if log:
+            log(f"autotune alpha={alpha} ups={ups} w={ws} lv_block={lv_block} lv_bch={lv_bch}: {ms:.3f} ms, "
+                f"err {err:.2e}, n {info['n_fine']}")
+        return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "ms": ms, "err": err,
+                "n_fine": info["n_fine"]}
+
+    table = [trial(ups, max(4, min(16, w0 + dw))) for ups, dw in cands]
     ok = [c for c in table if "ms" in c and c["err"] < tol]
     if not ok:
         raise RuntimeError(f"autotune: no admissible candidate for {key}: {table}")
     best = min(ok, key=lambda c: c["ms"])
-    res = {"upsamp": best["upsamp"], "wspread": best["wspread"], "ms": best["ms"], "err": best["err"],
-           "table": table, "delta": delta}
+    tile_table = []
+    if tiles:
+        tile_table = [trial(best["upsamp"], best["wspread"], nb, bc) for nb, bc in tile_candidates(batch)]
+        ok2 = [c for c in tile_table if "ms" in c and c["err"] < tol]
+        if ok2:
+            best = min(ok2 + [best], key=lambda c: c["ms"])
+    res = {"upsamp": best["upsamp"], "wspread": best["wspread"], "lv_block": best["lv_block"],
+           "lv_bch": best["lv_bch"], "ms": best["ms"], "err": best["err"], "table": table,
+           "tile_table": tile_table, "delta": delta}
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -288,11 +288,17 @@ struct GmresWs {
 
 static inline int gmres_nblk(int64_t n) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + BT - 1) / BT)); }
 
-static mhk_status nys_alloc(double **p, int64_t count)
+// Device buffers of a Nystrom object are allocated and freed in the order
+// of its stream (hipFree would wait for every stream of the device, i.e.
+// for other plans' work); an allocation is waited for on that stream before
+// use, since the solves run on the plan's stream.
+static mhk_status nys_alloc(mhk_nystrom *N, double **p, int64_t count)
 {
     *p = nullptr;
-    if (hipMalloc((void **)p, sizeof(double) * (size_t)std::max<int64_t>(count, 1)) != hipSuccess) {
+    if (hipMallocAsync((void **)p, sizeof(double) * (size_t)std::max<int64_t>(count, 1), N->stream) != hipSuccess ||
+        hipStreamSynchronize(N->stream) != hipSuccess) {
         (void)hipGetLastError();
+        if (*p) (void)hipFreeAsync(*p, N->stream);
         *p = nullptr;
         set_error("device allocation of " + std::to_string(sizeof(double) * count) + " bytes failed");
         return MHK_ENOMEM;
@@ -300,13 +306,16 @@ static mhk_status nys_alloc(double **p, int64_t count)
     return MHK_OK;
 }
 
+static void nys_free(mhk_nystrom *N, double **p)
+{
+    if (*p) (void)hipFreeAsync(*p, N->stream);
+    *p = nullptr;
+}
+
 static void nys_free_ws(mhk_nystrom *N)
 {
-    for (double **p : {&N->V, &N->wv, &N->rv, &N->part, &N->hd, &N->yd}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
-    if (N->hh) (void)hipHostFree(N->hh);
+    for (double **p : {&N->V, &N->wv, &N->rv, &N->part, &N->hd, &N->yd}) nys_free(N, p);
+    delete[] N->hh;
     N->hh = nullptr;
     N->ws_bytes = 0;
     N->m_cap = 0;
@@ -317,18 +326,16 @@ static mhk_status nys_workspace(mhk_nystrom *N, int m)
     if (m <= N->m_cap) return MHK_OK;
     nys_free_ws(N);
     N->nblk = gmres_nblk(N->n);
-    BIE_TRY(nys_alloc(&N->V, (int64_t)(m + 1) * N->n));
-    BIE_TRY(nys_alloc(&N->wv, N->n));
-    BIE_TRY(nys_alloc(&N->rv, N->n));
-    BIE_TRY(nys_alloc(&N->part, (int64_t)(m + 1) * N->nblk));
-    BIE_TRY(nys_alloc(&N->hd, 2 * (m + 1) + 1));
-    BIE_TRY(nys_alloc(&N->yd, m));
-    if (hipHostMalloc((void **)&N->hh, sizeof(double) * (size_t)(2 * (m + 1) + 1 + m)) != hipSuccess) {
-        (void)hipGetLastError();
-        N->hh = nullptr;
-        set_error("pinned host allocation failed");
-        return MHK_ENOMEM;
-    }
+    BIE_TRY(nys_alloc(N, &N->V, (int64_t)(m + 1) * N->n));
+    BIE_TRY(nys_alloc(N, &N->wv, N->n));
+    BIE_TRY(nys_alloc(N, &N->rv, N->n));
+    BIE_TRY(nys_alloc(N, &N->part, (int64_t)(m + 1) * N->nblk));
+    BIE_TRY(nys_alloc(N, &N->hd, 2 * (m + 1) + 1));
+    BIE_TRY(nys_alloc(N, &N->yd, m));
+    // host mirror of the few Arnoldi values copied back per iteration
+    // (pageable: pinned host memory would have to be released with
+    // hipHostFree, which waits for the whole device)
+    N->hh = new double[(size_t)(2 * (m + 1) + 1 + m)];
     N->m_cap = m;
     N->ws_bytes = (int64_t)sizeof(double) * ((int64_t)(m + 3) * N->n + (int64_t)(m + 1) * N->nblk + 3 * (m + 1));
     return MHK_OK;
@@ -358,10 +365,9 @@ static mhk_status own_workspace(mhk_nystrom *N, int m, OwnWs &o)
 static mhk_status nys_scratch(mhk_nystrom *N, int64_t nout)
 {
     if (nout <= N->work_n) return MHK_OK;
-    if (N->work) (void)hipFree(N->work);
-    N->work = nullptr;
+    nys_free(N, &N->work);
     N->work_n = 0;
-    BIE_TRY(nys_alloc(&N->work, 2 * nout));
+    BIE_TRY(nys_alloc(N, &N->work, 2 * nout));
     N->work_n = nout;
     return MHK_OK;
 }
@@ -604,8 +610,8 @@ mhk_status mhk_nystrom_create(double alpha, const mhk_boundary *b, void *hip_str
     N->alpha = alpha;
     N->stream = (hipStream_t)hip_stream;
     double *geo = nullptr;
-    mhk_status st = nys_alloc(&N->K, n * N->ld);
-    if (st == MHK_OK) st = nys_alloc(&geo, 6 * n);
+    mhk_status st = nys_alloc(N, &N->K, n * N->ld);
+    if (st == MHK_OK) st = nys_alloc(N, &geo, 6 * n);
     if (st != MHK_OK) {
         mhk_nystrom_destroy(N);
         return st;
@@ -631,7 +637,7 @@ mhk_status mhk_nystrom_create(double alpha, const mhk_boundary *b, void *hip_str
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(geo);
+    nys_free(N, &geo);
     if (e != hipSuccess) {
         set_error(std::string("Nystrom assembly: ") + hipGetErrorString(e));
         mhk_nystrom_destroy(N);
@@ -870,11 +876,11 @@ mhk_status mhk_heat_step(mhk_plan *P, mhk_nystrom *N, const double *u_n, const d
 void mhk_nystrom_destroy(mhk_nystrom *N)
 {
     if (!N) return;
-    if (N->stream) (void)hipStreamSynchronize(N->stream);
-    else (void)hipDeviceSynchronize();
+    (void)hipStreamSynchronize(N->stream);
     nys_free_ws(N);
-    if (N->K) (void)hipFree(N->K);
-    if (N->work) (void)hipFree(N->work);
+    nys_free(N, &N->K);
+    nys_free(N, &N->work);
+    (void)hipStreamSynchronize(N->stream);
     delete N;
 }
 

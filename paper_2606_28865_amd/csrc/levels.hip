@@ -215,19 +215,19 @@ __device__ inline void horner1(const PairGeo<double> &g, double &ks, double &kd)
     }
 }
 
-template <int BCH, typename T, int STRIDE>
-__global__ void __launch_bounds__(LV_BLOCK) k_level_sums(LevelArgs<T> A)
+template <int BCH, typename T, int STRIDE, int NB>
+__global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
 {
     extern __shared__ double lds[];
     T *s_tab = reinterpret_cast<T *>(lds);                // [nseg + 1][STRIDE], the last segment zero
     const int tid = threadIdx.x;
-    for (int i = tid; i < (A.nseg + 1) * STRIDE; i += LV_BLOCK) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
+    for (int i = tid; i < (A.nseg + 1) * STRIDE; i += NB) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
     __syncthreads();
 
     const int lane = tid % LV_WAVE;
     // one wavefront = LV_WAVE consecutive targets with their own source list
     // (the wave number is wave-uniform)
-    const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (LV_BLOCK / LV_WAVE) + tid / LV_WAVE]);
+    const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (NB / LV_WAVE) + tid / LV_WAVE]);
     const int64_t t = (int64_t)wave * LV_WAVE + lane;
     double x = 0.0, y = 0.0;
     if (t < A.nout) {
@@ -337,6 +337,27 @@ hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void
     return P->p.prec == MHK_FP64 ? level_q<double>(P, st, j, sigma, mu) : level_q<float>(P, st, j, sigma, mu);
 }
 
+template <int BCH, typename T, int STRIDE, int NB>
+static void level_launch(const LevelArgs<T> &A, dim3 grid, size_t lds, hipStream_t st)
+{
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_level_sums<BCH, T, STRIDE, NB>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_level_sums<BCH, T, STRIDE, NB>), grid, dim3(NB), lds, st, A);
+}
+
+template <int BCH, typename T, int STRIDE>
+static void level_launch_nb(int nb, const LevelArgs<T> &A, int64_t nwave, size_t lds, hipStream_t st, int nbatch)
+{
+    // exactly nwave wavefronts (the lists are padded to whole workgroups of
+    // either shape), the batch in chunks of BCH along y
+    const dim3 grid((unsigned)(nwave / (nb / LV_WAVE)), (unsigned)nbatch);
+    if (nb == 512)
+        level_launch<BCH, T, STRIDE, 512>(A, grid, lds, st);
+    else
+        level_launch<BCH, T, STRIDE, 256>(A, grid, lds, st);
+}
+
 template <typename T, int STRIDE>
 static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
@@ -365,20 +386,20 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     A.want_s = want_s;
     A.want_d = want_d;
     A.init = init;
-    const int bch = B == 1 ? 1 : LV_BCH;
-    dim3 grid((unsigned)((P->nout + LV_BLOCK - 1) / LV_BLOCK), (unsigned)((B + bch - 1) / bch));
+    // densities per pass: the plan's lv_bch, or fewer for a smaller batch
+    // (rounded up to an instantiated size; missing densities of the last
+    // pass are skipped)
+    const int want = std::min(B, P->p.lv_bch);
+    const int bch = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
+    const int nby = (B + bch - 1) / bch;
     const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    if (bch == 1) {
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void *)k_level_sums<1, T, STRIDE>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<1, T, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
-    } else {
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute((const void *)k_level_sums<LV_BCH, T, STRIDE>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL((k_level_sums<LV_BCH, T, STRIDE>), grid, dim3(LV_BLOCK), lds, st, A);
+    const int nb = P->p.lv_block;
+    switch (bch) {
+    case 1: level_launch_nb<1, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
+    case 2: level_launch_nb<2, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
+    case 4: level_launch_nb<4, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
+    default: level_launch_nb<8, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
     }
     return hipGetLastError();
 }

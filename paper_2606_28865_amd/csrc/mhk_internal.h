@@ -41,9 +41,8 @@ constexpr int COL_NMAX = 8192;   // longest history-grid column transformed in L
 constexpr int COL_MAXPASS = 16;  // radix passes of a column transform
 constexpr int LV_CDIV = 4;       // level cells are R_j / LV_CDIV wide
 constexpr int MAXW = 16;         // maximum spreading window width
-constexpr int LV_BLOCK = 256;    // targets per level-sum workgroup
+constexpr int LV_BLOCK_MAX = 512;  // largest level-sum workgroup (targets); 256 or 512 per plan
 constexpr int LV_WAVE = 64;      // lanes per level-sum wavefront
-constexpr int LV_BCH = 4;        // densities per pass of the level-sum kernel
 constexpr int LOCAL_GEO_N1 = 10; // doubles of local geometry per target, first-order plans
 constexpr int LOCAL_GEO_N2 = 27; // the same with the second-order terms (local_order = 2)
 
@@ -77,6 +76,7 @@ struct Level {
     int32_t *wave_order = nullptr;                // wavefronts in decreasing order of candidate work
     int32_t *wave_src = nullptr;                  // [n_cand]
     int64_t n_cand = 0;
+    int64_t n_wave = 0;                           // wavefronts of LV_WAVE targets (whole LV_BLOCK_MAX workgroups)
     double *interp = nullptr;                     // [nchild][16][16] parent -> child values
     double *tab = nullptr;                        // [nseg][TAB_STRIDE]: K_j^S per segment (K_j^D from its derivative)
     float *tabf = nullptr;                        // FP32 path: [nseg][TABF_STRIDE]
@@ -199,7 +199,8 @@ struct mhk_plan {
     mhk::Level lev[mhk::MAXJ];
     mhk::History hist;
     mhk::Local loc;
-    std::vector<void *> allocs;
+    std::vector<void *> allocs;                 // stream-ordered allocations on `stream`
+    std::vector<std::vector<char>> stage;       // host bytes of uploads in flight during creation
     int64_t bytes = 0;
     // stage timing: ev[0..7] history stages and local part on the plan's
     // stream, ev[8] start of the side work, ev[9] end of the local geometry

@@ -223,6 +223,16 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         double kmax = 0.9 * M_PI / p.dx;
         p.delta = log(1.0 / p.tol) / (kmax * kmax + p.alpha * p.alpha);
     }
+    if (p.lv_block == 0) p.lv_block = 256;
+    if (p.lv_block != 256 && p.lv_block != 512) {
+        set_error("lv_block must be 0, 256 or 512");
+        return MHK_EINVAL;
+    }
+    if (p.lv_bch == 0) p.lv_bch = 4;
+    if (p.lv_bch != 1 && p.lv_bch != 2 && p.lv_bch != 4 && p.lv_bch != 8) {
+        set_error("lv_bch must be 0, 1, 2, 4 or 8");
+        return MHK_EINVAL;
+    }
     if (p.local_order == 0) p.local_order = 1;
     if (p.local_order != 1 && p.local_order != 2) {
         set_error("local_order must be 0, 1 or 2");
@@ -293,16 +303,21 @@ using namespace mhk;
 // ---------------------------------------------------------------------------
 // Allocation helper
 // ---------------------------------------------------------------------------
+// Plan buffers are allocated and freed in the order of the plan's stream
+// (stream-ordered allocation): hipFree would wait for every stream of the
+// device, so destroying or building a plan would drain the work of other
+// plans running beside it.
 template <typename T>
 static mhk_status dalloc(mhk_plan *P, T **ptr, int64_t count)
 {
     *ptr = nullptr;
     if (count <= 0) count = 1;
     size_t bytes = sizeof(T) * (size_t)count;
-    hipError_t e = hipMalloc((void **)ptr, bytes);
+    hipError_t e = hipMallocAsync((void **)ptr, bytes, P->stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        *ptr = nullptr;
+        set_error("device allocation of " + std::to_string(bytes) + " bytes failed");
         return MHK_ENOMEM;
     }
     P->allocs.push_back(*ptr);
@@ -310,12 +325,19 @@ static mhk_status dalloc(mhk_plan *P, T **ptr, int64_t count)
     return MHK_OK;
 }
 
+// Host data copied into a plan buffer, in the order of the plan's stream; the
+// host bytes are staged in the plan until creation has synchronised its
+// stream.
 template <typename T>
 static mhk_status upload(mhk_plan *P, T **ptr, const T *host, int64_t count)
 {
     mhk_status s = dalloc(P, ptr, count);
     if (s != MHK_OK) return s;
-    if (count > 0) MHK_HIP(hipMemcpy(*ptr, host, sizeof(T) * count, hipMemcpyHostToDevice));
+    if (count > 0) {
+        const size_t bytes = sizeof(T) * (size_t)count;
+        P->stage.emplace_back((const char *)host, (const char *)host + bytes);
+        MHK_HIP(hipMemcpyAsync(*ptr, P->stage.back().data(), bytes, hipMemcpyHostToDevice, P->stream));
+    }
     return MHK_OK;
 }
 
@@ -371,7 +393,11 @@ struct StreamTmp {
 static void free_plan(mhk_plan *P)
 {
     if (!P) return;
-    for (void *p : P->allocs) (void)hipFree(p);
+    // uploads of a failed creation may still read the staged host bytes
+    if (!P->stage.empty()) (void)hipStreamSynchronize(P->stream);
+    // stream-ordered frees: after the plan's queued work, without waiting
+    // for other streams
+    for (void *p : P->allocs) (void)hipFreeAsync(p, P->stream);
     if (P->hist.fwd) rocfft_plan_destroy(P->hist.fwd);
     if (P->hist.inv) rocfft_plan_destroy(P->hist.inv);
     if (P->hist.exec) rocfft_execution_info_destroy(P->hist.exec);
@@ -575,7 +601,10 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
     // filled on the device); wavefronts past the last target get empty lists
     {
         const int64_t nout = P->nout;
-        const int64_t nwave = ((nout + LV_BLOCK - 1) / LV_BLOCK) * (LV_BLOCK / LV_WAVE);
+        // padded to whole workgroups of the larger tile shape, so that
+        // either one launches exactly nwave wavefronts
+        const int64_t nwave = ((nout + LV_BLOCK_MAX - 1) / LV_BLOCK_MAX) * (LV_BLOCK_MAX / LV_WAVE);
+        L.n_wave = nwave;
         const double R = L.radius, R2 = R * R * (1.0 + 1e-9);
         int32_t *cnt = nullptr;
         int64_t *tot = nullptr;
@@ -1437,6 +1466,8 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     // only the plan's own stream is waited for: work of other plans on other
     // streams keeps running while a plan is created
     MHK_HIP(hipStreamSynchronize(P->stream));
+    P->stage.clear();
+    P->stage.shrink_to_fit();
     lap(4);
     P->info.ms_plan[5] = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
     int32_t noconv = 0;

@@ -22,7 +22,11 @@ def test_cache_key_and_hit(tmp_path):
     k1 = autotune._key(geo, 10.0, 1e-6, 1, 1)
     # every tuned quantity is part of the key
     assert len({k1, autotune._key(geo, 10.0, 1e-6, 1, 64), autotune._key(geo, 3.0, 1e-6, 1, 1),
-                autotune._key(geo, 10.0, 1e-10, 1, 1), autotune._key(geo, 10.0, 1e-6, 0, 1)}) == 5
+                autotune._key(geo, 10.0, 1e-10, 1, 1), autotune._key(geo, 10.0, 1e-6, 0, 1),
+                autotune._key(geo, 10.0, 1e-6, 1, 1, tiles=False)}) == 6
+    # tile shapes tried on the chosen grid: densities per pass only with a batch
+    assert autotune.tile_candidates(1) == [(256, 1), (512, 1)]
+    assert autotune.tile_candidates(64) == [(n, b) for n in (256, 512) for b in (2, 4, 8)]
     entry = {"upsamp": 1.5, "wspread": 9, "ms": 1.0, "err": 1e-7, "table": [], "delta": 1e-3}
     cache = tmp_path / "tune.json"
     cache.write_text(json.dumps({k1: entry}))
@@ -42,11 +46,12 @@ def test_tuned_plan_matches_oracle():
     print("case autotune config0 fp32 batch 2", flush=True)
     res = autotune.tune(_geometry(w), alpha, tol, M.MHK_FP32, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx,
                         batch=2, candidates=[(2.0, 0), (1.5, 1), (1.25, 2)], reps=2, cache=None)
-    ok = [c for c in res["table"] if "ms" in c and c["err"] < tol]
+    ok = [c for c in res["table"] + res["tile_table"] if "ms" in c and c["err"] < tol]
     assert ok and res["err"] < tol
     assert res["ms"] == min(c["ms"] for c in ok)
+    assert len(res["tile_table"]) == 2
     prm = M.make_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, delta=res["delta"], upsamp=res["upsamp"],
-                        wspread=res["wspread"])
+                        wspread=res["wspread"], lv_block=res["lv_block"], lv_bch=res["lv_bch"])
     plan = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
     out = plan.eval(f32(w.sigma), f32(w.mu), f32(w.f_vol), f32(w.f_trg))
