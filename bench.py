@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8000.0          # GB/s
+FP32_PEAK = 157.3
 FP64_PEAK = 78.6           # TFLOP/s, vector FP64
 
 
@@ -51,6 +52,9 @@ def parse():
                          "on its own stream, the three evaluations of a step concurrent)")
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--max-batch", type=int, default=4,
+                    help="serve: requests of one plan coalesced into one launch")
+    ap.add_argument("--heat-steps", type=int, default=8, help="serve: steps of each heat chain")
     return ap.parse_args()
 
 
@@ -468,8 +472,13 @@ def run_precision(a):
 def run_batched(a):
     """64 densities per call on one 65536-node multi-body geometry (~1M volume
     nodes, 1M targets + boundary nodes), evaluated by replaying a captured HIP
-    graph; grid parameters from the autotuner, timed at the same batch size;
-    alpha in {3, 30}, FP32 and FP64."""
+    graph; grid and level-sum tile shapes from the autotuner, timed at the
+    same batch size; alpha in {3, 30}, FP32 and FP64.  Beside each, the same
+    geometry and parameters with one density per call (its own captured
+    graph), so that the per-density gain of batching is measured, and the
+    level sums' roofline fraction of both forms (algorithmic flops of the
+    pairs within the level radius, times the densities, over the level
+    stage's HIP-event time of an eager evaluation)."""
     import torch
 
     import paper_2606_28865_amd as M
@@ -494,39 +503,66 @@ def run_batched(a):
     fv = amp[:, None] * w.f_vol[None, :]
     ft = amp[:, None] * w.f_trg[None, :]
     geometry = {"boundary": w.boundary, "volume": w.volume, "targets": (w.tx, w.ty, w.inside), "on_surface": True}
+    pairs_cache = {}
+
+    def form(prm, ins, dt, nb):
+        """Captured-graph time per call and the level stage of an eager call."""
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            p = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=stream)
+            out = p.capture(*ins)
+            for _ in range(a.warmup):
+                p.replay()
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(a.steps):
+                p.replay()
+            e1.record(stream)
+            stream.synchronize()
+            ms = e0.elapsed_time(e1) / a.steps
+            p.set_timing(True)
+            p.eval(*ins, out=out)
+            info = p.info()
+            p.set_timing(False)
+        key = (info["alpha"], info["delta"])
+        if key not in pairs_cache:
+            pairs_cache[key] = level_pairs(w, info)
+        flops = pairs_cache[key] * LEVEL_FLOPS_PER_PAIR * nb
+        ach = flops / (info["ms_levels"] * 1e-3) / 1e12
+        peak = FP64_PEAK if dt == torch.float64 else FP32_PEAK
+        res = {"ms_per_call": ms, "densities": nb, "ms_per_density": ms / nb,
+               "target_evals_per_s": nb * p.n_out / (ms * 1e-3), "grid": info["n_fine"],
+               "level_sums": {"ms": info["ms_levels"], "achieved_tflops": ach, "peak_tflops": peak,
+                              "frac": ach / peak, "flops": flops},
+               "stage_ms": {k2: info[k2] for k2 in ("ms_spread", "ms_fft", "ms_multiply", "ms_interp", "ms_levels",
+                                                    "ms_local", "ms_total")}}
+        p.close()
+        del out
+        torch.cuda.empty_cache()
+        return res
+
     res = {}
     for alpha in (3.0, 30.0):
         for prec, dt, name, tol in ((M.MHK_FP32, torch.float32, "fp32", 1e-6), (M.MHK_FP64, torch.float64, "fp64", 1e-10)):
             tun = autotune.tune(geometry, alpha, tol, prec, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx, batch=B,
                                 cache=None, log=log)
-            stream = torch.cuda.Stream()
-            with torch.cuda.stream(stream):
-                t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
-                ins = (t(sig), t(mu), t(fv), t(ft))
-                p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=prec, delta=tun["delta"], batch=B,
-                                         upsamp=tun["upsamp"], wspread=tun["wspread"]),
-                           w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=stream)
-                out = p.capture(*ins)
-                for _ in range(a.warmup):
-                    p.replay()
-                stream.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for _ in range(a.steps):
-                    p.replay()
-                e1.record(stream)
-                stream.synchronize()
-            ms = e0.elapsed_time(e1) / a.steps
-            evals = B * p.n_out
+            mk = lambda b, bch: M.make_params(alpha=alpha, tol=tol, prec=prec, delta=tun["delta"], batch=b,
+                                              upsamp=tun["upsamp"], wspread=tun["wspread"],
+                                              lv_block=tun["lv_block"], lv_bch=bch)
+            t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+            batched = form(mk(B, tun["lv_bch"]), (t(sig), t(mu), t(fv), t(ft)), dt, B)
+            single = form(mk(1, 0), (t(sig[:1]), t(mu[:1]), t(fv[:1]), t(ft[:1])), dt, 1)
             key = f"{name}_alpha{alpha:g}"
-            res[key] = {"ms_per_replay": ms, "target_evals_per_s": evals / (ms * 1e-3), "batch": B,
-                        "upsamp": tun["upsamp"], "wspread": tun["wspread"], "grid": p.info()["n_fine"],
-                        "autotune": [{k2: v for k2, v in c.items() if k2 != "sigma_eff"} for c in tun["table"]]}
-            log(f"{key}: {ms:.1f} ms per replay of {B} densities -> {evals / (ms * 1e-3):.3e} target-evals/s")
-            p.close()
-            del ins, out
-            torch.cuda.empty_cache()
-    best = max(v["target_evals_per_s"] for v in res.values())
+            res[key] = {"batched": batched, "single": single,
+                        "speedup_per_density": single["ms_per_call"] * B / batched["ms_per_call"],
+                        "upsamp": tun["upsamp"], "wspread": tun["wspread"], "lv_block": tun["lv_block"],
+                        "lv_bch": tun["lv_bch"],
+                        "autotune": tun["table"], "autotune_tiles": tun["tile_table"]}
+            log(f"{key}: {batched['ms_per_call']:.1f} ms per {B} densities ({batched['ms_per_density']:.3f} ms each, "
+                f"levels {batched['level_sums']['frac']:.3f} of peak) vs {single['ms_per_call']:.3f} ms for one "
+                f"(levels {single['level_sums']['frac']:.3f}): x{res[key]['speedup_per_density']:.2f} per density")
+    best = max(v["batched"]["target_evals_per_s"] for v in res.values())
     line = {"metric": "target evals/s, 64 densities per call under a captured HIP graph", "value": best,
             "unit": "target-evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
             "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -566,13 +602,35 @@ def run_serve(a):
         return Request(rid, geo, alpha, tol, 1 if tol >= 1e-6 else 0, w.sigma * s, w.mu * s, w.f_vol * s,
                        w.f_trg * s, arrival=arrival, dx=w.dx)
 
-    srv = Server(budget_bytes=int(torch.cuda.mem_get_info()[0] * 0.7), max_inflight=8)
+    def sweep_loads(srv, loads, mean_svc, tag):
+        out, done_all, evals_all, span_all = [], [], 0, 0.0
+        for util in loads:                   # offered load, fraction of one-at-a-time capacity
+            lam = util / mean_svc
+            t = 0.0
+            reqs = []
+            for rid in range(a.requests):
+                t += g.exponential(1.0 / lam)
+                reqs.append(make_req(rid, int(g.integers(len(sims))), t))
+            t0 = time.perf_counter()
+            done = list(srv.run(reqs))
+            span = time.perf_counter() - t0
+            srv.finished.clear()
+            st = latency_stats(done)
+            evals = sum(r.geometry.n_out for r in done)
+            out.append({"offered_util": util, "arrival_rate_per_s": lam, "served_evals_per_s": evals / span,
+                        "span_s": span, "mean_batched_with": float(np.mean([r.batched_with for r in done])), **st})
+            log(f"{tag} util {util}: {st}, {evals / span:.3e} evals/s, "
+                f"mean coalesced {out[-1]['mean_batched_with']:.2f}")
+            evals_all += evals
+            span_all += span
+            done_all += done
+        return out, done_all, evals_all, span_all
+
+    budget = int(torch.cuda.mem_get_info()[0] * 0.7)
+    srv = Server(budget_bytes=budget, max_inflight=8, max_batch=a.max_batch)
     # warm-up: one request per simulation (plan creation), also gives service times
     warm = [make_req(-1 - i, i, 0.0) for i in range(len(sims))]
     srv.run(warm)
-    svc = {}
-    for r in warm:
-        svc[r.geometry.key] = r.done - r.admitted
     srv.finished.clear()
     # measured service time per request when run alone
     alone = []
@@ -582,37 +640,84 @@ def run_serve(a):
         alone.append(r.done - r.admitted)
     srv.finished.clear()
     mean_svc = float(np.mean(alone))
-    sweep = []
-    evals_all, span_all, done_all = 0, 0.0, []
-    for util in (0.5, 0.8, 0.95):            # offered load, fraction of one-at-a-time capacity
-        lam = util / mean_svc
-        t = 0.0
-        reqs = []
-        for rid in range(a.requests):
-            t += g.exponential(1.0 / lam)
-            reqs.append(make_req(rid, int(g.integers(len(sims))), t))
-        t0 = time.perf_counter()
-        done = list(srv.run(reqs))
-        span = time.perf_counter() - t0
-        srv.finished.clear()
-        st = latency_stats(done)
-        evals = sum(r.geometry.n_out for r in done)
-        sweep.append({"offered_util": util, "arrival_rate_per_s": lam, "served_evals_per_s": evals / span,
-                      "span_s": span, **st})
-        log(f"util {util}: {st}, {evals / span:.3e} evals/s")
-        evals_all += evals
-        span_all += span
-        done_all += done
+    sweep, done_all, evals_all, span_all = sweep_loads(srv, (0.5, 0.8, 0.95, 1.5), mean_svc,
+                                                       f"coalesced (max_batch {a.max_batch})")
     srv.close()
+    # the same stream without coalescing, at the two highest loads
+    plain = Server(budget_bytes=budget, max_inflight=8, max_batch=1)
+    plain.run([make_req(-200 - i, i, 0.0) for i in range(len(sims))])
+    plain.finished.clear()
+    sweep_plain, _, _, _ = sweep_loads(plain, (0.95, 1.5), mean_svc, "not coalesced")
+    plain.close()
+    heat = run_serve_heat(a, make_req, mean_svc, len(sims))
     st = latency_stats(done_all)
     line = {"metric": "served target evals/s with p50/p99 request latency", "value": evals_all / span_all,
             "unit": "target-evals/s", "n_gpus": 1, "steps": len(done_all), "warmup": len(warm),
             "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32+f64", "data": "synthetic",
             "config": {"workload": "rothe-serving", "simulations": len(sims), "requests_per_load": a.requests,
-                       "sizes": sizes},
-            "latency": st, "sweep": sweep, "alone_service_ms": [round(x * 1e3, 3) for x in alone]}
+                       "sizes": sizes, "max_batch": a.max_batch},
+            "latency": st, "sweep": sweep, "sweep_not_coalesced": sweep_plain,
+            "alone_service_ms": [round(x * 1e3, 3) for x in alone], "heat_chains": heat}
     print(json.dumps(line), flush=True)
+
+
+def run_serve_heat(a, make_req, mean_svc, n_sims):
+    """Heat-equation simulations (elliptic marching) driven through the
+    server: each chain's step n + 1 is submitted when step n is done, with
+    its result as input, beside a Poisson stream of eval requests at half
+    the one-at-a-time load.  Returns per-step latency and node updates/s."""
+    import torch
+
+    import synth
+    from paper_2606_28865_amd.serve import Geometry, HeatChain, Server, latency_stats
+    g = np.random.default_rng(9)
+    k = np.pi
+    chains = []
+    for i, (nbod, nb, nv, alpha) in enumerate([(3, 2048, 50_000, 10.0), (10, 16384, 1_000_000, 10.0),
+                                               (6, 8192, 300_000, 30.0)]):
+        w = synth.multibody(cfg=300 + i, n_bodies=nbod, n_boundary=nb, n_volume=nv, n_targets=10,
+                            box=1.0)
+        vol = w.volume
+        geo = Geometry(f"heat{i}", w.boundary, vol, (vol["x"], vol["y"], np.ones(len(vol["x"]), np.int8)), True)
+        X = np.concatenate([vol["x"], w.boundary["x"]])
+        Y = np.concatenate([vol["y"], w.boundary["y"]])
+        u0 = np.sin(k * (X + 0.3)) * np.sin(k * (Y + 0.2))
+        c = alpha ** 2 / (alpha ** 2 + 2 * k * k)
+        gb = u0[len(vol["x"]):]
+        chains.append((HeatChain(i, geo, alpha, 1e-10, u0, lambda n, gb=gb, c=c: c ** n * gb, a.heat_steps,
+                                 dx=w.dx, rid0=10_000 * (i + 1)), u0, c))
+        log(f"heat chain {i}: {nbod} bodies, nb {w.n_b}, nv {len(vol['x'])}, alpha {alpha}")
+    srv = Server(budget_bytes=int(torch.cuda.mem_get_info()[0] * 0.7), max_inflight=8, max_batch=a.max_batch)
+    # plans and Nystrom matrices built before timing: one step of each chain
+    warm = [HeatChain(100 + c.sid, c.geometry, c.alpha, c.tol, u0, c.g_of_step, 1, dx=c.dx, rid0=-1000 * (i + 1))
+            for i, (c, u0, _) in enumerate(chains)]
+    srv.run([wc.first() for wc in warm])
+    srv.finished.clear()
+    lam = 0.5 / mean_svc
+    t = 0.0
+    evals = []
+    for rid in range(a.requests):
+        t += g.exponential(1.0 / lam)
+        evals.append(make_req(50_000 + rid, int(g.integers(n_sims)), t))
+    t0 = time.perf_counter()
+    srv.run([c.first() for c, _, _ in chains] + evals)
+    span = time.perf_counter() - t0
+    steps = [r for c, _, _ in chains for r in c.steps]
+    st_heat = latency_stats(steps)
+    st_eval = latency_stats([r for r in srv.finished if r.kind == "eval"])
+    updates = sum(c.geometry.n_out * len(c.steps) for c, _, _ in chains)
+    errs = []
+    for c, u0, cc in chains:
+        ex = cc ** c.nsteps * u0
+        got = c.steps[-1].result[0].cpu().numpy()
+        errs.append(float(np.abs(got - ex).max() / np.abs(ex).max()))
+    srv.close()
+    log(f"heat chains: steps {st_heat}, evals beside them {st_eval}, {updates / span:.3e} node updates/s, "
+        f"errors vs c^n u0 {errs}")
+    return {"chains": len(chains), "steps_per_chain": a.heat_steps, "span_s": span,
+            "node_updates_per_s": updates / span, "step_latency": st_heat, "eval_latency_beside": st_eval,
+            "rel_err_vs_closed_form": errs}
 
 
 def run_bie(a):

@@ -137,10 +137,15 @@ typedef struct {
     /* milliseconds of the last timed eval per stage (see mhk_plan_set_timing)   */
     double ms_spread, ms_fft, ms_multiply, ms_interp, ms_levels, ms_local, ms_total;
     int history_truncated; /* 1: smoothly truncated history kernel, tabulated spectrum */
-    int64_t n_noconv;      /* targets inside a local band whose closest-point Newton
-                              iteration did not converge (read with a wait): plan
-                              creation fails with MHK_ENOCONV when it is nonzero, and
-                              evaluations with MHK_PART_GEOMETRY add to it            */
+    int64_t n_noconv;      /* targets whose closest-point Newton iteration did not
+                              converge where the local part uses the closest point's
+                              parameter (layer bands; exterior targets and, with
+                              local_order 2, all targets in the volume band) -- the
+                              first-order interior volume term needs only the
+                              distance, which the safeguarded iteration minimises even
+                              where it stalls (past a centre of curvature); read with
+                              a wait: plan creation fails with MHK_ENOCONV when it is
+                              nonzero, and evaluations with MHK_PART_GEOMETRY add to it */
     double ms_geometry;    /* closest points and local coefficients of the last timed
                               eval with MHK_PART_GEOMETRY (beside the history part)  */
     double ms_plan[6];     /* host-clock milliseconds of plan creation: [0] input checks
@@ -191,6 +196,15 @@ mhk_status mhk_eval_V(mhk_plan *plan, const void *f_vol, const void *f_trg, void
 mhk_status mhk_eval_parts(mhk_plan *plan, int parts, const void *sigma, const void *mu,
                           const void *f_vol, const void *f_trg, void *out_S, void *out_D,
                           void *out_V);
+
+/* As mhk_eval_parts for the first nbatch densities only, 1 <= nbatch <=
+ * params.batch of the plan: inputs [nbatch][N], outputs [nbatch][n_out],
+ * and every stage runs over nbatch densities, so a plan sized for a batch
+ * serves smaller ones at their own cost (requests coalesced as they arrive,
+ * Section 1's time steps of several simulations).  EINVAL for nbatch out of
+ * range. */
+mhk_status mhk_eval_batch(mhk_plan *plan, int nbatch, int parts, const void *sigma, const void *mu,
+                          const void *f_vol, const void *f_trg, void *out_S, void *out_D, void *out_V);
 
 /* Record one evaluation (the arguments of mhk_eval_parts) into a HIP graph
  * owned by the plan, bound to these device pointers, without running it; the

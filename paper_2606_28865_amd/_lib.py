@@ -74,7 +74,7 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
-           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_plan_capture", "mhk_plan_launch_graph",
+           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_eval_batch", "mhk_plan_capture", "mhk_plan_launch_graph",
            "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error",
            "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_nystrom_solve_noalloc",
            "mhk_solve_dirichlet",
@@ -99,6 +99,7 @@ def lib():
         L.mhk_eval_D.argtypes = [C.c_void_p] * 3
         L.mhk_eval_V.argtypes = [C.c_void_p] * 4
         L.mhk_eval_parts.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
+        L.mhk_eval_batch.argtypes = [C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 7
         L.mhk_plan_capture.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
         L.mhk_plan_launch_graph.argtypes = [C.c_void_p]
         L.mhk_plan_set_timing.argtypes = [C.c_void_p, C.c_int]
@@ -239,21 +240,23 @@ class Plan:
     def set_timing(self, on=True):
         _check(lib().mhk_plan_set_timing(self._h, int(bool(on))))
 
-    def _dev(self, t, n):
+    def _dev(self, t, n, nb=None):
         import torch
         if t is None:
             return None
+        nb = self.batch if nb is None else nb
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.dtype and t.is_contiguous()):
             raise TypeError("densities must be contiguous device tensors of the plan's dtype")
-        if t.numel() != self.batch * n:
-            raise ValueError(f"expected {self.batch} x {n} values, got {t.numel()}")
+        if t.numel() != nb * n:
+            raise ValueError(f"expected {nb} x {n} values, got {t.numel()}")
         return t
 
-    def _outs(self, out, ins):
+    def _outs(self, out, ins, nb=None):
         """Output tensors: allocated when out is None, else checked like the
         inputs (a short or mistyped output would be written past its end)."""
         import torch
-        shape = (self.batch, self.n_out)
+        nb = self.batch if nb is None else nb
+        shape = (nb, self.n_out)
         if out is None:
             return tuple(torch.empty(shape, dtype=self.dtype, device="cuda") if x is not None else None
                          for x in ins)
@@ -264,7 +267,7 @@ class Plan:
                 continue
             if o is None:
                 raise ValueError(f"out[{name}] is missing for a given input")
-            self._dev(o, self.n_out)
+            self._dev(o, self.n_out, nb)
         return tuple(out)
 
     def _streams(self):
@@ -296,8 +299,10 @@ class Plan:
     def replay(self):
         _check(lib().mhk_plan_launch_graph(self._h))
 
-    def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None, join=True):
+    def eval(self, sigma=None, mu=None, f_vol=None, f_trg=None, parts=PART_ALL, out=None, join=True, nbatch=None):
         """Returns (S, D, V) device tensors [batch, n_out] (None where not requested).
+        nbatch (1..batch): evaluate only that many densities (inputs and
+        outputs [nbatch, ...]; mhk_eval_batch).
 
         The work runs on the plan's stream.  When the caller's current stream
         is another one, the plan's stream first waits for it (the inputs may
@@ -305,17 +310,24 @@ class Plan:
         stream, and with join=True the caller's stream then waits for the
         evaluation, so that the outputs can be used on it directly; join=False
         leaves that wait to the caller (several plans overlapping)."""
-        sigma = self._dev(sigma, self.nb)
-        mu = self._dev(mu, self.nb)
-        f_vol = self._dev(f_vol, self.nv)
-        f_trg = self._dev(f_trg, self.f_rows * self.n_out)
-        out = self._outs(out, (sigma, mu, f_vol))
+        nb = self.batch if nbatch is None else int(nbatch)
+        if not 1 <= nb <= self.batch:
+            raise ValueError(f"nbatch must be in [1, {self.batch}]")
+        sigma = self._dev(sigma, self.nb, nb)
+        mu = self._dev(mu, self.nb, nb)
+        f_vol = self._dev(f_vol, self.nv, nb)
+        f_trg = self._dev(f_trg, self.f_rows * self.n_out, nb)
+        out = self._outs(out, (sigma, mu, f_vol), nb)
         cur, other = self._streams()
         if other:
             self.stream.wait_stream(cur)
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
-        _check(lib().mhk_eval_parts(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
-                                    ptr(out[0]), ptr(out[1]), ptr(out[2])))
+        if nb == self.batch:
+            _check(lib().mhk_eval_parts(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
+                                        ptr(out[0]), ptr(out[1]), ptr(out[2])))
+        else:
+            _check(lib().mhk_eval_batch(self._h, nb, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
+                                        ptr(out[0]), ptr(out[1]), ptr(out[2])))
         if other:
             for t in (sigma, mu, f_vol, f_trg) + tuple(out):
                 if t is not None:

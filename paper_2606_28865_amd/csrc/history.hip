@@ -820,7 +820,7 @@ static hipError_t spread_t(mhk_plan *P, const void *sigma, const void *mu, const
     A.nb = P->nb;
     A.nv = P->nv;
     A.ntile = G.ntile;
-    A.B = P->p.batch;
+    A.B = P->bat;
     A.tbx0 = G.colpath ? G.sx0 / TILE : 0;
     A.tby0 = G.colpath ? G.sy0 / TILE : 0;
     A.ntbx = G.colpath ? (G.sx1 - 1) / TILE - A.tbx0 + 1 : G.ntile;
@@ -845,9 +845,9 @@ template <typename T>
 static hipError_t multiply_t(mhk_plan *P)
 {
     const History &G = P->hist;
-    const int64_t tot = G.n * (G.n / 2 + 1) * P->p.batch;
+    const int64_t tot = G.n * (G.n / 2 + 1) * P->bat;
     hipLaunchKernelGGL(k_multiply<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, G.n,
-                       P->p.batch, G.field, (T *)G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha,
+                       P->bat, G.field, (T *)G.grid, G.fac, G.mult_c, P->p.alpha * P->p.alpha,
                        2.0 * M_PI / G.period, G.trunc ? G.mtab : nullptr, G.lmax);
     return hipGetLastError();
 }
@@ -859,7 +859,7 @@ static hipError_t columns_t(mhk_plan *P)
     ColArgs<T> A;
     A.n = G.n;
     A.field = G.field;
-    A.B = P->p.batch;
+    A.B = P->bat;
     A.ncol = G.ncol;
     A.npass = G.npass;
     for (int i = 0; i < COL_MAXPASS; ++i) A.radix[i] = G.radix[i];
@@ -880,7 +880,7 @@ static hipError_t columns_t(mhk_plan *P)
     const void *fn = G.n <= COL_NMAX / 2 ? (const void *)k_columns<T, COL_NMAX / 2> : (const void *)k_columns<T, COL_NMAX>;
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (G.ncol == 0) return hipSuccess;     // the multiplier is zero everywhere
-    dim3 grid((unsigned)(((G.ncol + 7) / 8) * 8), (unsigned)P->p.batch, 3u);
+    dim3 grid((unsigned)(((G.ncol + 7) / 8) * 8), (unsigned)P->bat, 3u);
     if (G.n <= COL_NMAX / 2)
         hipLaunchKernelGGL((k_columns<T, COL_NMAX / 2>), grid, dim3(CT), lds, P->stream, A);
     else
@@ -906,7 +906,7 @@ static hipError_t rows_t(mhk_plan *P)
     A.m0 = (INV ? G.tx0 : G.sx0) / 2;
     A.m1 = ((INV ? G.tx1 : G.sx1) + 1) / 2;
     const size_t lds = sizeof(typename Vec2<T>::type) * (size_t)(G.n / 2);
-    const int64_t rows = (INV ? 3 : 4) * (int64_t)P->p.batch * A.nrow;
+    const int64_t rows = (INV ? 3 : 4) * (int64_t)P->bat * A.nrow;
     if (rows <= 0) return hipSuccess;
     if (G.n <= COL_NMAX / 2)
         hipLaunchKernelGGL((k_rows<INV, T, COL_NMAX / 2>), dim3((unsigned)rows), dim3(RT), lds, P->stream, A);
@@ -940,7 +940,7 @@ static hipError_t interp_t(mhk_plan *P, bool want_s, bool want_d, bool want_v)
     A.field = G.field;
     A.nout = P->nout;
     A.ntile = G.ntile;
-    A.B = P->p.batch;
+    A.B = P->bat;
     A.beta = G.beta;
     A.ox = G.ox;
     A.oy = G.oy;

@@ -327,7 +327,7 @@ static hipError_t level_q(mhk_plan *P, hipStream_t st, int j, const void *sigma,
     Level &L = P->lev[j - 1];
     const int64_t n = L.n_src;
     dim3 grid((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(k_level_q<T>, grid, dim3(256), 0, st, n, L.nchild, P->p.batch, P->nb, L.code,
+    hipLaunchKernelGGL(k_level_q<T>, grid, dim3(256), 0, st, n, L.nchild, P->bat, P->nb, L.code,
                        L.interp, L.sw, L.swx, L.swy, (const T *)sigma, (const T *)mu, (T *)L.q);
     return hipGetLastError();
 }
@@ -362,7 +362,7 @@ template <typename T, int STRIDE>
 static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
     Level &L = P->lev[j - 1];
-    const int B = P->p.batch;
+    const int B = P->bat;
     LevelArgs<T> A;
     A.nout = P->nout;
     A.n_src = L.n_src;

@@ -450,8 +450,16 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
             }
             r = sqrt(d2b);
             // a closest point that is not a converged Newton solution is
-            // only an approximation: count it when the local part uses it
-            if (!conv && r < fmax(A.band_s, A.band_v) && A.noconv) atomicAdd(A.noconv, 1);
+            // only an approximation: count it where the local part uses its
+            // parameter (the layer terms, the exterior volume term through f
+            // at the closest point, the second-order volume terms).  The
+            // first-order interior volume term needs only the distance,
+            // which the safeguarded iteration has minimised; past the
+            // curve's centre of curvature (volume bands wider than the
+            // radius of curvature) the distance is flat in the parameter and
+            // the iteration can stall without harm to it.
+            const bool uses_t = r < A.band_s || (r < A.band_v && (!inside || ORDER >= 2));
+            if (!conv && uses_t && A.noconv) atomicAdd(A.noconv, 1);
         }
         // volume part (Lemma 4.8 first order inside the band, Cor. 4.11
         // beyond).  Exterior targets in the band: the local integral over
@@ -756,9 +764,9 @@ hipError_t launch_fill(mhk_plan *P, void *p, int64_t n)
 template <typename T>
 static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd)
 {
-    const int64_t tot = P->npan * NGL * P->p.batch;
+    const int64_t tot = P->npan * NGL * P->bat;
     hipLaunchKernelGGL(k_panel_coeffs<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, P->stream, P->npan,
-                       P->p.batch, P->loc.leg, (const T *)sigma, (const T *)mu, (const T *)f_bnd, P->nout,
+                       P->bat, P->loc.leg, (const T *)sigma, (const T *)mu, (const T *)f_bnd, P->nout,
                        P->p.local_order >= 2 ? 6 : 1, P->nt,
                        P->loc.csig, P->loc.cmu, P->loc.cf);
     return hipGetLastError();
@@ -777,7 +785,7 @@ static void fill_args(mhk_plan *P, LocalArgs<T> &A)
     A.nt = P->nt;
     A.nb = P->nb;
     A.npan = P->npan;
-    A.B = P->p.batch;
+    A.B = P->bat;
     A.parts = MHK_PART_ALL;
     A.tx = P->tx;
     A.ty = P->ty;

@@ -183,6 +183,7 @@ struct mhk_plan {
     mhk_info info{};
     hipStream_t stream = nullptr;
     bool timing = false;
+    int bat = 1;                                 // densities of the evaluation being enqueued (<= p.batch)
     int64_t nb = 0, npan = 0, nv = 0, nt = 0, nout = 0;
     bool targets_are_volume = false;            // targets == volume nodes, same order
     int J = 3;

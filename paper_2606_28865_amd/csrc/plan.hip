@@ -1659,12 +1659,16 @@ mhk_status collect_timing(mhk_plan *P)
 
 // Enqueue one evaluation on P->stream (no synchronisation).
 mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol, const void *f_trg,
-                   void *out_s, void *out_d, void *out_v)
+                   void *out_s, void *out_d, void *out_v, int nbatch)
 {
+    // densities of this evaluation (<= the plan's batch): every launch below
+    // runs over P->bat of them, with [P->bat][..] strides in the grids and
+    // accumulators
+    P->bat = nbatch;
     const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if (!ws && !wd && !wv) return MHK_OK;
     hipStream_t st = P->stream;
-    const int B = P->p.batch;
+    const int B = P->bat;
     const int64_t nout = P->nout;
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[0], st));
     // The level sums share no data with the history part: they run on the
@@ -1749,7 +1753,18 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma, const void 
                           const void *f_trg, void *out_s, void *out_d, void *out_v)
 {
     TRY(validate_eval(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v));
-    return enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v);
+    return enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v, P->p.batch);
+}
+
+mhk_status mhk_eval_batch(mhk_plan *P, int nbatch, int parts, const void *sigma, const void *mu, const void *f_vol,
+                          const void *f_trg, void *out_s, void *out_d, void *out_v)
+{
+    TRY(validate_eval(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v));
+    if (nbatch < 1 || nbatch > P->p.batch) {
+        set_error("nbatch must be in [1, batch] of the plan");
+        return MHK_EINVAL;
+    }
+    return enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v, nbatch);
 }
 
 mhk_status mhk_plan_capture(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_vol,
@@ -1771,7 +1786,7 @@ mhk_status mhk_plan_capture(mhk_plan *P, int parts, const void *sigma, const voi
         set_error(std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
         st = MHK_EHIP;
     } else {
-        st = enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v);
+        st = enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v, P->p.batch);
         e = hipStreamEndCapture(P->cap, &g);
         if (st == MHK_OK && e != hipSuccess) {
             set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));

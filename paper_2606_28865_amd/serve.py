@@ -191,26 +191,28 @@ class TorchDevice:
 
     def launch(self, plan, group: List[Request]):
         """Upload the inputs and enqueue the work on the plan's stream (eval:
-        the group's densities stacked into the plan's batch, unused rows zero;
-        heat: the solve in a worker thread); returns a handle polled by done()."""
+        the group's densities stacked, evaluated as a batch of that size on
+        the plan sized for max_batch; heat: the solve in a worker thread);
+        returns a handle polled by done()."""
         torch = self.torch
         if group[0].kind == "heat":
             return self._launch_heat(plan, group[0])
         dt = torch.float64 if group[0].prec == 0 else torch.float32
         s = plan.stream
-        B = plan.batch
+        G = len(group)
         with torch.cuda.stream(s):
             def stack(name, n):
                 if getattr(group[0], name) is None:
                     return None
-                h = np.zeros((B, n), np.float64 if dt == torch.float64 else np.float32)
+                h = np.empty((G, n), np.float64 if dt == torch.float64 else np.float32)
                 for i, r in enumerate(group):
                     h[i] = np.asarray(getattr(r, name)).ravel()
                 return self._dev(h, dt)
             nb, nv, no = plan.nb, plan.nv, plan.n_out
             sig, mu, fv = stack("sigma", nb), stack("mu", nb), stack("f_vol", nv)
             ft = stack("f_trg", plan.f_rows * no) if fv is not None else None
-            out = plan.eval(sig, mu, fv, ft)
+            # the group's densities only: a launch costs what it carries
+            out = plan.eval(sig, mu, fv, ft, nbatch=G)
             host = [None if o is None else torch.empty(o.shape, dtype=dt, pin_memory=True) for o in out]
             for h, o in zip(host, out):
                 if o is not None:

@@ -90,3 +90,50 @@ def test_batch_chunks_match_single(prec):
         for o, r in zip(out, ref):
             e = rel_err(o[k].double().cpu().numpy(), r.double().cpu().numpy())
             assert e < (1e-13 if prec == 0 else 1e-6), (k, e)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fewer_densities_than_the_batch(prec):
+    """mhk_eval_batch: a plan sized for 6 densities evaluates 1, 3 and 6 of
+    them (each stage over that many), equal to single-density evaluations;
+    a full-batch graph captured afterwards still replays all 6."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    B = 6
+    dt = torch.float64 if prec == 0 else torch.float32
+    tol = 1e-10 if prec == 0 else 1e-6
+    lim = 1e-13 if prec == 0 else 1e-6
+    g = np.random.default_rng(21)
+    sig = np.stack([w.sigma * (1 + 0.1 * k) + 0.05 * g.standard_normal(w.n_b) for k in range(B)])
+    mu = np.stack([w.mu * (1 - 0.1 * k) for k in range(B)])
+    fv = np.stack([w.f_vol * (k + 1) for k in range(B)])
+    ft = np.stack([w.f_trg * (k + 1) for k in range(B)])
+    prm = lambda b: M.make_params(alpha=10.0, tol=tol, prec=prec, dx=w.dx, batch=b)
+    plan = M.Plan(prm(B), w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    single = M.Plan(prm(1), w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    ref = [single.eval(_t(sig[k], dt), _t(mu[k], dt), _t(fv[k], dt), _t(ft[k], dt)) for k in range(B)]
+    ref = [[o.cpu().numpy().ravel() for o in r] for r in ref]
+    for nb in (1, 3, 6, 2):
+        print(f"case nbatch={nb} of {B} prec={prec}", flush=True)
+        out = plan.eval(_t(sig[:nb], dt), _t(mu[:nb], dt), _t(fv[:nb], dt), _t(ft[:nb], dt), nbatch=nb)
+        torch.cuda.synchronize()
+        assert out[0].shape == (nb, w.n_t + w.n_b)
+        for k in range(nb):
+            for o, r in zip(out, ref[k]):
+                assert rel_err(o[k].cpu().numpy(), r) < lim, (nb, k, rel_err(o[k].cpu().numpy(), r))
+    with pytest.raises(ValueError):
+        plan.eval(_t(sig[:1], dt), _t(mu[:1], dt), _t(fv[:1], dt), _t(ft[:1], dt), nbatch=B + 1)
+    # the library itself rejects a count beyond the plan's batch
+    import ctypes as C
+    x = _t(sig, dt)
+    o = torch.empty((B, w.n_t + w.n_b), dtype=dt, device="cuda")
+    rc = M.lib().mhk_eval_batch(plan._h, B + 1, M.PART_ALL, C.c_void_p(x.data_ptr()), None, None, None,
+                                C.c_void_p(o.data_ptr()), None, None)
+    assert rc == -1
+    ins = (_t(sig, dt), _t(mu, dt), _t(fv, dt), _t(ft, dt))
+    gout = plan.capture(*ins)
+    plan.replay()
+    torch.cuda.synchronize()
+    for k in range(B):
+        for o, r in zip(gout, ref[k]):
+            assert rel_err(o[k].cpu().numpy(), r) < lim
