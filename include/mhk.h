@@ -21,7 +21,8 @@
  *  - Densities, sources and outputs passed to the eval calls are DEVICE
  *    pointers (e.g. a torch tensor's data_ptr()), contiguous, in the caller's
  *    node order, with the batch index outermost: sigma[b][N_B].  Their type
- *    is double when params.prec == MHK_FP64 and float when MHK_FP32.
+ *    is double when params.prec == MHK_FP64 and float when MHK_FP32 (inputs
+ *    double for an FP32 plan with params.in64 = 1).
  *  - Eval calls are asynchronous on the stream given at plan creation; the
  *    outputs are valid once that stream has been synchronised (the plan's
  *    internal second stream, which runs the level sums, is joined back into
@@ -101,6 +102,11 @@ typedef struct {
                         256 or 512 (0: 256); the same sums in another order       */
     int lv_bch;      /* densities per pass of the level sums for batch > 1: 1, 2, 4
                         or 8 (0: 4); each kernel-table evaluation serves them all */
+    int in64;        /* MHK_FP32 plans only: 1 = sigma, mu, f_vol, f_trg are given as
+                        double; spreading and the level sums take them rounded to
+                        float once, the local part (which differentiates sigma and
+                        mu twice along the boundary, Lemma 4.5) reads them as
+                        given.  Outputs stay float.  0 for FP64 plans.          */
 } mhk_params;
 
 typedef struct {

@@ -23,7 +23,7 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("prec", C.c_int), ("J", C.c_int),
                 ("delta", C.c_double), ("dx", C.c_double), ("batch", C.c_int),
                 ("upsamp", C.c_double), ("wspread", C.c_int), ("local_order", C.c_int),
-                ("lv_block", C.c_int), ("lv_bch", C.c_int)]
+                ("lv_block", C.c_int), ("lv_bch", C.c_int), ("in64", C.c_int)]
 
 
 class Boundary(C.Structure):
@@ -137,9 +137,9 @@ def _check(rc):
 
 
 def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0, local_order=1,
-                lv_block=0, lv_bch=0):
+                lv_block=0, lv_bch=0, in64=0):
     return Params(float(alpha), float(tol), int(prec), int(J), float(delta), float(dx), int(batch),
-                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch))
+                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch), int(in64))
 
 
 def resolve_params(**kw):
@@ -218,6 +218,8 @@ class Plan:
         self.n_out = self.nt + (self.nb if on_surface else 0)
         self.batch = int(params.batch)
         self.dtype = torch.float64 if params.prec == MHK_FP64 else torch.float32
+        # densities and f as given by the caller (double for FP32 plans with in64)
+        self.in_dtype = torch.float64 if (params.prec == MHK_FP64 or params.in64) else torch.float32
         # f at the targets: the value, or (local_order 2) the value, gradient and Hessian
         self.f_rows = 6 if int(params.local_order) == 2 else 1
 
@@ -240,13 +242,14 @@ class Plan:
     def set_timing(self, on=True):
         _check(lib().mhk_plan_set_timing(self._h, int(bool(on))))
 
-    def _dev(self, t, n, nb=None):
+    def _dev(self, t, n, nb=None, dtype=None):
         import torch
         if t is None:
             return None
         nb = self.batch if nb is None else nb
-        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.dtype and t.is_contiguous()):
-            raise TypeError("densities must be contiguous device tensors of the plan's dtype")
+        dtype = self.in_dtype if dtype is None else dtype
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise TypeError(f"expected a contiguous {dtype} device tensor")
         if t.numel() != nb * n:
             raise ValueError(f"expected {nb} x {n} values, got {t.numel()}")
         return t
@@ -267,7 +270,7 @@ class Plan:
                 continue
             if o is None:
                 raise ValueError(f"out[{name}] is missing for a given input")
-            self._dev(o, self.n_out, nb)
+            self._dev(o, self.n_out, nb, self.dtype)
         return tuple(out)
 
     def _streams(self):

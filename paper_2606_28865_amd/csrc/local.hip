@@ -242,7 +242,9 @@ __device__ inline double v2_far(double c)
     return (-expm1(-x) - x * exp(-x)) / (x * x);
 }
 
-template <typename T>
+// T: the plan's precision (accumulators, outputs); TI: the type of the
+// caller's densities and f_trg (double for an FP32 plan given FP64 inputs)
+template <typename T, typename TI = T>
 struct LocalArgs {
     int64_t nout, nt, nb, npan;
     int B;
@@ -251,7 +253,7 @@ struct LocalArgs {
     const int8_t *tin;
     const int32_t *tidx;
     const double *bx, *by, *bk;
-    const T *sigma, *mu, *f_trg;
+    const TI *sigma, *mu, *f_trg;
     const double *cs, *cm;
     const double *cf;      // Legendre coefficients of f on the boundary, or NULL
     const double *geo;     // per-plan local geometry (k_local_geom)
@@ -281,8 +283,8 @@ struct LocalArgs {
 // below 1e-12, after one more Newton step.  Returns whether the iteration
 // converged (that, or a damped step below 1e-15, possibly held at an end
 // point).
-template <typename T>
-__device__ inline bool panel_min(const LocalArgs<T> &A, int p, double px, double py, double &tbest, double &d2best)
+template <typename Args>
+__device__ inline bool panel_min(const Args &A, int p, double px, double py, double &tbest, double &d2best)
 {
     const double *cx = A.pcx + (size_t)p * NGL, *cy = A.pcy + (size_t)p * NGL;
     // start: best of the two end points and the 16 nodes
@@ -591,8 +593,8 @@ __global__ void __launch_bounds__(256) k_local_geom(LocalArgs<double> A, double 
 
 // Local part of an evaluation from the per-plan geometry, added to the
 // accumulated history and level sums, and the scatter to the caller's order.
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
+template <typename T, typename TI, int ORDER>
+__global__ void __launch_bounds__(256) k_local(LocalArgs<T, TI> A)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nout) return;
@@ -718,7 +720,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T> A)
             double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
             if (do_local) {
                 // f (and with second order its gradient and Hessian) at the target
-                const T *fr = A.f_trg + (size_t)b * A.frows * A.nout + idx;
+                const TI *fr = A.f_trg + (size_t)b * A.frows * A.nout + idx;
                 double f;
                 if (ext)
                     f = A.cf ? leg1(A.cf + ((size_t)b * A.npan + pbest) * NGL, tbest) : NAN;
@@ -772,14 +774,16 @@ static hipError_t panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, c
     return hipGetLastError();
 }
 
+// the densities as the caller gives them: FP64 for FP64 plans and for FP32
+// plans created with in64
 hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd)
 {
-    return P->p.prec == MHK_FP64 ? panel_coeffs<double>(P, sigma, mu, f_bnd)
-                                 : panel_coeffs<float>(P, sigma, mu, f_bnd);
+    return (P->p.prec == MHK_FP64 || P->p.in64) ? panel_coeffs<double>(P, sigma, mu, f_bnd)
+                                                : panel_coeffs<float>(P, sigma, mu, f_bnd);
 }
 
-template <typename T>
-static void fill_args(mhk_plan *P, LocalArgs<T> &A)
+template <typename T, typename TI>
+static void fill_args(mhk_plan *P, LocalArgs<T, TI> &A)
 {
     A.nout = P->nout;
     A.nt = P->nt;
@@ -845,26 +849,26 @@ hipError_t launch_local_geom(mhk_plan *P, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename TI>
 static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
                           void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
 {
-    LocalArgs<T> A;
+    LocalArgs<T, TI> A;
     fill_args(P, A);
     A.lev = have_lev ? (const T *)P->acc_lev : nullptr;
     A.parts = parts;
-    A.sigma = (const T *)sigma;
-    A.mu = (const T *)mu;
-    A.f_trg = (const T *)f_trg;
+    A.sigma = (const TI *)sigma;
+    A.mu = (const TI *)mu;
+    A.f_trg = (const TI *)f_trg;
     A.cf = have_fb ? P->loc.cf : nullptr;
     A.out_s = (T *)out_s;
     A.out_d = (T *)out_d;
     A.out_v = (T *)out_v;
     const dim3 grid((unsigned)((P->nout + 255) / 256));
     if (P->p.local_order >= 2)
-        hipLaunchKernelGGL((k_local<T, 2>), grid, dim3(256), 0, P->stream, A);
+        hipLaunchKernelGGL((k_local<T, TI, 2>), grid, dim3(256), 0, P->stream, A);
     else
-        hipLaunchKernelGGL((k_local<T, 1>), grid, dim3(256), 0, P->stream, A);
+        hipLaunchKernelGGL((k_local<T, TI, 1>), grid, dim3(256), 0, P->stream, A);
     return hipGetLastError();
 }
 
@@ -872,8 +876,25 @@ hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *m
                         void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
 {
     if (P->p.prec == MHK_FP64)
-        return local_t<double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
-    return local_t<float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+        return local_t<double, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+    if (P->p.in64)
+        return local_t<float, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+    return local_t<float, float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+}
+
+// FP32 copies of FP64 inputs (FP32 plans with in64): n values, rounded once
+__global__ void __launch_bounds__(256) k_round32(const double *__restrict__ x, float *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+hipError_t launch_round32(mhk_plan *P, const void *x, void *y, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_round32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, P->stream, (const double *)x,
+                       (float *)y, n);
+    return hipGetLastError();
 }
 
 }  // namespace mhk

@@ -184,6 +184,7 @@ struct mhk_plan {
     hipStream_t stream = nullptr;
     bool timing = false;
     int bat = 1;                                 // densities of the evaluation being enqueued (<= p.batch)
+    float *in32 = nullptr;                       // FP32 plans with in64: [batch][2 N_B + N_V] rounded inputs
     int64_t nb = 0, npan = 0, nv = 0, nt = 0, nout = 0;
     bool targets_are_volume = false;            // targets == volume nodes, same order
     int J = 3;
@@ -234,6 +235,7 @@ hipError_t launch_columns(mhk_plan *P);
 hipError_t launch_rows(mhk_plan *P, bool inverse);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
+hipError_t launch_round32(mhk_plan *P, const void *x, void *y, int64_t n);
 hipError_t launch_trunc_kernel_samples(double *buf, int64_t M, double h, double alpha, double delta, double rmid,
                                        double slope, const double *gl_t, const double *gl_w, hipStream_t s);
 hipError_t launch_cos_step(const double *in, int64_t K, int64_t NA, int64_t NB, int n, const double *costab,

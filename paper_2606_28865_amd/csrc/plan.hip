@@ -223,6 +223,11 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         double kmax = 0.9 * M_PI / p.dx;
         p.delta = log(1.0 / p.tol) / (kmax * kmax + p.alpha * p.alpha);
     }
+    if (p.in64 != 0 && p.in64 != 1) {
+        set_error("in64 must be 0 or 1");
+        return MHK_EINVAL;
+    }
+    if (p.prec == MHK_FP64) p.in64 = 0;
     if (p.lv_block == 0) p.lv_block = 256;
     if (p.lv_block != 256 && p.lv_block != 512) {
         set_error("lv_block must be 0, 256 or 512");
@@ -1453,6 +1458,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
         char *l = nullptr;
         TRY(dalloc(P, &l, 2 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
         P->acc_lev = l;
+        if (P->p.in64) TRY(dalloc(P, &P->in32, (int64_t)P->p.batch * (2 * P->nb + P->nv)));
     }
     for (auto &e : P->ev) MHK_HIP(hipEventCreate(&e));
     MHK_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
@@ -1540,6 +1546,7 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
     }
     s += nb * (8 * 3 + 4) + 3 * B * nb * 8;   // local
     s += nout * ((p.local_order >= 2 ? LOCAL_GEO_N2 : LOCAL_GEO_N1) * 8 + 4 + 1);   // local geometry per target
+    if (p.in64) s += B * (2 * nb + nv) * 4;   // FP32 copies of FP64 inputs
     if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {
@@ -1668,6 +1675,18 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if (!ws && !wd && !wv) return MHK_OK;
     hipStream_t st = P->stream;
+    // FP32 plan given FP64 inputs: spreading and the level sums read float
+    // copies (rounded once here), the local part the caller's doubles
+    const void *sig_h = sigma, *mu_h = mu, *fv_h = f_vol;
+    if (P->p.in64) {
+        float *s32 = P->in32, *m32 = P->in32 + (size_t)nbatch * P->nb, *f32 = P->in32 + (size_t)2 * nbatch * P->nb;
+        if (ws) MHK_HIP(launch_round32(P, sigma, s32, (int64_t)nbatch * P->nb));
+        if (wd) MHK_HIP(launch_round32(P, mu, m32, (int64_t)nbatch * P->nb));
+        if (wv) MHK_HIP(launch_round32(P, f_vol, f32, (int64_t)nbatch * P->nv));
+        sig_h = s32;
+        mu_h = m32;
+        fv_h = f32;
+    }
     const int B = P->bat;
     const int64_t nout = P->nout;
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[0], st));
@@ -1694,7 +1713,7 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
             if (P->timing) MHK_HIP(hipEventRecord(P->ev[9], P->side));
         }
         for (int j = 1; j <= P->J; ++j) {
-            MHK_HIP(launch_level_densities(P, P->side, j, ws ? sigma : nullptr, wd ? mu : nullptr));
+            MHK_HIP(launch_level_densities(P, P->side, j, ws ? sig_h : nullptr, wd ? mu_h : nullptr));
             MHK_HIP(launch_level_sums(P, P->side, j, ws, wd, j == 1));
         }
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], P->side));
@@ -1703,7 +1722,7 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     // history part writes the accumulators (or zeros them)
     bool hist = (parts & MHK_PART_HISTORY) && P->hist.active;
     if (hist) {
-        MHK_HIP(launch_spread(P, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_vol : nullptr));
+        MHK_HIP(launch_spread(P, ws ? sig_h : nullptr, wd ? mu_h : nullptr, wv ? fv_h : nullptr));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[1], st));
         void *buf[1] = {P->hist.grid};
         // column path: row transforms, column transforms with the

@@ -36,14 +36,11 @@ def small_multibody(n_bodies=3, n_boundary=2048, n_volume=40_000, n_targets=6000
 def stratified_subset(w, band, n_each=64, seed=5):
     """Target indices in output order: some on-surface nodes, some off-surface
     targets inside the given distance band of a node, some elsewhere."""
+    from scipy.spatial import cKDTree
     g = np.random.default_rng(seed)
     nt, nb = w.n_t, w.n_b
     bx, by = w.boundary["x"], w.boundary["y"]
-    d = np.full(nt, np.inf)
-    for k in range(0, nb, 256):
-        dx = w.tx[:, None] - bx[None, k:k + 256]
-        dy = w.ty[:, None] - by[None, k:k + 256]
-        d = np.minimum(d, np.sqrt(dx * dx + dy * dy).min(1))
+    d, _ = cKDTree(np.column_stack([bx, by])).query(np.column_stack([w.tx, w.ty]))
     near = np.nonzero(d < band)[0]
     far = np.nonzero(d >= band)[0]
     pick = lambda a, n: a if len(a) <= n else g.choice(a, n, replace=False)
