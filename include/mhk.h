@@ -119,6 +119,16 @@ typedef struct {
 typedef struct {
     int64_t n;                        /* N_V volume quadrature nodes (may be 0)     */
     const double *x, *y, *w;          /* host [N_V] nodes and weights (eq. (vol_quad)) */
+    int32_t group;                    /* 0: no structure; 6: the nodes come in consecutive
+                                         groups of six, the 6-point rule of one triangle
+                                         each (Section 3.1).  Then f at the targets may be
+                                         omitted (f_trg NULL in the eval calls): the plan
+                                         takes f, and for local_order 2 its gradient and
+                                         Hessian, from the quadratic through the six nodal
+                                         values of the triangle holding the target's nearest
+                                         node (slivers with nearly collinear nodes
+                                         excluded), at targets inside the domain and at the
+                                         boundary nodes                                     */
 } mhk_volume;
 
 typedef struct {
@@ -211,6 +221,14 @@ mhk_status mhk_eval_parts(mhk_plan *plan, int parts, const void *sigma, const vo
  * range. */
 mhk_status mhk_eval_batch(mhk_plan *plan, int nbatch, int parts, const void *sigma, const void *mu,
                           const void *f_vol, const void *f_trg, void *out_S, void *out_D, void *out_V);
+
+/* f at the targets as the plan reconstructs it from the volume quadrature
+ * when an eval call gets f_trg = NULL (volume.group = 6): f_vol [batch][N_V]
+ * in, f_trg [batch][rows][n_out] out (rows 1, or 6 for local_order 2: f,
+ * f_x, f_y, f_xx, f_xy, f_yy; zero at exterior off-surface targets, which
+ * never need it), caller order, the precision of the eval inputs;
+ * asynchronous on the plan's stream.  EINVAL without the grouped volume. */
+mhk_status mhk_plan_f_targets(mhk_plan *plan, const void *f_vol, void *f_trg);
 
 /* Record one evaluation (the arguments of mhk_eval_parts) into a HIP graph
  * owned by the plan, bound to these device pointers, without running it; the

@@ -33,7 +33,7 @@ class Boundary(C.Structure):
 
 
 class Volume(C.Structure):
-    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("w", C.c_void_p)]
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("w", C.c_void_p), ("group", C.c_int32)]
 
 
 class Targets(C.Structure):
@@ -74,7 +74,7 @@ class SolveInfo(C.Structure):
 
 
 EXPORTS = ["mhk_resolve_params", "mhk_plan_create", "mhk_plan_footprint", "mhk_eval", "mhk_eval_S",
-           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_eval_batch", "mhk_plan_capture", "mhk_plan_launch_graph",
+           "mhk_eval_D", "mhk_eval_V", "mhk_eval_parts", "mhk_eval_batch", "mhk_plan_f_targets", "mhk_plan_capture", "mhk_plan_launch_graph",
            "mhk_plan_set_timing", "mhk_plan_info", "mhk_plan_destroy", "mhk_last_error",
            "mhk_nystrom_create", "mhk_nystrom_apply", "mhk_nystrom_solve", "mhk_nystrom_solve_noalloc",
            "mhk_solve_dirichlet",
@@ -100,6 +100,7 @@ def lib():
         L.mhk_eval_V.argtypes = [C.c_void_p] * 4
         L.mhk_eval_parts.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
         L.mhk_eval_batch.argtypes = [C.c_void_p, C.c_int, C.c_int] + [C.c_void_p] * 7
+        L.mhk_plan_f_targets.argtypes = [C.c_void_p] * 3
         L.mhk_plan_capture.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 7
         L.mhk_plan_launch_graph.argtypes = [C.c_void_p]
         L.mhk_plan_set_timing.argtypes = [C.c_void_p, C.c_int]
@@ -172,9 +173,10 @@ def _structs(boundary, volume, targets, on_surface, keep):
     B = Boundary(nb // NGL, len(ofs) - 1, keep.typed(ofs, np.int64), keep.f64(b["x"]), keep.f64(b["y"]),
                  keep.f64(b["nx"]), keep.f64(b["ny"]), keep.f64(b["w"]), keep.f64(b["kappa"]))
     if volume is not None and len(volume["x"]) > 0:
-        V = Volume(len(volume["x"]), keep.f64(volume["x"]), keep.f64(volume["y"]), keep.f64(volume["w"]))
+        V = Volume(len(volume["x"]), keep.f64(volume["x"]), keep.f64(volume["y"]), keep.f64(volume["w"]),
+                   int(volume.get("group", 0)))
     else:
-        V = Volume(0, None, None, None)
+        V = Volume(0, None, None, None, 0)
     if targets is not None:
         tx, ty, ins = targets
         T = Targets(len(tx), keep.f64(tx), keep.f64(ty), keep.typed(np.asarray(ins).astype(np.int8), np.int8),
@@ -297,6 +299,22 @@ class Plan:
         _check(lib().mhk_plan_capture(self._h, int(parts), ptr(sigma), ptr(mu), ptr(f_vol), ptr(f_trg),
                                       ptr(out[0]), ptr(out[1]), ptr(out[2])))
         self._bound = (sigma, mu, f_vol, f_trg, out)
+        return out
+
+    def f_targets(self, f_vol, out=None):
+        """f at the targets as reconstructed from the volume triangles (the
+        f_trg an eval uses when given none): [batch, rows, n_out]."""
+        import torch
+        f_vol = self._dev(f_vol, self.nv)
+        if out is None:
+            out = torch.empty((self.batch, self.f_rows, self.n_out), dtype=self.in_dtype, device="cuda")
+        self._dev(out, self.f_rows * self.n_out, None, self.in_dtype)
+        cur, other = self._streams()
+        if other:
+            self.stream.wait_stream(cur)
+        _check(lib().mhk_plan_f_targets(self._h, C.c_void_p(f_vol.data_ptr()), C.c_void_p(out.data_ptr())))
+        if other:
+            cur.wait_stream(self.stream)
         return out
 
     def replay(self):

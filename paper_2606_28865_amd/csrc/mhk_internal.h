@@ -178,6 +178,17 @@ struct Local {
 
 }  // namespace mhk
 
+namespace mhk {
+// f at the targets from the volume quadrature (volume nodes in groups of six)
+struct FJets {
+    bool active = false;
+    double *minv = nullptr;      // [ntri][6][6] inverse of the monomial matrix at the six nodes
+    double *tc = nullptr;        // [ntri][3] centroid x, y and scale h
+    int32_t *tri = nullptr;      // [n_out] sorted target -> triangle (-1: f not needed)
+    void *frec = nullptr;        // per eval: [batch][rows][n_out] f (and jets), caller order, input precision
+};
+}  // namespace mhk
+
 struct mhk_plan {
     mhk_params p{};
     mhk_info info{};
@@ -201,6 +212,7 @@ struct mhk_plan {
     mhk::Level lev[mhk::MAXJ];
     mhk::History hist;
     mhk::Local loc;
+    mhk::FJets fj;
     std::vector<void *> allocs;                 // stream-ordered allocations on `stream`
     std::vector<std::vector<char>> stage;       // host bytes of uploads in flight during creation
     int64_t bytes = 0;
@@ -236,6 +248,11 @@ hipError_t launch_rows(mhk_plan *P, bool inverse);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
 hipError_t launch_round32(mhk_plan *P, const void *x, void *y, int64_t n);
+hipError_t launch_fjets(mhk_plan *P, const void *f_vol, void *out);
+hipError_t dev_fj_setup(int64_t ntri, const double *vx, const double *vy, double *minv, double *tc, uint8_t *good,
+                        hipStream_t st);
+hipError_t dev_fj_nearest(mhk_plan *P, const double *vx, const double *vy, const uint8_t *good, double ox,
+                          double oy, double cell, int64_t ncx, int64_t ncy, int32_t *tri, hipStream_t st);
 hipError_t launch_trunc_kernel_samples(double *buf, int64_t M, double h, double alpha, double delta, double rmid,
                                        double slope, const double *gl_t, const double *gl_w, hipStream_t s);
 hipError_t launch_cos_step(const double *in, int64_t K, int64_t NA, int64_t NB, int n, const double *costab,

@@ -472,6 +472,10 @@ mhk_status check_inputs(const mhk_params *p, const mhk_boundary *b, const mhk_vo
         set_error("negative volume size");
         return MHK_EINVAL;
     }
+    if (v && v->group != 0 && (v->group != 6 || v->n % 6 != 0)) {
+        set_error("volume group must be 0 or 6 (with a multiple of 6 nodes)");
+        return MHK_EINVAL;
+    }
     if (v && v->n > 0) {
         if (!v->x || !v->y || !v->w || v->n > (int64_t)1 << 30) {
             set_error("volume arrays missing or too large");
@@ -1369,6 +1373,40 @@ mhk_status build_local(mhk_plan *P, Host &H)
     return MHK_OK;
 }
 
+// f at the targets from the volume quadrature (volume nodes in groups of
+// six per triangle): per-triangle quadratic fits and each target's triangle
+mhk_status build_fjets(mhk_plan *P, Host &H)
+{
+    FJets &F = P->fj;
+    const int64_t nv = P->nv, ntri = nv / 6;
+    const hipStream_t st = P->stream;
+    StreamTmp tmp(st);
+    double *vx = nullptr, *vy = nullptr;
+    uint8_t *good = nullptr;
+    TRY(tmp.upload(&vx, H.v->x, nv));
+    TRY(tmp.upload(&vy, H.v->y, nv));
+    TRY(tmp.alloc(&good, ntri));
+    TRY(dalloc(P, &F.minv, 36 * ntri));
+    TRY(dalloc(P, &F.tc, 3 * ntri));
+    TRY(dalloc(P, &F.tri, P->nout));
+    MHK_HIP(dev_fj_setup(ntri, vx, vy, F.minv, F.tc, good, st));
+    // cells of about two node spacings over the box of nodes and targets
+    const double lx = H.xmax - H.xmin, ly = H.ymax - H.ymin;
+    double cell = 2.0 * sqrt(std::max(lx * ly, 1e-300) / (double)nv);
+    cell = std::max(cell, std::max(lx, ly) / 4096.0);
+    const double ox = H.xmin - 1e-9, oy = H.ymin - 1e-9;
+    const int64_t ncx = (int64_t)floor((H.xmax - ox) / cell) + 1, ncy = (int64_t)floor((H.ymax - oy) / cell) + 1;
+    MHK_HIP(dev_fj_nearest(P, vx, vy, good, ox, oy, cell, ncx, ncy, F.tri, st));
+    const int rows = P->p.local_order >= 2 ? 6 : 1;
+    const int64_t es_in = (P->p.prec == MHK_FP64 || P->p.in64) ? 8 : 4;
+    char *fr = nullptr;
+    TRY(dalloc(P, &fr, (int64_t)P->p.batch * rows * P->nout * es_in));
+    F.frec = fr;
+    F.active = true;
+    MHK_HIP(hipStreamSynchronize(st));   // the uploads read the caller's arrays
+    return MHK_OK;
+}
+
 mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_volume *v,
                   const mhk_targets *t, void *stream, mhk_plan *P)
 {
@@ -1450,6 +1488,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     MHK_HIP(hipStreamSynchronize(P->stream));
     lap(3);
     TRY(build_local(P, H));
+    if (H.v && v->group == 6) TRY(build_fjets(P, H));
     MHK_HIP(launch_local_geom(P, P->stream));
     {
         char *a = nullptr;
@@ -1547,6 +1586,8 @@ mhk_status mhk_plan_footprint(const mhk_params *params, const mhk_boundary *b, c
     s += nb * (8 * 3 + 4) + 3 * B * nb * 8;   // local
     s += nout * ((p.local_order >= 2 ? LOCAL_GEO_N2 : LOCAL_GEO_N1) * 8 + 4 + 1);   // local geometry per target
     if (p.in64) s += B * (2 * nb + nv) * 4;   // FP32 copies of FP64 inputs
+    if (v && v->group == 6)                    // f at the targets from the volume triangles
+        s += (nv / 6) * 39 * 8 + nout * 4 + B * (p.local_order >= 2 ? 6 : 1) * nout * 8;
     if (I.kmax > 0) {                         // history grid
         double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
         auto acc = [&](double x, double y) {
@@ -1622,8 +1663,9 @@ mhk_status validate_eval(const mhk_plan *P, int parts, const void *sigma, const 
         set_error("an input density was given without its output array");
         return MHK_EINVAL;
     }
-    if (f_vol && out_v && !f_trg && (parts & MHK_PART_LOCAL)) {
-        set_error("f_trg is required with f_vol for the local part of V");
+    if (f_vol && out_v && !f_trg && (parts & MHK_PART_LOCAL) && !P->fj.active) {
+        set_error("f_trg is required with f_vol for the local part of V (unless the volume nodes come in "
+                  "groups of six per triangle, from which f at the targets is reconstructed)");
         return MHK_EINVAL;
     }
     if (f_vol && P->nv == 0) {
@@ -1675,6 +1717,12 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     const bool ws = sigma && out_s, wd = mu && out_d, wv = f_vol && out_v;
     if (!ws && !wd && !wv) return MHK_OK;
     hipStream_t st = P->stream;
+    // f (and its derivatives) at the targets from the volume quadrature when
+    // the caller gives none
+    if (wv && !f_trg && (parts & MHK_PART_LOCAL) && P->fj.active) {
+        MHK_HIP(launch_fjets(P, f_vol, P->fj.frec));
+        f_trg = P->fj.frec;
+    }
     // FP32 plan given FP64 inputs: spreading and the level sums read float
     // copies (rounded once here), the local part the caller's doubles
     const void *sig_h = sigma, *mu_h = mu, *fv_h = f_vol;
@@ -1773,6 +1821,21 @@ mhk_status mhk_eval_parts(mhk_plan *P, int parts, const void *sigma, const void 
 {
     TRY(validate_eval(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v));
     return enqueue(P, parts, sigma, mu, f_vol, f_trg, out_s, out_d, out_v, P->p.batch);
+}
+
+mhk_status mhk_plan_f_targets(mhk_plan *P, const void *f_vol, void *f_trg)
+{
+    if (!P || !f_vol || !f_trg) {
+        set_error("plan, f_vol and f_trg are required");
+        return MHK_EINVAL;
+    }
+    if (!P->fj.active) {
+        set_error("the plan's volume nodes are not in groups of six per triangle");
+        return MHK_EINVAL;
+    }
+    P->bat = P->p.batch;
+    MHK_HIP(launch_fjets(P, f_vol, f_trg));
+    return MHK_OK;
 }
 
 mhk_status mhk_eval_batch(mhk_plan *P, int nbatch, int parts, const void *sigma, const void *mu, const void *f_vol,

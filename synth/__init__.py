@@ -414,7 +414,10 @@ def cut_cell_volume(curves, dx, box=None, max_depth=4):
         TI = inside_any(curves, TX.ravel(), TY.ravel()).reshape(-1, 3)
     x = np.concatenate(xs); y = np.concatenate(ys); w = np.concatenate(ws)
     m = w > 0
-    return {"x": x[m], "y": y[m], "w": w[m]}
+    # unused slots have weight 0 six at a time: the kept nodes are in groups
+    # of six, one triangle's 6-point rule each
+    assert m.sum() % 6 == 0
+    return {"x": x[m], "y": y[m], "w": w[m], "group": 6}
 
 
 def polar_volume(curve: Curve, n_rho: int, n_theta: int):
