@@ -62,6 +62,9 @@ def lib():
         L.or_refine_level.argtypes = [C.POINTER(_Problem), i] + [C.c_void_p] * 7
         L.or_closest_point.restype = i
         L.or_closest_point.argtypes = [C.POINTER(_Problem), d, d, C.c_void_p]
+        L.or_level_sum_S.restype = None
+        L.or_level_sum_S.argtypes = [d, d, i, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_eval.restype = i
         L.or_eval.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_void_p]
@@ -98,6 +101,15 @@ def KD(r, alpha, delta, j):
 
 LOCAL_NAMES = ["Phim", "Phip", "Z", "P0", "P1", "P2", "P3", "Q0", "Q1",
                "U0", "U1", "U2", "U3", "U4", "lam", "W0", "W1"]
+
+
+def level_sum_S(alpha, delta, j, sx, sy, q, tx, ty):
+    """sum_s q_s K_j^S(|x_t - y_s|) at every target, direct."""
+    sx, sy, q, tx, ty = (np.ascontiguousarray(a, dtype=np.float64) for a in (sx, sy, q, tx, ty))
+    out = np.zeros(len(tx))
+    lib().or_level_sum_S(float(alpha), float(delta), int(j), len(sx), sx.ctypes.data, sy.ctypes.data,
+                         q.ctypes.data, len(tx), tx.ctypes.data, ty.ctypes.data, out.ctypes.data)
+    return out
 
 
 def local_coeffs(c1, c2):

@@ -857,3 +857,28 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
     free(cs); free(cm); free(ck); free(cf);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* A dyadic level of the volume potential: out[t] = sum_s q[s] K_j^S(|x_t -  */
+/* y_s|) over every source, directly (the level term of V when its local     */
+/* part is split in time like the layer potentials', Section 4.2).  Pairs    */
+/* with r^2/(4 delta_j) > 40 (K below 1e-17 of K(0)) are skipped.            */
+/* ------------------------------------------------------------------------ */
+void or_level_sum_S(double alpha, double delta, int j, int64_t ns, const double *sx, const double *sy,
+                    const double *q, int64_t nt, const double *tx, const double *ty, double *out)
+{
+    or_init();
+    const double dj = delta / pow(4.0, j - 1);
+    const double rmax2 = 160.0 * dj;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < nt; ++t) {
+        double acc = 0.0;
+        for (int64_t s = 0; s < ns; ++s) {
+            const double dx = tx[t] - sx[s], dy = ty[t] - sy[s];
+            const double r2 = dx * dx + dy * dy;
+            if (r2 > rmax2) continue;
+            acc += q[s] * or_KS(sqrt(r2), alpha, delta, j);
+        }
+        out[t] = acc;
+    }
+}
