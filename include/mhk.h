@@ -102,6 +102,15 @@ typedef struct {
                         256 or 512 (0: 256); the same sums in another order       */
     int lv_bch;      /* densities per pass of the level sums for batch > 1: 1, 2, 4
                         or 8 (0: 4); each kernel-table evaluation serves them all */
+    int v_levels;    /* 1: the volume potential gets the J dyadic levels too (its
+                        local part split in time like the layer potentials', Section
+                        4.2): V = V_H(delta) + sum_j V_j + V_L(delta*), V_j the level
+                        sums of f over a level-j volume quadrature (every triangle's
+                        reference triangle split into 4^j, mapped by the quadratic
+                        through its six nodes, f by the reconstruction of
+                        mhk_volume.group), V_L with delta* = delta/4^J in place of
+                        delta (band_volume then uses delta*).  Needs volume.group = 6,
+                        volume.rule and J >= 1.  0: the paper's choice, V_L at delta */
     int in64;        /* MHK_FP32 plans only: 1 = sigma, mu, f_vol, f_trg are given as
                         double; spreading and the level sums take them rounded to
                         float once, the local part (which differentiates sigma and
@@ -129,6 +138,10 @@ typedef struct {
                                          node (slivers with nearly collinear nodes
                                          excluded), at targets inside the domain and at the
                                          boundary nodes                                     */
+    const double *rule;               /* host [6][3] or NULL: the reference rule of the groups,
+                                         (s_i, t_i, W_i) with node i of a group the image of
+                                         (s_i, t_i) on {s, t >= 0, s + t <= 1} and sum W_i = 1;
+                                         needed for params.v_levels                         */
 } mhk_volume;
 
 typedef struct {
@@ -146,7 +159,7 @@ typedef struct {
     int64_t n_fine;       /* fine grid points per dimension                          */
     int wspread;          /* window width                                            */
     double band_layer;    /* sqrt(delta*)(12 + 2 alpha sqrt(delta*)), Remark 4.3      */
-    double band_volume;   /* sqrt(delta)(12 + 2 alpha sqrt(delta))                   */
+    double band_volume;   /* sqrt(d)(12 + 2 alpha sqrt(d)), d = delta (delta* with v_levels) */
     double level_radius[8];
     int64_t n_boundary, n_volume, n_targets, n_out;
     int64_t device_bytes; /* device memory owned by the plan                         */

@@ -30,8 +30,9 @@ nodes come in groups of six per triangle:
     with corner (a + 1, b + 1)/n, a + b <= n - 2), each carrying the rule
     mapped onto it;
   * node y = x(s, t) at a mapped point, weight W_i |det Dx(s, t)| / (2 4^j);
-  * f(y) by the rule of oracle.fjets (the quadratic of the triangle holding
-    the nearest usable volume node).
+  * f(y) from the quadratic of oracle.fjets fitted to the six nodal values
+    of the node's own triangle; for the slivers that rule excludes, the
+    quadratic of the triangle holding the nearest usable volume node.
 """
 from __future__ import annotations
 
@@ -85,12 +86,31 @@ def level_nodes(volume, rule, j):
     return x.ravel(), y.ravel(), w.ravel()
 
 
+def level_f(volume, f_vol, j, x, y):
+    """f at the level-j nodes (x, y), in the order of level_nodes."""
+    cen, h, thin, A = fjets.triangles(volume["x"], volume["y"])
+    ntri = len(h)
+    per_tri = len(x) // ntri
+    parent = np.arange(len(x)) // per_tri
+    usable = thin >= fjets.THIN_MIN
+    c = np.zeros((ntri, GROUP))
+    c[usable] = np.linalg.solve(A[usable], np.asarray(f_vol, np.float64).reshape(-1, GROUP)[usable][..., None])[..., 0]
+    X = (x - cen[parent, 0]) / h[parent]
+    Y = (y - cen[parent, 1]) / h[parent]
+    cp = c[parent]
+    f = cp[:, 0] + cp[:, 1] * X + cp[:, 2] * Y + cp[:, 3] * X * X + cp[:, 4] * X * Y + cp[:, 5] * Y * Y
+    bad = np.nonzero(thin[parent] < fjets.THIN_MIN)[0]
+    if len(bad):
+        f[bad] = fjets.jets(volume["x"], volume["y"], f_vol, x[bad], y[bad])[0]
+    return f
+
+
 def levels(volume, rule, f_vol, alpha, delta, J, px, py):
     """sum_{j=1..J} V_j at the points (px, py) and the per-level values."""
     per = []
     for j in range(1, J + 1):
         x, y, w = level_nodes(volume, rule, j)
-        f = fjets.jets(volume["x"], volume["y"], f_vol, x, y)[0]
+        f = level_f(volume, f_vol, j, x, y)
         per.append(O.level_sum_S(alpha, delta, j, x, y, w * f, px, py))
     return np.sum(per, 0), per
 

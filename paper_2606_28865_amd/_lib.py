@@ -23,7 +23,7 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("prec", C.c_int), ("J", C.c_int),
                 ("delta", C.c_double), ("dx", C.c_double), ("batch", C.c_int),
                 ("upsamp", C.c_double), ("wspread", C.c_int), ("local_order", C.c_int),
-                ("lv_block", C.c_int), ("lv_bch", C.c_int), ("in64", C.c_int)]
+                ("lv_block", C.c_int), ("lv_bch", C.c_int), ("v_levels", C.c_int), ("in64", C.c_int)]
 
 
 class Boundary(C.Structure):
@@ -33,7 +33,8 @@ class Boundary(C.Structure):
 
 
 class Volume(C.Structure):
-    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("w", C.c_void_p), ("group", C.c_int32)]
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("w", C.c_void_p), ("group", C.c_int32),
+                ("rule", C.c_void_p)]
 
 
 class Targets(C.Structure):
@@ -138,9 +139,10 @@ def _check(rc):
 
 
 def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0, local_order=1,
-                lv_block=0, lv_bch=0, in64=0):
+                lv_block=0, lv_bch=0, in64=0, v_levels=0):
     return Params(float(alpha), float(tol), int(prec), int(J), float(delta), float(dx), int(batch),
-                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch), int(in64))
+                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch), int(v_levels),
+                  int(in64))
 
 
 def resolve_params(**kw):
@@ -173,10 +175,11 @@ def _structs(boundary, volume, targets, on_surface, keep):
     B = Boundary(nb // NGL, len(ofs) - 1, keep.typed(ofs, np.int64), keep.f64(b["x"]), keep.f64(b["y"]),
                  keep.f64(b["nx"]), keep.f64(b["ny"]), keep.f64(b["w"]), keep.f64(b["kappa"]))
     if volume is not None and len(volume["x"]) > 0:
+        rule = volume.get("rule")
         V = Volume(len(volume["x"]), keep.f64(volume["x"]), keep.f64(volume["y"]), keep.f64(volume["w"]),
-                   int(volume.get("group", 0)))
+                   int(volume.get("group", 0)), None if rule is None else keep.f64(np.asarray(rule).ravel()))
     else:
-        V = Volume(0, None, None, None, 0)
+        V = Volume(0, None, None, None, 0, None)
     if targets is not None:
         tx, ty, ins = targets
         T = Targets(len(tx), keep.f64(tx), keep.f64(ty), keep.typed(np.asarray(ins).astype(np.int8), np.int8),

@@ -213,34 +213,98 @@ hipError_t dev_fj_setup(int64_t ntri, const double *vx, const double *vy, double
     return hipGetLastError();
 }
 
+// cell list of the nodes of usable triangles (kept by the plan: the level
+// nodes of the volume potential are located with it too) and each sorted
+// target's triangle
 hipError_t dev_fj_nearest(mhk_plan *P, const double *vx, const double *vy, const uint8_t *good, double ox,
                           double oy, double cell, int64_t ncx, int64_t ncy, int32_t *tri, hipStream_t st)
 {
+    FJets &F = P->fj;
     const int64_t nv = P->nv;
     uint32_t *key = nullptr;
-    int32_t *perm = nullptr, *start = nullptr;
     hipError_t e = hipMallocAsync((void **)&key, sizeof(uint32_t) * nv, st);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&perm, sizeof(int32_t) * nv, st);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&start, sizeof(int32_t) * (ncx * ncy + 2), st);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fj_keys, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, nv, vx, vy, good, ox, oy,
-                           cell, ncx, ncy, key, perm);
+                           cell, ncx, ncy, key, F.perm);
         e = hipGetLastError();
     }
     int bits = 1;
     while (bits < 32 && ((int64_t)1 << bits) <= ncx * ncy) ++bits;
-    if (e == hipSuccess) e = dev_sort_pairs(key, perm, nv, bits, st);
+    if (e == hipSuccess) e = dev_sort_pairs(key, F.perm, nv, bits, st);
     // starts of the ncx * ncy cells and of the unusable tail
-    if (e == hipSuccess) e = dev_cell_starts(key, nv, ncx * ncy + 1, start, st);
+    if (e == hipSuccess) e = dev_cell_starts(key, nv, ncx * ncy + 1, F.start, st);
+    F.ox = ox;
+    F.oy = oy;
+    F.cell = cell;
+    F.ncx = ncx;
+    F.ncy = ncy;
     if (e == hipSuccess && P->nout > 0) {
         hipLaunchKernelGGL(k_fj_nearest, dim3((unsigned)((P->nout + 255) / 256)), dim3(256), 0, st, P->nout, P->nt,
-                           P->tx, P->ty, P->tin, P->tidx, vx, vy, perm, start, ox, oy, cell, ncx, ncy, tri);
+                           P->tx, P->ty, P->tin, P->tidx, vx, vy, F.perm, F.start, ox, oy, cell, ncx, ncy, tri);
         e = hipGetLastError();
     }
     if (key) (void)hipFreeAsync(key, st);
-    if (perm) (void)hipFreeAsync(perm, st);
-    if (start) (void)hipFreeAsync(start, st);
     return e;
+}
+
+// the triangle of the nearest usable node for arbitrary points (the level
+// nodes of the volume potential), with the cell list above; the points must
+// lie in the box the cells cover
+__global__ void __launch_bounds__(256) k_fj_nearest_pts(int64_t n, const double *__restrict__ px_,
+                                                        const double *__restrict__ py_,
+                                                        const int32_t *__restrict__ parent,
+                                                        const uint8_t *__restrict__ good,
+                                                        const double *__restrict__ vx, const double *__restrict__ vy,
+                                                        const int32_t *__restrict__ perm,
+                                                        const int32_t *__restrict__ start, double ox, double oy,
+                                                        double cell, int64_t ncx, int64_t ncy,
+                                                        int32_t *__restrict__ tri)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    // a point of a usable triangle keeps it
+    if (parent && good[parent[s]]) {
+        tri[s] = parent[s];
+        return;
+    }
+    const double px = px_[s], py = py_[s];
+    const int64_t cx = min(ncx - 1, max((int64_t)0, (int64_t)floor((px - ox) / cell)));
+    const int64_t cy = min(ncy - 1, max((int64_t)0, (int64_t)floor((py - oy) / cell)));
+    double best = INFINITY;
+    int32_t bi = INT32_MAX;
+    const int64_t rmax = max(ncx, ncy);
+    for (int64_t r = 0; r <= rmax; ++r) {
+        for (int64_t iy = cy - r; iy <= cy + r; ++iy) {
+            if (iy < 0 || iy >= ncy) continue;
+            const bool edge_row = iy == cy - r || iy == cy + r;
+            for (int64_t ix = cx - r; ix <= cx + r; ix += (edge_row || r == 0) ? 1 : 2 * r) {
+                if (ix < 0 || ix >= ncx) continue;
+                const int64_t c = iy * ncx + ix;
+                for (int32_t k = start[c]; k < start[c + 1]; ++k) {
+                    const int32_t i = perm[k];
+                    const double dx = vx[i] - px, dy = vy[i] - py;
+                    const double d2 = dx * dx + dy * dy;
+                    if (d2 < best || (d2 == best && i < bi)) {
+                        best = d2;
+                        bi = i;
+                    }
+                }
+            }
+        }
+        const double reach = (double)r * cell;
+        if (best < reach * reach) break;
+    }
+    tri[s] = bi == INT32_MAX ? 0 : bi / FJ_GROUP;
+}
+
+hipError_t dev_fj_nearest_pts(mhk_plan *P, int64_t n, const double *px, const double *py, const int32_t *parent,
+                              const double *vx, const double *vy, int32_t *tri, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const FJets &F = P->fj;
+    hipLaunchKernelGGL(k_fj_nearest_pts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, px, py, parent,
+                       F.good, vx, vy, F.perm, F.start, F.ox, F.oy, F.cell, F.ncx, F.ncy, tri);
+    return hipGetLastError();
 }
 
 hipError_t launch_fjets(mhk_plan *P, const void *f_vol, void *out)

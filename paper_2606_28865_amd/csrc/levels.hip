@@ -404,6 +404,58 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     return hipGetLastError();
 }
 
+// the volume potential's level j: the same kernel table, the volume level
+// nodes as sources (single-layer sums only), into acc_vlev
+template <typename T, int STRIDE>
+static hipError_t level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init)
+{
+    Level &L = P->lev[j - 1];
+    VLevel &V = P->vlev[j - 1];
+    const int B = P->bat;
+    LevelArgs<T> A;
+    A.nout = P->nout;
+    A.n_src = V.n_src;
+    A.tx = P->tx;
+    A.ty = P->ty;
+    A.inv4d = L.inv4d;
+    A.a_max = L.a_max;
+    A.seg_inv = L.seg_inv;
+    A.d_scale = level_d_scale(L);
+    A.nseg = L.nseg;
+    A.B = B;
+    A.wave_ofs = V.wave_ofs;
+    A.wave_src = V.wave_src;
+    A.wave_order = V.wave_order;
+    A.sx = V.sx;
+    A.sy = V.sy;
+    A.q = (const T *)V.q;
+    A.tab = (const T *)L.tab_dev;
+    A.acc_s = (T *)P->acc_vlev;
+    A.acc_d = (T *)P->acc_vlev;            // not written (want_d = 0)
+    A.want_s = 1;
+    A.want_d = 0;
+    A.init = init;
+    const int want = std::min(B, P->p.lv_bch);
+    const int bch = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
+    const int nby = (B + bch - 1) / bch;
+    const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const int nb = P->p.lv_block;
+    switch (bch) {
+    case 1: level_launch_nb<1, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
+    case 2: level_launch_nb<2, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
+    case 4: level_launch_nb<4, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
+    default: level_launch_nb<8, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init)
+{
+    if (P->p.prec == MHK_FP64) return level_sums_v<double, TAB_STRIDE>(P, st, j, init);
+    return level_sums_v<float, TABF_STRIDE>(P, st, j, init);
+}
+
 hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bool want_d, bool init)
 {
     if (P->p.prec == MHK_FP64) return level_sums<double, TAB_STRIDE>(P, st, j, want_s, want_d, init);

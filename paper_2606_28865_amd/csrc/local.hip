@@ -269,6 +269,7 @@ struct LocalArgs {
     int frows;             // rows of f_trg per density: 1 (f) or 6 (f and its gradient and Hessian)
     const T *acc;          // [3][B][nout]: S, D, V in sorted order (history part)
     const T *lev;          // [2][B][nout]: S, D of the level sums, or null
+    const T *vlev;         // [B][nout]: the volume potential's level sums, or null
     T *out_s, *out_d, *out_v;
 };
 
@@ -718,6 +719,7 @@ __global__ void __launch_bounds__(256) k_local(LocalArgs<T, TI> A)
         }
         if (wv) {
             double v = (double)A.acc[(size_t)2 * A.B * A.nout + ab];
+            if (A.vlev) v += (double)A.vlev[ab];
             if (do_local) {
                 // f (and with second order its gradient and Hessian) at the target
                 const TI *fr = A.f_trg + (size_t)b * A.frows * A.nout + idx;
@@ -826,13 +828,14 @@ static void fill_args(mhk_plan *P, LocalArgs<T, TI> &A)
     A.ncx = P->loc.ncx;
     A.ncy = P->loc.ncy;
     A.alpha = P->p.alpha;
-    A.delta = P->delta;
+    A.delta = P->delta_v;                 // V's local part: delta, or delta* with volume levels
     A.dstar = P->dstar;
     A.band_s = P->info.band_layer;
     A.band_v = P->info.band_volume;
     A.frows = P->p.local_order >= 2 ? 6 : 1;
     A.acc = (const T *)P->acc;
     A.lev = nullptr;
+    A.vlev = nullptr;
     A.out_s = A.out_d = A.out_v = nullptr;
 }
 
@@ -851,11 +854,12 @@ hipError_t launch_local_geom(mhk_plan *P, hipStream_t st)
 
 template <typename T, typename TI>
 static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                          void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
+                          void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev, bool have_vlev)
 {
     LocalArgs<T, TI> A;
     fill_args(P, A);
     A.lev = have_lev ? (const T *)P->acc_lev : nullptr;
+    A.vlev = have_vlev ? (const T *)P->acc_vlev : nullptr;
     A.parts = parts;
     A.sigma = (const TI *)sigma;
     A.mu = (const TI *)mu;
@@ -873,13 +877,13 @@ static hipError_t local_t(mhk_plan *P, int parts, const void *sigma, const void 
 }
 
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu, const void *f_trg,
-                        void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev)
+                        void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev, bool have_vlev)
 {
     if (P->p.prec == MHK_FP64)
-        return local_t<double, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+        return local_t<double, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev, have_vlev);
     if (P->p.in64)
-        return local_t<float, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
-    return local_t<float, float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev);
+        return local_t<float, double>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev, have_vlev);
+    return local_t<float, float>(P, parts, sigma, mu, f_trg, out_s, out_d, out_v, have_fb, have_lev, have_vlev);
 }
 
 // FP32 copies of FP64 inputs (FP32 plans with in64): n values, rounded once

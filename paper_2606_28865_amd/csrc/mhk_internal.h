@@ -186,6 +186,31 @@ struct FJets {
     double *tc = nullptr;        // [ntri][3] centroid x, y and scale h
     int32_t *tri = nullptr;      // [n_out] sorted target -> triangle (-1: f not needed)
     void *frec = nullptr;        // per eval: [batch][rows][n_out] f (and jets), caller order, input precision
+    // cell list of the nodes of usable triangles
+    int32_t *perm = nullptr, *start = nullptr;
+    uint8_t *good = nullptr;     // [ntri] usable triangle (not a sliver)
+    double ox = 0, oy = 0, cell = 0;
+    int64_t ncx = 0, ncy = 0;
+};
+
+// reference rule of the volume triangles (points (s_i, t_i) on T0, weights
+// W_i) and the inverse of the monomial matrix 1, s, t, s^2, st, t^2 at the
+// points (the quadratic map of a triangle from its six nodes)
+struct VRule {
+    double rinv[36];
+    double s[6], t[6], W[6];
+};
+
+// dyadic level j of the volume potential: the level nodes sorted by cells of
+// side R_j/4, their triangles for f, per-wavefront candidate lists
+struct VLevel {
+    int64_t n_src = 0;
+    double *sx = nullptr, *sy = nullptr, *sw = nullptr;
+    int32_t *tri = nullptr;
+    int32_t *cell_start = nullptr;
+    int32_t *wave_ofs = nullptr, *wave_src = nullptr, *wave_order = nullptr;
+    int64_t n_wave = 0, n_cand = 0;
+    void *q = nullptr;           // per eval: [batch][n_src], plan precision
 };
 }  // namespace mhk
 
@@ -213,6 +238,9 @@ struct mhk_plan {
     mhk::History hist;
     mhk::Local loc;
     mhk::FJets fj;
+    mhk::VLevel vlev[mhk::MAXJ];                // volume levels (params.v_levels)
+    void *acc_vlev = nullptr;                    // [batch][n_out] their sums, sorted order
+    double delta_v = 0;                          // time split of V's local part: delta, or delta* with volume levels
     std::vector<void *> allocs;                 // stream-ordered allocations on `stream`
     std::vector<std::vector<char>> stage;       // host bytes of uploads in flight during creation
     int64_t bytes = 0;
@@ -240,7 +268,8 @@ hipError_t launch_level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
 hipError_t launch_panel_coeffs(mhk_plan *P, const void *sigma, const void *mu, const void *f_bnd);
 hipError_t launch_local_geom(mhk_plan *P, hipStream_t st);
 hipError_t launch_local(mhk_plan *P, int parts, const void *sigma, const void *mu,
-                        const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev);
+                        const void *f_trg, void *out_s, void *out_d, void *out_v, bool have_fb, bool have_lev,
+                        bool have_vlev);
 hipError_t launch_spread(mhk_plan *P, const void *sigma, const void *mu, const void *f_vol);
 hipError_t launch_multiply(mhk_plan *P);
 hipError_t launch_columns(mhk_plan *P);
@@ -249,6 +278,14 @@ hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
 hipError_t launch_round32(mhk_plan *P, const void *x, void *y, int64_t n);
 hipError_t launch_fjets(mhk_plan *P, const void *f_vol, void *out);
+hipError_t dev_fj_nearest_pts(mhk_plan *P, int64_t n, const double *px, const double *py, const int32_t *parent,
+                              const double *vx, const double *vy, int32_t *tri, hipStream_t st);
+hipError_t dev_vlevel_nodes(int64_t ntri, int j, const VRule &M, const double *vx, const double *vy, double ox,
+                            double oy, double cell, int64_t ncx, int64_t ncy, double *sx, double *sy, double *sw,
+                            int32_t *parent, int32_t *cell_start, hipStream_t st);
+hipError_t launch_vlevel_q(mhk_plan *P, hipStream_t st, int j, const void *f_vol);
+// level j's single-layer sums over the volume level nodes into acc_vlev
+hipError_t launch_level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init);
 hipError_t dev_fj_setup(int64_t ntri, const double *vx, const double *vy, double *minv, double *tc, uint8_t *good,
                         hipStream_t st);
 hipError_t dev_fj_nearest(mhk_plan *P, const double *vx, const double *vy, const uint8_t *good, double ox,

@@ -260,7 +260,16 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
     I->delta_star = p.delta / pow(4.0, p.J);
     I->prec = p.prec;
     I->batch = p.batch;
-    double sq = sqrt(I->delta_star), sv = sqrt(p.delta);
+    if (p.v_levels != 0 && p.v_levels != 1) {
+        set_error("v_levels must be 0 or 1");
+        return MHK_EINVAL;
+    }
+    if (p.v_levels && p.J < 1) {
+        set_error("v_levels needs J >= 1");
+        return MHK_EINVAL;
+    }
+    // V's local part: delta, or delta* when V has the dyadic levels too
+    double sq = sqrt(I->delta_star), sv = sqrt(p.v_levels ? I->delta_star : p.delta);
     // Remark 4.3: the local layer part is negligible beyond sqrt(d*)(12 + 2 alpha sqrt(d*))
     I->band_layer = sq * (12.0 + 2.0 * p.alpha * sq);
     I->band_volume = sv * (12.0 + 2.0 * p.alpha * sv);
@@ -1382,10 +1391,10 @@ mhk_status build_fjets(mhk_plan *P, Host &H)
     const hipStream_t st = P->stream;
     StreamTmp tmp(st);
     double *vx = nullptr, *vy = nullptr;
-    uint8_t *good = nullptr;
     TRY(tmp.upload(&vx, H.v->x, nv));
     TRY(tmp.upload(&vy, H.v->y, nv));
-    TRY(tmp.alloc(&good, ntri));
+    TRY(dalloc(P, &F.good, ntri));
+    uint8_t *good = F.good;
     TRY(dalloc(P, &F.minv, 36 * ntri));
     TRY(dalloc(P, &F.tc, 3 * ntri));
     TRY(dalloc(P, &F.tri, P->nout));
@@ -1394,8 +1403,14 @@ mhk_status build_fjets(mhk_plan *P, Host &H)
     const double lx = H.xmax - H.xmin, ly = H.ymax - H.ymin;
     double cell = 2.0 * sqrt(std::max(lx * ly, 1e-300) / (double)nv);
     cell = std::max(cell, std::max(lx, ly) / 4096.0);
-    const double ox = H.xmin - 1e-9, oy = H.ymin - 1e-9;
-    const int64_t ncx = (int64_t)floor((H.xmax - ox) / cell) + 1, ncy = (int64_t)floor((H.ymax - oy) / cell) + 1;
+    // the box of every point searched: nodes, targets and (volume levels)
+    // the level nodes of the curved triangles' maps, which can bulge a
+    // little past the nodes
+    const double mg = 0.05 * std::max(lx, ly) + cell;
+    const double ox = H.xmin - mg, oy = H.ymin - mg;
+    const int64_t ncx = (int64_t)floor((H.xmax + mg - ox) / cell) + 1, ncy = (int64_t)floor((H.ymax + mg - oy) / cell) + 1;
+    TRY(dalloc(P, &F.perm, nv));
+    TRY(dalloc(P, &F.start, ncx * ncy + 2));
     MHK_HIP(dev_fj_nearest(P, vx, vy, good, ox, oy, cell, ncx, ncy, F.tri, st));
     const int rows = P->p.local_order >= 2 ? 6 : 1;
     const int64_t es_in = (P->p.prec == MHK_FP64 || P->p.in64) ? 8 : 4;
@@ -1404,6 +1419,111 @@ mhk_status build_fjets(mhk_plan *P, Host &H)
     F.frec = fr;
     F.active = true;
     MHK_HIP(hipStreamSynchronize(st));   // the uploads read the caller's arrays
+    return MHK_OK;
+}
+
+// Dyadic levels of the volume potential: the level-j nodes of every volume
+// triangle (4^j sub-triangles of its reference triangle, mapped by the
+// quadratic through its six nodes), sorted by the cells of the layer level
+// j, each node's triangle for f, and the per-wavefront candidate lists
+mhk_status build_vlevels(mhk_plan *P, Host &H)
+{
+    const mhk_volume *v = H.v;
+    const int64_t nv = P->nv, ntri = nv / 6;
+    const hipStream_t st = P->stream;
+    VRule M;
+    {
+        // monomials 1, s, t, s^2, st, t^2 at the rule points, inverted (Gauss-Jordan, long double)
+        long double A[6][12];
+        for (int i = 0; i < 6; ++i) {
+            const long double s_ = v->rule[i * 3 + 0], t_ = v->rule[i * 3 + 1];
+            M.s[i] = v->rule[i * 3 + 0];
+            M.t[i] = v->rule[i * 3 + 1];
+            M.W[i] = v->rule[i * 3 + 2];
+            const long double row[6] = {1.0L, s_, t_, s_ * s_, s_ * t_, t_ * t_};
+            for (int k = 0; k < 6; ++k) {
+                A[i][k] = row[k];
+                A[i][6 + k] = i == k ? 1.0L : 0.0L;
+            }
+        }
+        for (int c = 0; c < 6; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < 6; ++r)
+                if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+            if (fabsl(A[piv][c]) < 1e-12L) {
+                set_error("volume rule: the six points do not determine a quadratic");
+                return MHK_EINVAL;
+            }
+            for (int k = 0; k < 12; ++k) std::swap(A[c][k], A[piv][k]);
+            const long double inv = 1.0L / A[c][c];
+            for (int k = 0; k < 12; ++k) A[c][k] *= inv;
+            for (int r = 0; r < 6; ++r)
+                if (r != c) {
+                    const long double f = A[r][c];
+                    for (int k = 0; k < 12; ++k) A[r][k] -= f * A[c][k];
+                }
+        }
+        // rinv[m][l]: coefficient m of the map from the node values l
+        for (int m = 0; m < 6; ++m)
+            for (int l = 0; l < 6; ++l) M.rinv[m * 6 + l] = (double)A[m][6 + l];
+    }
+    StreamTmp tmp(st);
+    double *vx = nullptr, *vy = nullptr;
+    TRY(tmp.upload(&vx, v->x, nv));
+    TRY(tmp.upload(&vy, v->y, nv));
+    {
+        char *a = nullptr;
+        TRY(dalloc(P, &a, (int64_t)P->p.batch * P->nout * (int64_t)P->es));
+        P->acc_vlev = a;
+    }
+    const int64_t nout = P->nout;
+    const int64_t nwave = ((nout + LV_BLOCK_MAX - 1) / LV_BLOCK_MAX) * (LV_BLOCK_MAX / LV_WAVE);
+    for (int j = 1; j <= P->J; ++j) {
+        const Level &L = P->lev[j - 1];
+        VLevel &V = P->vlev[j - 1];
+        V.n_src = ntri * ((int64_t)1 << (2 * j)) * 6;
+        if (V.n_src > (int64_t)INT32_MAX) {
+            set_error("volume level nodes beyond 2^31");
+            return MHK_EUNSUPPORTED;
+        }
+        TRY(dalloc(P, &V.sx, V.n_src));
+        TRY(dalloc(P, &V.sy, V.n_src));
+        TRY(dalloc(P, &V.sw, V.n_src));
+        TRY(dalloc(P, &V.tri, V.n_src));
+        TRY(dalloc(P, &V.cell_start, (int64_t)L.ncx * L.ncy + 1));
+        {
+            char *q = nullptr;
+            TRY(dalloc(P, &q, (int64_t)P->p.batch * V.n_src * (int64_t)P->es));
+            V.q = q;
+        }
+        int32_t *parent = nullptr;
+        TRY(tmp.alloc(&parent, V.n_src));
+        MHK_HIP(dev_vlevel_nodes(ntri, j, M, vx, vy, L.ox, L.oy, L.cell, L.ncx, L.ncy, V.sx, V.sy, V.sw, parent,
+                                 V.cell_start, st));
+        MHK_HIP(dev_fj_nearest_pts(P, V.n_src, V.sx, V.sy, parent, vx, vy, V.tri, st));
+        V.n_wave = nwave;
+        const double R = L.radius, R2 = R * R * (1.0 + 1e-9);
+        int32_t *cnt = nullptr;
+        int64_t *tot = nullptr;
+        TRY(tmp.alloc(&cnt, nwave));
+        TRY(tmp.alloc(&tot, 1));
+        TRY(dalloc(P, &V.wave_ofs, nwave + 1));
+        TRY(dalloc(P, &V.wave_order, nwave));
+        MHK_HIP(dev_wave_counts(P->tx, P->ty, nout, nwave, R, R2, L.ox, L.oy, L.cell, L.ncx, L.ncy, V.cell_start,
+                                V.sx, V.sy, cnt, st));
+        MHK_HIP(dev_scan(cnt, V.wave_ofs, nwave, tot, st));
+        int64_t total = 0;
+        TRY(tmp.fetch(&total, tot, 1));
+        if (total > (int64_t)INT32_MAX) {
+            set_error("volume level candidate lists too large");
+            return MHK_EUNSUPPORTED;
+        }
+        V.n_cand = total;
+        TRY(dalloc(P, &V.wave_src, std::max<int64_t>(1, total)));
+        MHK_HIP(dev_wave_fill(P->tx, P->ty, nout, nwave, R, R2, L.ox, L.oy, L.cell, L.ncx, L.ncy, V.cell_start, V.sx,
+                              V.sy, V.wave_ofs, V.wave_src, V.wave_order, st));
+    }
+    MHK_HIP(hipStreamSynchronize(st));
     return MHK_OK;
 }
 
@@ -1426,6 +1546,11 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     P->J = P->p.J;
     P->delta = P->info.delta;
     P->dstar = P->info.delta_star;
+    P->delta_v = P->p.v_levels ? P->dstar : P->delta;
+    if (P->p.v_levels && (!v || v->n == 0 || v->group != 6 || !v->rule)) {
+        set_error("v_levels needs a volume with group 6 and its rule");
+        return MHK_EINVAL;
+    }
     P->npan = b->n_panels;
     P->nb = b->n_panels * NGL;
     P->nv = v ? v->n : 0;
@@ -1489,6 +1614,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
     lap(3);
     TRY(build_local(P, H));
     if (H.v && v->group == 6) TRY(build_fjets(P, H));
+    if (P->p.v_levels) TRY(build_vlevels(P, H));
     MHK_HIP(launch_local_geom(P, P->stream));
     {
         char *a = nullptr;
@@ -1743,16 +1869,19 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
     // two overlap (the level sums are bound by LDS and FP64 issue, the FFTs by
     // memory).  They write acc_lev; the local part adds it.
     const bool levels = (parts & MHK_PART_LEVELS) && (ws || wd) && P->J > 0;
+    // the volume potential's levels (v_levels) run there too
+    const bool vlevels = (parts & MHK_PART_LEVELS) && wv && P->p.v_levels;
+    const bool side = levels || vlevels;
     // the local geometry (closest points, MHK_PART_GEOMETRY) depends on
     // nothing but the plan: it goes first on the side stream, beside the
     // history part, or on the plan's stream when there are no level sums
     const bool geom = (parts & MHK_PART_GEOMETRY) && (parts & MHK_PART_LOCAL);
-    if (geom && !levels) {
+    if (geom && !side) {
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[8], st));
         MHK_HIP(launch_local_geom(P, st));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[9], st));
     }
-    if (levels) {
+    if (side) {
         MHK_HIP(hipEventRecord(P->fork_ev, st));
         MHK_HIP(hipStreamWaitEvent(P->side, P->fork_ev, 0));
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[8], P->side));
@@ -1760,10 +1889,16 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
             MHK_HIP(launch_local_geom(P, P->side));
             if (P->timing) MHK_HIP(hipEventRecord(P->ev[9], P->side));
         }
-        for (int j = 1; j <= P->J; ++j) {
-            MHK_HIP(launch_level_densities(P, P->side, j, ws ? sig_h : nullptr, wd ? mu_h : nullptr));
-            MHK_HIP(launch_level_sums(P, P->side, j, ws, wd, j == 1));
-        }
+        if (levels)
+            for (int j = 1; j <= P->J; ++j) {
+                MHK_HIP(launch_level_densities(P, P->side, j, ws ? sig_h : nullptr, wd ? mu_h : nullptr));
+                MHK_HIP(launch_level_sums(P, P->side, j, ws, wd, j == 1));
+            }
+        if (vlevels)
+            for (int j = 1; j <= P->J; ++j) {
+                MHK_HIP(launch_vlevel_q(P, P->side, j, f_vol));
+                MHK_HIP(launch_level_sums_v(P, P->side, j, j == 1));
+            }
         if (P->timing) MHK_HIP(hipEventRecord(P->ev[6], P->side));
         MHK_HIP(hipEventRecord(P->join_ev, P->side));
     }
@@ -1795,18 +1930,19 @@ mhk_status enqueue(mhk_plan *P, int parts, const void *sigma, const void *mu, co
             for (int e = 1; e <= 4; ++e) MHK_HIP(hipEventRecord(P->ev[e], st));
     }
     if (P->timing) MHK_HIP(hipEventRecord(P->ev[5], st));
-    if (levels) MHK_HIP(hipStreamWaitEvent(st, P->join_ev, 0));
+    if (side) MHK_HIP(hipStreamWaitEvent(st, P->join_ev, 0));
     // f at the boundary nodes (the on-surface entries of f_trg) gives the
     // local volume part at exterior targets near the boundary
     const bool have_fb = wv && (parts & MHK_PART_LOCAL) && P->nout > P->nt;
     if ((parts & MHK_PART_LOCAL) && (ws || wd || have_fb))
         MHK_HIP(launch_panel_coeffs(P, ws ? sigma : nullptr, wd ? mu : nullptr, have_fb ? f_trg : nullptr));
     MHK_HIP(launch_local(P, parts, ws ? sigma : nullptr, wd ? mu : nullptr, wv ? f_trg : nullptr,
-                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb, levels));
+                         ws ? out_s : nullptr, wd ? out_d : nullptr, wv ? out_v : nullptr, have_fb, levels,
+                         vlevels));
     if (P->timing) {
         MHK_HIP(hipEventRecord(P->ev[7], st));
         P->t_pending = true;
-        P->t_levels = levels;
+        P->t_levels = side;
         P->t_geom = geom;
     }
     return MHK_OK;

@@ -417,7 +417,9 @@ def cut_cell_volume(curves, dx, box=None, max_depth=4):
     # unused slots have weight 0 six at a time: the kept nodes are in groups
     # of six, one triangle's 6-point rule each
     assert m.sum() % 6 == 0
-    return {"x": x[m], "y": y[m], "w": w[m], "group": 6}
+    bary, W = triangle_rule6()
+    rule = np.column_stack([bary[:, 1], bary[:, 2], W])     # (s, t, W) of the nodes of every group
+    return {"x": x[m], "y": y[m], "w": w[m], "group": 6, "rule": rule}
 
 
 def polar_volume(curve: Curve, n_rho: int, n_theta: int):
