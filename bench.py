@@ -555,17 +555,17 @@ def run_batched(a):
         for prec, dt, name, tol in ((M.MHK_FP32, torch.float32, "fp32", 1e-6), (M.MHK_FP64, torch.float64, "fp64", 1e-10)):
             tun = autotune.tune(geometry, alpha, tol, prec, (w.sigma, w.mu, w.f_vol, w.f_trg), dx=w.dx, batch=B,
                                 cache=None, log=log)
-            mk = lambda b, bch: M.make_params(alpha=alpha, tol=tol, prec=prec, delta=tun["delta"], batch=b,
-                                              upsamp=tun["upsamp"], wspread=tun["wspread"],
-                                              lv_block=tun["lv_block"], lv_bch=bch)
+            mk = lambda b, bch, ps: M.make_params(alpha=alpha, tol=tol, prec=prec, delta=tun["delta"], batch=b,
+                                                  upsamp=tun["upsamp"], wspread=tun["wspread"],
+                                                  lv_block=tun["lv_block"], lv_bch=bch, lv_persist=ps)
             t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
-            batched = form(mk(B, tun["lv_bch"]), (t(sig), t(mu), t(fv), t(ft)), dt, B)
-            single = form(mk(1, 0), (t(sig[:1]), t(mu[:1]), t(fv[:1]), t(ft[:1])), dt, 1)
+            batched = form(mk(B, tun["lv_bch"], tun["lv_persist"]), (t(sig), t(mu), t(fv), t(ft)), dt, B)
+            single = form(mk(1, 0, 0), (t(sig[:1]), t(mu[:1]), t(fv[:1]), t(ft[:1])), dt, 1)
             key = f"{name}_alpha{alpha:g}"
             res[key] = {"batched": batched, "single": single,
                         "speedup_per_density": single["ms_per_call"] * B / batched["ms_per_call"],
                         "upsamp": tun["upsamp"], "wspread": tun["wspread"], "lv_block": tun["lv_block"],
-                        "lv_bch": tun["lv_bch"],
+                        "lv_bch": tun["lv_bch"], "lv_persist": tun["lv_persist"],
                         "autotune": tun["table"], "autotune_tiles": tun["tile_table"]}
             log(f"{key}: {batched['ms_per_call']:.1f} ms per {B} densities ({batched['ms_per_density']:.3f} ms each, "
                 f"levels {batched['level_sums']['frac']:.3f} of peak) vs {single['ms_per_call']:.3f} ms for one "

@@ -102,6 +102,10 @@ typedef struct {
                         256 or 512 (0: 256); the same sums in another order       */
     int lv_bch;      /* densities per pass of the level sums for batch > 1: 1, 2, 4
                         or 8 (0: 4); each kernel-table evaluation serves them all */
+    int lv_persist;  /* 1: the level sums run as one persistent launch per level (a
+                        grid that fills the device once, wavefronts taking (target
+                        wavefront, density chunk) items from a counter); 0: one
+                        wavefront per item                                        */
     int v_levels;    /* 1: the volume potential gets the J dyadic levels too (its
                         local part split in time like the layer potentials', Section
                         4.2): V = V_H(delta) + sum_j V_j + V_L(delta*), V_j the level

@@ -23,7 +23,8 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("tol", C.c_double), ("prec", C.c_int), ("J", C.c_int),
                 ("delta", C.c_double), ("dx", C.c_double), ("batch", C.c_int),
                 ("upsamp", C.c_double), ("wspread", C.c_int), ("local_order", C.c_int),
-                ("lv_block", C.c_int), ("lv_bch", C.c_int), ("v_levels", C.c_int), ("in64", C.c_int)]
+                ("lv_block", C.c_int), ("lv_bch", C.c_int), ("lv_persist", C.c_int), ("v_levels", C.c_int),
+                ("in64", C.c_int)]
 
 
 class Boundary(C.Structure):
@@ -139,10 +140,10 @@ def _check(rc):
 
 
 def make_params(alpha, tol, prec=MHK_FP64, J=3, delta=0.0, dx=0.0, batch=1, upsamp=0.0, wspread=0, local_order=1,
-                lv_block=0, lv_bch=0, in64=0, v_levels=0):
+                lv_block=0, lv_bch=0, in64=0, v_levels=0, lv_persist=0):
     return Params(float(alpha), float(tol), int(prec), int(J), float(delta), float(dx), int(batch),
-                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch), int(v_levels),
-                  int(in64))
+                  float(upsamp), int(wspread), int(local_order), int(lv_block), int(lv_bch), int(lv_persist),
+                  int(v_levels), int(in64))
 
 
 def resolve_params(**kw):

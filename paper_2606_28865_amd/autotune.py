@@ -13,8 +13,8 @@ terms amplify through the density's second derivative): a candidate is
 admissible when its relative max-norm difference to the reference is below
 the tolerance for S, D and V.  The fastest admissible candidate wins.
 Then, on that grid, the level-sum tile shapes (lv_block 256 or 512 targets
-per workgroup; lv_bch 2, 4 or 8 densities per pass when batch > 1) are timed
-the same way; they change only the order of the sums, so their results are
+per workgroup; lv_bch 2, 4 or 8 densities per pass when batch > 1; one persistent launch per level or one wavefront
+per work item) are timed the same way; they change only the order of the sums, so their results are
 checked against the same reference and the fastest is kept.  Results are
 cached in a JSON file keyed by the problem's sizes and parameters.
 
@@ -51,9 +51,9 @@ def _rel(a, b):
 
 
 def tile_candidates(batch):
-    """(lv_block, lv_bch) pairs tried on the chosen grid."""
+    """(lv_block, lv_bch, lv_persist) triples tried on the chosen grid."""
     bchs = (1,) if batch == 1 else tuple(b for b in (2, 4, 8) if b <= max(2, batch))
-    return [(nb, bc) for nb in (256, 512) for bc in bchs]
+    return [(nb, bc, ps) for ps in (0, 1) for nb in (256, 512) for bc in bchs]
 
 
 def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, candidates=None, reps=3,
@@ -89,12 +89,14 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
     ref_plan.close()
     ins = [dev(x, dt) for x in densities]
     w0 = L.resolve_params(alpha=alpha, tol=tol, prec=prec, delta=delta)["wspread"]
-    def trial(ups, ws, lv_block=0, lv_bch=0):
+    def trial(ups, ws, lv_block=0, lv_bch=0, lv_persist=0):
         try:
             p = L.Plan(L.make_params(alpha=alpha, tol=tol, prec=prec, delta=delta, batch=batch, upsamp=ups,
-                                     wspread=ws, lv_block=lv_block, lv_bch=lv_bch), *geo, on_surface=on)
+                                     wspread=ws, lv_block=lv_block, lv_bch=lv_bch, lv_persist=lv_persist), *geo,
+                       on_surface=on)
         except L.MhkError as e:
-            return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "error": str(e)}
+            return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "lv_persist": lv_persist,
+                    "error": str(e)}
         out = p.eval(*ins)
         torch.cuda.synchronize()
         err = max(_rel(o[0], r[0]) for o, r in zip(out, ref))
@@ -109,10 +111,10 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
         p.close()
         del out
         if log:
-            log(f"autotune alpha={alpha} ups={ups} w={ws} lv_block={lv_block} lv_bch={lv_bch}: {ms:.3f} ms, "
-                f"err {err:.2e}, n {info['n_fine']}")
-        return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "ms": ms, "err": err,
-                "n_fine": info["n_fine"]}
+            log(f"autotune alpha={alpha} ups={ups} w={ws} lv_block={lv_block} lv_bch={lv_bch} "
+                f"lv_persist={lv_persist}: {ms:.3f} ms, err {err:.2e}, n {info['n_fine']}")
+        return {"upsamp": ups, "wspread": ws, "lv_block": lv_block, "lv_bch": lv_bch, "lv_persist": lv_persist,
+                "ms": ms, "err": err, "n_fine": info["n_fine"]}
 
     table = [trial(ups, max(4, min(16, w0 + dw))) for ups, dw in cands]
     ok = [c for c in table if "ms" in c and c["err"] < tol]
@@ -121,12 +123,13 @@ def tune(geometry, alpha, tol, prec, densities, dx=0.0, delta=0.0, batch=1, cand
     best = min(ok, key=lambda c: c["ms"])
     tile_table = []
     if tiles:
-        tile_table = [trial(best["upsamp"], best["wspread"], nb, bc) for nb, bc in tile_candidates(batch)]
+        tile_table = [trial(best["upsamp"], best["wspread"], nb, bc, ps) for nb, bc, ps in tile_candidates(batch)]
         ok2 = [c for c in tile_table if "ms" in c and c["err"] < tol]
         if ok2:
             best = min(ok2 + [best], key=lambda c: c["ms"])
     res = {"upsamp": best["upsamp"], "wspread": best["wspread"], "lv_block": best["lv_block"],
-           "lv_bch": best["lv_bch"], "ms": best["ms"], "err": best["err"], "table": table,
+           "lv_bch": best["lv_bch"], "lv_persist": best["lv_persist"], "ms": best["ms"], "err": best["err"],
+           "table": table,
            "tile_table": tile_table, "delta": delta}
     if cache:
         try:

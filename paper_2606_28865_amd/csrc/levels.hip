@@ -94,6 +94,8 @@ struct LevelArgs {
     T *acc_s, *acc_d;     // [B][nout] each (sorted order)
     int want_s, want_d;
     int init;             // store (first level) instead of add
+    int64_t n_wave;       // wavefront lists (persistent launch: work items n_wave x density chunks)
+    int *counter;         // persistent launch: next work item, zero at the launch
 };
 
 
@@ -215,26 +217,18 @@ __device__ inline void horner1(const PairGeo<double> &g, double &ks, double &kd)
     }
 }
 
-template <int BCH, typename T, int STRIDE, int NB>
-__global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
+// One work item: the LV_WAVE targets of wavefront list `wave` against its
+// candidate sources, for the densities of chunk `chunk` (BCH of them).
+template <int BCH, typename T, int STRIDE>
+__device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, int lane, int wave, int chunk)
 {
-    extern __shared__ double lds[];
-    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg + 1][STRIDE], the last segment zero
-    const int tid = threadIdx.x;
-    for (int i = tid; i < (A.nseg + 1) * STRIDE; i += NB) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
-    __syncthreads();
-
-    const int lane = tid % LV_WAVE;
-    // one wavefront = LV_WAVE consecutive targets with their own source list
-    // (the wave number is wave-uniform)
-    const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (NB / LV_WAVE) + tid / LV_WAVE]);
     const int64_t t = (int64_t)wave * LV_WAVE + lane;
     double x = 0.0, y = 0.0;
     if (t < A.nout) {
         x = A.tx[t];
         y = A.ty[t];
     }
-    const int b0 = blockIdx.y * BCH, nbh = min(BCH, A.B - b0);
+    const int b0 = chunk * BCH, nbh = min(BCH, A.B - b0);
     // segment coordinate f = a seg_inv = r^2 inv4d seg_inv in one product
     const T fscale = (T)(A.inv4d * A.seg_inv), f_max = (T)(A.a_max * A.seg_inv);
     const int zseg = A.nseg;
@@ -321,6 +315,40 @@ __global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
     }
 }
 
+// The kernel table is loaded into LDS once per workgroup.  PERSIST = false:
+// one work item per wavefront (wave list from the launch position, density
+// chunk from blockIdx.y).  PERSIST = true: a grid sized to fill the device
+// once; every wavefront takes work items (list-major: the density chunks of
+// one list follow each other, so its candidates stay in cache) from a
+// counter in device memory, zeroed before the launch, until none is left --
+// the exit every wavefront reaches.
+template <int BCH, typename T, int STRIDE, int NB, bool PERSIST>
+__global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
+{
+    extern __shared__ double lds[];
+    T *s_tab = reinterpret_cast<T *>(lds);                // [nseg + 1][STRIDE], the last segment zero
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (A.nseg + 1) * STRIDE; i += NB) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
+    __syncthreads();
+    const int lane = tid % LV_WAVE;
+    if (!PERSIST) {
+        // the wave number is wave-uniform
+        const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (NB / LV_WAVE) + tid / LV_WAVE]);
+        level_item<BCH, T, STRIDE>(A, s_tab, lane, wave, blockIdx.y);
+        return;
+    }
+    const int nchunk = (A.B + BCH - 1) / BCH;
+    const int64_t nitems = A.n_wave * nchunk;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(A.counter, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        if (item >= nitems) break;
+        const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[item / nchunk]);
+        level_item<BCH, T, STRIDE>(A, s_tab, lane, wave, item % nchunk);
+    }
+}
+
 template <typename T>
 static hipError_t level_q(mhk_plan *P, hipStream_t st, int j, const void *sigma, const void *mu)
 {
@@ -337,25 +365,38 @@ hipError_t launch_level_densities(mhk_plan *P, hipStream_t st, int j, const void
     return P->p.prec == MHK_FP64 ? level_q<double>(P, st, j, sigma, mu) : level_q<float>(P, st, j, sigma, mu);
 }
 
-template <int BCH, typename T, int STRIDE, int NB>
+template <int BCH, typename T, int STRIDE, int NB, bool PERSIST>
 static void level_launch(const LevelArgs<T> &A, dim3 grid, size_t lds, hipStream_t st)
 {
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_level_sums<BCH, T, STRIDE, NB>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_level_sums<BCH, T, STRIDE, NB>), grid, dim3(NB), lds, st, A);
+    const void *fn = (const void *)k_level_sums<BCH, T, STRIDE, NB, PERSIST>;
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (PERSIST) {
+        // as many workgroups as are resident at once, at most one per item
+        int per_cu = 0, dev = 0, ncu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NB, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+        const int64_t items = A.n_wave * grid.y;
+        const int64_t wg = std::min<int64_t>((int64_t)per_cu * std::max(ncu, 1), (items + NB / LV_WAVE - 1) / (NB / LV_WAVE));
+        grid = dim3((unsigned)std::max<int64_t>(1, wg), 1u);
+    }
+    hipLaunchKernelGGL((k_level_sums<BCH, T, STRIDE, NB, PERSIST>), grid, dim3(NB), lds, st, A);
 }
 
 template <int BCH, typename T, int STRIDE>
-static void level_launch_nb(int nb, const LevelArgs<T> &A, int64_t nwave, size_t lds, hipStream_t st, int nbatch)
+static void level_launch_nb(int nb, bool persist, const LevelArgs<T> &A, int64_t nwave, size_t lds, hipStream_t st,
+                            int nbatch)
 {
     // exactly nwave wavefronts (the lists are padded to whole workgroups of
     // either shape), the batch in chunks of BCH along y
     const dim3 grid((unsigned)(nwave / (nb / LV_WAVE)), (unsigned)nbatch);
-    if (nb == 512)
-        level_launch<BCH, T, STRIDE, 512>(A, grid, lds, st);
-    else
-        level_launch<BCH, T, STRIDE, 256>(A, grid, lds, st);
+    if (nb == 512) {
+        if (persist) level_launch<BCH, T, STRIDE, 512, true>(A, grid, lds, st);
+        else level_launch<BCH, T, STRIDE, 512, false>(A, grid, lds, st);
+    } else {
+        if (persist) level_launch<BCH, T, STRIDE, 256, true>(A, grid, lds, st);
+        else level_launch<BCH, T, STRIDE, 256, false>(A, grid, lds, st);
+    }
 }
 
 template <typename T, int STRIDE>
@@ -395,11 +436,18 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int nb = P->p.lv_block;
+    const bool pers = P->p.lv_persist != 0;
+    A.n_wave = L.n_wave;
+    A.counter = P->lv_counter;
+    if (pers) {
+        const hipError_t e = launch_fill_int(P->lv_counter, 1, st);
+        if (e != hipSuccess) return e;
+    }
     switch (bch) {
-    case 1: level_launch_nb<1, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
-    case 2: level_launch_nb<2, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
-    case 4: level_launch_nb<4, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
-    default: level_launch_nb<8, T, STRIDE>(nb, A, L.n_wave, lds, st, nby); break;
+    case 1: level_launch_nb<1, T, STRIDE>(nb, pers, A, L.n_wave, lds, st, nby); break;
+    case 2: level_launch_nb<2, T, STRIDE>(nb, pers, A, L.n_wave, lds, st, nby); break;
+    case 4: level_launch_nb<4, T, STRIDE>(nb, pers, A, L.n_wave, lds, st, nby); break;
+    default: level_launch_nb<8, T, STRIDE>(nb, pers, A, L.n_wave, lds, st, nby); break;
     }
     return hipGetLastError();
 }
@@ -441,11 +489,18 @@ static hipError_t level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init)
     const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int nb = P->p.lv_block;
+    const bool pers = P->p.lv_persist != 0;
+    A.n_wave = V.n_wave;
+    A.counter = P->lv_counter;
+    if (pers) {
+        const hipError_t e = launch_fill_int(P->lv_counter, 1, st);
+        if (e != hipSuccess) return e;
+    }
     switch (bch) {
-    case 1: level_launch_nb<1, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
-    case 2: level_launch_nb<2, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
-    case 4: level_launch_nb<4, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
-    default: level_launch_nb<8, T, STRIDE>(nb, A, V.n_wave, lds, st, nby); break;
+    case 1: level_launch_nb<1, T, STRIDE>(nb, pers, A, V.n_wave, lds, st, nby); break;
+    case 2: level_launch_nb<2, T, STRIDE>(nb, pers, A, V.n_wave, lds, st, nby); break;
+    case 4: level_launch_nb<4, T, STRIDE>(nb, pers, A, V.n_wave, lds, st, nby); break;
+    default: level_launch_nb<8, T, STRIDE>(nb, pers, A, V.n_wave, lds, st, nby); break;
     }
     return hipGetLastError();
 }

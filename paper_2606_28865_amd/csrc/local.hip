@@ -757,6 +757,13 @@ __global__ void k_zero(uint32_t *p, int64_t n)
     if (i < n) p[i] = 0u;
 }
 
+hipError_t launch_fill_int(int *p, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n)
 {
     const int64_t words = n * (int64_t)P->es / 4;

@@ -220,6 +220,7 @@ struct mhk_plan {
     hipStream_t stream = nullptr;
     bool timing = false;
     int bat = 1;                                 // densities of the evaluation being enqueued (<= p.batch)
+    int *lv_counter = nullptr;                   // work-item counter of the persistent level sums
     float *in32 = nullptr;                       // FP32 plans with in64: [batch][2 N_B + N_V] rounded inputs
     int64_t nb = 0, npan = 0, nv = 0, nt = 0, nout = 0;
     bool targets_are_volume = false;            // targets == volume nodes, same order
@@ -276,6 +277,7 @@ hipError_t launch_columns(mhk_plan *P);
 hipError_t launch_rows(mhk_plan *P, bool inverse);
 hipError_t launch_interp(mhk_plan *P, bool want_s, bool want_d, bool want_v);
 hipError_t launch_fill(mhk_plan *P, void *p, int64_t n);
+hipError_t launch_fill_int(int *p, int64_t n, hipStream_t st);   // zero n ints on st (a kernel, graph-safe)
 hipError_t launch_round32(mhk_plan *P, const void *x, void *y, int64_t n);
 hipError_t launch_fjets(mhk_plan *P, const void *f_vol, void *out);
 hipError_t dev_fj_nearest_pts(mhk_plan *P, int64_t n, const double *px, const double *py, const int32_t *parent,

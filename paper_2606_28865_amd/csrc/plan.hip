@@ -233,6 +233,10 @@ static mhk_status resolve(const mhk_params *pp, mhk_info *I, mhk_params *out)
         set_error("lv_block must be 0, 256 or 512");
         return MHK_EINVAL;
     }
+    if (p.lv_persist != 0 && p.lv_persist != 1) {
+        set_error("lv_persist must be 0 or 1");
+        return MHK_EINVAL;
+    }
     if (p.lv_bch == 0) p.lv_bch = 4;
     if (p.lv_bch != 1 && p.lv_bch != 2 && p.lv_bch != 4 && p.lv_bch != 8) {
         set_error("lv_bch must be 0, 1, 2, 4 or 8");
@@ -1624,6 +1628,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
         TRY(dalloc(P, &l, 2 * (int64_t)P->p.batch * P->nout * (int64_t)P->es));
         P->acc_lev = l;
         if (P->p.in64) TRY(dalloc(P, &P->in32, (int64_t)P->p.batch * (2 * P->nb + P->nv)));
+        TRY(dalloc(P, &P->lv_counter, 1));
     }
     for (auto &e : P->ev) MHK_HIP(hipEventCreate(&e));
     MHK_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));

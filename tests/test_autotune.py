@@ -25,8 +25,8 @@ def test_cache_key_and_hit(tmp_path):
                 autotune._key(geo, 10.0, 1e-10, 1, 1), autotune._key(geo, 10.0, 1e-6, 0, 1),
                 autotune._key(geo, 10.0, 1e-6, 1, 1, tiles=False)}) == 6
     # tile shapes tried on the chosen grid: densities per pass only with a batch
-    assert autotune.tile_candidates(1) == [(256, 1), (512, 1)]
-    assert autotune.tile_candidates(64) == [(n, b) for n in (256, 512) for b in (2, 4, 8)]
+    assert autotune.tile_candidates(1) == [(n, 1, p) for p in (0, 1) for n in (256, 512)]
+    assert autotune.tile_candidates(64) == [(n, b, p) for p in (0, 1) for n in (256, 512) for b in (2, 4, 8)]
     entry = {"upsamp": 1.5, "wspread": 9, "ms": 1.0, "err": 1e-7, "table": [], "delta": 1e-3}
     cache = tmp_path / "tune.json"
     cache.write_text(json.dumps({k1: entry}))
@@ -49,9 +49,10 @@ def test_tuned_plan_matches_oracle():
     ok = [c for c in res["table"] + res["tile_table"] if "ms" in c and c["err"] < tol]
     assert ok and res["err"] < tol
     assert res["ms"] == min(c["ms"] for c in ok)
-    assert len(res["tile_table"]) == 2
+    assert len(res["tile_table"]) == 4
     prm = M.make_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, delta=res["delta"], upsamp=res["upsamp"],
-                        wspread=res["wspread"], lv_block=res["lv_block"], lv_bch=res["lv_bch"])
+                        wspread=res["wspread"], lv_block=res["lv_block"], lv_bch=res["lv_bch"],
+                        lv_persist=res["lv_persist"])
     plan = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
     f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
     out = plan.eval(f32(w.sigma), f32(w.mu), f32(w.f_vol), f32(w.f_trg))

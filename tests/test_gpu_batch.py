@@ -137,3 +137,34 @@ def test_fewer_densities_than_the_batch(prec):
     for k in range(B):
         for o, r in zip(gout, ref[k]):
             assert rel_err(o[k].cpu().numpy(), r) < lim
+
+
+def test_persistent_level_sums_graph_replay():
+    """The persistent level-sum launch (its work counter zeroed by a kernel
+    before each launch) inside a captured graph, replayed with new inputs,
+    equals eager evaluations of a non-persistent plan."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    B = 3
+    print("case persistent level sums under graph replay", flush=True)
+    mk = lambda ps: M.Plan(M.make_params(alpha=10.0, tol=1e-10, dx=w.dx, batch=B, lv_persist=ps), w.boundary,
+                           w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    plan, ref = mk(1), mk(0)
+    sig = torch.zeros((B, w.n_b), dtype=torch.float64, device="cuda")
+    mu = torch.zeros_like(sig)
+    fv = torch.zeros((B, w.n_v), dtype=torch.float64, device="cuda")
+    ft = torch.zeros((B, w.n_t + w.n_b), dtype=torch.float64, device="cuda")
+    out = plan.capture(sig, mu, fv, ft)
+    g = np.random.default_rng(5)
+    for rep in range(3):
+        sig.copy_(_t(np.stack([w.sigma * g.uniform(0.5, 1.5) for _ in range(B)])))
+        mu.copy_(_t(np.stack([w.mu * g.uniform(0.5, 1.5) for _ in range(B)])))
+        fv.copy_(_t(np.stack([w.f_vol * (k + 1) for k in range(B)])))
+        ft.copy_(_t(np.stack([w.f_trg * (k + 1) for k in range(B)])))
+        torch.cuda.synchronize()
+        plan.replay()
+        torch.cuda.synchronize()
+        e = ref.eval(sig, mu, fv, ft)
+        torch.cuda.synchronize()
+        for a, b in zip(out, e):
+            assert rel_err(a.cpu().numpy(), b.cpu().numpy()) < 1e-13, rep

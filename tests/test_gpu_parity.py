@@ -147,7 +147,7 @@ def test_batch_matches_single(cfg0):
 @pytest.mark.parametrize("lv_block", [256, 512])
 def test_level_tile_shapes(cfg0, lv_block):
     """Every tile shape of the level sums (targets per workgroup, densities
-    per pass) gives the same S and D, up to the order of the sums: five
+    per pass, persistent launch or not) gives the same S and D, up to the order of the sums: five
     densities through each shape against one single-density plan, the last
     density against the oracle."""
     w = cfg0
@@ -157,13 +157,13 @@ def test_level_tile_shapes(cfg0, lv_block):
     mu = np.stack([w.mu * (1 - 0.2 * k) for k in range(B)])
     single = _plan(w, 10.0)
     ref = [_run(single, w, sig[k], mu[k], None, None, parts=O.PART_LEVELS)[:2] for k in range(B)]
-    for bch in (1, 2, 4, 8):
-        print(f"case level tiles lv_block={lv_block} lv_bch={bch}", flush=True)
-        plan = _plan(w, 10.0, batch=B, lv_block=lv_block, lv_bch=bch)
+    for bch, pers in [(b, p) for p in (0, 1) for b in (1, 2, 4, 8)]:
+        print(f"case level tiles lv_block={lv_block} lv_bch={bch} lv_persist={pers}", flush=True)
+        plan = _plan(w, 10.0, batch=B, lv_block=lv_block, lv_bch=bch, lv_persist=pers)
         S, D, _ = _run(plan, w, sig, mu, np.zeros((B, w.n_v)), np.zeros((B, w.n_t + w.n_b)), parts=O.PART_LEVELS,
                        batch=B)
         for k in range(B):
-            assert rel_err(S[k], ref[k][0][0]) < 1e-13 and rel_err(D[k], ref[k][1][0]) < 1e-13, (bch, k)
+            assert rel_err(S[k], ref[k][0][0]) < 1e-13 and rel_err(D[k], ref[k][1][0]) < 1e-13, (bch, pers, k)
         plan.close()
     plan = _plan(w, 10.0, batch=B, lv_block=lv_block, lv_bch=4)
     S, D, V = _run(plan, w, sig, mu, np.stack([w.f_vol] * B), np.stack([w.f_trg] * B), batch=B)
