@@ -38,6 +38,8 @@ def parse():
                     help="outputs per stratum and alpha of the parity check against the oracle")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the parity check and the CPU baseline (profiling runs only)")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 half of the metric (its 4M-target workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device-to-device 4 times (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="multibody",
@@ -189,6 +191,16 @@ def main():
     if not a.no_check:
         check, cpu = parity_check(w, infos, alphas, outs, a.check_each)
 
+    # the FP32 half of the metric (tol 1e-6) on its own workload, after the
+    # FP64 plans are released
+    fp32 = None
+    if not a.no_fp32:
+        for p in plans:
+            p.close()
+        del outs
+        torch.cuda.empty_cache()
+        fp32 = fp32_half(a, precision_workload())
+
     line = {
         "metric": "target evals/s at rel err 1e-10 (FP64) vs 1e-6 (FP32); p50/p99 request latency",
         "value": value,
@@ -219,12 +231,19 @@ def main():
         "rel_err_vs_oracle": check,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fp32": fp32,
+        "latency_note": "p50/p99 request latency: bench.py --workload serve",
     }
     print(json.dumps(line), flush=True)
     if check is not None:
         worst = max(v for per in check["alpha"].values() for v in per.values())
         if not worst <= a.tol:
             log(f"parity FAILED: max relative error {worst:.3e} > {a.tol:g}")
+            sys.exit(1)
+    if fp32 is not None and "rel_err_vs_oracle_fp64_inputs" in fp32:
+        worst = max(fp32["rel_err_vs_oracle_fp64_inputs"].values())
+        if not worst <= fp32["bar"]:
+            log(f"FP32 parity FAILED: max relative error {worst:.3e} > {fp32['bar']:g}")
             sys.exit(1)
 
 
@@ -420,16 +439,63 @@ def _sample_errors(w, info, alpha, outs, n_each=12, seed=3, round32=False):
     return errs, dt
 
 
+def precision_workload():
+    import synth
+    t0 = time.time()
+    w = synth.multibody(cfg=2, n_boundary=65536, n_volume=4_000_000, n_targets=4_000_000, alphas=(30.0,), tol=1e-6)
+    log(f"workload {w.name} generated in {time.time() - t0:.1f} s")
+    return w
+
+
+def fp32_half(a, w):
+    """The FP32 half of the headline metric: the FP32 path (FP64 densities,
+    in64) at tol 1e-6 on the precision workload (65536 boundary nodes, ~4M
+    volume nodes, 4M targets, alpha = 30), its rate and its error against
+    the FP64 oracle on the same FP64 inputs (stratified sample)."""
+    import torch
+
+    import paper_2606_28865_amd as M
+    alpha, tol = 30.0, 1e-6
+    d64 = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    ins = (d64(w.sigma), d64(w.mu), d64(w.f_vol), d64(w.f_trg))
+    t1 = time.time()
+    p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, dx=w.dx, in64=1), w.boundary, w.volume,
+               (w.tx, w.ty, w.inside), on_surface=True)
+    plan_s = time.time() - t1
+    out = p.eval(*ins)
+    for _ in range(a.warmup):
+        p.eval(*ins, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.steps):
+        p.eval(*ins, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    info = p.info()
+    res = {"workload": "multibody-precision", "n_boundary": w.n_b, "n_volume": w.n_v, "n_targets": w.n_t,
+           "alpha": alpha, "tol": tol, "inputs": "FP64 (in64)", "ms_per_eval": ms,
+           "target_evals_per_s": p.n_out / (ms * 1e-3), "grid": info["n_fine"], "plan_s": round(plan_s, 3)}
+    if not a.no_check:
+        errs, _ = _sample_errors(w, info, alpha, out, n_each=6)
+        res["rel_err_vs_oracle_fp64_inputs"] = {"S": errs[0], "D": errs[1], "V": errs[2]}
+        res["bar"] = tol
+    log(f"fp32 half: {ms:.3f} ms per eval, {res['target_evals_per_s']:.3e} target-evals/s, "
+        f"errors {res.get('rel_err_vs_oracle_fp64_inputs')}")
+    p.close()
+    del ins, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_precision(a):
     """FP32 vs FP64 at tol 1e-6 on the multi-body generator at 65536
     boundary nodes, ~4M volume nodes and 4M targets, alpha = 30."""
     import torch
 
     import paper_2606_28865_amd as M
-    import synth
-    t0 = time.time()
-    w = synth.multibody(cfg=2, n_boundary=65536, n_volume=4_000_000, n_targets=4_000_000, alphas=(30.0,), tol=1e-6)
-    log(f"workload {w.name} generated in {time.time() - t0:.1f} s")
+    w = precision_workload()
     alpha, tol = 30.0, 1e-6
     res = {}
     for prec, dt, name in ((M.MHK_FP32, torch.float32, "fp32"), (M.MHK_FP64, torch.float64, "fp64")):

@@ -175,21 +175,22 @@ __global__ void __launch_bounds__(BT) k_scan_apply(const int32_t *__restrict__ i
     if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
 }
 
-// first index of each key in a sorted key array: start[c] for c in [0, nkeys]
+// first index of each key in a sorted key array: start[c] for c in [0, nkeys],
+// the lower bound of c by binary search (one thread per cell)
 __global__ void __launch_bounds__(BT) k_cell_starts(const uint32_t *__restrict__ keys, int64_t n, int64_t nkeys,
                                                     int32_t *__restrict__ start)
 {
-    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    if (n == 0) {
-        for (int64_t c = i; c <= nkeys; c += (int64_t)gridDim.x * BT) start[c] = 0;
-        return;
+    for (int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x; c <= nkeys; c += (int64_t)gridDim.x * BT) {
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)keys[mid] < c)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        start[c] = (int32_t)lo;
     }
-    if (i >= n) return;
-    const int64_t k = keys[i];
-    const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
-    for (int64_t c = kp + 1; c <= k; ++c) start[c] = (int32_t)i;
-    if (i == n - 1)
-        for (int64_t c = k + 1; c <= nkeys; ++c) start[c] = (int32_t)n;
 }
 
 __global__ void __launch_bounds__(BT) k_iota(int32_t *__restrict__ v, int64_t n)
@@ -255,8 +256,8 @@ hipError_t dev_scan(const int32_t *in, int32_t *out, int64_t n, int64_t *total, 
 
 hipError_t dev_cell_starts(const uint32_t *keys, int64_t n, int64_t nkeys, int32_t *start, hipStream_t st)
 {
-    const int64_t work = n == 0 ? nkeys + 1 : n;
-    hipLaunchKernelGGL(k_cell_starts, dim3(nblocks(work, BT)), dim3(BT), 0, st, keys, n, nkeys, start);
+    const unsigned nbk = (unsigned)std::min<int64_t>(65536, nblocks(nkeys + 1, BT));
+    hipLaunchKernelGGL(k_cell_starts, dim3(nbk), dim3(BT), 0, st, keys, n, nkeys, start);
     return hipGetLastError();
 }
 
