@@ -151,7 +151,13 @@ typedef struct {
 typedef struct {
     int64_t n;                        /* N_T off-surface targets (may be 0)         */
     const double *x, *y;              /* host [N_T]                                  */
-    const int8_t *inside;             /* host [N_T], 1 inside Omega, 0 outside       */
+    const int8_t *inside;             /* host [N_T], 1 inside Omega, 0 outside; or NULL:
+                                         computed at plan creation as the parity of the
+                                         crossings of a ray with the boundary curves (the
+                                         polygon through each panel's end points and nodes,
+                                         corrected between each edge and the panel's
+                                         interpolated arc); targets on the curve itself,
+                                         to rounding, may fall on either side           */
     int on_surface;                   /* 1: append the N_B boundary nodes as targets */
 } mhk_targets;
 

@@ -183,7 +183,8 @@ def _structs(boundary, volume, targets, on_surface, keep):
         V = Volume(0, None, None, None, 0, None)
     if targets is not None:
         tx, ty, ins = targets
-        T = Targets(len(tx), keep.f64(tx), keep.f64(ty), keep.typed(np.asarray(ins).astype(np.int8), np.int8),
+        T = Targets(len(tx), keep.f64(tx), keep.f64(ty),
+                    None if ins is None else keep.typed(np.asarray(ins).astype(np.int8), np.int8),
                     int(bool(on_surface)))
     else:
         T = Targets(0, None, None, None, int(bool(on_surface)))
@@ -203,7 +204,8 @@ class Plan:
 
     boundary: dict of host arrays x, y, nx, ny, w, kappa (16 Gauss-Legendre
     nodes per panel, panel contiguous) and curve_panel_ofs; volume: dict x, y,
-    w or None; targets: (x, y, inside) host arrays.
+    w or None; targets: (x, y, inside) host arrays, inside None to have the
+    plan compute it.
     """
 
     def __init__(self, params: Params, boundary, volume=None, targets=None, on_surface=False, stream=None):

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhk.so")
-SOURCES = ["plan.hip", "bin.hip", "levels.hip", "local.hip", "history.hip", "bie.hip", "fjets.hip", "vlevels.hip"]
+SOURCES = ["plan.hip", "bin.hip", "levels.hip", "local.hip", "history.hip", "bie.hip", "fjets.hip", "vlevels.hip",
+           "mask.hip"]
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:

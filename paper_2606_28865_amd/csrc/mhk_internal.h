@@ -308,6 +308,23 @@ hipError_t dev_sort_pairs(uint32_t *keys, int32_t *vals, int64_t n, int bits, hi
 hipError_t dev_scan(const int32_t *in, int32_t *out, int64_t n, int64_t *total, hipStream_t st);
 // start[c], c in [0, nkeys]: first index of key c in a sorted key array.
 hipError_t dev_cell_starts(const uint32_t *keys, int64_t n, int64_t nkeys, int32_t *start, hipStream_t st);
+// Inside mask of n targets (caller order) from the polygon through the
+// panels' end points and nodes, corrected in the lunes between its edges and
+// the panels' arcs; edges listed per horizontal strip.
+struct MaskArgs {
+    int64_t n;
+    const double *tx, *ty;
+    double ylo, yhi, hinv;
+    int nstrip;
+    const int32_t *strip_start, *strip_edge;   // [nstrip + 1], edge indices
+    const double *edge;                        // [E][4]: x0, y0, x1, y1
+    const double *sag;                         // [E]: arc-to-chord bound, 0 for no lune
+    const int32_t *edge_pan;                   // [E]: panel of the arc
+    const double *edge_t;                      // [E][2]: panel parameters of the edge's ends
+    const double *bx, *by;                     // boundary nodes [N_B]
+    const double *gl_t, *lam;                  // Gauss-Legendre nodes and barycentric weights [16]
+};
+hipError_t dev_inside_mask(const MaskArgs &A, int8_t *out, hipStream_t st);
 // Targets sorted by the Morton key of cells of side hh from (ox, oy).
 hipError_t dev_sort_targets(const double *x, const double *y, const int8_t *in, int64_t n, double ox, double oy,
                             double hh, double *sx, double *sy, int8_t *sin, int32_t *sidx, hipStream_t st);

@@ -447,6 +447,11 @@ struct Host {
     // all targets (off-surface then boundary), in output order
     std::vector<double> tx, ty;
     std::vector<int8_t> tin;
+    bool mask_needed = false;          // no caller mask: computed on the device
+    // host side of the computed mask (kept until plan creation ends, as the
+    // uploads read them asynchronously)
+    std::vector<double> m_edge, m_sag, m_et, m_glt, m_lam;
+    std::vector<int32_t> m_pan, m_start, m_list;
 };
 
 mhk_status check_inputs(const mhk_params *p, const mhk_boundary *b, const mhk_volume *v,
@@ -500,7 +505,7 @@ mhk_status check_inputs(const mhk_params *p, const mhk_boundary *b, const mhk_vo
                 return MHK_EINVAL;
             }
     }
-    if (!t || t->n < 0 || (t->n > 0 && (!t->x || !t->y || !t->inside))) {
+    if (!t || t->n < 0 || (t->n > 0 && (!t->x || !t->y))) {
         set_error("targets missing");
         return MHK_EINVAL;
     }
@@ -548,8 +553,9 @@ void host_common(Host &H)
     for (int64_t i = 0; i < nt; ++i) {
         H.tx[i] = H.t->x[i];
         H.ty[i] = H.t->y[i];
-        H.tin[i] = H.t->inside[i] ? 1 : 0;
+        H.tin[i] = H.t->inside ? (H.t->inside[i] ? 1 : 0) : 0;
     }
+    H.mask_needed = nt > 0 && !H.t->inside;
     for (int64_t i = nt; i < nout; ++i) {
         H.tx[i] = b->x[i - nt];
         H.ty[i] = b->y[i - nt];
@@ -565,6 +571,128 @@ void host_common(Host &H)
         for (int64_t i = 0; i < H.v->n; ++i) acc(H.v->x[i], H.v->y[i]);
     for (int64_t i = 0; i < nout; ++i) acc(H.tx[i], H.ty[i]);
     H.xmin = x0; H.xmax = x1; H.ymin = y0; H.ymax = y1;
+}
+
+// Inside mask of the off-surface targets when the caller passes none: the
+// polygon through every panel's end points and 16 nodes, closed along each
+// curve, with a bound of each edge's arc-to-chord deviation for the lune
+// correction, edges listed per horizontal strip; the kernel writes the mask
+// of the first N_T entries of rin (caller order).
+static mhk_status build_mask(mhk_plan *P, Host &H, StreamTmp &tmp, int8_t *rin)
+{
+    const mhk_boundary *b = H.b;
+    const int64_t npan = b->n_panels;
+    std::vector<double> row(NGL);
+    auto eval = [&](int64_t p, double t, double &x, double &y) {
+        lagrange_row(H.gl_t, H.bary, t, row.data());
+        x = y = 0;
+        for (int i = 0; i < NGL; ++i) {
+            x += row[i] * b->x[p * NGL + i];
+            y += row[i] * b->y[p * NGL + i];
+        }
+    };
+    // per panel: vertices gamma(-1), nodes, gamma(1); the edges between them
+    // carry lunes; gamma_p(1) -> gamma_next(-1) closes the gap between panels
+    std::vector<double> &E = H.m_edge, &SG = H.m_sag, &ET = H.m_et;
+    std::vector<int32_t> &EP = H.m_pan;
+    std::vector<double> ends(npan * 4);
+    for (int64_t p = 0; p < npan; ++p) {
+        eval(p, -1.0, ends[p * 4 + 0], ends[p * 4 + 1]);
+        eval(p, 1.0, ends[p * 4 + 2], ends[p * 4 + 3]);
+    }
+    const int64_t nedge = npan * (NGL + 2);
+    E.reserve(nedge * 4);
+    SG.reserve(nedge);
+    ET.reserve(nedge * 2);
+    EP.reserve(nedge);
+    double ylo = 1e300, yhi = -1e300;
+    for (int64_t p = 0; p < npan; ++p) {
+        double vx[NGL + 2], vy[NGL + 2], vt[NGL + 2];
+        vx[0] = ends[p * 4 + 0]; vy[0] = ends[p * 4 + 1]; vt[0] = -1.0;
+        for (int i = 0; i < NGL; ++i) {
+            vx[i + 1] = b->x[p * NGL + i];
+            vy[i + 1] = b->y[p * NGL + i];
+            vt[i + 1] = H.gl_t[i];
+        }
+        vx[NGL + 1] = ends[p * 4 + 2]; vy[NGL + 1] = ends[p * 4 + 3]; vt[NGL + 1] = 1.0;
+        for (int k = 0; k <= NGL + 1; ++k) {
+            double x0, y0, x1, y1, sag = 0.0, t0 = 0.0, t1 = 0.0;
+            if (k <= NGL) {
+                x0 = vx[k]; y0 = vy[k]; x1 = vx[k + 1]; y1 = vy[k + 1];
+                t0 = vt[k]; t1 = vt[k + 1];
+                // the arc's largest distance from the chord at 15 interior
+                // points, doubled, plus a rounding margin
+                const double ex = x1 - x0, ey = y1 - y0, l = std::hypot(ex, ey);
+                double dev = 0.0;
+                for (int m = 1; m < 16; ++m) {
+                    double ax, ay;
+                    eval(p, t0 + (t1 - t0) * m / 16.0, ax, ay);
+                    dev = std::max(dev, std::fabs(ex * (ay - y0) - ey * (ax - x0)) / l);
+                }
+                sag = 2.0 * dev + 1e-14 * (std::fabs(x0) + std::fabs(y0) + l);
+            } else {
+                const int64_t q = H.next[p];
+                x0 = vx[NGL + 1]; y0 = vy[NGL + 1]; x1 = ends[q * 4 + 0]; y1 = ends[q * 4 + 1];
+            }
+            E.insert(E.end(), {x0, y0, x1, y1});
+            SG.push_back(sag);
+            ET.push_back(t0);
+            ET.push_back(t1);
+            EP.push_back((int32_t)p);
+            ylo = std::min(ylo, std::min(y0, y1) - sag);
+            yhi = std::max(yhi, std::max(y0, y1) + sag);
+        }
+    }
+    const int64_t ne = (int64_t)SG.size();
+    const int nstrip = (int)std::max<int64_t>(1, std::min<int64_t>(1 << 20, ne / 4));
+    yhi = std::nextafter(yhi, 1e300);
+    const double hinv = nstrip / (yhi - ylo);
+    auto strip = [&](double y) { return (int64_t)std::min<double>(nstrip - 1, std::max(0.0, std::floor((y - ylo) * hinv))); };
+    std::vector<int32_t> &st = H.m_start, &li = H.m_list;
+    st.assign(nstrip + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t s0 = std::max<int64_t>(0, strip(std::min(E[e * 4 + 1], E[e * 4 + 3]) - SG[e]) - 1);
+        const int64_t s1 = std::min<int64_t>(nstrip - 1, strip(std::max(E[e * 4 + 1], E[e * 4 + 3]) + SG[e]) + 1);
+        for (int64_t s = s0; s <= s1; ++s) ++st[s + 1];
+    }
+    for (int s = 0; s < nstrip; ++s) st[s + 1] += st[s];
+    li.assign(st[nstrip], 0);
+    {
+        std::vector<int32_t> fill(st.begin(), st.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) {
+            const int64_t s0 = std::max<int64_t>(0, strip(std::min(E[e * 4 + 1], E[e * 4 + 3]) - SG[e]) - 1);
+            const int64_t s1 = std::min<int64_t>(nstrip - 1, strip(std::max(E[e * 4 + 1], E[e * 4 + 3]) + SG[e]) + 1);
+            for (int64_t s = s0; s <= s1; ++s) li[fill[s]++] = (int32_t)e;
+        }
+    }
+    H.m_glt.assign(H.gl_t.begin(), H.gl_t.end());
+    H.m_lam.resize(NGL);
+    for (int i = 0; i < NGL; ++i) H.m_lam[i] = (double)H.bary[i];
+    MaskArgs A{};
+    A.n = H.t->n;
+    A.ylo = ylo;
+    A.yhi = yhi;
+    A.hinv = hinv;
+    A.nstrip = nstrip;
+    double *tx = nullptr, *ty = nullptr, *edge = nullptr, *sag = nullptr, *et = nullptr, *bx = nullptr,
+           *by = nullptr, *glt = nullptr, *lam = nullptr;
+    int32_t *sst = nullptr, *sli = nullptr, *pan = nullptr;
+    TRY(tmp.upload(&tx, H.tx.data(), A.n));
+    TRY(tmp.upload(&ty, H.ty.data(), A.n));
+    TRY(tmp.upload(&edge, E.data(), ne * 4));
+    TRY(tmp.upload(&sag, SG.data(), ne));
+    TRY(tmp.upload(&et, ET.data(), ne * 2));
+    TRY(tmp.upload(&pan, EP.data(), ne));
+    TRY(tmp.upload(&sst, st.data(), (int64_t)st.size()));
+    TRY(tmp.upload(&sli, li.data(), (int64_t)li.size()));
+    TRY(tmp.upload(&bx, b->x, npan * NGL));
+    TRY(tmp.upload(&by, b->y, npan * NGL));
+    TRY(tmp.upload(&glt, H.m_glt.data(), NGL));
+    TRY(tmp.upload(&lam, H.m_lam.data(), NGL));
+    A.tx = tx; A.ty = ty; A.edge = edge; A.sag = sag; A.edge_t = et; A.edge_pan = pan;
+    A.strip_start = sst; A.strip_edge = sli; A.bx = bx; A.by = by; A.gl_t = glt; A.lam = lam;
+    MHK_HIP(dev_inside_mask(A, rin, P->stream));
+    return MHK_OK;
 }
 
 // Dyadic level j (Section 4.2): every panel bisected j times; child nodes are
@@ -1604,6 +1732,7 @@ mhk_status create(const mhk_params *params, const mhk_boundary *b, const mhk_vol
         TRY(tmp.upload(&rx, H.tx.data(), nout));
         TRY(tmp.upload(&ry, H.ty.data(), nout));
         TRY(tmp.upload(&rin, H.tin.data(), nout));
+        if (H.mask_needed) TRY(build_mask(P, H, tmp, rin));
         TRY(dalloc(P, &P->tx, nout));
         TRY(dalloc(P, &P->ty, nout));
         TRY(dalloc(P, &P->tin, nout));
