@@ -7,14 +7,25 @@
 //  * boundary: the caller's panel-contiguous SoA arrays, plus per-panel
 //    Legendre coefficients of x, y and kappa for the closest-point search;
 //  * dyadic level j: the N_B 2^j child nodes of the bisected panels, sorted
-//    row-major by square cells of side R_j, as SoA x/y/w nx/w ny/w, with a
+//    row-major by square cells of side R_j/4, as SoA x/y/w nx/w ny/w, with a
 //    code giving (panel, child, node) for the per-eval interpolation of the
-//    densities, and per-eval strengths q_S = w sigma, q_Dx = w nu_x mu,
-//    q_Dy = w nu_y mu in the same sorted order;
-//  * history: boundary and volume sources sorted by 32x32 tiles of the fine
-//    grid, the fine grids [4][batch][n][n+2] (S, V, D_x, D_y sources, real,
-//    rows padded for in-place real-to-complex FFTs) and the 1D factors of the
-//    Fourier multiplier.
+//    densities, per-eval strengths q_S = w sigma, q_Dx = w nu_x mu,
+//    q_Dy = w nu_y mu in the same sorted order, and per target wavefront a
+//    flat list of the child nodes within R_j of its targets;
+//  * history: per-tile lists of the boundary and volume sources whose windows
+//    meet each 32x32 tile of the fine grid, the fine grids
+//    [4][batch][n][n+2] (S, V, D_x, D_y sources, real, rows padded for
+//    in-place real-to-complex FFTs; only the rows and columns of the sources'
+//    and targets' windows are touched) and the 1D factors of the Fourier
+//    multiplier or the truncated kernel's spectrum;
+//  * local: per sorted target the closest panel, parameter and the
+//    density-independent coefficients of the local expansions;
+//  * f-jets and volume levels (6-node volume groups): per triangle the
+//    inverse of its scaled 6x6 Vandermonde and centroid/scale, per target the
+//    nearest usable triangle; per volume level the refined nodes sorted by
+//    cells, with their parent triangles and wavefront lists.
+// Everything is built on the device at plan creation, in stream order on the
+// plan's stream.
 #pragma once
 
 #include <hip/hip_runtime.h>
