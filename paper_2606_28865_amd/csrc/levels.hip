@@ -33,6 +33,8 @@
 // table's three highest coefficients, each below 4e-8 of K_j(0), as floats
 // and starts Horner's rule over them in FP32 (52 bytes of table per pair
 // instead of 64); the rest is FP64.
+#include <type_traits>
+
 #include "mhk_internal.h"
 
 namespace mhk {
@@ -127,12 +129,13 @@ struct SrcBatch {
 template <typename T>
 struct PairGeo {
     T dx, dy, v;
-    const T *c;
+    const T *c;          // the segment's row
+    const float *c7;     // FP64 table: the segment's c_7
 };
 
 template <typename T, int STRIDE>
 __device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv, T fscale, T f_max,
-                                      const T *s_tab, int zseg, bool &in)
+                                      const T *s_tab, const float *s_c7, int zseg, bool &in)
 {
     PairGeo<T> g;
     g.dx = (T)(x - sxv);
@@ -142,6 +145,7 @@ __device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv
     const int sg = in ? (int)f : zseg;
     g.v = in ? (T)2 * frac_part(f) - (T)1 : (T)0;
     g.c = s_tab + __umul24((unsigned)sg, (unsigned)STRIDE);
+    if constexpr (std::is_same<T, double>::value) g.c7 = s_c7 + sg;
     return g;
 }
 
@@ -164,24 +168,45 @@ __device__ inline void horner2(const PairGeo<float> &g0, const PairGeo<float> &g
     }
 }
 
-// FP64 table: c_0..c_4 as doubles, then c_5..c_7 as floats; the high part
-// goes through Horner's rule in FP32 and the result continues in FP64 (the
-// same order as the plan's accuracy check of the table).
-__device__ inline void horner_hi(const double *c, double v, float &ks, float &kd)
+// FP64 table row (48 bytes, 16-byte aligned): c_0..c_4 as doubles and c_5,
+// c_6 as two floats, read as three 16-byte LDS loads; c_7 (float) from the
+// array after the rows.  The high part goes through Horner's rule in FP32
+// and the result continues in FP64 (the same order as the plan's accuracy
+// check of the table).
+struct Row64 {
+    double c[TAB_NC64];
+    float c5, c6, c7;
+};
+__device__ inline Row64 load_row(const PairGeo<double> &g)
 {
-    const float *h = reinterpret_cast<const float *>(c + TAB_NC64);
+    const double2 *r = reinterpret_cast<const double2 *>(g.c);
+    const double2 a = r[0], b = r[1], h = r[2];
+    Row64 w;
+    w.c[0] = a.x;
+    w.c[1] = a.y;
+    w.c[2] = b.x;
+    w.c[3] = b.y;
+    w.c[4] = h.x;
+    w.c5 = __int_as_float(__double2loint(h.y));
+    w.c6 = __int_as_float(__double2hiint(h.y));
+    w.c7 = *g.c7;
+    return w;
+}
+__device__ inline void horner_hi(const Row64 &w, double v, float &ks, float &kd)
+{
     const float vf = (float)v;
-    kd = h[2];
-    ks = fmaf(kd, vf, h[1]);
+    kd = w.c7;
+    ks = fmaf(kd, vf, w.c6);
     kd = fmaf(kd, vf, ks);
-    ks = fmaf(ks, vf, h[0]);
+    ks = fmaf(ks, vf, w.c5);
 }
 __device__ inline void horner2(const PairGeo<double> &g0, const PairGeo<double> &g1, double &ks0, double &kd0,
                                double &ks1, double &kd1)
 {
+    const Row64 w0 = load_row(g0), w1 = load_row(g1);
     float hs0, hd0, hs1, hd1;
-    horner_hi(g0.c, g0.v, hs0, hd0);
-    horner_hi(g1.c, g1.v, hs1, hd1);
+    horner_hi(w0, g0.v, hs0, hd0);
+    horner_hi(w1, g1.v, hs1, hd1);
     ks0 = hs0;
     kd0 = hd0;
     ks1 = hs1;
@@ -190,8 +215,8 @@ __device__ inline void horner2(const PairGeo<double> &g0, const PairGeo<double> 
     for (int m = TAB_NC64 - 1; m >= 0; --m) {
         kd0 = fma(kd0, g0.v, ks0);
         kd1 = fma(kd1, g1.v, ks1);
-        ks0 = fma(ks0, g0.v, g0.c[m]);
-        ks1 = fma(ks1, g1.v, g1.c[m]);
+        ks0 = fma(ks0, g0.v, w0.c[m]);
+        ks1 = fma(ks1, g1.v, w1.c[m]);
     }
 }
 __device__ inline void horner1(const PairGeo<float> &g, float &ks, float &kd)
@@ -206,21 +231,23 @@ __device__ inline void horner1(const PairGeo<float> &g, float &ks, float &kd)
 }
 __device__ inline void horner1(const PairGeo<double> &g, double &ks, double &kd)
 {
+    const Row64 w = load_row(g);
     float hs, hd;
-    horner_hi(g.c, g.v, hs, hd);
+    horner_hi(w, g.v, hs, hd);
     ks = hs;
     kd = hd;
 #pragma unroll
     for (int m = TAB_NC64 - 1; m >= 0; --m) {
         kd = fma(kd, g.v, ks);
-        ks = fma(ks, g.v, g.c[m]);
+        ks = fma(ks, g.v, w.c[m]);
     }
 }
 
 // One work item: the LV_WAVE targets of wavefront list `wave` against its
 // candidate sources, for the densities of chunk `chunk` (BCH of them).
 template <int BCH, typename T, int STRIDE>
-__device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, int lane, int wave, int chunk)
+__device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const float *s_c7, int lane, int wave,
+                                  int chunk)
 {
     const int64_t t = (int64_t)wave * LV_WAVE + lane;
     double x = 0.0, y = 0.0;
@@ -278,9 +305,9 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, int lan
                 // the far-away source of zero strength)
                 bool in0, in1;
                 const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
-                                                          s_tab, zseg, in0);
+                                                          s_tab, s_c7, zseg, in0);
                 const PairGeo<T> g1 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k + 1), bcast(cur.y, k + 1), fscale,
-                                                          f_max, s_tab, zseg, in1);
+                                                          f_max, s_tab, s_c7, zseg, in1);
                 if (__ballot(in0 || in1) == 0) continue;
                 T ks0, kd0, ks1, kd1;
                 horner2(g0, g1, ks0, kd0, ks1, kd1);
@@ -293,7 +320,7 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, int lan
             for (int k = 0; k < cnt; ++k) {
                 bool in0;
                 const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
-                                                          s_tab, zseg, in0);
+                                                          s_tab, s_c7, zseg, in0);
                 if (__ballot(in0) == 0) continue;
                 T ks0, kd0;
                 horner1(g0, ks0, kd0);
@@ -329,12 +356,19 @@ __global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
     T *s_tab = reinterpret_cast<T *>(lds);                // [nseg + 1][STRIDE], the last segment zero
     const int tid = threadIdx.x;
     for (int i = tid; i < (A.nseg + 1) * STRIDE; i += NB) s_tab[i] = i < A.nseg * STRIDE ? A.tab[i] : (T)0;
+    // FP64 table: c_7 of every segment (the zero segment's last) after the rows
+    float *s_c7 = nullptr;
+    if constexpr (std::is_same<T, double>::value) {
+        s_c7 = reinterpret_cast<float *>(s_tab + (A.nseg + 1) * STRIDE);
+        const float *g7 = reinterpret_cast<const float *>(A.tab + (size_t)A.nseg * STRIDE);
+        for (int i = tid; i <= A.nseg; i += NB) s_c7[i] = i < A.nseg ? g7[i] : 0.0f;
+    }
     __syncthreads();
     const int lane = tid % LV_WAVE;
     if (!PERSIST) {
         // the wave number is wave-uniform
         const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[blockIdx.x * (NB / LV_WAVE) + tid / LV_WAVE]);
-        level_item<BCH, T, STRIDE>(A, s_tab, lane, wave, blockIdx.y);
+        level_item<BCH, T, STRIDE>(A, s_tab, s_c7, lane, wave, blockIdx.y);
         return;
     }
     const int nchunk = (A.B + BCH - 1) / BCH;
@@ -345,8 +379,18 @@ __global__ void __launch_bounds__(NB) k_level_sums(LevelArgs<T> A)
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
         if (item >= nitems) break;
         const int wave = __builtin_amdgcn_readfirstlane(A.wave_order[item / nchunk]);
-        level_item<BCH, T, STRIDE>(A, s_tab, lane, wave, item % nchunk);
+        level_item<BCH, T, STRIDE>(A, s_tab, s_c7, lane, wave, item % nchunk);
     }
+}
+
+// LDS bytes of a level's table: the rows of nseg + 1 segments (the last zero)
+// and, FP64, their c_7 as floats
+template <typename T, int STRIDE>
+static size_t level_lds(int nseg)
+{
+    size_t b = sizeof(T) * (size_t)(nseg + 1) * STRIDE;
+    if (std::is_same<T, double>::value) b += sizeof(float) * (size_t)(nseg + 2);
+    return b;
 }
 
 template <typename T>
@@ -433,7 +477,7 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     const int want = std::min(B, P->p.lv_bch);
     const int bch = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
     const int nby = (B + bch - 1) / bch;
-    const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
+    const size_t lds = level_lds<T, STRIDE>(L.nseg);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int nb = P->p.lv_block;
     const bool pers = P->p.lv_persist != 0;
@@ -486,7 +530,7 @@ static hipError_t level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init)
     const int want = std::min(B, P->p.lv_bch);
     const int bch = want <= 1 ? 1 : want <= 2 ? 2 : want <= 4 ? 4 : 8;
     const int nby = (B + bch - 1) / bch;
-    const size_t lds = sizeof(T) * (size_t)(L.nseg + 1) * STRIDE;
+    const size_t lds = level_lds<T, STRIDE>(L.nseg);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     const int nb = P->p.lv_block;
     const bool pers = P->p.lv_persist != 0;

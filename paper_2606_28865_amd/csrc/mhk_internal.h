@@ -44,7 +44,8 @@ constexpr int TILE = 32;         // fine-grid tile edge of spreading/interpolati
 constexpr int MAXJ = 8;          // maximum number of dyadic levels
 constexpr int TAB_NC = 8;        // coefficients per table segment (degree 7)
 constexpr int TAB_NC64 = 5;      // FP64 path: c_0..c_4 stored as doubles, c_5..c_7 as floats
-constexpr int TAB_STRIDE = 7;    // doubles per segment in LDS: c_0..c_4, three floats and a pad
+constexpr int TAB_STRIDE = 6;    // doubles per segment row: c_0..c_4 and c_5, c_6 as two floats (48 bytes);
+                                 // c_7 (float) in an array of its own after the rows
                                  // (14 dwords: spreads segments over the banks)
 constexpr int TABF_NC = 8;       // FP32 path: coefficients per segment (degree 7)
 constexpr int TABF_STRIDE = 9;   // FP32 path: floats per segment

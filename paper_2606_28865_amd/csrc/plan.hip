@@ -804,12 +804,14 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
     const int nc = fp64 ? TAB_NC : TABF_NC, stride = fp64 ? TAB_STRIDE : TABF_STRIDE;
     const double tab_tol = fp64 ? 1e-12 : 1e-8;
     std::vector<double> tab;
+    std::vector<float> tab7;         // FP64 path: c_7 of each segment
     // segment width halved while the table (or its derivative) misses tab_tol
     // (large alpha^2 delta_j makes K_j decay like e^{-4a})
     for (double seg_w = fp64 ? 0.0625 : 0.25;; seg_w *= 0.5) {
         L.seg_inv = 1.0 / seg_w;
         L.nseg = (int)ceil(L.a_max / seg_w) + 1;
         tab.assign((size_t)L.nseg * stride, 0.0);
+        tab7.assign((size_t)L.nseg, 0.0f);
         std::vector<double> node(nc);
         for (int i = 0; i < nc; ++i) node[i] = cos(M_PI * (i + 0.5) / nc);
         for (int sgi = 0; sgi < L.nseg; ++sgi) {
@@ -847,9 +849,9 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
             double *row = &tab[(size_t)sgi * stride];
             if (fp64) {
                 for (int k = 0; k < TAB_NC64; ++k) row[k] = (double)mono[k];
-                float hi[2 * (TAB_STRIDE - TAB_NC64)] = {};
-                for (int k = TAB_NC64; k < nc; ++k) hi[k - TAB_NC64] = (float)mono[k];
+                const float hi[2] = {(float)mono[TAB_NC64], (float)mono[TAB_NC64 + 1]};
                 memcpy(row + TAB_NC64, hi, sizeof hi);
+                tab7[sgi] = (float)mono[TAB_NC - 1];
             } else {
                 for (int k = 0; k < nc; ++k) row[k] = (double)mono[k];
             }
@@ -873,7 +875,8 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
             if (fp64) {
                 // the device's order: Horner over c_7..c_5 in FP32, then c_4..c_0 in FP64
                 float hi[TAB_NC - TAB_NC64];
-                memcpy(hi, c + TAB_NC64, sizeof hi);
+                memcpy(hi, c + TAB_NC64, 2 * sizeof(float));
+                hi[2] = tab7[sgi];
                 const float vf = (float)v;
                 float kd = hi[2], ks = fmaf(kd, vf, hi[1]);
                 kd = fmaf(kd, vf, ks);
@@ -911,6 +914,10 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
         L.tab_dev = L.tabf;
         return MHK_OK;
     }
+    // the rows, then c_7 of every segment as floats (two per double)
+    const size_t nrow = tab.size();
+    tab.resize(nrow + ((size_t)L.nseg + 1) / 2, 0.0);
+    memcpy(tab.data() + nrow, tab7.data(), sizeof(float) * (size_t)L.nseg);
     TRY(upload(P, &L.tab, tab.data(), (int64_t)tab.size()));
     L.tab_dev = L.tab;
     return MHK_OK;
