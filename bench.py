@@ -527,7 +527,7 @@ def run_precision(a):
             e64, _ = _sample_errors(w, info, alpha, out, n_each=6)
             res[name]["rel_err_vs_oracle_fp64_inputs"] = {"S": e64[0], "D": e64[1], "V": e64[2]}
         res[name].update({
-                     "stage_ms": {k: round(info[k], 4) for k in info if k.startswith("ms_")},
+                     "stage_ms": {k: round(info[k], 4) for k in info if k.startswith("ms_") and not isinstance(info[k], list)},
                      "grid": info["n_fine"], "wspread": info["wspread"]})
         log(f"{name}: {ms:.2f} ms, errs {errs}")
         p.close()
