@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=4,
                     help="serve: requests of one plan coalesced into one launch")
     ap.add_argument("--heat-steps", type=int, default=8, help="serve: steps of each heat chain")
+    ap.add_argument("--lv-block", type=int, default=0, help="level-sum workgroup size (0: the plan's default)")
+    ap.add_argument("--lv-persist", type=int, default=0, help="1: persistent level-sum launch")
     return ap.parse_args()
 
 
@@ -115,7 +117,7 @@ def main():
     plans, plan_s = [], []
     for al, s in zip(alphas, streams):
         t1 = time.time()
-        prm = M.make_params(alpha=al, tol=a.tol, dx=w.dx)
+        prm = M.make_params(alpha=al, tol=a.tol, dx=w.dx, lv_block=a.lv_block, lv_persist=a.lv_persist)
         p = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=s)
         torch.cuda.synchronize()
         plan_s.append(time.time() - t1)
