@@ -725,6 +725,16 @@ def run_serve(a):
     plain.finished.clear()
     sweep_plain, _, _, _ = sweep_loads(plain, (0.95, 1.5), mean_svc, "not coalesced")
     plain.close()
+    # cold start: a fresh server at 80% load, every plan built on its
+    # simulation's first request (in the server's build thread, beside the
+    # requests of plans already built)
+    cold = Server(budget_bytes=budget, max_inflight=8, max_batch=a.max_batch)
+    sweep_cold, done_cold, _, _ = sweep_loads(cold, (0.8,), mean_svc, "cold start")
+    first = {}
+    for r in sorted(done_cold, key=lambda r: r.arrival):
+        first.setdefault(r.geometry.key, r)
+    sweep_cold[0]["first_request_ms"] = {k: round((r.done - r.arrival) * 1e3, 1) for k, r in first.items()}
+    cold.close()
     heat = run_serve_heat(a, make_req, mean_svc, len(sims))
     st = latency_stats(done_all)
     line = {"metric": "served target evals/s with p50/p99 request latency", "value": evals_all / span_all,
@@ -733,7 +743,7 @@ def run_serve(a):
             "dtype": "f32+f64", "data": "synthetic",
             "config": {"workload": "rothe-serving", "simulations": len(sims), "requests_per_load": a.requests,
                        "sizes": sizes, "max_batch": a.max_batch},
-            "latency": st, "sweep": sweep, "sweep_not_coalesced": sweep_plain,
+            "latency": st, "sweep": sweep, "sweep_not_coalesced": sweep_plain, "cold_start": sweep_cold[0],
             "alone_service_ms": [round(x * 1e3, 3) for x in alone], "heat_chains": heat}
     print(json.dumps(line), flush=True)
 

@@ -12,6 +12,8 @@
 #include <cstring>
 #include <numeric>
 
+#include <mutex>
+
 #include "mhk_internal.h"
 
 namespace mhk {
@@ -429,7 +431,15 @@ static void free_plan(mhk_plan *P)
     delete P;
 }
 
-static bool g_rocfft_ready = false;
+// rocFFT's one-time setup, once per process even when plans are created
+// from several threads at a time
+static std::once_flag g_rocfft_once;
+static rocfft_status g_rocfft_setup = rocfft_status_success;
+static rocfft_status rocfft_ready()
+{
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    return g_rocfft_setup;
+}
 
 // ---------------------------------------------------------------------------
 // Plan construction
@@ -1101,10 +1111,7 @@ mhk_status build_history(mhk_plan *P, Host &H)
     History &G = P->hist;
     const double alpha = P->p.alpha, delta = P->delta;
     if (!G.active) return MHK_OK;
-    if (!g_rocfft_ready) {
-        MHK_FFT(rocfft_setup());
-        g_rocfft_ready = true;
-    }
+    MHK_FFT(rocfft_ready());
 
     // window polynomials: phi at grid point m0 + k of a source at g, as a
     // function of t = 2(m0 - g + w/2) - 1 in [-1, 1), fitted by Chebyshev
@@ -1277,10 +1284,7 @@ mhk_status build_history(mhk_plan *P, Host &H)
         G.grid = g;
     }
     const rocfft_precision fprec = P->p.prec == MHK_FP64 ? rocfft_precision_double : rocfft_precision_single;
-    if (!g_rocfft_ready) {
-        MHK_FFT(rocfft_setup());
-        g_rocfft_ready = true;
-    }
+    MHK_FFT(rocfft_ready());
     // column path: the column transforms in LDS need n <= COL_NMAX and
     // radices 8, 9, 6, 4, 2, 3, 5 (the grid sizes are 2^a 3^b 5^c)
     auto factor = [](int64_t m, int8_t *radix, int &np) -> bool {

@@ -250,8 +250,20 @@ class TorchDevice:
 
 
 class Server:
+    """Request loop over a device (TorchDevice, or a fake one in tests).
+
+    async_build: create new plans in worker threads (default: on for the
+    real device; build_workers of them, each plan on its own stream), so
+    that the loop keeps retiring and admitting requests of other plans while
+    new geometries' plans are built; a request waits behind its plan, whose
+    footprint is reserved while it is built."""
+
     def __init__(self, device=None, budget_bytes: Optional[int] = None, max_inflight: int = 8,
-                 clock: Callable[[], float] = time.perf_counter, max_batch: int = 1):
+                 clock: Callable[[], float] = time.perf_counter, max_batch: int = 1,
+                 async_build: Optional[bool] = None, build_workers: int = 2):
+        self.async_build = (device is None) if async_build is None else bool(async_build)
+        self.builder = (concurrent.futures.ThreadPoolExecutor(max_workers=max(1, int(build_workers)))
+                        if self.async_build else None)
         self.dev = device if device is not None else TorchDevice()
         if budget_bytes is None:
             import torch
@@ -268,6 +280,7 @@ class Server:
         self.used = 0
         self.finished: List[Request] = []
         self.rejected: List[Request] = []
+        self.build_errors: Dict[Tuple, Exception] = {}
 
     def _batch(self, req: Request) -> int:
         """Batch capacity of the plan a request runs on."""
@@ -316,12 +329,33 @@ class Server:
             if nxt is not None:
                 self.submit(nxt)
 
+    def _poll_builds(self):
+        """Plans built in the worker thread: resident once done (their
+        reservation replaced by their actual size), or dropped with the
+        error that the next request of the plan will carry."""
+        for key, ent in list(self.plans.items()):
+            fut = ent.get("building")
+            if fut is None or not fut.done():
+                continue
+            ent["building"] = None
+            try:
+                plan, pbytes = fut.result()
+            except Exception as e:
+                self.used -= ent["bytes"]
+                del self.plans[key]
+                self.build_errors[key] = e
+                continue
+            self.used += pbytes - ent["bytes"]
+            ent.update(plan=plan, bytes=pbytes, busy=False)
+
     def step(self) -> int:
         """Retire finished launches, admit what fits; returns the number of
         requests admitted in this pass.  A request whose footprint, plan
         creation or launch raises is rejected with its error; the plan's
         state and the memory accounting are rolled back and the other
         requests stay queued."""
+        if self.async_build:
+            self._poll_builds()
         still = []
         for group, h, io in self.inflight:
             try:
@@ -354,6 +388,9 @@ class Server:
                 if len(self.inflight) >= self.max_inflight or key in blocked_keys:
                     waiting.append(req)
                     continue
+                if key in self.build_errors:
+                    self._fail(req, self.build_errors.pop(key))
+                    continue
                 ent = self.plans.get(key)
                 if ent is not None and ent["busy"]:
                     blocked_keys.add(key)
@@ -372,6 +409,16 @@ class Server:
                     self.rejected.append(req)
                     continue
                 if not self._evict_for(need, key):
+                    blocked_keys.add(key)
+                    waiting.append(req)
+                    continue
+                if ent is None and self.async_build:
+                    # build in the worker thread, the footprint reserved;
+                    # the request waits for its plan
+                    fp = need - io
+                    self.plans[key] = {"plan": None, "bytes": fp, "busy": True,
+                                       "building": self.builder.submit(self.dev.create_plan, req, B)}
+                    self.used += fp
                     blocked_keys.add(key)
                     waiting.append(req)
                     continue
@@ -433,13 +480,18 @@ class Server:
                 self.queue.append(r)
                 i += 1
             n = self.step()
-            if n == 0 and (self.inflight or (i < len(arrivals))):
+            building = any(e.get("building") is not None for e in self.plans.values())
+            if n == 0 and (self.inflight or building or (i < len(arrivals))):
                 time.sleep(poll_s)
         return self.finished
 
     def close(self):
+        if self.builder is not None:
+            self.builder.shutdown(wait=True)
+            self._poll_builds()
         for ent in self.plans.values():
-            self.dev.destroy_plan(ent["plan"])
+            if ent["plan"] is not None:
+                self.dev.destroy_plan(ent["plan"])
         self.plans.clear()
         self.used = 0
         if hasattr(self.dev, "close"):

@@ -236,3 +236,63 @@ def test_heat_chain_steps_depend_on_each_other():
     assert all(c.finished for c in chains)
     assert [s.step for s in chains[0].steps] == [1, 2, 3]
     assert sorted(r.rid for r in srv.finished) == [101, 102, 103, 201, 202, 203]
+
+
+def test_async_plan_build_keeps_other_plans_running():
+    """A new geometry's plan is built in the worker thread: meanwhile the
+    loop admits and retires requests of a resident plan; the new plan's
+    request runs once the build is done; its footprint is reserved while it
+    is built and replaced by the plan's size afterwards; a failed build
+    fails the request that waited for it and releases the reservation."""
+    import threading
+    import time as _time
+
+    clk = FakeClock()
+    gate = threading.Event()
+
+    class SlowBuild(FakeDevice):
+        def create_plan(self, req, batch=1):
+            if req.geometry.key == "B":
+                assert gate.wait(10.0)
+                if req.alpha == 99.0:
+                    raise RuntimeError("build failed")
+            return super().create_plan(req, batch)
+
+    dev = SlowBuild(clk, {"A": 100, "B": 200}, {"A": 1.0, "B": 1.0})
+    srv = Server(dev, budget_bytes=1000, max_inflight=4, clock=clk, async_build=True)
+    srv.submit(_req(0, "A"))
+    for _ in range(200):                       # A's plan built in the worker thread
+        srv.step()
+        if dev.launched == [0]:
+            break
+        _time.sleep(0.005)
+    assert dev.launched == [0]
+    srv.submit(_req(1, "B"))
+    srv.step()                                 # B's build starts and blocks
+    assert srv.used == 100 + 10 + 200          # A resident + its io, B reserved
+    clk.t = 1.0
+    srv.submit(_req(2, "A"))
+    srv.step()                                 # A's first request retires, the second runs, B still building
+    assert [r.rid for r in srv.finished] == [0]
+    assert dev.launched == [0, 2]
+    gate.set()
+    for _ in range(200):
+        srv.step()
+        if 1 in dev.launched:
+            break
+        _time.sleep(0.005)
+    assert dev.launched == [0, 2, 1]
+    assert srv.used == 100 + 10 + 200 + 10
+    # a failing build: its waiting request is rejected, the reservation released
+    clk.t = 2.0
+    srv.step()
+    used = srv.used
+    srv.submit(_req(3, "B", alpha=99.0))
+    for _ in range(200):
+        srv.step()
+        if srv.rejected:
+            break
+        _time.sleep(0.005)
+    assert [r.rid for r in srv.rejected] == [3] and "build failed" in srv.rejected[0].error
+    assert srv.used == used
+    srv.close()
