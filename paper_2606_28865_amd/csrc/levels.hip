@@ -7,8 +7,11 @@
 // from one piecewise-polynomial table of K_j^S in a = r^2/(4 delta_j) held in
 // LDS: Horner's rule gives the polynomial and its derivative together, and
 // K_j^D is a constant times dK_j^S/da, applied once per target at the end
-// (the table reads, which bound the loop, serve both kernels).  Pairs with
-// a >= a_max are below the requested accuracy and skipped.
+// (the table reads serve both kernels).  Pairs with a >= a_max are below
+// the requested accuracy and skipped (a lane beyond it reads the table's
+// zero segment).  Target and source coordinates are scaled by sqrt(seg_inv / (4 delta_j)),
+// so that the squared separation is the segment coordinate a seg_inv itself;
+// the double-layer sum is rescaled once per target.
 //
 // Work decomposition: a wavefront owns 64 consecutive targets of the Morton
 // order, one per lane, and a flat list (built at plan time) of the sources
@@ -17,13 +20,13 @@
 // loaded while the current one is summed -- and hands each source to all
 // lanes with readlane; each lane keeps its target's sums in registers: no
 // atomics, no barriers in the loop, deterministic summation order.  Sources
-// are taken two at a time with no branch per lane: a lane out of range of a
-// source reads the table's last segment, which is zero, and a pair of
-// sources out of range of every lane is skipped as a whole.  The two
-// polynomial evaluations are independent, so their table reads and
-// multiply-adds interleave.  The kernel table sits in LDS (shared by the
-// wavefronts of a workgroup) with a padded segment stride so that the
-// per-lane gathers of different segments spread over the LDS banks.
+// are taken two at a time with no branch per lane, and a pair of sources out
+// of range of every lane is skipped as a whole.  The two polynomial
+// evaluations are independent, so their table reads and multiply-adds
+// interleave.  The kernel table sits in LDS (shared by the wavefronts of a
+// workgroup) in rows of 48 bytes, an odd multiple of 16, read as aligned
+// 16-byte loads, so that neighbouring segments fall in different bank
+// groups.
 //
 // Precision: T = double (FP64 path) or float (FP32 path).  In the FP32 path
 // the separation x - x_q is formed in FP64 from FP64 positions and rounded
@@ -89,6 +92,7 @@ struct LevelArgs {
     int64_t nout, n_src;
     const double *tx, *ty;
     double inv4d, a_max, seg_inv, d_scale;
+    double pscale;        // sqrt(inv4d seg_inv): coordinates scaled by it give f = a seg_inv = |dx|^2
     int nseg, B;
     const int32_t *wave_ofs, *wave_src, *wave_order;
     const double *sx, *sy;
@@ -134,16 +138,20 @@ struct PairGeo {
 };
 
 template <typename T, int STRIDE>
-__device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv, T fscale, T f_max,
-                                      const T *s_tab, const float *s_c7, int zseg, bool &in)
+__device__ inline PairGeo<T> pair_geo(double x, double y, double sxv, double syv, T f_max, T f_zero,
+                                      const T *s_tab, const float *s_c7, bool &in)
 {
     PairGeo<T> g;
     g.dx = (T)(x - sxv);
     g.dy = (T)(y - syv);
-    const T f = (g.dx * g.dx + g.dy * g.dy) * fscale;
+    // coordinates are scaled so that |dx|^2 is the segment coordinate
+    // f = a seg_inv; a pair beyond the cut-off reads the zero segment f_zero
+    // (at v = -1), which adds exactly nothing
+    const T f = g.dx * g.dx + g.dy * g.dy;
     in = f < f_max;
-    const int sg = in ? (int)f : zseg;
-    g.v = in ? (T)2 * frac_part(f) - (T)1 : (T)0;
+    const T fc = in ? f : f_zero;
+    const int sg = (int)fc;
+    g.v = (T)2 * frac_part(fc) - (T)1;
     g.c = s_tab + __umul24((unsigned)sg, (unsigned)STRIDE);
     if constexpr (std::is_same<T, double>::value) g.c7 = s_c7 + sg;
     return g;
@@ -250,15 +258,14 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
                                   int chunk)
 {
     const int64_t t = (int64_t)wave * LV_WAVE + lane;
+    const double ps = A.pscale;
     double x = 0.0, y = 0.0;
     if (t < A.nout) {
-        x = A.tx[t];
-        y = A.ty[t];
+        x = A.tx[t] * ps;
+        y = A.ty[t] * ps;
     }
     const int b0 = chunk * BCH, nbh = min(BCH, A.B - b0);
-    // segment coordinate f = a seg_inv = r^2 inv4d seg_inv in one product
-    const T fscale = (T)(A.inv4d * A.seg_inv), f_max = (T)(A.a_max * A.seg_inv);
-    const int zseg = A.nseg;
+    const T f_max = (T)(A.a_max * A.seg_inv), f_zero = (T)A.nseg;
     T S[BCH], D[BCH];
 #pragma unroll
     for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
@@ -270,8 +277,8 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
     auto load = [&](int pos, int end, SrcBatch<T, BCH> &sb) {
         if (pos < end) {
             const int s = A.wave_src[pos];
-            sb.x = A.sx[s];
-            sb.y = A.sy[s];
+            sb.x = A.sx[s] * ps;
+            sb.y = A.sy[s] * ps;
 #pragma unroll
             for (int b = 0; b < BCH; ++b) {
                 const T *qb = q0 + (size_t)min(b, nbh - 1) * A.n_src + s;
@@ -304,10 +311,10 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
                 // sources k and k + 1 (past the batch's end: a lane holding
                 // the far-away source of zero strength)
                 bool in0, in1;
-                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
-                                                          s_tab, s_c7, zseg, in0);
-                const PairGeo<T> g1 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k + 1), bcast(cur.y, k + 1), fscale,
-                                                          f_max, s_tab, s_c7, zseg, in1);
+                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), f_max, f_zero,
+                                                          s_tab, s_c7, in0);
+                const PairGeo<T> g1 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k + 1), bcast(cur.y, k + 1), f_max,
+                                                          f_zero, s_tab, s_c7, in1);
                 if (__ballot(in0 || in1) == 0) continue;
                 T ks0, kd0, ks1, kd1;
                 horner2(g0, g1, ks0, kd0, ks1, kd1);
@@ -319,8 +326,8 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
             // the registers, so one source at a time
             for (int k = 0; k < cnt; ++k) {
                 bool in0;
-                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), fscale, f_max,
-                                                          s_tab, s_c7, zseg, in0);
+                const PairGeo<T> g0 = pair_geo<T, STRIDE>(x, y, bcast(cur.x, k), bcast(cur.y, k), f_max, f_zero,
+                                                          s_tab, s_c7, in0);
                 if (__ballot(in0) == 0) continue;
                 T ks0, kd0;
                 horner1(g0, ks0, kd0);
@@ -456,7 +463,8 @@ static hipError_t level_sums(mhk_plan *P, hipStream_t st, int j, bool want_s, bo
     A.inv4d = L.inv4d;
     A.a_max = L.a_max;
     A.seg_inv = L.seg_inv;
-    A.d_scale = level_d_scale(L);
+    A.pscale = sqrt(L.inv4d * L.seg_inv);
+    A.d_scale = level_d_scale(L) / A.pscale;       // D was summed over scaled separations
     A.nseg = L.nseg;
     A.B = B;
     A.wave_ofs = L.wave_ofs;
@@ -512,7 +520,8 @@ static hipError_t level_sums_v(mhk_plan *P, hipStream_t st, int j, bool init)
     A.inv4d = L.inv4d;
     A.a_max = L.a_max;
     A.seg_inv = L.seg_inv;
-    A.d_scale = level_d_scale(L);
+    A.pscale = sqrt(L.inv4d * L.seg_inv);
+    A.d_scale = level_d_scale(L) / A.pscale;       // D was summed over scaled separations
     A.nseg = L.nseg;
     A.B = B;
     A.wave_ofs = V.wave_ofs;
