@@ -183,8 +183,36 @@ def main():
     log(f"resident local geometry: {ms_res:.3f} ms/step")
     noconv = [int(p.info()["n_noconv"]) for p in plans]
 
+    # per-potential rates: S alone, D alone, V alone at every output of every
+    # plan, closest points included
+    per_pot = {}
+    for name, args in (("S", (sigma, None, None, None)), ("D", (None, mu, None, None)),
+                       ("V", (None, None, fv, ft))):
+        po = [p.eval(*args, parts=fresh) for p in plans]
+
+        def pstep(args=args, po=po):
+            for i in order:
+                plans[i].eval(*args, out=po[i], parts=fresh, join=False)
+            for s in streams:
+                if s is not cur:
+                    cur.wait_stream(s)
+        for _ in range(a.warmup):
+            pstep()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(a.steps):
+            pstep()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_p = ev0.elapsed_time(ev1) / a.steps
+        per_pot[name] = {"ms_per_step": round(ms_p, 4), "target_evals_per_s": evals / (ms_p * 1e-3)}
+        del po
+    log(f"per potential: {per_pot}")
+
     # dominant kernel: the level sums (largest summed stage time)
     roof = roofline(stage, infos, w)
+    stage_roof = stage_rooflines(stage, infos, w, roof)
 
     # parity against the oracle on a stratified sample of every plan's
     # outputs; the oracle's time on it is the CPU baseline
@@ -192,6 +220,8 @@ def main():
     cpu = None
     if not a.no_check:
         check, cpu = parity_check(w, infos, alphas, outs, a.check_each)
+        # the oracle's time for one whole step at its measured rate
+        cpu["extrapolated_step_s"] = evals / cpu["value"]
 
     # the FP32 half of the metric (tol 1e-6) on its own workload, after the
     # FP64 plans are released
@@ -232,6 +262,8 @@ def main():
         "wall_s": round(wall, 3),
         "rel_err_vs_oracle": check,
         "roofline": roof,
+        "per_potential": per_pot,
+        "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
         "fp32": fp32,
         "latency_note": "p50/p99 request latency: bench.py --workload serve",
@@ -268,6 +300,57 @@ def roofline(stage, infos, w):
             "flops_per_launch": flops / launches, "ms_per_launch": ms / launches,
             "frac_kernel_count": ach * LEVEL_FLOPS_PER_PAIR_KERNEL / LEVEL_FLOPS_PER_PAIR / FP64_PEAK,
             "flops_per_pair_kernel": LEVEL_FLOPS_PER_PAIR_KERNEL}
+
+
+def stage_rooflines(stage, infos, w, roof):
+    """Roofline fractions of the hot-path stages from their algorithmic work
+    (the per-unit counts below) over their measured HIP-event times (the
+    last timed step, the three plans overlapping), summed over the plans,
+    and the time-weighted fraction over the stages counted.  The row and
+    column transforms with the multiplier are timed but not counted: they
+    move only the rows and columns of the sources' and targets' windows, and
+    their measured HBM bytes are in the committed counter profile.
+      spread (a3): per source component (S, D_x, D_y at the boundary nodes,
+        V at the volume nodes) 2W^2 + 20W flops (window values and products);
+      interpolation (a7): per output and result (S, D, V) 2W^2 + 20W flops,
+        16 B of position read and 8 B written;
+      level sums (a9): 23 flops per in-range pair (the dominant kernel);
+      closest point and local part (a10-a11): per output in a local band
+        ~600 flops (Newton on the panels, the coefficients), transcendentals
+        not counted."""
+    from scipy.spatial import cKDTree
+    X = np.concatenate([w.tx, w.boundary["x"]])
+    Y = np.concatenate([w.ty, w.boundary["y"]])
+    d, _ = cKDTree(np.column_stack([w.boundary["x"], w.boundary["y"]])).query(np.column_stack([X, Y]))
+    n_comp = 3 * w.n_b + w.n_v
+    out = {}
+    fl_sp = fl_in = fl_loc = 0.0
+    for info in infos:
+        W = int(info["wspread"])
+        per = 2 * W * W + 20 * W
+        fl_sp += n_comp * per
+        fl_in += 3 * len(X) * per
+        band = max(info["band_layer"], info["band_volume"])
+        fl_loc += 600.0 * float(np.count_nonzero(d < band))
+    t_sp = sum(stage["ms_spread"]) * 1e-3
+    t_in = sum(stage["ms_interp"]) * 1e-3
+    t_loc = (sum(stage["ms_geometry"]) + sum(stage["ms_local"])) * 1e-3
+    t_lv = sum(stage["ms_levels"]) * 1e-3
+    t_fft = (sum(stage["ms_fft"]) + sum(stage["ms_multiply"])) * 1e-3
+    bytes_in = len(infos) * len(X) * (16 + 3 * 8)
+    ent = lambda fl, t: {"ms": round(t * 1e3, 4), "achieved_tflops": fl / t / 1e12,
+                         "frac": fl / t / 1e12 / FP64_PEAK, "bound": "alu (FP64)"}
+    out["a3_spread"] = ent(fl_sp, t_sp)
+    out["a7_interp"] = dict(ent(fl_in, t_in), achieved_gbs=bytes_in / t_in / 1e9,
+                            frac_hbm=bytes_in / t_in / 1e9 / HBM_PEAK)
+    out["a9_levels"] = {"ms": round(t_lv * 1e3, 4), "achieved_tflops": roof["achieved"], "frac": roof["frac"],
+                        "bound": "alu (FP64)"}
+    out["a10_a11_local"] = ent(fl_loc, t_loc)
+    counted = [("a3_spread", t_sp), ("a7_interp", t_in), ("a9_levels", t_lv), ("a10_a11_local", t_loc)]
+    tw = sum(t for _, t in counted)
+    out["time_weighted_frac"] = sum(out[k]["frac"] * t for k, t in counted) / tw
+    out["fft_multiply_ms_not_counted"] = round(t_fft * 1e3, 4)
+    return out
 
 
 # Algorithmic flops of one (target, child node) pair with r < R_j, as the
