@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--heat-steps", type=int, default=8, help="serve: steps of each heat chain")
     ap.add_argument("--lv-block", type=int, default=0, help="level-sum workgroup size (0: the plan's default)")
     ap.add_argument("--lv-persist", type=int, default=0, help="1: persistent level-sum launch")
+    ap.add_argument("--no-per-potential", action="store_true",
+                    help="skip the per-potential rates (profiling runs: only the step's own launches)")
     return ap.parse_args()
 
 
@@ -186,8 +188,8 @@ def main():
     # per-potential rates: S alone, D alone, V alone at every output of every
     # plan, closest points included
     per_pot = {}
-    for name, args in (("S", (sigma, None, None, None)), ("D", (None, mu, None, None)),
-                       ("V", (None, None, fv, ft))):
+    for name, args in () if a.no_per_potential else (("S", (sigma, None, None, None)), ("D", (None, mu, None, None)),
+                                                      ("V", (None, None, fv, ft))):
         po = [p.eval(*args, parts=fresh) for p in plans]
 
         def pstep(args=args, po=po):
@@ -514,7 +516,14 @@ def _sample_errors(w, info, alpha, outs, n_each=12, seed=3, round32=False):
                   inside=w.inside, on_surface=True, sigma=r(w.sigma), mu=r(w.mu), f_vol=r(w.f_vol),
                   f_trg=r(w.f_trg))
     t0 = time.perf_counter()
-    ref = P.eval(sub)
+    # in chunks of 16 outputs (one per host thread), with a progress line for
+    # each (the oracle sums every source directly: seconds per output on the
+    # large workloads)
+    parts = []
+    for c in range(0, len(sub), 16):
+        parts.append(P.eval(sub[c:c + 16]))
+        log(f"oracle sample: {min(c + 16, len(sub))}/{len(sub)} outputs, {time.perf_counter() - t0:.1f} s")
+    ref = [np.concatenate([q[k] for q in parts]) for k in range(3)]
     dt = time.perf_counter() - t0
     errs = []
     for o, rr in zip(outs, ref):
@@ -547,21 +556,31 @@ def fp32_half(a, w):
     p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=M.MHK_FP32, dx=w.dx, in64=1), w.boundary, w.volume,
                (w.tx, w.ty, w.inside), on_surface=True)
     plan_s = time.time() - t1
-    out = p.eval(*ins)
-    for _ in range(a.warmup):
-        p.eval(*ins, out=out)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(a.steps):
-        p.eval(*ins, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
+    # like the FP64 line: closest points and local coefficients recomputed in
+    # every evaluation; the rate with them kept from plan creation beside
+    fresh = M.PART_ALL | M.PART_GEOMETRY
+
+    def timed(parts):
+        for _ in range(a.warmup):
+            p.eval(*ins, out=out, parts=parts)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            p.eval(*ins, out=out, parts=parts)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / a.steps
+    out = p.eval(*ins, parts=fresh)
+    ms = timed(fresh)
+    ms_res = timed(M.PART_ALL)
+    p.eval(*ins, out=out, parts=fresh)
     info = p.info()
     res = {"workload": "multibody-precision", "n_boundary": w.n_b, "n_volume": w.n_v, "n_targets": w.n_t,
            "alpha": alpha, "tol": tol, "inputs": "FP64 (in64)", "ms_per_eval": ms,
-           "target_evals_per_s": p.n_out / (ms * 1e-3), "grid": info["n_fine"], "plan_s": round(plan_s, 3)}
+           "target_evals_per_s": p.n_out / (ms * 1e-3), "step": "closest points included",
+           "resident_geometry": {"ms_per_eval": ms_res, "target_evals_per_s": p.n_out / (ms_res * 1e-3)},
+           "grid": info["n_fine"], "plan_s": round(plan_s, 3)}
     if not a.no_check:
         errs, _ = _sample_errors(w, info, alpha, out, n_each=6)
         res["rel_err_vs_oracle_fp64_inputs"] = {"S": errs[0], "D": errs[1], "V": errs[2]}
@@ -588,19 +607,21 @@ def run_precision(a):
         ins = (t(w.sigma), t(w.mu), t(w.f_vol), t(w.f_trg))
         p = M.Plan(M.make_params(alpha=alpha, tol=tol, prec=prec, dx=w.dx), w.boundary, w.volume,
                    (w.tx, w.ty, w.inside), on_surface=True)
-        out = p.eval(*ins)
+        # closest points recomputed in every evaluation, as in the default line
+        fresh = M.PART_ALL | M.PART_GEOMETRY
+        out = p.eval(*ins, parts=fresh)
         for _ in range(a.warmup):
-            p.eval(*ins, out=out)
+            p.eval(*ins, out=out, parts=fresh)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(a.steps):
-            p.eval(*ins, out=out)
+            p.eval(*ins, out=out, parts=fresh)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
         p.set_timing(True)
-        p.eval(*ins, out=out)
+        p.eval(*ins, out=out, parts=fresh)
         info = p.info()
         errs, odt = _sample_errors(w, info, alpha, out, n_each=6, round32=(name == "fp32"))
         res[name] = {"ms_per_eval": ms, "target_evals_per_s": p.n_out / (ms * 1e-3),
@@ -669,7 +690,8 @@ def run_batched(a):
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             p = M.Plan(prm, w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True, stream=stream)
-            out = p.capture(*ins)
+            # closest points recomputed in every call (shared by its densities)
+            out = p.capture(*ins, parts=M.PART_ALL | M.PART_GEOMETRY)
             for _ in range(a.warmup):
                 p.replay()
             stream.synchronize()
@@ -681,7 +703,7 @@ def run_batched(a):
             stream.synchronize()
             ms = e0.elapsed_time(e1) / a.steps
             p.set_timing(True)
-            p.eval(*ins, out=out)
+            p.eval(*ins, out=out, parts=M.PART_ALL | M.PART_GEOMETRY)
             info = p.info()
             p.set_timing(False)
         key = (info["alpha"], info["delta"])

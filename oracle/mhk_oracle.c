@@ -745,7 +745,7 @@ int or_eval(const or_problem *P, const int64_t *subset, int64_t n_subset,
         }
     }
 
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t o = 0; o < nout; ++o) {
         int64_t it = subset ? subset[o] : o;
         int on = it >= P->n_trg;
@@ -870,7 +870,7 @@ void or_level_sum_S(double alpha, double delta, int j, int64_t ns, const double 
     or_init();
     const double dj = delta / pow(4.0, j - 1);
     const double rmax2 = 160.0 * dj;
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nt; ++t) {
         double acc = 0.0;
         for (int64_t s = 0; s < ns; ++s) {

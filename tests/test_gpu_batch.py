@@ -19,14 +19,16 @@ def _t(a, dt=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_graph_replay_matches_eager(prec):
+@pytest.mark.parametrize("prec,geom", [(0, False), (1, False), (0, True)])
+def test_graph_replay_matches_eager(prec, geom):
+    """geom: the closest points recomputed inside the graph (MHK_PART_GEOMETRY)."""
     import paper_2606_28865_amd as M
     w = synth.config0()
     B = 5
     dt = torch.float64 if prec == 0 else torch.float32
     tol = 1e-10 if prec == 0 else 1e-6
-    print(f"case graph replay prec={prec} batch={B}", flush=True)
+    parts = M.PART_ALL | (M.PART_GEOMETRY if geom else 0)
+    print(f"case graph replay prec={prec} batch={B} geometry={geom}", flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         prm = M.make_params(alpha=10.0, tol=tol, prec=prec, dx=w.dx, batch=B)
@@ -36,7 +38,7 @@ def test_graph_replay_matches_eager(prec):
         mu = torch.zeros_like(sig)
         fv = torch.zeros((B, w.n_v), dtype=dt, device="cuda")
         ft = torch.zeros((B, w.n_t + w.n_b), dtype=dt, device="cuda")
-        out = plan.capture(sig, mu, fv, ft)
+        out = plan.capture(sig, mu, fv, ft, parts=parts)
         g = np.random.default_rng(11)
         for rep in range(4):
             scale = g.uniform(0.5, 2.0, B)
