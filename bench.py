@@ -30,8 +30,8 @@ FP64_PEAK = 78.6           # TFLOP/s, vector FP64
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--alphas", type=str, default="1,10,100")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--check-each", type=int, default=8,
