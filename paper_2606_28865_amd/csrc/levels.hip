@@ -267,8 +267,12 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
     const int b0 = chunk * BCH, nbh = min(BCH, A.B - b0);
     const T f_max = (T)(A.a_max * A.seg_inv), f_zero = (T)A.nseg;
     T S[BCH], D[BCH];
+    // FP32 path: the sums of each batch of 64 sources are added into FP64
+    // totals (a volume level sums thousands of nodes per target, where one
+    // running FP32 sum would lose about sqrt(N) roundings)
+    double S64[BCH], D64[BCH];
 #pragma unroll
-    for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0;
+    for (int b = 0; b < BCH; ++b) S[b] = D[b] = (T)0, S64[b] = D64[b] = 0.0;
     // strengths of density b0 + b: q[c][b0 + b][s] for c = S, D_x, D_y
     const size_t fstride = (size_t)A.B * A.n_src;
     const T *q0 = A.q + (size_t)b0 * A.n_src;
@@ -334,14 +338,32 @@ __device__ inline void level_item(const LevelArgs<T> &A, const T *s_tab, const f
                 accumulate(cur, k, g0, ks0, kd0);
             }
         }
+        if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+            for (int b = 0; b < BCH; ++b) {
+                S64[b] += (double)S[b];
+                D64[b] += (double)D[b];
+                S[b] = D[b] = 0.0f;
+            }
+        }
         cur = nxt;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+        for (int b = 0; b < BCH; ++b) {
+            S[b] = (float)S64[b];
+            D[b] = (float)(D64[b] * A.d_scale);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < BCH; ++b) D[b] *= A.d_scale;
     }
     if (t < A.nout) {
 #pragma unroll
         for (int b = 0; b < BCH; ++b) {
             if (b < nbh) {
                 const size_t o = (size_t)(b0 + b) * A.nout + t;
-                const T s = S[b], d = D[b] * (T)A.d_scale;
+                const T s = S[b], d = D[b];
                 if (A.want_s) A.acc_s[o] = A.init ? s : A.acc_s[o] + s;
                 if (A.want_d) A.acc_d[o] = A.init ? d : A.acc_d[o] + d;
             }

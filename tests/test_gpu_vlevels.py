@@ -76,3 +76,47 @@ def test_volume_levels_disk_closed_form():
         plan.close()
     print(f"disk V[1] errors (targets, boundary nodes): plain {errs[0]}, volume levels {errs[1]}", flush=True)
     assert errs[1][0] < errs[0][0] and errs[1][1] < errs[0][1]
+
+
+def test_volume_levels_fp32_fp64_inputs():
+    """An FP32 plan (FP64 inputs) with volume levels against the FP64 oracle
+    with volume levels: the FP32 level sums over the volume level nodes,
+    within the FP32 bar of 1e-6."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    alpha = 10.0
+    print("case volume levels fp32 config0", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=1e-6, prec=M.MHK_FP32, in64=1, dx=w.dx, v_levels=1), w.boundary,
+                  w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    V = plan.eval(None, None, _dev(w.f_vol), _dev(w.f_trg))[2].cpu().numpy().astype(np.float64).ravel()
+    torch.cuda.synchronize()
+    sub = stratified_subset(w, info["band_layer"] * 8, n_each=48, seed=4)
+    Vo = vlevels.volume_potential(w, alpha, info["delta"], info["J"], w.volume["rule"], w.f_trg, subset=sub)
+    ev = rel_err(V[sub], Vo)
+    print(f"volume levels fp32: V {ev:.2e}", flush=True)
+    assert ev < 1e-6
+
+
+def test_volume_levels_second_order():
+    """A second-order plan with volume levels against the oracle at the same
+    order (f's gradient and Hessian from the analytic sources), FP64 at
+    1e-10."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    alpha = 10.0
+    X = np.concatenate([w.tx, w.boundary["x"]])
+    Y = np.concatenate([w.ty, w.boundary["y"]])
+    jet = w.meta["fsrc"].jet(X, Y)
+    print("case volume levels order 2 config0", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx, v_levels=1, local_order=2), w.boundary, w.volume,
+                  (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    V = plan.eval(None, None, _dev(w.f_vol), _dev(jet))[2].cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    sub = stratified_subset(w, info["band_layer"] * 8, n_each=48, seed=4)
+    Vo = vlevels.volume_potential(w, alpha, info["delta"], info["J"], w.volume["rule"], jet[0], subset=sub,
+                                  order=2, f_jet=jet[1:])
+    ev = rel_err(V[sub], Vo)
+    print(f"volume levels order 2: V {ev:.2e}", flush=True)
+    assert ev < TOL
