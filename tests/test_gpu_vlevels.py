@@ -120,3 +120,47 @@ def test_volume_levels_second_order():
     ev = rel_err(V[sub], Vo)
     print(f"volume levels order 2: V {ev:.2e}", flush=True)
     assert ev < TOL
+
+
+def test_volume_levels_without_f_trg():
+    """Volume levels with f at the targets reconstructed by the plan (f_trg
+    omitted) against the oracle fed the oracle's reconstruction."""
+    import paper_2606_28865_amd as M
+    from oracle import fjets
+    w = synth.config0()
+    alpha = 10.0
+    print("case volume levels without f_trg config0", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx, v_levels=1), w.boundary, w.volume,
+                  (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    V = plan.eval(None, None, _dev(w.f_vol), None)[2].cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    ftrg = fjets.f_at_targets(w.volume, w.f_vol, w.tx, w.ty, w.inside, w.boundary, rows=1)[0]
+    sub = stratified_subset(w, info["band_layer"] * 8, n_each=48, seed=4)
+    Vo = vlevels.volume_potential(w, alpha, info["delta"], info["J"], w.volume["rule"], ftrg, subset=sub)
+    ev = rel_err(V[sub], Vo)
+    print(f"volume levels without f_trg: V {ev:.2e}", flush=True)
+    assert ev < TOL
+
+
+def test_volume_levels_batch_matches_single():
+    """A batch of three sources through the volume levels equals each source
+    evaluated alone (FP64, 1e-13)."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    alpha = 10.0
+    B = 3
+    scale = np.array([1.0, -0.5, 2.0])
+    print("case volume levels batch 3 config0", flush=True)
+    pb = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx, v_levels=1, batch=B), w.boundary, w.volume,
+                (w.tx, w.ty, w.inside), on_surface=True)
+    p1 = M.Plan(M.make_params(alpha=alpha, tol=TOL, dx=w.dx, v_levels=1), w.boundary, w.volume,
+                (w.tx, w.ty, w.inside), on_surface=True)
+    fv = np.stack([w.f_vol * s for s in scale])
+    ft = np.stack([w.f_trg * s for s in scale])
+    Vb = pb.eval(None, None, _dev(fv), _dev(ft))[2].cpu().numpy()
+    for k in range(B):
+        V1 = p1.eval(None, None, _dev(fv[k]), _dev(ft[k]))[2].cpu().numpy().ravel()
+        e = rel_err(Vb[k], V1)
+        print(f"density {k}: {e:.2e}", flush=True)
+        assert e < 1e-13
