@@ -99,3 +99,23 @@ def test_order2_multibody_sampled(alpha):
             rel_err(V.cpu().numpy().ravel()[sub], Vo)]
     print(f"order2 multibody alpha={alpha}: errors {errs}", flush=True)
     assert max(errs) < TOL, errs
+
+
+def test_order2_fp32_fp64_inputs():
+    """A second-order FP32 plan (FP64 inputs; the local part is FP64 at both
+    precisions) against the second-order FP64 oracle, within the FP32 bar
+    of 1e-6."""
+    import paper_2606_28865_amd as M
+    w = synth.config0()
+    alpha = 10.0
+    print("case order2 fp32 config0", flush=True)
+    plan = M.Plan(M.make_params(alpha=alpha, tol=1e-6, prec=M.MHK_FP32, in64=1, dx=w.dx, local_order=2),
+                  w.boundary, w.volume, (w.tx, w.ty, w.inside), on_surface=True)
+    info = plan.info()
+    jet, fv = _jets(w)
+    S, D, V = [o.cpu().numpy().astype(np.float64) for o in plan.eval(_dev(w.sigma), _dev(w.mu), _dev(fv), _dev(jet))]
+    torch.cuda.synchronize()
+    So, Do, Vo = _oracle(w, alpha, info["delta"], w.sigma, w.mu, fv, jet)
+    errs = [rel_err(S, So), rel_err(D, Do), rel_err(V, Vo)]
+    print(f"order2 fp32: errors {errs}", flush=True)
+    assert max(errs) < 1e-6, errs
