@@ -12,6 +12,7 @@
 #include <cstring>
 #include <numeric>
 
+#include <map>
 #include <mutex>
 
 #include "mhk_internal.h"
@@ -131,26 +132,47 @@ static double expint_e1(double x)
 // a = r^2/(4 delta_j), b = alpha^2 delta_j (eqs. (diffker_s), (diffker_dlp)).
 // Composite 16-point Gauss-Legendre on 12 panels.
 struct LevelQuad {
-    std::vector<double> t, w;
-    LevelQuad() { gauss_legendre(16, t, w); }
+    // nodes e^u and weights of the composite rule (12 panels of 16
+    // Gauss-Legendre points on [0, ln 4]), formed once
+    static constexpr int NQ = 12 * 16;
+    double eu[NQ], ieu[NQ], wq[NQ];
+    LevelQuad()
+    {
+        std::vector<double> t, w;
+        gauss_legendre(16, t, w);
+        const double hh = log(4.0) / 12;
+        for (int p = 0; p < 12; ++p)
+            for (int q = 0; q < 16; ++q) {
+                const double u = hh * (p + 0.5 * (1 + t[q]));
+                eu[p * 16 + q] = exp(u);
+                ieu[p * 16 + q] = exp(-u);
+                wq[p * 16 + q] = w[q] * 0.5 * hh;
+            }
+    }
     void eval(double a, double b, double &i0, double &i1) const
     {
-        const double L = log(4.0);
-        const int m = 12;
-        const double hh = L / m;
-        long double s0 = 0, s1 = 0;
-        for (int p = 0; p < m; ++p)
-            for (int q = 0; q < 16; ++q) {
-                double u = hh * (p + 0.5 * (1 + t[q]));
-                double eu = exp(u);
-                long double e = w[q] * exp(-a * eu - b / eu);
-                s0 += e;
-                s1 += e * eu;
-            }
-        i0 = (double)(s0 * 0.5 * hh);
-        i1 = (double)(s1 * 0.5 * hh);
+        double s0 = 0, s1 = 0;
+        for (int k = 0; k < NQ; ++k) {
+            const double e = wq[k] * exp(-a * eu[k] - b * ieu[k]);
+            s0 += e;
+            s1 += e * eu[k];
+        }
+        i0 = s0;
+        i1 = s1;
     }
 };
+
+// Kernel tables depend only on alpha^2 delta_j, the cut-off and the
+// precision: plans created again for the same parameters (a moving geometry
+// stepped in time) take them from this cache.
+struct TableEntry {
+    std::vector<double> tab;
+    std::vector<float> tab7;
+    double seg_inv = 0, tab_err = 0;
+    int nseg = 0;
+};
+static std::mutex g_table_mu;
+static std::map<std::array<uint64_t, 3>, TableEntry> g_tables;
 
 static int64_t good_fft_size(int64_t nmin)
 {
@@ -815,9 +837,29 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
     const double tab_tol = fp64 ? 1e-12 : 1e-8;
     std::vector<double> tab;
     std::vector<float> tab7;         // FP64 path: c_7 of each segment
+    std::array<uint64_t, 3> tkey{};
+    {
+        uint64_t kb, ka;
+        memcpy(&kb, &b_j, 8);
+        memcpy(&ka, &L.a_max, 8);
+        tkey = {kb, ka, (uint64_t)fp64};
+    }
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(g_table_mu);
+        auto it = g_tables.find(tkey);
+        if (it != g_tables.end()) {
+            tab = it->second.tab;
+            tab7 = it->second.tab7;
+            L.seg_inv = it->second.seg_inv;
+            L.nseg = it->second.nseg;
+            L.tab_err = it->second.tab_err;
+            cached = true;
+        }
+    }
     // segment width halved while the table (or its derivative) misses tab_tol
     // (large alpha^2 delta_j makes K_j decay like e^{-4a})
-    for (double seg_w = fp64 ? 0.0625 : 0.25;; seg_w *= 0.5) {
+    for (double seg_w = fp64 ? 0.0625 : 0.25; !cached; seg_w *= 0.5) {
         L.seg_inv = 1.0 / seg_w;
         L.nseg = (int)ceil(L.a_max / seg_w) + 1;
         tab.assign((size_t)L.nseg * stride, 0.0);
@@ -910,7 +952,17 @@ mhk_status build_level(mhk_plan *P, Host &H, int j)
             emax = std::max(emax, fabs(dS * dscale - i1 * cD) / k0D);
         }
         L.tab_err = emax;
-        if (emax <= tab_tol) break;
+        if (emax <= tab_tol) {
+            std::lock_guard<std::mutex> lock(g_table_mu);
+            if (g_tables.size() >= 256) g_tables.clear();
+            TableEntry &e = g_tables[tkey];
+            e.tab = tab;
+            e.tab7 = tab7;
+            e.seg_inv = L.seg_inv;
+            e.nseg = L.nseg;
+            e.tab_err = emax;
+            break;
+        }
         if (seg_w < 0.01) {
             char msg[128];
             snprintf(msg, sizeof msg, "level kernel table not accurate: %.3e of K_j(0)", emax);

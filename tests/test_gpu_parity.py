@@ -264,3 +264,22 @@ def test_exterior_volume_targets():
         print(f"exterior V batch {b}: err {e:.2e}, finite {np.isfinite(Vo).all()}", flush=True)
         assert np.isfinite(Vo).all()
         assert e < TOL
+
+
+def test_plan_recreated_reuses_tables(cfg0):
+    """A plan created again for the same parameters (a geometry stepped in
+    time keeps alpha and delta) takes its level kernel tables from the
+    process-wide cache: the same outputs, bit for bit in the level sums and
+    the local part."""
+    w = cfg0
+    print("case plan recreated", flush=True)
+    p1 = _plan(w, 7.0)
+    a = _run(p1, w, parts=O.PART_LEVELS | O.PART_LOCAL)
+    t1 = p1.info()["ms_plan"]
+    p1.close()
+    p2 = _plan(w, 7.0)
+    b = _run(p2, w, parts=O.PART_LEVELS | O.PART_LOCAL)
+    t2 = p2.info()["ms_plan"]
+    print(f"level phase of plan creation: first {t1[2]:.1f} ms, again {t2[2]:.1f} ms", flush=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.nan_to_num(x, nan=1e300), np.nan_to_num(y, nan=1e300))
