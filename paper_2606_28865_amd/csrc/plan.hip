@@ -1506,15 +1506,22 @@ mhk_status build_local(mhk_plan *P, Host &H)
             const double ey = std::max(0.0, std::max(bb[2] - yc, yc - bb[3]));
             return ex * ex + ey * ey;
         };
-        std::sort(pairs.begin(), pairs.end(), [&](const std::array<int64_t, 2> &a, const std::array<int64_t, 2> &c) {
-            if (a[0] != c[0]) return a[0] < c[0];
-            const double da = dist_c(a[0], a[1]), dc = dist_c(c[0], c[1]);
-            return da != dc ? da < dc : a[1] < c[1];
+        // (the distance formed once per pair, not per comparison)
+        struct Key {
+            int64_t cell;
+            double d;
+            int64_t panel;
+        };
+        std::vector<Key> keys(pairs.size());
+        for (size_t k = 0; k < pairs.size(); ++k) keys[k] = {pairs[k][0], dist_c(pairs[k][0], pairs[k][1]), pairs[k][1]};
+        std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &c) {
+            if (a.cell != c.cell) return a.cell < c.cell;
+            return a.d != c.d ? a.d < c.d : a.panel < c.panel;
         });
-        cand.resize(std::max<size_t>(1, pairs.size()));
-        for (size_t k = 0; k < pairs.size(); ++k) {
-            start[pairs[k][0] + 1]++;
-            cand[k] = (int32_t)pairs[k][1];
+        cand.resize(std::max<size_t>(1, keys.size()));
+        for (size_t k = 0; k < keys.size(); ++k) {
+            start[keys[k].cell + 1]++;
+            cand[k] = (int32_t)keys[k].panel;
         }
         for (int64_t c = 0; c < ncx * ncy; ++c) start[c + 1] += start[c];
         TRY(upload(P, &C.cand, cand.data(), (int64_t)cand.size()));
