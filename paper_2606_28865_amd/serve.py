@@ -132,13 +132,17 @@ class HeatChain:
 
 
 class TorchDevice:
-    """The real device: plans of libmhk on their own torch streams."""
+    """The real device: plans of libmhk on their own torch streams, on the
+    device current when it is constructed (or `device`).  Worker threads
+    start on device 0, so every plan's stream is made on that device and
+    the work of a plan runs inside its stream's context, which selects it."""
 
-    def __init__(self, workers: int = 4):
+    def __init__(self, workers: int = 4, device: Optional[int] = None):
         import torch
         from . import _lib as L
         self.torch = torch
         self.L = L
+        self.index = torch.cuda.current_device() if device is None else int(device)
         self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=workers)
 
     def _params(self, req: Request, batch: int):
@@ -163,7 +167,7 @@ class TorchDevice:
     def create_plan(self, req: Request, batch: int = 1):
         torch = self.torch
         g = req.geometry
-        stream = torch.cuda.Stream()
+        stream = torch.cuda.Stream(device=self.index)
         with torch.cuda.stream(stream):
             plan = self.L.Plan(self._params(req, batch), g.boundary, g.volume, g.targets, on_surface=g.on_surface,
                                stream=stream)
