@@ -212,6 +212,30 @@ def test_edge_cases(cfg0):
     assert rel_err(S.cpu().numpy(), So) < TOL
 
 
+def test_single_target(cfg0):
+    """One off-surface output (n_out = 1: a partial wavefront, workgroup and
+    tile in every kernel): the interior target nearest the boundary, so that
+    the level sums, the closest point and the layer and volume local terms
+    all run for it."""
+    from scipy.spatial import cKDTree
+    w = cfg0
+    M = _M()
+    d, _ = cKDTree(np.column_stack([w.boundary["x"], w.boundary["y"]])).query(np.column_stack([w.tx, w.ty]))
+    d = np.where(w.inside != 0, d, np.inf)
+    k = int(np.argmin(d))
+    tx, ty, ins, ft = w.tx[k:k + 1], w.ty[k:k + 1], w.inside[k:k + 1], w.f_trg[k:k + 1]
+    print(f"case single target: index {k}, distance {d[k]:.2e}", flush=True)
+    plan = M.Plan(M.make_params(alpha=10.0, tol=TOL, dx=w.dx), w.boundary, w.volume, (tx, ty, ins),
+                  on_surface=False)
+    assert plan.n_out == 1
+    out = plan.eval(_dev(w.sigma), _dev(w.mu), _dev(w.f_vol), _dev(ft))
+    torch.cuda.synchronize()
+    P = O.Problem(10.0, plan.info()["delta"], 3, w.boundary, volume=w.volume, targets=(tx, ty), inside=ins,
+                  on_surface=False, sigma=w.sigma, mu=w.mu, f_vol=w.f_vol, f_trg=ft)
+    for g, o in zip(out, P.eval()):
+        assert rel_err(g.cpu().numpy(), o) < TOL
+
+
 @pytest.mark.parametrize("alpha,trunc", [(1.0, 1), (30.0, 0)])
 def test_multibody_sampled(alpha, trunc):
     """Small multi-body workload (3 bodies, 2048 boundary nodes, ~40k volume
